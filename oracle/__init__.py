@@ -1,0 +1,186 @@
+"""FP64 CPU oracle for WNNC normal orientation -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the GPU library
+and never imports it.
+
+Contents (paper: Lin, Shi, Liu 2024, WNNC normal orientation):
+
+* ``normalize``            -- the input normalization of Sec. 4.1.1.
+* ``direct``               -- exact O(N^2) FP64 sums of A, A^T, G with the
+                              smoothing cutoff (Thm. 1, Sec. 3.2, Sec. 3.4),
+                              in C (``liboracle.so``).
+* ``direct_np``            -- the same sums in vectorized numpy for small N
+                              (a second, independent transcription).
+* ``Tree``                 -- the paper's treecode (Sec. 3.5, Alg. 4) in C.
+* ``grad_step``/``orient`` -- Alg. 2 and Alg. 3 (``iterate.py``).
+
+Parity pins: see the module docstrings of ``direct_np`` and ``iterate`` and
+the ``tests/test_oracle_*.py`` files.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+OP_A, OP_AT, OP_G = 0, 1, 2
+_OPS = {"A": OP_A, "AT": OP_AT, "G": OP_G}
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = _build.build(force=False)
+    lib = ctypes.CDLL(path)
+    d = ctypes.POINTER(ctypes.c_double)
+    i64 = ctypes.c_int64
+    lib.or_direct.argtypes = [ctypes.c_int, d, i64, d, d, i64, ctypes.c_double, d, d]
+    lib.or_direct.restype = None
+    lib.or_tree_new.argtypes = [d, i64, ctypes.c_int, ctypes.c_int]
+    lib.or_tree_new.restype = ctypes.c_void_p
+    lib.or_tree_free.argtypes = [ctypes.c_void_p]
+    lib.or_tree_nnodes.argtypes = [ctypes.c_void_p]
+    lib.or_tree_nnodes.restype = i64
+    p32 = ctypes.POINTER(ctypes.c_int32)
+    p64 = ctypes.POINTER(ctypes.c_int64)
+    lib.or_tree_export.argtypes = [ctypes.c_void_p, p32, p32, p64, p64, p64]
+    lib.or_tree_reps.argtypes = [ctypes.c_void_p, d, ctypes.c_int, d, d, d]
+    lib.or_tree_apply.argtypes = [ctypes.c_void_p, ctypes.c_int, d, ctypes.c_double,
+                                  ctypes.c_double, d, i64, d, d, p64]
+    lib.or_num_threads.restype = ctypes.c_int
+    lib.or_set_threads.argtypes = [ctypes.c_int]
+    _lib = lib
+    return lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def num_threads() -> int:
+    return int(_load().or_num_threads())
+
+
+def set_threads(n: int) -> None:
+    _load().or_set_threads(int(n))
+
+
+def normalize(points):
+    """Sec. 4.1.1: fit the cloud into [-1,1]^3 with a margin of 1/11.
+
+    Reading: centre = midpoint of the bounding box; one uniform scale so that
+    the largest half-extent becomes 1 - 1/11 = 10/11.  Computed in FP64 from
+    the FP32 input and rounded once to FP32.  Returns (x32, center, scale)
+    with x = (p - center) * scale.
+    """
+    p = np.asarray(points, dtype=np.float32).astype(np.float64)
+    lo = p.min(axis=0)
+    hi = p.max(axis=0)
+    center = (lo + hi) / 2.0
+    half = float(((hi - lo) / 2.0).max())
+    scale = (10.0 / 11.0) / half if half > 0 else 1.0
+    x = ((p - center) * scale).astype(np.float32)
+    return x, center, scale
+
+
+def direct(op: str, x, nu, w: float, targets=None, with_mag: bool = False):
+    """Exact FP64 sum of operator op in {"A","AT","G"} over all source points x
+    (n,3) with attributes nu ((n,3) for A and G, (n,) for AT), evaluated at
+    targets (default: the points themselves)."""
+    lib = _load()
+    o = _OPS[op]
+    x = _f64(x, (-1, 3))
+    nu = _f64(nu, (x.shape[0], -1) if o != OP_AT else (x.shape[0],))
+    t = x if targets is None else _f64(targets, (-1, 3))
+    dout = 1 if o == OP_A else 3
+    out = np.zeros((t.shape[0], dout))
+    mag = np.zeros(t.shape[0])
+    lib.or_direct(o, _dp(x), x.shape[0], _dp(nu), _dp(t), t.shape[0], float(w), _dp(out), _dp(mag))
+    out = out[:, 0] if dout == 1 else out
+    return (out, mag) if with_mag else out
+
+
+class Tree:
+    """The paper's octree and treecode (Sec. 3.5, Alg. 4), FP64, in C."""
+
+    def __init__(self, x, max_depth: int = 15, leaf_cap: int = 1):
+        lib = _load()
+        self.x = _f64(x, (-1, 3))
+        self.n = self.x.shape[0]
+        self.max_depth = int(max_depth)
+        self.leaf_cap = int(leaf_cap)
+        self._h = lib.or_tree_new(_dp(self.x), self.n, self.max_depth, self.leaf_cap)
+        if not self._h:
+            raise ValueError("invalid tree parameters")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.or_tree_free(h)
+            self._h = None
+
+    @property
+    def nnodes(self) -> int:
+        return int(_load().or_tree_nnodes(self._h))
+
+    def export(self):
+        """(depth, leaf, begin, end, order): node member sets are
+        order[begin[k]:end[k]] (caller indices)."""
+        m = self.nnodes
+        depth = np.zeros(m, np.int32)
+        leaf = np.zeros(m, np.int32)
+        begin = np.zeros(m, np.int64)
+        end = np.zeros(m, np.int64)
+        order = np.zeros(self.n, np.int64)
+        P32 = ctypes.POINTER(ctypes.c_int32)
+        P64 = ctypes.POINTER(ctypes.c_int64)
+        _load().or_tree_export(self._h, depth.ctypes.data_as(P32), leaf.ctypes.data_as(P32),
+                               begin.ctypes.data_as(P64), end.ctypes.data_as(P64),
+                               order.ctypes.data_as(P64))
+        return depth, leaf, begin, end, order
+
+    def reps(self, nu):
+        """nu-representatives of every node: (x_B (m,3), nu_B (m,3|1), W (m,))."""
+        nu = np.asarray(nu, dtype=np.float64)
+        dim = 1 if nu.ndim == 1 else 3
+        nu = _f64(nu, (self.n, dim))
+        m = self.nnodes
+        xB = np.zeros((m, 3))
+        nuB = np.zeros((m, 3))
+        W = np.zeros(m)
+        _load().or_tree_reps(self._h, _dp(nu), dim, _dp(xB), _dp(nuB), _dp(W))
+        return xB, (nuB[:, 0] if dim == 1 else nuB), W
+
+    def apply(self, op: str, nu, w: float, c: float = 2.0, targets=None, with_stats: bool = False):
+        """Treecode operator; returns out (and per-target magnitude sums and
+        pair counts with with_stats)."""
+        lib = _load()
+        o = _OPS[op]
+        nu = _f64(nu, (self.n, 3) if o != OP_AT else (self.n,))
+        t = self.x if targets is None else _f64(targets, (-1, 3))
+        dout = 1 if o == OP_A else 3
+        out = np.zeros((t.shape[0], dout))
+        mag = np.zeros(t.shape[0])
+        pairs = np.zeros(t.shape[0], np.int64)
+        lib.or_tree_apply(self._h, o, _dp(nu), float(w), float(c), _dp(t), t.shape[0],
+                          _dp(out), _dp(mag), pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+        out = out[:, 0] if dout == 1 else out
+        return (out, mag, pairs) if with_stats else out
+
+
+from .iterate import grad_step, orient, width_schedule, rescale  # noqa: E402
+from . import direct_np  # noqa: E402,F401

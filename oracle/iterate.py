@@ -1,0 +1,112 @@
+"""Alg. 2 (grad_step) and Alg. 3 (WNNC iteration with smoothing) in FP64.
+
+Test infrastructure only.  The operators come from either the exact direct
+sums or the paper's treecode, both in this package.
+
+Alg. 3, per iteration i = 1..n:
+  w = w2 (n-i)/(n-1) + w1 (i-1)/(n-1)              (width schedule)
+  mu <- grad_step(mu; A_w, b),  b = (1/2, ..., 1/2)  (Alg. 2)
+  mu^ <- G_w(mu)                                     (WNNC update)
+  mu_i <- mu^_i |mu_i| / |mu^_i|                     (rescale)
+starting from mu = 0 (Sec. 3.3).
+
+Alg. 2 for E(mu) = ||A mu - b||^2:
+  r <- A^T b - A^T A mu,  alpha <- r^T r / (r^T A^T A r),  mu <- mu + alpha r
+
+Readings (where the paper leaves a choice):
+* r is evaluated as one adjoint application to the residual, r = A^T(b - A mu),
+  and r^T A^T A r as |A r|^2, so one step costs A, A^T, A.  With the exact
+  operators this is the printed formula; with the treecode it is the natural
+  way to apply it (the treecode adjoint is not linear in its argument).
+* alpha = 0 when |A r|^2 = 0.
+* rescale keeps mu_i unchanged when |mu^_i| is 0 or not finite, and a zero
+  mu_i stays zero.
+* n = 1 uses w = w1.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def width_schedule(i: int, n: int, w1: float, w2: float) -> float:
+    """Linear width schedule of Alg. 3 (i is 1-based)."""
+    if n <= 1:
+        return float(w1)
+    return w2 * (n - i) / (n - 1) + w1 * (i - 1) / (n - 1)
+
+
+def rescale(mu, mu_hat):
+    """mu_i <- mu^_i |mu_i| / |mu^_i| (Alg. 3); kept when |mu^_i| is 0 or
+    not finite."""
+    mu = np.asarray(mu, dtype=np.float64)
+    mu_hat = np.asarray(mu_hat, dtype=np.float64)
+    nh = np.linalg.norm(mu_hat, axis=1)
+    nm = np.linalg.norm(mu, axis=1)
+    ok = np.isfinite(nh) & (nh > 0)
+    out = mu.copy()
+    out[ok] = mu_hat[ok] * (nm[ok] / nh[ok])[:, None]
+    return out
+
+
+class _Ops:
+    """A, A^T, G at width w through the chosen backend."""
+
+    def __init__(self, x, backend, c=2.0, max_depth=15, leaf_cap=1):
+        from . import Tree, direct
+        self.x = np.asarray(x, dtype=np.float64)
+        self.backend = backend
+        self.c = c
+        if backend == "tree":
+            self.tree = Tree(self.x, max_depth=max_depth, leaf_cap=leaf_cap)
+        elif backend == "direct":
+            self._direct = direct
+        elif backend == "numpy":
+            from . import direct_np
+            self._np = direct_np
+        else:
+            raise ValueError(backend)
+
+    def __call__(self, op, nu, w):
+        if self.backend == "tree":
+            return self.tree.apply(op, nu, w, self.c)
+        if self.backend == "direct":
+            return self._direct(op, self.x, nu, w)
+        return getattr(self._np, op)(self.x, nu, w)
+
+
+def grad_step(ops, mu, w, b=0.5):
+    """Alg. 2 for ||A_w mu - b||^2; returns (mu_new, alpha, r, E) where E is
+    the energy of the incoming mu."""
+    s = ops("A", mu, w)
+    rho = b - s
+    r = ops("AT", rho, w)
+    t = ops("A", r, w)
+    den = float((t * t).sum())
+    alpha = float((r * r).sum()) / den if den > 0 else 0.0
+    return mu + alpha * r, alpha, r, float((rho * rho).sum())
+
+
+def orient(x, iters=40, w1=0.002, w2=0.016, mu0=None, backend="tree", c=2.0,
+           max_depth=15, leaf_cap=1, start_iter=1, grad=True, wnnc=True,
+           do_rescale=True, callback=None):
+    """Alg. 3 on normalized points x (n,3).  Returns mu (n,3) in FP64.
+
+    grad / wnnc / do_rescale switch the three steps off for the ablations of
+    Sec. 4.7 (defaults: the full method).  callback(i, mu, info) is called
+    after every iteration.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    ops = _Ops(x, backend, c, max_depth, leaf_cap)
+    mu = np.zeros_like(x) if mu0 is None else np.array(mu0, dtype=np.float64)
+    for i in range(start_iter, iters + 1):
+        w = width_schedule(i, iters, w1, w2)
+        info = {"w": w}
+        if grad:
+            mu, alpha, _, E = grad_step(ops, mu, w)
+            info.update(alpha=alpha, E=E)
+        if wnnc:
+            mu_hat = ops("G", mu, w)
+            mu = rescale(mu, mu_hat) if do_rescale else mu_hat
+        if callback is not None:
+            callback(i, mu, info)
+    return mu

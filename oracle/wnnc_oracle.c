@@ -1,0 +1,366 @@
+/*
+ * wnnc_oracle.c -- FP64 CPU oracle for the WNNC operators.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain reference the GPU
+ * library is checked against.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark load it; the library never does, and this
+ * file shares no code, header, table or helper with the GPU path.
+ *
+ * Everything is double precision.  Point arrays are row-major (n, 3) in the
+ * caller's order.  Notation follows the paper (Lin, Shi, Liu 2024,
+ * "Fast and Globally Consistent Normal Orientation based on the Winding
+ * Number Normal Consistency"):
+ *
+ *   Phi(y)      = 1 / (4 pi |y|)                       (Thm. 1)
+ *   grad Phi(y) = -y / (4 pi |y|^3)                    (Thm. 1)
+ *   H Phi(y)    = -I/(4 pi |y|^3) + 3 y y^T/(4 pi |y|^5)  (Sec. 3.2)
+ *
+ *   A  : mu -> s,     s_i   = sum_j gradPhi(x_i - x_j) . mu_j     (Sec. 3.3, E)
+ *   A^T: rho -> v,    v_j   = sum_i rho_i gradPhi(x_i - x_j)      (Alg. 2)
+ *   G  : mu -> mu^,   mu^_i = -grad F(x_i; mu)
+ *                            = -sum_j HPhi(x_i - x_j) mu_j        (Sec. 3.2)
+ *
+ * Smoothing (Sec. 3.4): a pair term is set to 0 when |x_i - x_j| < w.  The
+ * coincident pair |y| = 0 is also 0 (it is excluded for every w > 0 anyway).
+ *
+ * Treecode (Sec. 3.5, Alg. 4): an octree over [-1,1]^3 is built by recursive
+ * partition; a node is split while it holds more than `leaf_cap` points
+ * (1 in the paper) and its depth is below the maximum depth D (15 in the
+ * paper).  Child membership: a coordinate equal to the split plane goes to
+ * the upper child.  For attribute nu the node representative sits at
+ * x_B = sum |nu_i| x_i / sum |nu_j| and carries nu_B = sum nu_i (eqs. for the
+ * nu-representatives).  A node whose weight sum |nu| is 0 carries nothing and
+ * is skipped.  Per target, starting from the root: if |x - x_B| > c * width(B)
+ * the representative stands for the node (with the w cutoff); otherwise an
+ * internal node recurses into its children and a leaf sums its points
+ * directly (with the w cutoff).  width(B) = 2^(1 - depth(B)).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_PI 3.14159265358979323846
+#define OR_OP_A 0
+#define OR_OP_AT 1
+#define OR_OP_G 2
+
+/* ---------------------------------------------------------------- pairs -- */
+
+/* One pair term: target at xt, source (point or representative) at xs with
+ * attribute nu (3 values for A and G, 1 value for A^T).  The 1/(4 pi) factor
+ * is applied here so that every term is the paper's expression verbatim.
+ * Adds the term to out (1 value for A, 3 for A^T and G) and its magnitude to
+ * *mag.  A pair closer than w (or coincident) adds nothing. */
+static void pair_term(int op, const double *xt, const double *xs, const double *nu,
+                      double w, double *out, double *mag)
+{
+    double y[3] = {xt[0] - xs[0], xt[1] - xs[1], xt[2] - xs[2]};
+    double r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+    double r = sqrt(r2);
+    if (r == 0.0 || r < w)
+        return;
+    double r3 = r2 * r;
+    if (op == OR_OP_A) {
+        /* gradPhi(y) . mu = -(y . mu) / (4 pi r^3) */
+        double t = -(y[0] * nu[0] + y[1] * nu[1] + y[2] * nu[2]) / (4.0 * OR_PI * r3);
+        out[0] += t;
+        *mag += fabs(t);
+    } else if (op == OR_OP_AT) {
+        /* target j, source i: rho_i gradPhi(x_i - x_j) = rho_i (x_j - x_i)/(4 pi r^3),
+         * and y = x_j - x_i here. */
+        double f = nu[0] / (4.0 * OR_PI * r3);
+        double t0 = f * y[0], t1 = f * y[1], t2 = f * y[2];
+        out[0] += t0;
+        out[1] += t1;
+        out[2] += t2;
+        *mag += sqrt(t0 * t0 + t1 * t1 + t2 * t2);
+    } else {
+        /* -HPhi(y) mu = mu/(4 pi r^3) - 3 (y . mu) y /(4 pi r^5) */
+        double r5 = r3 * r2;
+        double ym = y[0] * nu[0] + y[1] * nu[1] + y[2] * nu[2];
+        double t[3];
+        for (int k = 0; k < 3; ++k)
+            t[k] = nu[k] / (4.0 * OR_PI * r3) - 3.0 * ym * y[k] / (4.0 * OR_PI * r5);
+        out[0] += t[0];
+        out[1] += t[1];
+        out[2] += t[2];
+        *mag += sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    }
+}
+
+static int op_in_dim(int op) { return op == OR_OP_AT ? 1 : 3; }
+static int op_out_dim(int op) { return op == OR_OP_A ? 1 : 3; }
+
+/* ---------------------------------------------------------- direct sums -- */
+
+/* Exact O(n_src * n_tgt) sums.  tgt may equal src.  out: (n_tgt, out_dim).
+ * mag (optional): per target sum of term magnitudes. */
+void or_direct(int op, const double *src, int64_t n_src, const double *nu,
+               const double *tgt, int64_t n_tgt, double w, double *out, double *mag)
+{
+    int din = op_in_dim(op), dout = op_out_dim(op);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n_tgt; ++i) {
+        double acc[3] = {0, 0, 0}, m = 0.0;
+        for (int64_t j = 0; j < n_src; ++j)
+            pair_term(op, tgt + 3 * i, src + 3 * j, nu + din * j, w, acc, &m);
+        for (int k = 0; k < dout; ++k)
+            out[dout * i + k] = acc[k];
+        if (mag)
+            mag[i] = m;
+    }
+}
+
+/* ------------------------------------------------------------- octree -- */
+
+typedef struct {
+    int depth;
+    int leaf;
+    int64_t begin, end;      /* member range in tree->order */
+    int nchild;
+    int64_t child[8];
+    double center[3];
+} or_node;
+
+typedef struct {
+    int64_t n;
+    const double *x;         /* borrowed: (n, 3) */
+    double *xc;              /* own copy of the points */
+    int64_t *order;          /* point indices grouped by node */
+    or_node *nodes;
+    int64_t nnodes, cap;
+    int max_depth, leaf_cap;
+    /* per-call representatives */
+    double *rep_x, *rep_nu, *rep_w;
+} or_tree;
+
+static int64_t push_node(or_tree *T)
+{
+    if (T->nnodes == T->cap) {
+        T->cap = T->cap ? 2 * T->cap : 1024;
+        T->nodes = (or_node *)realloc(T->nodes, (size_t)T->cap * sizeof(or_node));
+    }
+    memset(&T->nodes[T->nnodes], 0, sizeof(or_node));
+    return T->nnodes++;
+}
+
+/* Recursive partition of node `id` (points order[begin:end]).  Children are
+ * created for non-empty octants only, in octant order
+ * oct = (x >= cx) * 4 + (y >= cy) * 2 + (z >= cz). */
+static void split(or_tree *T, int64_t id, int64_t *scratch)
+{
+    or_node nd = T->nodes[id];
+    int64_t cnt = nd.end - nd.begin;
+    if (cnt <= T->leaf_cap || nd.depth >= T->max_depth) {
+        T->nodes[id].leaf = 1;
+        return;
+    }
+    int64_t bucket_n[8] = {0};
+    int8_t *oct = (int8_t *)malloc((size_t)cnt);
+    for (int64_t k = 0; k < cnt; ++k) {
+        const double *p = T->xc + 3 * T->order[nd.begin + k];
+        int o = (p[0] >= nd.center[0]) * 4 + (p[1] >= nd.center[1]) * 2 + (p[2] >= nd.center[2]);
+        oct[k] = (int8_t)o;
+        bucket_n[o]++;
+    }
+    int64_t start[8], pos[8];
+    int64_t s = nd.begin;
+    for (int o = 0; o < 8; ++o) {
+        start[o] = s;
+        pos[o] = s;
+        s += bucket_n[o];
+    }
+    for (int64_t k = 0; k < cnt; ++k)
+        scratch[pos[oct[k]]++] = T->order[nd.begin + k];
+    memcpy(T->order + nd.begin, scratch + nd.begin, (size_t)cnt * sizeof(int64_t));
+    free(oct);
+    double q = ldexp(1.0, -(nd.depth + 1)); /* quarter of width: child half-width */
+    T->nodes[id].leaf = 0;
+    T->nodes[id].nchild = 0;
+    for (int o = 0; o < 8; ++o) {
+        if (bucket_n[o] == 0)
+            continue;
+        int64_t c = push_node(T);
+        or_node *ch = &T->nodes[c];
+        ch->depth = nd.depth + 1;
+        ch->begin = start[o];
+        ch->end = start[o] + bucket_n[o];
+        ch->center[0] = nd.center[0] + ((o & 4) ? q : -q);
+        ch->center[1] = nd.center[1] + ((o & 2) ? q : -q);
+        ch->center[2] = nd.center[2] + ((o & 1) ? q : -q);
+        or_node *par = &T->nodes[id];
+        par->child[par->nchild++] = c;
+        split(T, c, scratch);
+    }
+}
+
+or_tree *or_tree_new(const double *x, int64_t n, int max_depth, int leaf_cap)
+{
+    if (n <= 0 || max_depth < 0 || leaf_cap < 1)
+        return NULL;
+    or_tree *T = (or_tree *)calloc(1, sizeof(or_tree));
+    T->n = n;
+    T->max_depth = max_depth;
+    T->leaf_cap = leaf_cap;
+    T->xc = (double *)malloc((size_t)n * 3 * sizeof(double));
+    memcpy(T->xc, x, (size_t)n * 3 * sizeof(double));
+    T->x = T->xc;
+    T->order = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i)
+        T->order[i] = i;
+    int64_t *scratch = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int64_t root = push_node(T);
+    T->nodes[root].depth = 0;
+    T->nodes[root].begin = 0;
+    T->nodes[root].end = n;
+    T->nodes[root].center[0] = T->nodes[root].center[1] = T->nodes[root].center[2] = 0.0;
+    split(T, root, scratch);
+    free(scratch);
+    T->rep_x = (double *)malloc((size_t)T->nnodes * 3 * sizeof(double));
+    T->rep_nu = (double *)malloc((size_t)T->nnodes * 3 * sizeof(double));
+    T->rep_w = (double *)malloc((size_t)T->nnodes * sizeof(double));
+    return T;
+}
+
+void or_tree_free(or_tree *T)
+{
+    if (!T)
+        return;
+    free(T->xc);
+    free(T->order);
+    free(T->nodes);
+    free(T->rep_x);
+    free(T->rep_nu);
+    free(T->rep_w);
+    free(T);
+}
+
+int64_t or_tree_nnodes(const or_tree *T) { return T->nnodes; }
+
+/* Export: per node depth, leaf flag, member range [begin,end) into order[],
+ * and order[] itself (n entries). */
+void or_tree_export(const or_tree *T, int32_t *depth, int32_t *leaf, int64_t *begin,
+                    int64_t *end, int64_t *order)
+{
+    for (int64_t k = 0; k < T->nnodes; ++k) {
+        depth[k] = T->nodes[k].depth;
+        leaf[k] = T->nodes[k].leaf;
+        begin[k] = T->nodes[k].begin;
+        end[k] = T->nodes[k].end;
+    }
+    memcpy(order, T->order, (size_t)T->n * sizeof(int64_t));
+}
+
+/* nu-representatives of every node from its own member points (direct
+ * sums, no reuse between levels). dim = 3 (vector nu) or 1 (scalar nu). */
+static void compute_reps(or_tree *T, const double *nu, int dim)
+{
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t k = 0; k < T->nnodes; ++k) {
+        const or_node *B = &T->nodes[k];
+        double W = 0.0, X[3] = {0, 0, 0}, V[3] = {0, 0, 0};
+        for (int64_t m = B->begin; m < B->end; ++m) {
+            int64_t i = T->order[m];
+            const double *v = nu + dim * i;
+            double a = dim == 3 ? sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) : fabs(v[0]);
+            W += a;
+            for (int c = 0; c < 3; ++c)
+                X[c] += a * T->x[3 * i + c];
+            for (int c = 0; c < dim; ++c)
+                V[c] += v[c];
+        }
+        T->rep_w[k] = W;
+        for (int c = 0; c < 3; ++c) {
+            T->rep_x[3 * k + c] = W > 0.0 ? X[c] / W : 0.0;
+            T->rep_nu[3 * k + c] = V[c];
+        }
+    }
+}
+
+/* Export the representatives of the last call (or compute them for nu). */
+void or_tree_reps(or_tree *T, const double *nu, int dim, double *xB, double *nuB, double *W)
+{
+    compute_reps(T, nu, dim);
+    memcpy(xB, T->rep_x, (size_t)T->nnodes * 3 * sizeof(double));
+    memcpy(nuB, T->rep_nu, (size_t)T->nnodes * 3 * sizeof(double));
+    memcpy(W, T->rep_w, (size_t)T->nnodes * sizeof(double));
+}
+
+typedef struct {
+    int op;
+    double w, c;
+    const double *nu;
+    int din;
+} apply_args;
+
+/* Alg. 4 for one target xt starting at node id. */
+static void apply_node(const or_tree *T, const apply_args *a, int64_t id, const double *xt,
+                       double *acc, double *mag, int64_t *pairs)
+{
+    const or_node *B = &T->nodes[id];
+    if (T->rep_w[id] == 0.0)
+        return; /* nothing to carry: every attribute in B is zero */
+    const double *xB = T->rep_x + 3 * id;
+    double dx = xt[0] - xB[0], dy = xt[1] - xB[1], dz = xt[2] - xB[2];
+    double dist = sqrt(dx * dx + dy * dy + dz * dz);
+    double width = ldexp(2.0, -B->depth);
+    if (dist > a->c * width) {
+        pair_term(a->op, xt, xB, T->rep_nu + 3 * id, a->w, acc, mag);
+        (*pairs)++;
+    } else if (!B->leaf) {
+        for (int k = 0; k < B->nchild; ++k)
+            apply_node(T, a, B->child[k], xt, acc, mag, pairs);
+    } else {
+        for (int64_t m = B->begin; m < B->end; ++m) {
+            int64_t j = T->order[m];
+            pair_term(a->op, xt, T->x + 3 * j, a->nu + a->din * j, a->w, acc, mag);
+            (*pairs)++;
+        }
+    }
+}
+
+/* Treecode operator over targets tgt (n_tgt x 3).  Computes the
+ * representatives for nu first (every call, as they move with nu).
+ * out: (n_tgt, out_dim); mag, pairs optional per-target outputs. */
+void or_tree_apply(or_tree *T, int op, const double *nu, double w, double c,
+                   const double *tgt, int64_t n_tgt, double *out, double *mag, int64_t *pairs)
+{
+    int din = op_in_dim(op), dout = op_out_dim(op);
+    compute_reps(T, nu, din);
+    apply_args a = {op, w, c, nu, din};
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n_tgt; ++i) {
+        double acc[3] = {0, 0, 0}, m = 0.0;
+        int64_t np = 0;
+        apply_node(T, &a, 0, tgt + 3 * i, acc, &m, &np);
+        for (int k = 0; k < dout; ++k)
+            out[dout * i + k] = acc[k];
+        if (mag)
+            mag[i] = m;
+        if (pairs)
+            pairs[i] = np;
+    }
+}
+
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
