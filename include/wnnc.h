@@ -1,0 +1,200 @@
+/*
+ * wnnc.h -- C ABI of the MI355X WNNC library.
+ *
+ * The library evaluates, on one AMD Instinct MI355X (gfx950), the three
+ * operators of WNNC normal orientation (Lin, Shi, Liu 2024) with the paper's
+ * treecode, and runs the full WNNC iteration on the device:
+ *
+ *   winding number  s_i    = F(x_i; mu)  = sum_j gradPhi(x_i - x_j) . mu_j
+ *                                                  (eq. wnf-discretization)
+ *   gradient        grad F(x_i; mu)      = sum_j HPhi(x_i - x_j) mu_j
+ *                                                  (Sec. 3.2; G = -grad F)
+ *   adjoint         (A^T s)_j            = sum_i s_i gradPhi(x_i - x_j)
+ *                                                  (Alg. 2)
+ *   orientation     Alg. 3 (Alg. 2 gradient step, WNNC update, rescale)
+ *
+ * with gradPhi(y) = -y/(4 pi |y|^3) and HPhi(y) = -I/(4 pi |y|^3) +
+ * 3 y y^T/(4 pi |y|^5); every pair closer than the smoothing width w (and
+ * every coincident pair) contributes zero (Sec. 3.4).  mu_j = n_j sigma_j is
+ * the oriented surface element: unit normal times area weight (Sec. 2).
+ *
+ * Treecode (Sec. 3.5, Alg. 4): an octree over [-1,1]^3 split while a node
+ * holds more than one point and is shallower than the maximum depth D; per
+ * call, nu-representatives x_B = sum |nu_i| x_i / sum |nu_i|, nu_B = sum nu_i;
+ * per target, a node is replaced by its representative when
+ * |x - x_B| > c * width(B), width(B) = 2^(1 - depth), otherwise its children
+ * are visited (a leaf sums its points directly).  Nodes whose attributes are
+ * all zero are skipped.
+ *
+ * Conventions
+ * -----------
+ * * Every float pointer is a DEVICE pointer to contiguous FP32 data owned by
+ *   the caller; (N,3) arrays are row-major (x0,y0,z0,x1,...), in the caller's
+ *   point order.  Host pointers are marked "host".
+ * * Calls enqueue work on the context's stream and return without waiting,
+ *   unless marked "synchronizes".  Outputs are valid once the stream has
+ *   reached the call.  Inputs must stay valid until then.
+ * * The context owns the octree, the point permutation and all scratch
+ *   memory; wnnc_destroy frees them.  The caller owns every I/O buffer.
+ * * A context is used by one host thread at a time.
+ * * Errors: every call returns a wnnc_status; on failure wnnc_last_error()
+ *   gives a message (thread-local, valid until the next failing call on the
+ *   thread).  Invalid arguments return WNNC_EINVAL before any work is
+ *   enqueued.  Non-finite inputs are not detected and give unspecified
+ *   (finite or not) results.
+ */
+#ifndef WNNC_H
+#define WNNC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wnnc_ctx_s *wnnc_ctx;
+
+typedef enum {
+    WNNC_OK = 0,
+    WNNC_EINVAL = -1,   /* bad argument (NULL, size, option range) */
+    WNNC_ENOMEM = -2,   /* device allocation failed */
+    WNNC_EDEVICE = -3,  /* a HIP runtime call or kernel launch failed */
+    WNNC_ESTATE = -4,   /* no tree built yet (call wnnc_build first) */
+} wnnc_status;
+
+/* Treecode options (Sec. 4.1.1 defaults in brackets). */
+typedef struct {
+    float c;        /* acceptance threshold c > 0 [2] */
+    int max_depth;  /* maximum octree depth D, 1..15 [15] */
+} wnnc_tree_opts;
+
+/* Alg. 3 options (Sec. 4.1.1 defaults in brackets). */
+typedef struct {
+    int iters;       /* n >= 1 [40] */
+    float w1, w2;    /* final and initial smoothing widths, normalized frame
+                        [0.002, 0.016]; w = w2 (n-i)/(n-1) + w1 (i-1)/(n-1),
+                        w = w1 when n = 1 */
+    int start_iter;  /* first iteration index i, 1..n [1]; with mu0 this
+                        resumes an interrupted run exactly */
+    int stop_iter;   /* last iteration index run, start_iter..n, or 0 for n
+                        [0]; (mu, i) is the whole state, so stopping at k and
+                        resuming at k+1 with the returned mu reproduces an
+                        uninterrupted run bit for bit */
+} wnnc_orient_opts;
+
+/* Instrumentation flags (wnnc_set_flags). */
+#define WNNC_FLAG_COUNT_PAIRS 1u  /* count pair evaluations (slower kernels) */
+#define WNNC_FLAG_TIME_KERNELS 2u /* time every launch with HIP events */
+
+/* Operator kinds, indices of the per-kind statistics. */
+#define WNNC_OP_A 0
+#define WNNC_OP_AT 1
+#define WNNC_OP_G 2
+
+typedef struct {
+    int64_t n_points;       /* N of the current tree */
+    int64_t n_nodes;        /* octree nodes */
+    int64_t calls[3];       /* operator applications per kind since reset */
+    int64_t pairs[3];       /* pair evaluations per kind (WNNC_FLAG_COUNT_PAIRS):
+                               accepted representatives plus points summed
+                               directly, cut-off pairs included */
+    double traverse_ms[3];  /* summed traversal-kernel time per kind
+                               (WNNC_FLAG_TIME_KERNELS) */
+    double moments_ms;      /* summed moment-pass time (WNNC_FLAG_TIME_KERNELS) */
+    double build_ms;        /* last wnnc_build, device time (always timed) */
+} wnnc_stats_t;
+
+/* Create a context on HIP device `device`, enqueuing on `stream`
+ * (a hipStream_t; NULL = the device's null stream).  Allocates nothing on
+ * the device yet. */
+wnnc_status wnnc_create(wnnc_ctx *out, int device, void *stream);
+
+/* Free the context and every device buffer it owns.  Synchronizes. */
+wnnc_status wnnc_destroy(wnnc_ctx ctx);
+
+/* Change the stream later calls enqueue on. */
+wnnc_status wnnc_set_stream(wnnc_ctx ctx, void *stream);
+
+/* Instrumentation flags, see WNNC_FLAG_*. */
+wnnc_status wnnc_set_flags(wnnc_ctx ctx, unsigned flags);
+
+/* Sec. 4.1.1 normalization: centre the bounding box at the origin and scale
+ * uniformly so that the largest half-extent is 10/11 ([-1,1]^3 with a margin
+ * of 1/11).  P, P_norm: (N,3), may alias.  center_scale (host, 4 doubles):
+ * centre x,y,z and scale s, so P_norm = (P - centre) * s computed in FP64
+ * and rounded once.  Widths and areas are in the normalized frame
+ * (areas scale by s^2).  Synchronizes. */
+wnnc_status wnnc_normalize(wnnc_ctx ctx, const float *P, int64_t N, float *P_norm,
+                           double *center_scale);
+
+/* Build the octree over normalized points P (N,3), 1 <= N < 2^31.  Points
+ * outside [-1,1]^3 are clamped into the boundary cells.  Replaces any
+ * previous tree.  opts NULL = paper defaults.  Synchronizes (reads back the
+ * node count). */
+wnnc_status wnnc_build(wnnc_ctx ctx, const float *P, int64_t N, const wnnc_tree_opts *opts);
+
+/* Winding number at the points: s_out[i] = F(x_i; mu), mu_j = n_j sigma_j.
+ * n: (N,3); sigma: (N) or NULL (then n already holds mu); w >= 0. */
+wnnc_status wnnc_winding(wnnc_ctx ctx, const float *n, const float *sigma, float w, float *s_out);
+
+/* Gradient of the winding number at the points: grad_out (N,3) =
+ * grad F(x_i; mu) = -G(mu)_i.  Arguments as wnnc_winding. */
+wnnc_status wnnc_gradient(wnnc_ctx ctx, const float *n, const float *sigma, float w,
+                          float *grad_out);
+
+/* Adjoint of the winding-number operator applied to s (N): out (N,3),
+ * out_j = sum_i s_i gradPhi(x_i - x_j) (with the treecode, using the
+ * |s|-weighted representatives). */
+wnnc_status wnnc_adjoint(wnnc_ctx ctx, const float *s, float w, float *out);
+
+/* Alg. 3 on the built tree.  mu0: (N,3) initial mu, or NULL for mu = 0 (the
+ * paper's initialization).  mu_out: (N,3) final mu (oriented surface
+ * elements in the normalized frame; normals are mu_i/|mu_i|).  mu_out may
+ * alias mu0.  opts NULL = paper defaults. */
+wnnc_status wnnc_orient(wnnc_ctx ctx, const wnnc_orient_opts *opts, const float *mu0,
+                        float *mu_out);
+
+/* Output of the method (Alg. 3 result to normals): n_out (N,3) = unit
+ * normals mu_i / |mu_i| (zero where mu_i = 0) and, if area_out (N) is not
+ * NULL, the solved areas |mu_i| / scale^2 in the frame of the points before
+ * wnnc_normalize (scale as returned by it; pass 1 to keep the normalized
+ * frame).  mu, n_out, area_out are caller-order device arrays; n_out may
+ * alias mu.  Independent of the tree. */
+wnnc_status wnnc_normals(wnnc_ctx ctx, const float *mu, int64_t N, double scale, float *n_out,
+                         float *area_out);
+
+/* Energies E = ||A_w mu - b||^2 of the mu entering each iteration of the
+ * last wnnc_orient (host, at least `count` doubles; entry k is iteration
+ * start_iter + k; count <= the number of iterations run).  Synchronizes. */
+wnnc_status wnnc_orient_energy(wnnc_ctx ctx, double *host_out, int count);
+
+/* Statistics since the last reset (host struct).  Synchronizes. */
+wnnc_status wnnc_stats(wnnc_ctx ctx, wnnc_stats_t *out);
+wnnc_status wnnc_reset_stats(wnnc_ctx ctx);
+
+/* Copy the octree to host memory for inspection, in the library's node
+ * order (depth-first pre-order).  Each array has n_nodes entries except
+ * perm (N): depth, leaf flag, and the node's points as the range
+ * [begin, end) of the sorted order, whose caller indices are
+ * perm[begin..end).  Any pointer may be NULL.  Synchronizes. */
+wnnc_status wnnc_tree_export(wnnc_ctx ctx, int32_t *depth, int32_t *leaf, int64_t *begin,
+                             int64_t *end, int64_t *perm);
+
+/* nu-representatives for attribute nu in caller order: (N,3) when dim = 3
+ * (vector, as for mu) or (N) when dim = 1 (scalar, as for s).  Copies to
+ * host, per node in wnnc_tree_export order: x_B (n_nodes,3), nu_B
+ * (n_nodes, dim) and the weight W = sum |nu_i| (n_nodes).  Synchronizes. */
+wnnc_status wnnc_moments_export(wnnc_ctx ctx, const float *nu, int dim, float *xB, float *nuB,
+                                float *W);
+
+/* Message of the last failing call on this thread. */
+const char *wnnc_last_error(void);
+
+/* Library version string. */
+const char *wnnc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WNNC_H */

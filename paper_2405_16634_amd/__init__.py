@@ -1,0 +1,358 @@
+"""Python binding of the MI355X WNNC library (libwnnc.so, C ABI in include/wnnc.h).
+
+The functions named ``wnnc_*`` mirror the C entry points one to one and only
+marshal arguments: torch CUDA tensors are passed as device pointers and the
+current torch stream is used unless a stream is given.  Every computation runs
+in the library's HIP kernels; there is no fallback.  If the shared library has
+not been built, importing the binding raises with the command to build it.
+
+``Context`` wraps a context handle for convenience; ``autograd`` holds the
+differentiable winding-number functions.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwnnc.so")
+
+WNNC_OK, WNNC_EINVAL, WNNC_ENOMEM, WNNC_EDEVICE, WNNC_ESTATE = 0, -1, -2, -3, -4
+FLAG_COUNT_PAIRS = 1
+FLAG_TIME_KERNELS = 2
+OP_A, OP_AT, OP_G = 0, 1, 2
+
+EXPORTED = [
+    "wnnc_create", "wnnc_destroy", "wnnc_set_stream", "wnnc_set_flags", "wnnc_normalize",
+    "wnnc_build", "wnnc_winding", "wnnc_gradient", "wnnc_adjoint", "wnnc_orient",
+    "wnnc_orient_energy", "wnnc_stats", "wnnc_reset_stats", "wnnc_tree_export",
+    "wnnc_moments_export", "wnnc_normals", "wnnc_last_error", "wnnc_version",
+]
+
+
+class WnncError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"wnnc status {status}: {msg}")
+        self.status = status
+
+
+class TreeOpts(ctypes.Structure):
+    _fields_ = [("c", ctypes.c_float), ("max_depth", ctypes.c_int)]
+
+
+class OrientOpts(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("w1", ctypes.c_float), ("w2", ctypes.c_float),
+                ("start_iter", ctypes.c_int), ("stop_iter", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_points", ctypes.c_int64), ("n_nodes", ctypes.c_int64),
+                ("calls", ctypes.c_int64 * 3), ("pairs", ctypes.c_int64 * 3),
+                ("traverse_ms", ctypes.c_double * 3), ("moments_ms", ctypes.c_double),
+                ("build_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return dict(n_points=self.n_points, n_nodes=self.n_nodes, calls=list(self.calls),
+                    pairs=list(self.pairs), traverse_ms=list(self.traverse_ms),
+                    moments_ms=self.moments_ms, build_ms=self.build_ms)
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libwnnc.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing; build it with `python -m paper_2405_16634_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i64, f32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_float, ctypes.c_double
+    P = ctypes.POINTER
+    sigs = {
+        "wnnc_create": [P(vp), ctypes.c_int, vp],
+        "wnnc_destroy": [vp],
+        "wnnc_set_stream": [vp, vp],
+        "wnnc_set_flags": [vp, ctypes.c_uint],
+        "wnnc_normalize": [vp, vp, i64, vp, P(dbl)],
+        "wnnc_build": [vp, vp, i64, P(TreeOpts)],
+        "wnnc_winding": [vp, vp, vp, f32, vp],
+        "wnnc_gradient": [vp, vp, vp, f32, vp],
+        "wnnc_adjoint": [vp, vp, f32, vp],
+        "wnnc_orient": [vp, P(OrientOpts), vp, vp],
+        "wnnc_orient_energy": [vp, P(dbl), ctypes.c_int],
+        "wnnc_stats": [vp, P(Stats)],
+        "wnnc_reset_stats": [vp],
+        "wnnc_tree_export": [vp, vp, vp, vp, vp, vp],
+        "wnnc_moments_export": [vp, vp, ctypes.c_int, vp, vp, vp],
+        "wnnc_normals": [vp, vp, i64, dbl, vp, vp],
+    }
+    for name, args in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.wnnc_last_error.argtypes = []
+    lib.wnnc_last_error.restype = ctypes.c_char_p
+    lib.wnnc_version.argtypes = []
+    lib.wnnc_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int) -> None:
+    if status != WNNC_OK:
+        msg = load_library().wnnc_last_error().decode(errors="replace")
+        raise WnncError(status, msg)
+
+
+def _dev(t, name, dtype=torch.float32, shape=None):
+    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# ------------------------------------------------------- C-ABI mirrors --
+
+def wnnc_version() -> str:
+    return load_library().wnnc_version().decode()
+
+
+def wnnc_last_error() -> str:
+    return load_library().wnnc_last_error().decode(errors="replace")
+
+
+def wnnc_create(device: int = 0, stream=None):
+    h = ctypes.c_void_p()
+    _check(load_library().wnnc_create(ctypes.byref(h), int(device), _stream_ptr(stream)))
+    return h
+
+
+def wnnc_destroy(ctx) -> None:
+    _check(load_library().wnnc_destroy(ctx))
+
+
+def wnnc_set_stream(ctx, stream=None) -> None:
+    _check(load_library().wnnc_set_stream(ctx, _stream_ptr(stream)))
+
+
+def wnnc_set_flags(ctx, flags: int) -> None:
+    _check(load_library().wnnc_set_flags(ctx, int(flags)))
+
+
+def wnnc_normalize(ctx, P, P_norm):
+    n = P.shape[0]
+    cs = (ctypes.c_double * 4)()
+    _check(load_library().wnnc_normalize(ctx, _dev(P, "P", shape=(n, 3)), n,
+                                         _dev(P_norm, "P_norm", shape=(n, 3)), cs))
+    return (cs[0], cs[1], cs[2]), cs[3]
+
+
+def wnnc_build(ctx, P, c: float = 2.0, max_depth: int = 15) -> None:
+    n = P.shape[0]
+    opts = TreeOpts(float(c), int(max_depth))
+    _check(load_library().wnnc_build(ctx, _dev(P, "P", shape=(n, 3)), n, ctypes.byref(opts)))
+
+
+def wnnc_winding(ctx, n, sigma, w: float, s_out) -> None:
+    N = n.shape[0]
+    _check(load_library().wnnc_winding(ctx, _dev(n, "n", shape=(N, 3)),
+                                       _dev(sigma, "sigma", shape=(N,)), float(w),
+                                       _dev(s_out, "s_out", shape=(N,))))
+
+
+def wnnc_gradient(ctx, n, sigma, w: float, grad_out) -> None:
+    N = n.shape[0]
+    _check(load_library().wnnc_gradient(ctx, _dev(n, "n", shape=(N, 3)),
+                                        _dev(sigma, "sigma", shape=(N,)), float(w),
+                                        _dev(grad_out, "grad_out", shape=(N, 3))))
+
+
+def wnnc_adjoint(ctx, s, w: float, out) -> None:
+    N = s.shape[0]
+    _check(load_library().wnnc_adjoint(ctx, _dev(s, "s", shape=(N,)), float(w),
+                                       _dev(out, "out", shape=(N, 3))))
+
+
+def wnnc_orient(ctx, mu_out, mu0=None, iters: int = 40, w1: float = 0.002, w2: float = 0.016,
+                start_iter: int = 1, stop_iter: int = 0) -> None:
+    N = mu_out.shape[0]
+    opts = OrientOpts(int(iters), float(w1), float(w2), int(start_iter), int(stop_iter))
+    _check(load_library().wnnc_orient(ctx, ctypes.byref(opts), _dev(mu0, "mu0", shape=(N, 3)),
+                                      _dev(mu_out, "mu_out", shape=(N, 3))))
+
+
+def wnnc_normals(ctx, mu, scale: float, n_out, area_out=None) -> None:
+    N = mu.shape[0]
+    _check(load_library().wnnc_normals(ctx, _dev(mu, "mu", shape=(N, 3)), N, float(scale),
+                                       _dev(n_out, "n_out", shape=(N, 3)),
+                                       _dev(area_out, "area_out", shape=(N,))))
+
+
+def wnnc_orient_energy(ctx, count: int):
+    buf = (ctypes.c_double * max(count, 1))()
+    _check(load_library().wnnc_orient_energy(ctx, buf, int(count)))
+    return [buf[i] for i in range(count)]
+
+
+def wnnc_stats(ctx) -> dict:
+    st = Stats()
+    _check(load_library().wnnc_stats(ctx, ctypes.byref(st)))
+    return st.as_dict()
+
+
+def wnnc_reset_stats(ctx) -> None:
+    _check(load_library().wnnc_reset_stats(ctx))
+
+
+def wnnc_tree_export(ctx):
+    """(depth, leaf, begin, end, perm) as numpy arrays (pre-order nodes)."""
+    import numpy as np
+    st = wnnc_stats(ctx)
+    m, n = st["n_nodes"], st["n_points"]
+    depth = np.zeros(m, np.int32)
+    leaf = np.zeros(m, np.int32)
+    begin = np.zeros(m, np.int64)
+    end = np.zeros(m, np.int64)
+    perm = np.zeros(n, np.int64)
+    ptr = lambda a: ctypes.c_void_p(a.ctypes.data)
+    _check(load_library().wnnc_tree_export(ctx, ptr(depth), ptr(leaf), ptr(begin), ptr(end),
+                                           ptr(perm)))
+    return depth, leaf, begin, end, perm
+
+
+def wnnc_moments_export(ctx, nu):
+    """(x_B, nu_B, W) per node for attribute nu ((N,3) or (N,) CUDA tensor)."""
+    import numpy as np
+    st = wnnc_stats(ctx)
+    m = st["n_nodes"]
+    dim = 3 if nu.dim() == 2 else 1
+    xB = np.zeros((m, 3), np.float32)
+    nuB = np.zeros((m, 3) if dim == 3 else (m,), np.float32)
+    W = np.zeros(m, np.float32)
+    ptr = lambda a: ctypes.c_void_p(a.ctypes.data)
+    _check(load_library().wnnc_moments_export(ctx, _dev(nu, "nu"), dim, ptr(xB), ptr(nuB), ptr(W)))
+    return xB, nuB, W
+
+
+# ----------------------------------------------------------- wrapper --
+
+@dataclass
+class Normalization:
+    center: tuple
+    scale: float
+
+
+class Context:
+    """One library context bound to a device and (by default) torch's current
+    stream at creation time."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.device = int(device)
+        self._h = wnnc_create(self.device, stream)
+        self.n = 0
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            wnnc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_flags(self, flags: int) -> None:
+        wnnc_set_flags(self._h, flags)
+
+    def set_stream(self, stream=None) -> None:
+        wnnc_set_stream(self._h, stream)
+
+    def normalize(self, P):
+        out = torch.empty_like(P)
+        c, s = wnnc_normalize(self._h, P, out)
+        return out, Normalization(c, s)
+
+    def build(self, P_norm, c: float = 2.0, max_depth: int = 15) -> None:
+        wnnc_build(self._h, P_norm, c, max_depth)
+        self.n = int(P_norm.shape[0])
+
+    def winding(self, mu, w: float, sigma=None):
+        out = torch.empty(mu.shape[0], device=mu.device, dtype=torch.float32)
+        wnnc_winding(self._h, mu, sigma, w, out)
+        return out
+
+    def gradient(self, mu, w: float, sigma=None):
+        out = torch.empty_like(mu)
+        wnnc_gradient(self._h, mu, sigma, w, out)
+        return out
+
+    def adjoint(self, s, w: float):
+        out = torch.empty(s.shape[0], 3, device=s.device, dtype=torch.float32)
+        wnnc_adjoint(self._h, s, w, out)
+        return out
+
+    def orient(self, iters: int = 40, w1: float = 0.002, w2: float = 0.016, mu0=None,
+               start_iter: int = 1, stop_iter: int = 0, out=None):
+        if out is None:
+            out = torch.empty(self.n, 3, device=f"cuda:{self.device}", dtype=torch.float32)
+        wnnc_orient(self._h, out, mu0, iters, w1, w2, start_iter, stop_iter)
+        return out
+
+    def normals(self, mu, scale: float = 1.0, with_area: bool = False):
+        nrm = torch.empty_like(mu)
+        area = torch.empty(mu.shape[0], device=mu.device, dtype=torch.float32) if with_area else None
+        wnnc_normals(self._h, mu, scale, nrm, area)
+        return (nrm, area) if with_area else nrm
+
+    def energy(self, count: int):
+        return wnnc_orient_energy(self._h, count)
+
+    def stats(self) -> dict:
+        return wnnc_stats(self._h)
+
+    def reset_stats(self) -> None:
+        wnnc_reset_stats(self._h)
+
+    def tree(self):
+        return wnnc_tree_export(self._h)
+
+    def moments(self, nu):
+        return wnnc_moments_export(self._h, nu)
+
+
+def orient_points(P, iters: int = 40, w1: float = 0.002, w2: float = 0.016, c: float = 2.0,
+                  max_depth: int = 15, device: int = 0):
+    """Normalize, build and run the WNNC iteration on a (N,3) CUDA tensor.
+    Returns (mu in the normalized frame, unit normals, Normalization)."""
+    ctx = Context(device)
+    try:
+        x, norm = ctx.normalize(P.contiguous().float())
+        ctx.build(x, c, max_depth)
+        mu = ctx.orient(iters, w1, w2)
+        nrm = ctx.normals(mu)
+        return mu, nrm, norm
+    finally:
+        ctx.close()

@@ -1,0 +1,544 @@
+// The C ABI (include/wnnc.h): argument checks, buffers, and the order of
+// kernel launches for the operators and for the WNNC iteration (Alg. 3).
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "common.h"
+#include "internal.h"
+
+using namespace wnnc;
+
+namespace {
+
+thread_local std::string g_err;
+
+wnnc_status fail(wnnc_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIPCHK(x)                                                                         \
+    do {                                                                                  \
+        hipError_t _e = (x);                                                              \
+        if (_e != hipSuccess)                                                             \
+            return fail(_e == hipErrorOutOfMemory ? WNNC_ENOMEM : WNNC_EDEVICE, "%s: %s", \
+                        #x, hipGetErrorString(_e));                                       \
+    } while (0)
+
+// Events around one launch when WNNC_FLAG_TIME_KERNELS is set.
+struct Timed {
+    wnnc_ctx_s *ctx;
+    int kind;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timed(wnnc_ctx_s *c, int k) : ctx(c), kind(k) {
+        if (!(ctx->flags & WNNC_FLAG_TIME_KERNELS)) return;
+        a = get();
+        b = get();
+        if (a && b) (void)hipEventRecord(a, ctx->stream);
+    }
+    hipEvent_t get() {
+        if (!ctx->event_pool.empty()) {
+            hipEvent_t e = ctx->event_pool.back();
+            ctx->event_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void done() {
+        if (!a || !b) return;
+        (void)hipEventRecord(b, ctx->stream);
+        ctx->pending.push_back({a, b, kind});
+        a = b = nullptr;
+    }
+};
+
+MomArgs mom_args(wnnc_ctx_s *c) {
+    MomArgs a;
+    memset(&a, 0, sizeof(a));
+    a.pts = c->pts.p;
+    a.topo = c->topo.p;
+    a.node_off = c->node_off.p;
+    a.node_strad = c->node_strad.p;
+    a.tail_off = c->tail_off.p;
+    a.tail_list = c->tail_list.p;
+    a.strad_node = c->strad_node.p;
+    a.perm = c->perm.p;
+    a.chunk_tot = c->chunk_tot.p;
+    a.head = c->head.p;
+    a.tail = c->tail.p;
+    a.mom = c->mom.p;
+    a.n = (int)c->n;
+    a.n_strad = c->n_strad;
+    return a;
+}
+
+TravArgs trav_args(wnnc_ctx_s *c, float w) {
+    TravArgs a;
+    memset(&a, 0, sizeof(a));
+    a.pts = c->pts.p;
+    a.topo = c->topo.p;
+    a.mom = c->mom.p;
+    a.perm = c->perm.p;
+    a.pairs = c->pair_ctr.p;
+    a.n = (int)c->n;
+    a.m = (int)c->m;
+    a.nblocks = trav_blocks(c->n);
+    a.w2 = (float)((double)w * (double)w);
+    for (int d = 0; d < 16; ++d) {
+        const double t = (double)c->c * ldexp(2.0, -d);
+        a.thr2[d] = (float)(t * t);
+    }
+    return a;
+}
+
+wnnc_status run_moments(wnnc_ctx_s *c, MomMode mode, const MomArgs &a) {
+    Timed tm(c, 3);
+    HIPCHK(launch_moments(c, mode, a));
+    tm.done();
+    return WNNC_OK;
+}
+
+wnnc_status run_traverse(wnnc_ctx_s *c, Op op, TravMode mode, const TravArgs &a) {
+    Timed tm(c, (int)op);
+    HIPCHK(launch_traverse(c, op, mode, (c->flags & WNNC_FLAG_COUNT_PAIRS) != 0, a));
+    tm.done();
+    c->calls[op] += 1;
+    return WNNC_OK;
+}
+
+bool finite_nonneg(float w) { return isfinite(w) && w >= 0.0f; }
+
+#define CHECK_CTX(ctx)                                                          \
+    do {                                                                        \
+        if (!(ctx)) return fail(WNNC_EINVAL, "null context");                   \
+        HIPCHK(hipSetDevice((ctx)->device));                                    \
+    } while (0)
+
+#define CHECK_BUILT(ctx)                                                                  \
+    do {                                                                                  \
+        if (!(ctx)->built) return fail(WNNC_ESTATE, "no tree: call wnnc_build first");    \
+    } while (0)
+
+#define RETURN_IF(x)                  \
+    do {                              \
+        wnnc_status _s = (x);         \
+        if (_s != WNNC_OK) return _s; \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char *wnnc_last_error(void) { return g_err.c_str(); }
+
+const char *wnnc_version(void) { return "wnnc-mi355x 0.1 (gfx950)"; }
+
+wnnc_status wnnc_create(wnnc_ctx *out, int device, void *stream) {
+    if (!out) return fail(WNNC_EINVAL, "out is null");
+    *out = nullptr;
+    int count = 0;
+    HIPCHK(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count)
+        return fail(WNNC_EINVAL, "device %d out of range (%d devices)", device, count);
+    wnnc_ctx_s *c = new (std::nothrow) wnnc_ctx_s();
+    if (!c) return fail(WNNC_ENOMEM, "host allocation failed");
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    *out = c;
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_destroy(wnnc_ctx ctx) {
+    if (!ctx) return WNNC_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->pts.release();
+    ctx->perm.release();
+    ctx->topo.release();
+    ctx->node_off.release();
+    ctx->node_strad.release();
+    ctx->strad_node.release();
+    ctx->tail_off.release();
+    ctx->tail_list.release();
+    ctx->chunk_tot.release();
+    ctx->head.release();
+    ctx->tail.release();
+    ctx->mom.release();
+    ctx->keys_a.release();
+    ctx->keys_b.release();
+    ctx->vals_b.release();
+    ctx->hist.release();
+    ctx->scan_tmp.release();
+    ctx->u32_tmp.release();
+    ctx->mflag.release();
+    ctx->mslot.release();
+    ctx->norm_tmp.release();
+    ctx->va.release();
+    ctx->vb.release();
+    ctx->vr.release();
+    ctx->rho.release();
+    ctx->partial.release();
+    ctx->scalars.release();
+    ctx->energy.release();
+    ctx->pair_ctr.release();
+    for (auto &t : ctx->pending) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+    delete ctx;
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_set_stream(wnnc_ctx ctx, void *stream) {
+    CHECK_CTX(ctx);
+    ctx->stream = (hipStream_t)stream;
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_set_flags(wnnc_ctx ctx, unsigned flags) {
+    CHECK_CTX(ctx);
+    if (flags & ~(WNNC_FLAG_COUNT_PAIRS | WNNC_FLAG_TIME_KERNELS))
+        return fail(WNNC_EINVAL, "unknown flags 0x%x", flags);
+    ctx->flags = flags;
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_normalize(wnnc_ctx ctx, const float *P, int64_t N, float *P_norm,
+                           double *center_scale) {
+    CHECK_CTX(ctx);
+    if (!P || !P_norm) return fail(WNNC_EINVAL, "null point pointer");
+    if (N < 1 || N > INT32_MAX) return fail(WNNC_EINVAL, "N = %lld out of range", (long long)N);
+    HIPCHK(ctx->norm_tmp.ensure(normalize_tmp_doubles(N)));
+    HIPCHK(launch_normalize(P, N, P_norm, ctx->norm_tmp.p, ctx->stream));
+    double cs[4];
+    HIPCHK(hipMemcpyAsync(cs, ctx->norm_tmp.p + normalize_tmp_doubles(N) - 8, 4 * sizeof(double),
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (center_scale) memcpy(center_scale, cs, sizeof(cs));
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_build(wnnc_ctx ctx, const float *P, int64_t N, const wnnc_tree_opts *opts) {
+    CHECK_CTX(ctx);
+    if (!P) return fail(WNNC_EINVAL, "null point pointer");
+    if (N < 1 || N > INT32_MAX - 1) return fail(WNNC_EINVAL, "N = %lld out of range", (long long)N);
+    wnnc_tree_opts o = {2.0f, 15};
+    if (opts) o = *opts;
+    if (!(isfinite(o.c) && o.c > 0.0f)) return fail(WNNC_EINVAL, "c must be finite and > 0");
+    if (o.max_depth < 1 || o.max_depth > kMaxDepth)
+        return fail(WNNC_EINVAL, "max_depth must be in 1..15");
+    ctx->built = false;
+    ctx->n = N;
+    ctx->c = o.c;
+    ctx->depth = o.max_depth;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, ctx->stream));
+    hipError_t e = build_tree(ctx, P);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return fail(e == hipErrorOutOfMemory ? WNNC_ENOMEM : WNNC_EDEVICE, "tree build: %s",
+                    hipGetErrorString(e));
+    }
+    HIPCHK(hipEventRecord(e1, ctx->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->build_ms = ms;
+    ctx->built = true;
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_winding(wnnc_ctx ctx, const float *n, const float *sigma, float w, float *s_out) {
+    CHECK_CTX(ctx);
+    CHECK_BUILT(ctx);
+    if (!n || !s_out) return fail(WNNC_EINVAL, "null pointer");
+    if (!finite_nonneg(w)) return fail(WNNC_EINVAL, "w must be finite and >= 0");
+    MomArgs ma = mom_args(ctx);
+    ma.cn = n;
+    ma.csig = sigma;
+    ma.out4 = ctx->va.p;
+    RETURN_IF(run_moments(ctx, MOM_VEC_CALLER, ma));
+    TravArgs ta = trav_args(ctx, w);
+    ta.src4 = ctx->va.p;
+    ta.out = s_out;
+    return run_traverse(ctx, OP_A, TR_OUT_CALLER, ta);
+}
+
+wnnc_status wnnc_gradient(wnnc_ctx ctx, const float *n, const float *sigma, float w,
+                          float *grad_out) {
+    CHECK_CTX(ctx);
+    CHECK_BUILT(ctx);
+    if (!n || !grad_out) return fail(WNNC_EINVAL, "null pointer");
+    if (!finite_nonneg(w)) return fail(WNNC_EINVAL, "w must be finite and >= 0");
+    MomArgs ma = mom_args(ctx);
+    ma.cn = n;
+    ma.csig = sigma;
+    ma.out4 = ctx->va.p;
+    RETURN_IF(run_moments(ctx, MOM_VEC_CALLER, ma));
+    TravArgs ta = trav_args(ctx, w);
+    ta.src4 = ctx->va.p;
+    ta.out = grad_out;
+    return run_traverse(ctx, OP_G, TR_OUT_CALLER, ta);
+}
+
+wnnc_status wnnc_adjoint(wnnc_ctx ctx, const float *s, float w, float *out) {
+    CHECK_CTX(ctx);
+    CHECK_BUILT(ctx);
+    if (!s || !out) return fail(WNNC_EINVAL, "null pointer");
+    if (!finite_nonneg(w)) return fail(WNNC_EINVAL, "w must be finite and >= 0");
+    MomArgs ma = mom_args(ctx);
+    ma.cs = s;
+    ma.outs = ctx->rho.p;
+    RETURN_IF(run_moments(ctx, MOM_SCALAR_CALLER, ma));
+    TravArgs ta = trav_args(ctx, w);
+    ta.srcs = ctx->rho.p;
+    ta.out = out;
+    return run_traverse(ctx, OP_AT, TR_OUT_CALLER, ta);
+}
+
+wnnc_status wnnc_orient(wnnc_ctx ctx, const wnnc_orient_opts *opts, const float *mu0,
+                        float *mu_out) {
+    CHECK_CTX(ctx);
+    CHECK_BUILT(ctx);
+    if (!mu_out) return fail(WNNC_EINVAL, "null mu_out");
+    wnnc_orient_opts o = {40, 0.002f, 0.016f, 1, 0};
+    if (opts) o = *opts;
+    if (o.iters < 1) return fail(WNNC_EINVAL, "iters must be >= 1");
+    if (o.start_iter < 1 || o.start_iter > o.iters)
+        return fail(WNNC_EINVAL, "start_iter must be in 1..iters");
+    const int stop = o.stop_iter == 0 ? o.iters : o.stop_iter;
+    if (stop < o.start_iter || stop > o.iters)
+        return fail(WNNC_EINVAL, "stop_iter must be 0 or in start_iter..iters");
+    if (!finite_nonneg(o.w1) || !finite_nonneg(o.w2))
+        return fail(WNNC_EINVAL, "widths must be finite and >= 0");
+    const int64_t N = ctx->n;
+    const int nb = trav_blocks(N);
+    hipStream_t st = ctx->stream;
+    const int count = stop - o.start_iter + 1;
+    HIPCHK(ctx->energy.ensure(count));
+
+    float4 *mu = ctx->va.p, *tmp = ctx->vb.p, *r = ctx->vr.p;
+    float *rho = ctx->rho.p;
+    const bool zero = mu0 == nullptr;
+    if (zero)
+        HIPCHK(launch_zero_f4(mu, N, st));
+    else
+        HIPCHK(launch_gather_vec(mu0, ctx->perm.p, mu, N, st));
+
+    for (int i = o.start_iter; i <= stop; ++i) {
+        const int n = o.iters;
+        const double w = n <= 1 ? (double)o.w1
+                                : (double)o.w2 * (n - i) / (n - 1) + (double)o.w1 * (i - 1) / (n - 1);
+        const float wf = (float)w;
+        double *eslot = ctx->energy.p + (i - o.start_iter);
+        // gradient step (Alg. 2): rho = b - A mu, r = A^T rho, t = A r
+        double e_const = -1.0;
+        if (zero && i == o.start_iter) {
+            // mu = 0: A mu = 0 exactly, so rho = 1/2 everywhere
+            MomArgs ma = mom_args(ctx);
+            ma.outs = rho;
+            RETURN_IF(run_moments(ctx, MOM_CONST_HALF, ma));
+            e_const = 0.25 * (double)N;
+        } else {
+            MomArgs ma = mom_args(ctx);
+            ma.src4 = mu;
+            RETURN_IF(run_moments(ctx, MOM_VEC_SORTED, ma));
+            TravArgs ta = trav_args(ctx, wf);
+            ta.src4 = mu;
+            ta.rho = rho;
+            ta.partial = ctx->partial.p;
+            RETURN_IF(run_traverse(ctx, OP_A, TR_RHO, ta));
+            MomArgs mb = mom_args(ctx);
+            mb.srcs = rho;
+            RETURN_IF(run_moments(ctx, MOM_SCALAR_SORTED, mb));
+        }
+        {
+            TravArgs ta = trav_args(ctx, wf);
+            ta.srcs = rho;
+            ta.out4 = r;
+            ta.partial = ctx->partial.p + nb;
+            RETURN_IF(run_traverse(ctx, OP_AT, TR_R, ta));
+        }
+        {
+            MomArgs ma = mom_args(ctx);
+            ma.src4 = r;
+            RETURN_IF(run_moments(ctx, MOM_VEC_SORTED, ma));
+            TravArgs ta = trav_args(ctx, wf);
+            ta.src4 = r;
+            ta.partial = ctx->partial.p + 2 * nb;
+            RETURN_IF(run_traverse(ctx, OP_A, TR_TSUM, ta));
+        }
+        HIPCHK(launch_alpha(ctx, nb, e_const, eslot));
+        // mu <- mu + alpha r, then the WNNC update and rescale
+        {
+            MomArgs ma = mom_args(ctx);
+            ma.src4 = mu;
+            ma.r4 = r;
+            ma.alpha = ctx->scalars.p;
+            ma.out4 = tmp;
+            RETURN_IF(run_moments(ctx, MOM_AXPY, ma));
+            TravArgs ta = trav_args(ctx, wf);
+            ta.src4 = tmp;
+            ta.out4 = mu;
+            RETURN_IF(run_traverse(ctx, OP_G, TR_RESCALE, ta));
+        }
+    }
+    HIPCHK(launch_scatter_vec(mu, ctx->perm.p, mu_out, N, st));
+    ctx->last_energy_count = count;
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_normals(wnnc_ctx ctx, const float *mu, int64_t N, double scale, float *n_out,
+                         float *area_out) {
+    CHECK_CTX(ctx);
+    if (!mu || !n_out) return fail(WNNC_EINVAL, "null pointer");
+    if (N < 1 || N > INT32_MAX) return fail(WNNC_EINVAL, "N = %lld out of range", (long long)N);
+    if (!(isfinite(scale) && scale > 0.0)) return fail(WNNC_EINVAL, "scale must be finite and > 0");
+    HIPCHK(launch_normals(mu, N, scale, n_out, area_out, ctx->stream));
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_orient_energy(wnnc_ctx ctx, double *host_out, int count) {
+    CHECK_CTX(ctx);
+    if (!host_out || count < 0) return fail(WNNC_EINVAL, "bad output");
+    if (count > ctx->last_energy_count)
+        return fail(WNNC_EINVAL, "only %d energies recorded", ctx->last_energy_count);
+    if (count == 0) return WNNC_OK;
+    HIPCHK(hipMemcpyAsync(host_out, ctx->energy.p, (size_t)count * sizeof(double),
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_stats(wnnc_ctx ctx, wnnc_stats_t *out) {
+    CHECK_CTX(ctx);
+    if (!out) return fail(WNNC_EINVAL, "null output");
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (auto &t : ctx->pending) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, t.a, t.b));
+        if (t.kind < 3)
+            ctx->trav_ms[t.kind] += ms;
+        else
+            ctx->mom_ms += ms;
+        ctx->event_pool.push_back(t.a);
+        ctx->event_pool.push_back(t.b);
+    }
+    ctx->pending.clear();
+    memset(out, 0, sizeof(*out));
+    out->n_points = ctx->built ? ctx->n : 0;
+    out->n_nodes = ctx->built ? ctx->m : 0;
+    unsigned long long pc[3] = {0, 0, 0};
+    if (ctx->pair_ctr.p) {
+        HIPCHK(hipMemcpy(pc, ctx->pair_ctr.p, sizeof(pc), hipMemcpyDeviceToHost));
+    }
+    for (int k = 0; k < 3; ++k) {
+        out->calls[k] = ctx->calls[k];
+        out->pairs[k] = (int64_t)pc[k];
+        out->traverse_ms[k] = ctx->trav_ms[k];
+    }
+    out->moments_ms = ctx->mom_ms;
+    out->build_ms = ctx->build_ms;
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_reset_stats(wnnc_ctx ctx) {
+    CHECK_CTX(ctx);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (auto &t : ctx->pending) {
+        ctx->event_pool.push_back(t.a);
+        ctx->event_pool.push_back(t.b);
+    }
+    ctx->pending.clear();
+    for (int k = 0; k < 3; ++k) {
+        ctx->calls[k] = 0;
+        ctx->trav_ms[k] = 0;
+    }
+    ctx->mom_ms = 0;
+    HIPCHK(ctx->pair_ctr.ensure(4));
+    HIPCHK(hipMemsetAsync(ctx->pair_ctr.p, 0, 4 * sizeof(unsigned long long), ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_tree_export(wnnc_ctx ctx, int32_t *depth, int32_t *leaf, int64_t *begin,
+                             int64_t *end, int64_t *perm) {
+    CHECK_CTX(ctx);
+    CHECK_BUILT(ctx);
+    std::vector<int4> topo((size_t)ctx->m);
+    std::vector<uint32_t> pm((size_t)ctx->n);
+    HIPCHK(hipMemcpyAsync(topo.data(), ctx->topo.p, (size_t)ctx->m * sizeof(int4),
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(pm.data(), ctx->perm.p, (size_t)ctx->n * sizeof(uint32_t),
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int64_t k = 0; k < ctx->m; ++k) {
+        if (depth) depth[k] = topo_depth(topo[k].w);
+        if (leaf) leaf[k] = topo_leaf(topo[k].w);
+        if (begin) begin[k] = topo[k].y;
+        if (end) end[k] = topo[k].z;
+    }
+    if (perm)
+        for (int64_t i = 0; i < ctx->n; ++i) perm[i] = pm[i];
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_moments_export(wnnc_ctx ctx, const float *nu, int dim, float *xB, float *nuB,
+                                float *W) {
+    CHECK_CTX(ctx);
+    CHECK_BUILT(ctx);
+    if (!nu) return fail(WNNC_EINVAL, "null nu");
+    if (dim != 1 && dim != 3) return fail(WNNC_EINVAL, "dim must be 1 or 3");
+    MomArgs ma = mom_args(ctx);
+    if (dim == 3) {
+        ma.cn = nu;
+        ma.out4 = ctx->vb.p;
+        RETURN_IF(run_moments(ctx, MOM_VEC_CALLER, ma));
+    } else {
+        ma.cs = nu;
+        ma.outs = ctx->rho.p;
+        RETURN_IF(run_moments(ctx, MOM_SCALAR_CALLER, ma));
+    }
+    std::vector<float4> mom((size_t)(2 * ctx->m));
+    HIPCHK(hipMemcpyAsync(mom.data(), ctx->mom.p, (size_t)(2 * ctx->m) * sizeof(float4),
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int64_t k = 0; k < ctx->m; ++k) {
+        const float4 p = mom[2 * k], v = mom[2 * k + 1];
+        if (xB) {
+            xB[3 * k] = p.x;
+            xB[3 * k + 1] = p.y;
+            xB[3 * k + 2] = p.z;
+        }
+        if (W) W[k] = p.w;
+        if (nuB) {
+            if (dim == 3) {
+                nuB[3 * k] = v.x;
+                nuB[3 * k + 1] = v.y;
+                nuB[3 * k + 2] = v.z;
+            } else {
+                nuB[k] = v.x;
+            }
+        }
+    }
+    return WNNC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,180 @@
+// Internal declarations shared by the library's HIP sources (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/wnnc.h"
+
+namespace wnnc {
+
+constexpr int kWave = 64;
+constexpr int kChunk = 256;      // points per moment-pass chunk (one workgroup)
+constexpr int kTravBlock = 256;  // traversal workgroup: 4 waves of 64 targets
+constexpr int kMaxDepth = 15;    // 15 levels below the root: 45-bit Morton keys
+
+// Node topology, one int4 per node in depth-first pre-order:
+//   x = skip: index of the first node after this node's subtree
+//   y = begin, z = end: the node's points are sorted positions [begin, end)
+//   w = depth | (leaf << 4)
+// The first child of an internal node is the next node (index + 1).
+__host__ __device__ inline int topo_depth(int meta) { return meta & 15; }
+__host__ __device__ inline int topo_leaf(int meta) { return (meta >> 4) & 1; }
+
+// Node moments, two float4 per node: (x_B, W) and (nu_B, 0).  W = sum |nu|.
+
+enum Op { OP_A = WNNC_OP_A, OP_AT = WNNC_OP_AT, OP_G = WNNC_OP_G };
+
+// Moment-pass input modes.
+enum MomMode {
+    MOM_VEC_SORTED = 0,    // nu = src4[i] (sorted float4)
+    MOM_SCALAR_SORTED = 1, // nu = srcs[i] (sorted float)
+    MOM_VEC_CALLER = 2,    // nu = n[perm[i]] * (sigma ? sigma[perm[i]] : 1); writes out4[i]
+    MOM_SCALAR_CALLER = 3, // nu = s[perm[i]]; writes outs[i]
+    MOM_AXPY = 4,          // nu = src4[i] + alpha * r4[i]; writes out4[i]
+    MOM_CONST_HALF = 5,    // nu = 1/2 (scalar); writes outs[i]
+};
+
+// Traversal epilogues.
+enum TravMode {
+    TR_OUT_CALLER = 0,  // write the operator value to caller order (API calls)
+    TR_RHO = 1,         // A: rho = 1/2 - s (sorted), block partial of rho^2
+    TR_R = 2,           // A^T: r (sorted float4), block partial of |r|^2
+    TR_TSUM = 3,        // A: block partial of s^2 only
+    TR_RESCALE = 4,     // G: mu <- G |mu| / |G| (sorted float4)
+};
+
+struct MomArgs {
+    const float4 *pts;       // sorted points
+    const int4 *topo;
+    const uint32_t *node_off;
+    const int32_t *node_strad;
+    const uint32_t *tail_off;
+    const int32_t *tail_list;
+    const int32_t *strad_node;
+    const uint32_t *perm;
+    const float4 *src4;      // sorted vector input
+    const float *srcs;       // sorted scalar input
+    const float4 *r4;        // axpy direction
+    const double *alpha;     // axpy step (device scalar)
+    const float *cn;         // caller-order (N,3) input
+    const float *csig;       // caller-order sigma (may be null)
+    const float *cs;         // caller-order scalar input
+    float4 *out4;
+    float *outs;
+    double *chunk_tot;       // 8 doubles per chunk
+    double *head;            // 8 doubles per straddler
+    double *tail;            // 8 doubles per straddler
+    float4 *mom;             // 2 float4 per node
+    int n;
+    int n_strad;
+};
+
+struct TravArgs {
+    const float4 *pts;
+    const int4 *topo;
+    const float4 *mom;
+    const float4 *src4;      // sorted vector attributes (A, G)
+    const float *srcs;       // sorted scalar attributes (A^T)
+    const uint32_t *perm;
+    float *out;              // TR_OUT_CALLER: caller-order output
+    float *rho;              // TR_RHO output
+    float4 *out4;            // TR_R / TR_RESCALE output
+    double *partial;         // per-block partial sums
+    unsigned long long *pairs;  // pair counter (counting variant)
+    int n, m;
+    int nblocks;
+    float w2;
+    float thr2[16];          // (c * 2^(1-d))^2 per depth d
+};
+
+}  // namespace wnnc
+
+// A device array that only grows.
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    int64_t cap = 0;
+    hipError_t ensure(int64_t need) {
+        if (need <= cap && p) return hipSuccess;
+        if (p) {
+            hipError_t e = hipFree(p);
+            p = nullptr;
+            cap = 0;
+            if (e != hipSuccess) return e;
+        }
+        int64_t c = need + need / 4 + 64;
+        hipError_t e = hipMalloc((void **)&p, (size_t)c * sizeof(T));
+        if (e != hipSuccess) {
+            p = nullptr;
+            return e;
+        }
+        cap = c;
+        return hipSuccess;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+// The context (opaque to callers).
+struct wnnc_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    unsigned flags = 0;
+
+    int64_t n = 0, m = 0;
+    float c = 2.0f;
+    int depth = 15;
+    bool built = false;
+
+    // tree (sorted order; nodes in depth-first pre-order)
+    DevBuf<float4> pts;            // n sorted normalized points
+    DevBuf<uint32_t> perm;         // n: sorted position -> caller index
+    DevBuf<int4> topo;             // m
+    DevBuf<uint32_t> node_off;     // n+1: first node started by each point
+    DevBuf<int32_t> node_strad;    // m: straddler slot or -1
+    DevBuf<int32_t> strad_node;    // n_strad
+    int32_t n_strad = 0;
+    DevBuf<uint32_t> tail_off;     // chunks+1
+    DevBuf<int32_t> tail_list;     // n_strad
+    DevBuf<double> chunk_tot;      // 8 per chunk
+    DevBuf<double> head, tail;     // 8 per straddler
+    DevBuf<float4> mom;            // 2 per node
+
+    // build scratch
+    DevBuf<unsigned long long> keys_a, keys_b;
+    DevBuf<uint32_t> vals_b;
+    DevBuf<uint32_t> hist;
+    DevBuf<uint32_t> scan_tmp;
+    DevBuf<uint32_t> u32_tmp;      // n+1
+    DevBuf<uint32_t> mflag, mslot; // m+1
+    DevBuf<double> norm_tmp;
+
+    // iteration buffers (sorted order)
+    DevBuf<float4> va, vb, vr;
+    DevBuf<float> rho;
+    DevBuf<double> partial;        // 3 * traversal blocks
+    DevBuf<double> scalars;        // [0] alpha
+    DevBuf<double> energy;
+    int last_energy_count = 0;
+    DevBuf<unsigned long long> pair_ctr;  // 3 counters
+
+    // statistics
+    int64_t calls[3] = {0, 0, 0};
+    double trav_ms[3] = {0, 0, 0};
+    double mom_ms = 0;
+    double build_ms = 0;
+
+    // event pairs of timed launches, resolved by wnnc_stats
+    struct Timed {
+        hipEvent_t a, b;
+        int kind;  // 0..2 traversal of an operator kind, 3 moment pass
+    };
+    std::vector<Timed> pending;
+    std::vector<hipEvent_t> event_pool;
+};

@@ -1,0 +1,36 @@
+// Host-side entry points shared between the library's translation units.
+#pragma once
+
+#include "common.h"
+
+namespace wnnc {
+
+int64_t scan_tmp_size(int64_t n);
+hipError_t exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp,
+                              hipStream_t st);
+
+// Tree build steps (tree.hip).
+hipError_t launch_normalize(const float *P, int64_t n, float *P_norm, double *dev_tmp,
+                            hipStream_t st);
+int64_t normalize_tmp_doubles(int64_t n);
+hipError_t build_tree(wnnc_ctx_s *ctx, const float *P);
+
+// Moment pass (moments.hip): two launches, chunk pass then straddler pass.
+hipError_t launch_moments(wnnc_ctx_s *ctx, MomMode mode, const MomArgs &a);
+
+// Traversal (traverse.hip).
+hipError_t launch_traverse(wnnc_ctx_s *ctx, Op op, TravMode mode, bool count, const TravArgs &a);
+int trav_blocks(int64_t n);
+
+// Glue (glue.hip).
+hipError_t launch_alpha(wnnc_ctx_s *ctx, int nblocks, double e_const, double *energy_slot);
+hipError_t launch_zero_f4(float4 *p, int64_t n, hipStream_t st);
+hipError_t launch_gather_vec(const float *src, const uint32_t *perm, float4 *dst, int64_t n,
+                             hipStream_t st);
+hipError_t launch_scatter_vec(const float4 *src, const uint32_t *perm, float *dst, int64_t n,
+                              hipStream_t st);
+
+hipError_t launch_normals(const float *mu, int64_t n, double scale, float *nrm, float *area,
+                          hipStream_t st);
+
+}  // namespace wnnc

@@ -1,0 +1,202 @@
+// The per-call moment pass: nu-representatives of every octree node
+// (Sec. 3.5, eqs. for the node representative location and vector):
+//   W_B = sum_{i in B} |nu_i|,  x_B = sum |nu_i| x_i / W_B,  nu_B = sum nu_i.
+//
+// Nodes are contiguous ranges of the Morton-sorted points.  The points are
+// cut into chunks of kChunk; one workgroup per chunk forms FP64 inclusive
+// prefix sums of (|nu|, |nu| x, nu) and finishes every node that lies inside
+// its chunk as a difference of two prefixes.  Nodes that cross a chunk
+// boundary ("straddlers") receive a head partial from their first chunk, a
+// tail partial from their last, and the totals of the chunks in between in a
+// second launch (one wavefront per straddler).  All sums run in a fixed
+// order, so the moments are bitwise reproducible from run to run.
+#include <float.h>
+
+#include "common.h"
+#include "internal.h"
+
+namespace wnnc {
+
+constexpr int kMomVals = 7;  // |nu|, |nu| x (3), nu (3)
+
+__device__ inline void write_moment(float4 *__restrict__ mom, int node, const double *s) {
+    const double W = s[0];
+    float4 p, v;
+    if (W > 0.0) {
+        p = make_float4((float)(s[1] / W), (float)(s[2] / W), (float)(s[3] / W),
+                        fmaxf((float)W, FLT_MIN));
+    } else {
+        p = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    v = make_float4((float)s[4], (float)s[5], (float)s[6], 0.f);
+    mom[2 * node] = p;
+    mom[2 * node + 1] = v;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kChunk) void k_moments_chunk(MomArgs a) {
+    __shared__ double P[kMomVals][kChunk];
+    __shared__ double wtot[kMomVals][kChunk / kWave];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wv = tid / kWave;
+    const int c = blockIdx.x;
+    const int c0 = c * kChunk;
+    const int cE = min(c0 + kChunk, a.n);
+    const int cnt = cE - c0;
+    const int i = c0 + tid;
+
+    double v[kMomVals];
+#pragma unroll
+    for (int k = 0; k < kMomVals; ++k) v[k] = 0.0;
+    if (i < a.n) {
+        const float4 x = a.pts[i];
+        float nu0 = 0.f, nu1 = 0.f, nu2 = 0.f;
+        bool scalar = false;
+        if (MODE == MOM_VEC_SORTED) {
+            const float4 q = a.src4[i];
+            nu0 = q.x, nu1 = q.y, nu2 = q.z;
+        } else if (MODE == MOM_SCALAR_SORTED) {
+            nu0 = a.srcs[i];
+            scalar = true;
+        } else if (MODE == MOM_VEC_CALLER) {
+            const int64_t j = a.perm[i];
+            const float sg = a.csig ? a.csig[j] : 1.0f;
+            nu0 = a.cn[3 * j] * sg, nu1 = a.cn[3 * j + 1] * sg, nu2 = a.cn[3 * j + 2] * sg;
+            a.out4[i] = make_float4(nu0, nu1, nu2, 0.f);
+        } else if (MODE == MOM_SCALAR_CALLER) {
+            nu0 = a.cs[a.perm[i]];
+            a.outs[i] = nu0;
+            scalar = true;
+        } else if (MODE == MOM_AXPY) {
+            const float al = (float)a.alpha[0];
+            const float4 q = a.src4[i], r = a.r4[i];
+            nu0 = fmaf(al, r.x, q.x), nu1 = fmaf(al, r.y, q.y), nu2 = fmaf(al, r.z, q.z);
+            a.out4[i] = make_float4(nu0, nu1, nu2, 0.f);
+        } else {  // MOM_CONST_HALF
+            nu0 = 0.5f;
+            a.outs[i] = nu0;
+            scalar = true;
+        }
+        const double d0 = nu0, d1 = nu1, d2 = nu2;
+        const double w = scalar ? fabs(d0) : sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        v[0] = w;
+        v[1] = w * (double)x.x;
+        v[2] = w * (double)x.y;
+        v[3] = w * (double)x.z;
+        v[4] = d0;
+        v[5] = d1;
+        v[6] = d2;
+    }
+    // inclusive scan over the chunk: wavefront shuffles, then wave totals
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+#pragma unroll
+        for (int k = 0; k < kMomVals; ++k) {
+            const double o = __shfl_up(v[k], d, kWave);
+            if (lane >= d) v[k] += o;
+        }
+    }
+    if (lane == kWave - 1) {
+#pragma unroll
+        for (int k = 0; k < kMomVals; ++k) wtot[k][wv] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kMomVals; ++k) {
+        double base = 0.0;
+        for (int w = 0; w < wv; ++w) base += wtot[k][w];
+        P[k][tid] = base + v[k];
+    }
+    __syncthreads();
+
+    if (tid < kMomVals) a.chunk_tot[8 * c + tid] = P[tid][cnt - 1];
+
+    // nodes started inside this chunk
+    const int nlo = (int)a.node_off[c0];
+    const int nhi = (int)a.node_off[cE];
+    for (int nd = nlo + tid; nd < nhi; nd += kChunk) {
+        const int4 t = a.topo[nd];
+        const int b = t.y - c0;
+        double s[kMomVals];
+        if (t.z <= cE) {
+            const int e = t.z - c0 - 1;
+#pragma unroll
+            for (int k = 0; k < kMomVals; ++k) s[k] = P[k][e] - (b > 0 ? P[k][b - 1] : 0.0);
+            write_moment(a.mom, nd, s);
+        } else {
+            const int sl = a.node_strad[nd];
+#pragma unroll
+            for (int k = 0; k < kMomVals; ++k)
+                a.head[8 * sl + k] = P[k][cnt - 1] - (b > 0 ? P[k][b - 1] : 0.0);
+        }
+    }
+    // straddlers whose range ends inside this chunk
+    const int tlo = (int)a.tail_off[c], thi = (int)a.tail_off[c + 1];
+    for (int q = tlo + tid; q < thi; q += kChunk) {
+        const int sl = a.tail_list[q];
+        const int e = a.topo[a.strad_node[sl]].z - c0 - 1;
+#pragma unroll
+        for (int k = 0; k < kMomVals; ++k) a.tail[8 * sl + k] = P[k][e];
+    }
+}
+
+// One wavefront per straddler: head + totals of the chunks in between + tail.
+__global__ __launch_bounds__(256) void k_moments_strad(MomArgs a) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int sl = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+    if (sl >= a.n_strad) return;
+    const int nd = a.strad_node[sl];
+    const int4 t = a.topo[nd];
+    const int cb = t.y / kChunk, ce = (t.z - 1) / kChunk;
+    double s[kMomVals];
+#pragma unroll
+    for (int k = 0; k < kMomVals; ++k) s[k] = 0.0;
+    for (int c = cb + 1 + lane; c < ce; c += kWave) {
+#pragma unroll
+        for (int k = 0; k < kMomVals; ++k) s[k] += a.chunk_tot[8 * c + k];
+    }
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+#pragma unroll
+        for (int k = 0; k < kMomVals; ++k) s[k] += __shfl_xor(s[k], d, kWave);
+    }
+    if (lane == 0) {
+        double tot[kMomVals];
+#pragma unroll
+        for (int k = 0; k < kMomVals; ++k) tot[k] = (a.head[8 * sl + k] + s[k]) + a.tail[8 * sl + k];
+        write_moment(a.mom, nd, tot);
+    }
+}
+
+hipError_t launch_moments(wnnc_ctx_s *ctx, MomMode mode, const MomArgs &a) {
+    const unsigned nchunks = (unsigned)((a.n + kChunk - 1) / kChunk);
+    hipStream_t st = ctx->stream;
+    switch (mode) {
+        case MOM_VEC_SORTED:
+            hipLaunchKernelGGL(k_moments_chunk<MOM_VEC_SORTED>, dim3(nchunks), dim3(kChunk), 0, st, a);
+            break;
+        case MOM_SCALAR_SORTED:
+            hipLaunchKernelGGL(k_moments_chunk<MOM_SCALAR_SORTED>, dim3(nchunks), dim3(kChunk), 0, st, a);
+            break;
+        case MOM_VEC_CALLER:
+            hipLaunchKernelGGL(k_moments_chunk<MOM_VEC_CALLER>, dim3(nchunks), dim3(kChunk), 0, st, a);
+            break;
+        case MOM_SCALAR_CALLER:
+            hipLaunchKernelGGL(k_moments_chunk<MOM_SCALAR_CALLER>, dim3(nchunks), dim3(kChunk), 0, st, a);
+            break;
+        case MOM_AXPY:
+            hipLaunchKernelGGL(k_moments_chunk<MOM_AXPY>, dim3(nchunks), dim3(kChunk), 0, st, a);
+            break;
+        case MOM_CONST_HALF:
+            hipLaunchKernelGGL(k_moments_chunk<MOM_CONST_HALF>, dim3(nchunks), dim3(kChunk), 0, st, a);
+            break;
+    }
+    if (a.n_strad > 0) {
+        const unsigned nb = (unsigned)((a.n_strad + 3) / 4);
+        hipLaunchKernelGGL(k_moments_strad, dim3(nb), dim3(256), 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace wnnc

@@ -1,0 +1,441 @@
+// Normalization (Sec. 4.1.1) and the octree build (Sec. 3.5) on the device.
+//
+// The octree over [-1,1]^3 with maximum depth D is the tree of Morton-code
+// prefixes: quantize each coordinate to 15 bits, interleave into a 45-bit
+// key, sort, and a node at depth d is a maximal run of sorted keys sharing
+// their top 3d bits whose parent run holds more than one point.  With sorted
+// keys this is decided locally: point i starts nodes at the depths
+// L+1 .. min(max(L,R)+1, D), where L and R are the numbers of leading octal
+// digits it shares with its left and right neighbours.  Numbering the nodes
+// point by point, shallow to deep, yields a depth-first pre-order in which
+// the first child of a node is the next node and a subtree is a contiguous
+// index range.
+#include <float.h>
+
+#include "common.h"
+#include "internal.h"
+
+namespace wnnc {
+
+// ------------------------------------------------------------ normalize --
+
+constexpr int kNormBlocks = 256;
+
+int64_t normalize_tmp_doubles(int64_t) { return kNormBlocks * 6 + 8; }
+
+__global__ __launch_bounds__(256) void k_minmax(const float *__restrict__ P, int64_t n,
+                                                double *__restrict__ part) {
+    float lo[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, hi[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            float v = P[3 * i + k];
+            lo[k] = fminf(lo[k], v);
+            hi[k] = fmaxf(hi[k], v);
+        }
+    }
+    __shared__ float s[6][256];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        s[k][threadIdx.x] = lo[k];
+        s[3 + k][threadIdx.x] = hi[k];
+    }
+    __syncthreads();
+    for (int d = 128; d > 0; d >>= 1) {
+        if (threadIdx.x < d) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                s[k][threadIdx.x] = fminf(s[k][threadIdx.x], s[k][threadIdx.x + d]);
+                s[3 + k][threadIdx.x] = fmaxf(s[3 + k][threadIdx.x], s[3 + k][threadIdx.x + d]);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+// One thread: reduce the block extremes and derive centre and scale in FP64.
+__global__ void k_norm_finalize(double *__restrict__ part, int nb) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = part[k];
+        hi[k] = part[3 + k];
+    }
+    for (int b = 1; b < nb; ++b)
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = fmin(lo[k], part[b * 6 + k]);
+            hi[k] = fmax(hi[k], part[b * 6 + 3 + k]);
+        }
+    double half = 0.0;
+    double *out = part + kNormBlocks * 6;
+    for (int k = 0; k < 3; ++k) {
+        out[k] = (lo[k] + hi[k]) / 2.0;
+        half = fmax(half, (hi[k] - lo[k]) / 2.0);
+    }
+    out[3] = half > 0.0 ? (10.0 / 11.0) / half : 1.0;
+}
+
+__global__ __launch_bounds__(256) void k_norm_apply(const float *P, int64_t n3, float *Q,
+                                                    const double *__restrict__ cs) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n3) return;
+    const int k = (int)(i % 3);
+    Q[i] = (float)(((double)P[i] - cs[k]) * cs[3]);
+}
+
+hipError_t launch_normalize(const float *P, int64_t n, float *P_norm, double *tmp,
+                            hipStream_t st) {
+    int nb = (int)((n + 255) / 256);
+    if (nb > kNormBlocks) nb = kNormBlocks;
+    hipLaunchKernelGGL(k_minmax, dim3(nb), dim3(256), 0, st, P, n, tmp);
+    hipLaunchKernelGGL(k_norm_finalize, dim3(1), dim3(64), 0, st, tmp, nb);
+    const int64_t n3 = 3 * n;
+    hipLaunchKernelGGL(k_norm_apply, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, P, n3,
+                       P_norm, tmp + kNormBlocks * 6);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------- morton --
+
+// Spread the low 15 bits of v so that bit b lands on bit 3b.
+__device__ inline unsigned long long spread3(unsigned v) {
+    unsigned long long x = v & 0x7fffu;
+    x = (x | (x << 16)) & 0x00000000ff0000ffull;
+    x = (x | (x << 8)) & 0x000000f00f00f00full;
+    x = (x | (x << 4)) & 0x00000c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x0000249249249249ull;
+    return x;
+}
+
+// Cell index of coordinate v along one axis at depth 15:
+// floor((v + 1) 2^14) clamped to [0, 2^15 - 1], evaluated as
+// floor(v 2^14) + 2^14, which is exact in FP32 (the scaling is by a power of
+// two).  A coordinate on a split plane goes to the upper cell.
+__device__ inline unsigned quantize15(float v) {
+    float f = floorf(v * 16384.0f) + 16384.0f;
+    f = fminf(fmaxf(f, 0.0f), 32767.0f);
+    return (unsigned)f;
+}
+
+__global__ __launch_bounds__(256) void k_morton(const float *__restrict__ P, int64_t n,
+                                                unsigned long long *__restrict__ keys,
+                                                uint32_t *__restrict__ vals) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    unsigned qx = quantize15(P[3 * i]), qy = quantize15(P[3 * i + 1]), qz = quantize15(P[3 * i + 2]);
+    keys[i] = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
+    vals[i] = (uint32_t)i;
+}
+
+// ------------------------------------------------------------ radix sort --
+// Stable LSD radix sort of (45-bit key, uint32 value), 8 bits per pass.
+
+constexpr int kRsThreads = 256;
+constexpr int kRsItems = 8;
+constexpr int kRsTile = kRsThreads * kRsItems;
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_hist(const unsigned long long *__restrict__ keys,
+                                                        int64_t n, int shift,
+                                                        uint32_t *__restrict__ hist, int ntiles) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+#pragma unroll
+    for (int k = 0; k < kRsItems; ++k) {
+        int64_t i = base + k * kRsThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(unsigned)(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(
+    const unsigned long long *__restrict__ kin, const uint32_t *__restrict__ vin,
+    unsigned long long *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n, int shift,
+    const uint32_t *__restrict__ offs, int ntiles) {
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wc[kRsThreads / kWave][256];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wv = tid / kWave;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    run[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    for (int r = 0; r < kRsItems; ++r) {
+#pragma unroll
+        for (int w = 0; w < kRsThreads / kWave; ++w) wc[w][tid] = 0;
+        __syncthreads();
+        const int64_t i = base + r * kRsThreads + tid;
+        const bool valid = i < n;
+        unsigned long long key = valid ? kin[i] : 0ull;
+        uint32_t val = valid ? vin[i] : 0u;
+        const unsigned dig = (unsigned)(key >> shift) & 255u;
+        unsigned long long peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (dig >> b) & 1u;
+            const unsigned long long m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const unsigned rank = (unsigned)__popcll(peers & lt);
+        if (valid && rank == 0) wc[wv][dig] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        {
+            uint32_t c[kRsThreads / kWave];
+#pragma unroll
+            for (int w = 0; w < kRsThreads / kWave; ++w) c[w] = wc[w][tid];
+            uint32_t b = run[tid];
+#pragma unroll
+            for (int w = 0; w < kRsThreads / kWave; ++w) {
+                wc[w][tid] = b;
+                b += c[w];
+            }
+            run[tid] = b;
+        }
+        __syncthreads();
+        if (valid) {
+            const uint32_t pos = wc[wv][dig] + rank;
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------- nodes --
+
+// Number of leading octal digits (of 15) shared by two keys.
+__device__ inline int lcp_digits(unsigned long long a, unsigned long long b) {
+    unsigned long long x = a ^ b;
+    if (x == 0ull) return 15;
+    return (__clzll(x) - 19) / 3;
+}
+
+__device__ inline void neighbour_lcp(const unsigned long long *keys, int64_t n, int64_t i, int D,
+                                     int *L, int *R) {
+    const unsigned long long k = keys[i];
+    int l = i > 0 ? lcp_digits(keys[i - 1], k) : -1;
+    int r = i + 1 < n ? lcp_digits(k, keys[i + 1]) : -1;
+    *L = l > D ? D : l;
+    *R = r > D ? D : r;
+}
+
+__global__ __launch_bounds__(256) void k_count_nodes(const unsigned long long *__restrict__ keys,
+                                                     int64_t n, int D,
+                                                     uint32_t *__restrict__ counts) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    if (i == n) {
+        counts[n] = 0;
+        return;
+    }
+    int L, R;
+    neighbour_lcp(keys, n, i, D, &L, &R);
+    int hi = (L > R ? L : R) + 1;
+    if (hi > D) hi = D;
+    counts[i] = L >= D ? 0u : (uint32_t)(hi - L);
+}
+
+// First sorted position after i whose key leaves the depth-d cell of key i.
+__device__ inline int64_t run_end(const unsigned long long *keys, int64_t n, int64_t i, int d) {
+    if (d == 0) return n;
+    const int shift = 3 * (15 - d);
+    const unsigned long long pre = keys[i] >> shift;
+    int64_t lo = i, step = 1;
+    while (lo + step < n && (keys[lo + step] >> shift) == pre) {
+        lo += step;
+        step <<= 1;
+    }
+    int64_t hi = lo + step < n ? lo + step : n;  // keys[hi] differs, or hi == n
+    while (hi - lo > 1) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if ((keys[mid] >> shift) == pre)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return hi;
+}
+
+__global__ __launch_bounds__(256) void k_emit_nodes(const unsigned long long *__restrict__ keys,
+                                                    int64_t n, int D,
+                                                    const uint32_t *__restrict__ node_off,
+                                                    int4 *__restrict__ topo,
+                                                    uint32_t *__restrict__ strad_flag) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int L, R;
+    neighbour_lcp(keys, n, i, D, &L, &R);
+    if (L >= D) return;
+    int hi = (L > R ? L : R) + 1;
+    if (hi > D) hi = D;
+    const uint32_t base = node_off[i];
+    for (int d = L + 1; d <= hi; ++d) {
+        const uint32_t idx = base + (uint32_t)(d - (L + 1));
+        const int64_t end = run_end(keys, n, i, d);
+        const int leaf = (end - i == 1) || (d == D);
+        topo[idx] = make_int4((int)node_off[end], (int)i, (int)end, d | (leaf << 4));
+        strad_flag[idx] = ((i / kChunk) != ((end - 1) / kChunk)) ? 1u : 0u;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gather_points(const float *__restrict__ P,
+                                                       const uint32_t *__restrict__ perm,
+                                                       int64_t n, float4 *__restrict__ pts) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t j = perm[i];
+    pts[i] = make_float4(P[3 * (int64_t)j], P[3 * (int64_t)j + 1], P[3 * (int64_t)j + 2], 0.0f);
+}
+
+// Straddlers: nodes whose point range crosses a chunk boundary.
+__global__ __launch_bounds__(256) void k_strad_compact(const uint32_t *__restrict__ flag,
+                                                       const uint32_t *__restrict__ slot,
+                                                       int64_t m, int32_t *__restrict__ node_strad,
+                                                       int32_t *__restrict__ strad_node) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    if (flag[k]) {
+        node_strad[k] = (int32_t)slot[k];
+        strad_node[slot[k]] = (int32_t)k;
+    } else {
+        node_strad[k] = -1;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_tail_count(const int32_t *__restrict__ strad_node,
+                                                    const int4 *__restrict__ topo, int ns,
+                                                    uint32_t *__restrict__ cnt) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= ns) return;
+    const int e = topo[strad_node[s]].z;
+    atomicAdd(&cnt[(e - 1) / kChunk], 1u);
+}
+
+__global__ __launch_bounds__(256) void k_tail_fill(const int32_t *__restrict__ strad_node,
+                                                   const int4 *__restrict__ topo, int ns,
+                                                   uint32_t *__restrict__ cursor,
+                                                   int32_t *__restrict__ list) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= ns) return;
+    const int e = topo[strad_node[s]].z;
+    const uint32_t q = atomicAdd(&cursor[(e - 1) / kChunk], 1u);
+    list[q] = s;
+}
+
+// ------------------------------------------------------------------- host --
+
+#define TRY(x)                           \
+    do {                                 \
+        hipError_t _e = (x);             \
+        if (_e != hipSuccess) return _e; \
+    } while (0)
+
+static inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t build_tree(wnnc_ctx_s *ctx, const float *P) {
+    const int64_t n = ctx->n;
+    const int D = ctx->depth;
+    hipStream_t st = ctx->stream;
+    const int64_t nchunks = (n + kChunk - 1) / kChunk;
+    const int ntiles = (int)((n + kRsTile - 1) / kRsTile);
+    const int64_t hsize = (int64_t)256 * ntiles;
+
+    TRY(ctx->pts.ensure(n));
+    TRY(ctx->perm.ensure(n));
+    TRY(ctx->node_off.ensure(n + 1));
+    TRY(ctx->keys_a.ensure(n));
+    TRY(ctx->keys_b.ensure(n));
+    TRY(ctx->vals_b.ensure(n));
+    TRY(ctx->u32_tmp.ensure(n + 1));
+    TRY(ctx->hist.ensure(hsize));
+    TRY(ctx->tail_off.ensure(nchunks + 1));
+    TRY(ctx->chunk_tot.ensure(8 * nchunks));
+    TRY(ctx->va.ensure(n));
+    TRY(ctx->vb.ensure(n));
+    TRY(ctx->vr.ensure(n));
+    TRY(ctx->rho.ensure(n));
+    TRY(ctx->partial.ensure(3 * (int64_t)trav_blocks(n)));
+    TRY(ctx->scalars.ensure(8));
+    TRY(ctx->pair_ctr.ensure(4));
+    {
+        int64_t big = hsize > n + 1 ? hsize : n + 1;
+        TRY(ctx->scan_tmp.ensure(scan_tmp_size(16 * big + 16)));
+    }
+
+    // Morton keys and the stable sort: 6 passes of 8 bits cover the 45 key
+    // bits, and an even pass count leaves the result in keys_a / perm.
+    hipLaunchKernelGGL(k_morton, dim3(blocks_for(n, 256)), dim3(256), 0, st, P, n, ctx->keys_a.p,
+                       ctx->perm.p);
+    unsigned long long *kin = ctx->keys_a.p, *kout = ctx->keys_b.p;
+    uint32_t *vin = ctx->perm.p, *vout = ctx->vals_b.p;
+    for (int pass = 0; pass < 6; ++pass) {
+        const int shift = 8 * pass;
+        hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(kRsThreads), 0, st, kin, n, shift,
+                           ctx->hist.p, ntiles);
+        TRY(exclusive_scan_u32(ctx->hist.p, ctx->hist.p, hsize, ctx->scan_tmp.p, st));
+        hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(kRsThreads), 0, st, kin, vin, kout,
+                           vout, n, shift, ctx->hist.p, ntiles);
+        unsigned long long *tk = kin;
+        kin = kout;
+        kout = tk;
+        uint32_t *tv = vin;
+        vin = vout;
+        vout = tv;
+    }
+    TRY(hipGetLastError());
+
+    // nodes started per point -> pre-order offsets; M is read back once
+    hipLaunchKernelGGL(k_count_nodes, dim3(blocks_for(n + 1, 256)), dim3(256), 0, st,
+                       ctx->keys_a.p, n, D, ctx->u32_tmp.p);
+    TRY(exclusive_scan_u32(ctx->u32_tmp.p, ctx->node_off.p, n + 1, ctx->scan_tmp.p, st));
+    uint32_t m32 = 0;
+    TRY(hipMemcpyAsync(&m32, ctx->node_off.p + n, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    TRY(hipStreamSynchronize(st));
+    const int64_t m = m32;
+    ctx->m = m;
+
+    TRY(ctx->topo.ensure(m));
+    TRY(ctx->node_strad.ensure(m));
+    TRY(ctx->mom.ensure(2 * m));
+    TRY(ctx->mflag.ensure(m + 1));
+    TRY(ctx->mslot.ensure(m + 1));
+
+    TRY(hipMemsetAsync(ctx->mflag.p, 0, (size_t)(m + 1) * sizeof(uint32_t), st));
+    hipLaunchKernelGGL(k_emit_nodes, dim3(blocks_for(n, 256)), dim3(256), 0, st, ctx->keys_a.p,
+                       n, D, ctx->node_off.p, ctx->topo.p, ctx->mflag.p);
+    hipLaunchKernelGGL(k_gather_points, dim3(blocks_for(n, 256)), dim3(256), 0, st, P,
+                       ctx->perm.p, n, ctx->pts.p);
+    TRY(exclusive_scan_u32(ctx->mflag.p, ctx->mslot.p, m + 1, ctx->scan_tmp.p, st));
+    uint32_t ns32 = 0;
+    TRY(hipMemcpyAsync(&ns32, ctx->mslot.p + m, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    TRY(hipStreamSynchronize(st));
+    const int64_t ns = ns32;
+    ctx->n_strad = (int32_t)ns;
+    TRY(ctx->strad_node.ensure(ns + 1));
+    TRY(ctx->tail_list.ensure(ns + 1));
+    TRY(ctx->head.ensure(8 * (ns + 1)));
+    TRY(ctx->tail.ensure(8 * (ns + 1)));
+    hipLaunchKernelGGL(k_strad_compact, dim3(blocks_for(m, 256)), dim3(256), 0, st, ctx->mflag.p,
+                       ctx->mslot.p, m, ctx->node_strad.p, ctx->strad_node.p);
+    // chunk -> straddlers whose range ends inside it (CSR); counts reuse mflag
+    uint32_t *tcnt = ctx->u32_tmp.p;  // n+1 >= chunks+1 entries
+    TRY(hipMemsetAsync(tcnt, 0, (size_t)(nchunks + 1) * sizeof(uint32_t), st));
+    if (ns > 0)
+        hipLaunchKernelGGL(k_tail_count, dim3(blocks_for(ns, 256)), dim3(256), 0, st,
+                           ctx->strad_node.p, ctx->topo.p, (int)ns, tcnt);
+    TRY(exclusive_scan_u32(tcnt, ctx->tail_off.p, nchunks + 1, ctx->scan_tmp.p, st));
+    uint32_t *cursor = ctx->mslot.p;  // free again: m+1 >= chunks+1 entries
+    TRY(hipMemcpyAsync(cursor, ctx->tail_off.p, (size_t)(nchunks + 1) * sizeof(uint32_t),
+                       hipMemcpyDeviceToDevice, st));
+    if (ns > 0)
+        hipLaunchKernelGGL(k_tail_fill, dim3(blocks_for(ns, 256)), dim3(256), 0, st,
+                           ctx->strad_node.p, ctx->topo.p, (int)ns, cursor, ctx->tail_list.p);
+    TRY(hipMemsetAsync(ctx->pair_ctr.p, 0, 4 * sizeof(unsigned long long), st));
+    return hipGetLastError();
+}
+
+}  // namespace wnnc

@@ -1,0 +1,50 @@
+"""The C-ABI library loads and exports every entry point include/wnnc.h
+declares (no device calls: this runs without a GPU)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wnnc.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(wnnc_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("wnnc_create", "wnnc_destroy", "wnnc_normalize", "wnnc_build",
+                     "wnnc_winding", "wnnc_gradient", "wnnc_adjoint", "wnnc_orient",
+                     "wnnc_normals", "wnnc_stats", "wnnc_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2405_16634_amd as w
+    lib = w.load_library()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert sorted(w.EXPORTED) == declared_functions()
+    assert "gfx950" in w.wnnc_version()
+
+
+def test_library_is_built_for_gfx950_only():
+    import re as _re
+    import paper_2405_16634_amd as w
+    data = open(w.LIB_PATH, "rb").read()
+    targets = set(_re.findall(rb"amdgcn-amd-amdhsa--(gfx[0-9a-f]+)", data))
+    assert targets == {b"gfx950"}
+
+
+def test_errors_are_reported_without_a_device():
+    """Argument checks that fail before any device work return EINVAL with
+    a message (a NULL output pointer for the context)."""
+    import paper_2405_16634_amd as w
+    lib = w.load_library()
+    st = lib.wnnc_create(None, 0, None)
+    assert st == w.WNNC_EINVAL
+    assert "null" in w.wnnc_last_error()
+    assert lib.wnnc_build(None, None, 0, None) == w.WNNC_EINVAL
