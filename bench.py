@@ -1,0 +1,239 @@
+"""Benchmark: WNNC normal orientation of a 500k-point cloud on one MI355X.
+
+One step = the whole hot path on one synthetic cloud already resident in
+device memory: normalization, octree build, 40 iterations of Alg. 3 (each a
+gradient step with A, A^T, A and a WNNC update with G, with the moment pass
+before every operator), and the unit-normal output.
+
+Prints one JSON line.  ``value`` is pair interactions per second over the
+whole step (every near and far pair evaluation of every operator call,
+counted in a separate counting run with identical decisions), ``ms_per_step``
+the 40-iteration wall time.  ``roofline`` is for the traversal kernel with
+the largest total time, timed with HIP events on the library's stream during
+the timed steps.  ``cpu_baseline`` times the FP64 oracle treecode on a sample
+of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "WNNC 40-iter time & Gpair-interactions/s at N=500k; warm-start vs plain speedup"
+FLOPS_PER_PAIR = {0: 18, 1: 18, 2: 31}  # A, A^T, G (FMA = 2, rsqrt = 1)
+KIND = {0: "A", 1: "AT", 2: "G"}
+PEAK_FP32_TFLOPS = 157.3
+TRAVERSE_SRC = os.path.join(ROOT, "paper_2405_16634_amd", "csrc", "traverse.hip")
+
+
+def source_digest(path: str) -> str:
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(kind: str):
+    """HBM bytes per launch from a committed rocprofv3 PMC summary, if it was
+    taken on the current traversal source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_traverse_{kind}_torusknot500k.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("source_sha") != source_digest(TRAVERSE_SRC):
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(cloud, w: float, c: float):
+    """The FP64 oracle treecode on the same cloud for one WNNC iteration's
+    four operator calls (A, A^T, A, G over all points; a run has 159), from
+    the ground-truth-normal state.  Reports pair interactions per second."""
+    import oracle
+    x, _, sc = oracle.normalize(cloud.points)
+    x = x.astype(np.float64)
+    mu = cloud.normals.astype(np.float64) * (cloud.area * sc * sc / cloud.n)
+    mu[~np.isfinite(mu).all(axis=1)] = 0.0
+    t0 = time.perf_counter()
+    T = oracle.Tree(x)
+    t1 = time.perf_counter()
+    p = 0
+    s, _, k = T.apply("A", mu, w, c, with_stats=True)
+    p += int(k.sum())
+    r, _, k = T.apply("AT", 0.5 - s, w, c, with_stats=True)
+    p += int(k.sum())
+    _, _, k = T.apply("A", r, w, c, with_stats=True)
+    p += int(k.sum())
+    _, _, k = T.apply("G", mu, w, c, with_stats=True)
+    p += int(k.sum())
+    t2 = time.perf_counter()
+    return {
+        "value": round(p / (t2 - t1) / 1e9, 4),
+        "unit": "Gpair-interactions/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"FP64 oracle treecode (C, OpenMP): one iteration's 4 operator calls (A, A^T, A, G; "
+                   f"159 per 40-iteration run) over all {cloud.n} points of the torus-knot cloud, "
+                   f"{p} pairs in {t2 - t1:.2f} s; oracle tree build {t1 - t0:.2f} s not included"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=500000)
+    ap.add_argument("--iters", type=int, default=40)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              f"(multi-GPU sharding is a design note only).", file=sys.stderr)
+        sys.exit(2)
+    rank = int(os.environ.get("RANK", "0"))
+
+    import torch
+    import paper_2405_16634_amd as w
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    w1, w2, c, depth = 0.002, 0.016, 2.0, 15
+    cloud = synth.torus_knot(args.n, 3)
+    P = torch.from_numpy(cloud.points).to(dev)
+    stream = torch.cuda.current_stream()
+    ctx = w.Context(0, stream)
+    Pn = torch.empty_like(P)
+    mu = torch.empty_like(P)
+    nrm = torch.empty_like(P)
+
+    def step():
+        cs = w.wnnc_normalize(ctx.handle, P, Pn)
+        w.wnnc_build(ctx.handle, Pn, c, depth)
+        w.wnnc_orient(ctx.handle, mu, None, args.iters, w1, w2)
+        w.wnnc_normals(ctx.handle, mu, cs[1], nrm)
+
+    # pair counts: one run with the counting kernels (same decisions)
+    ctx.set_flags(w.FLAG_COUNT_PAIRS)
+    ctx.reset_stats()
+    step()
+    torch.cuda.synchronize()
+    cst = ctx.stats()
+    pairs = cst["pairs"]
+    calls_per_run = cst["calls"]
+    total_pairs = int(sum(pairs))
+
+    ctx.set_flags(0)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # timed steps, with per-launch HIP events on the library's stream
+    ctx.set_flags(w.FLAG_TIME_KERNELS)
+    ctx.reset_stats()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_host0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_host1 = time.perf_counter()
+    ms_total = ev0.elapsed_time(ev1)
+    ms_step = ms_total / args.steps
+    st = ctx.stats()
+    ctx.set_flags(0)
+
+    # build time and the main loop, separately (one more untimed-kernel step)
+    torch.cuda.synchronize()
+    e_a = torch.cuda.Event(enable_timing=True)
+    e_b = torch.cuda.Event(enable_timing=True)
+    e_c = torch.cuda.Event(enable_timing=True)
+    e_a.record(stream)
+    cs = w.wnnc_normalize(ctx.handle, P, Pn)
+    w.wnnc_build(ctx.handle, Pn, c, depth)
+    e_b.record(stream)
+    w.wnnc_orient(ctx.handle, mu, None, args.iters, w1, w2)
+    w.wnnc_normals(ctx.handle, mu, cs[1], nrm)
+    e_c.record(stream)
+    torch.cuda.synchronize()
+    t_pre = e_a.elapsed_time(e_b)
+    t_main = e_b.elapsed_time(e_c)
+
+    # dominant traversal kernel
+    per_kind = {}
+    for k in range(3):
+        calls = st["calls"][k]
+        if calls == 0:
+            continue
+        avg_ms = st["traverse_ms"][k] / calls
+        pairs_per_launch = pairs[k] / max(calls_per_run[k], 1)
+        flop = pairs_per_launch * FLOPS_PER_PAIR[k]
+        per_kind[KIND[k]] = dict(total_ms=st["traverse_ms"][k] / args.steps, launches=calls // args.steps,
+                                 avg_ms=avg_ms, pairs_per_launch=pairs_per_launch,
+                                 tflops=flop / (avg_ms * 1e-3) / 1e12,
+                                 gpairs_per_s=pairs_per_launch / (avg_ms * 1e-3) / 1e9)
+    dom = max(per_kind, key=lambda k: per_kind[k]["total_ms"])
+    d = per_kind[dom]
+    traffic = load_traffic(dom)
+    roofline = {"bound": "alu", "achieved": round(d["tflops"], 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(d["tflops"] / PEAK_FP32_TFLOPS, 4),
+                "traffic": traffic, "kernel": f"k_traverse<{dom}>",
+                "avg_launch_ms": round(d["avg_ms"], 4),
+                "flop_per_launch": round(d["pairs_per_launch"] * FLOPS_PER_PAIR[{"A": 0, "AT": 1, "G": 2}[dom]])}
+
+    nrm_h = nrm.cpu().numpy()
+    ok = np.isfinite(cloud.normals).all(axis=1)
+    pco = float(((nrm_h[ok] * cloud.normals[ok]).sum(1) > 0).mean())
+    ae = float(((1.0 - (nrm_h[ok] * cloud.normals[ok]).sum(1)) / 2.0).mean())
+
+    out = {
+        "metric": METRIC,
+        "value": round(total_pairs / (ms_step * 1e-3) / 1e9, 3),
+        "unit": "Gpair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"torusknot{args.n // 1000}k", "n_points": args.n, "iters": args.iters,
+                   "w1": w1, "w2": w2, "c": c, "max_depth": depth, "outlier_frac": 0.02,
+                   "tube_radius": 0.05, "density_ratio": 10, "seed": 3},
+        "time_40iter_s": round(ms_step / 1e3, 4),
+        "t_pre_ms": round(t_pre, 3),
+        "t_main_ms": round(t_main, 3),
+        "pairs_per_step": total_pairs,
+        "pairs_per_kind": {KIND[k]: int(pairs[k]) for k in range(3)},
+        "operator_calls": {KIND[k]: int(calls_per_run[k]) for k in range(3)},
+        "traversal": per_kind,
+        "moments_ms_per_step": round(st["moments_ms"] / args.steps, 3),
+        "host_wall_s_per_step": round((t_host1 - t_host0) / args.steps, 4),
+        "accuracy_vs_generator": {"P_co": round(pco, 5), "AE_pcd": round(ae, 6)},
+        "context_paper_rtx3090_s": {"N=50k": 1.25, "N=500k": 31.63},
+        "roofline": roofline,
+    }
+    if rank == 0 and not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cloud, w1, c)
+    ctx.close()
+    if rank == 0:
+        print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
