@@ -1,0 +1,96 @@
+"""Differentiable winding numbers: autograd Functions over the C ABI.
+
+The adjoint operator is the backward of the winding-number operator
+(Sec. 3.5, last paragraph: A^T is exactly the backward function of A):
+
+* ``winding(ctx, mu, w)``   s = A_w(mu)          backward: g -> A_w^T g
+* ``adjoint(ctx, s, w)``    v = A_w^T s          backward: g -> A_w g
+* ``gradient(ctx, mu, w)``  grad F = -G_w(mu)    backward: g -> -G_w g
+  (G is symmetric: HPhi is an even, symmetric matrix field)
+
+All three evaluate with the context's treecode; every forward and backward
+runs in the library's kernels (argument marshalling only here).  With the
+treecode the backward is the treecode of the transposed operator, as in the
+paper; it equals the exact gradient of the treecode forward only up to the
+treecode's approximation error, because the representatives depend on |nu|.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import wnnc_adjoint, wnnc_gradient, wnnc_winding
+
+
+def _prep(t):
+    return t.detach().contiguous().float()
+
+
+class WindingNumber(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, handle, mu, w):
+        fctx.handle, fctx.w = handle, float(w)
+        out = torch.empty(mu.shape[0], device=mu.device, dtype=torch.float32)
+        wnnc_winding(handle, _prep(mu), None, fctx.w, out)
+        return out
+
+    @staticmethod
+    def backward(fctx, g):
+        gm = torch.empty(g.shape[0], 3, device=g.device, dtype=torch.float32)
+        wnnc_adjoint(fctx.handle, _prep(g), fctx.w, gm)
+        return None, gm, None
+
+
+class WindingAdjoint(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, handle, s, w):
+        fctx.handle, fctx.w = handle, float(w)
+        out = torch.empty(s.shape[0], 3, device=s.device, dtype=torch.float32)
+        wnnc_adjoint(handle, _prep(s), fctx.w, out)
+        return out
+
+    @staticmethod
+    def backward(fctx, g):
+        gs = torch.empty(g.shape[0], device=g.device, dtype=torch.float32)
+        wnnc_winding(fctx.handle, _prep(g), None, fctx.w, gs)
+        return None, gs, None
+
+
+class WindingGradient(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, handle, mu, w):
+        fctx.handle, fctx.w = handle, float(w)
+        out = torch.empty_like(mu, dtype=torch.float32)
+        wnnc_gradient(handle, _prep(mu), None, fctx.w, out)
+        return out
+
+    @staticmethod
+    def backward(fctx, g):
+        gm = torch.empty_like(g, dtype=torch.float32)
+        wnnc_gradient(fctx.handle, _prep(g), None, fctx.w, gm)
+        return None, gm, None
+
+
+def _handle(ctx):
+    return ctx.handle if hasattr(ctx, "handle") else ctx
+
+
+def winding(ctx, mu, w: float):
+    """s = A_w(mu) at the points of ctx's tree; differentiable in mu."""
+    return WindingNumber.apply(_handle(ctx), mu, w)
+
+
+def adjoint(ctx, s, w: float):
+    """A_w^T s; differentiable in s."""
+    return WindingAdjoint.apply(_handle(ctx), s, w)
+
+
+def gradient(ctx, mu, w: float):
+    """grad F(x_i; mu) = -G_w(mu)_i; differentiable in mu."""
+    return WindingGradient.apply(_handle(ctx), mu, w)
+
+
+def pgr_energy(ctx, mu, w: float, b: float = 0.5):
+    """E(mu) = ||A_w mu - b||^2 (eq. value-energy); its autograd gradient is
+    2 A_w^T (A_w mu - b) = -2 r of Alg. 2."""
+    s = winding(ctx, mu, w)
+    return ((s - b) ** 2).sum()

@@ -192,6 +192,7 @@ wnnc_status wnnc_destroy(wnnc_ctx ctx) {
     ctx->scalars.release();
     ctx->energy.release();
     ctx->pair_ctr.release();
+    ctx->wbuf.release();
     for (auto &t : ctx->pending) {
         (void)hipEventDestroy(t.a);
         (void)hipEventDestroy(t.b);
@@ -506,7 +507,9 @@ wnnc_status wnnc_moments_export(wnnc_ctx ctx, const float *nu, int dim, float *x
     CHECK_BUILT(ctx);
     if (!nu) return fail(WNNC_EINVAL, "null nu");
     if (dim != 1 && dim != 3) return fail(WNNC_EINVAL, "dim must be 1 or 3");
+    HIPCHK(ctx->wbuf.ensure(ctx->m));
     MomArgs ma = mom_args(ctx);
+    ma.wout = ctx->wbuf.p;
     if (dim == 3) {
         ma.cn = nu;
         ma.out4 = ctx->vb.p;
@@ -517,7 +520,10 @@ wnnc_status wnnc_moments_export(wnnc_ctx ctx, const float *nu, int dim, float *x
         RETURN_IF(run_moments(ctx, MOM_SCALAR_CALLER, ma));
     }
     std::vector<float4> mom((size_t)(2 * ctx->m));
+    std::vector<float> wv((size_t)ctx->m);
     HIPCHK(hipMemcpyAsync(mom.data(), ctx->mom.p, (size_t)(2 * ctx->m) * sizeof(float4),
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(wv.data(), ctx->wbuf.p, (size_t)ctx->m * sizeof(float),
                           hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     for (int64_t k = 0; k < ctx->m; ++k) {
@@ -527,7 +533,7 @@ wnnc_status wnnc_moments_export(wnnc_ctx ctx, const float *nu, int dim, float *x
             xB[3 * k + 1] = p.y;
             xB[3 * k + 2] = p.z;
         }
-        if (W) W[k] = p.w;
+        if (W) W[k] = wv[k];
         if (nuB) {
             if (dim == 3) {
                 nuB[3 * k] = v.x;

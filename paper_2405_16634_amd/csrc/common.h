@@ -23,7 +23,14 @@ constexpr int kMaxDepth = 15;    // 15 levels below the root: 45-bit Morton keys
 __host__ __device__ inline int topo_depth(int meta) { return meta & 15; }
 __host__ __device__ inline int topo_leaf(int meta) { return (meta >> 4) & 1; }
 
-// Node moments, two float4 per node: (x_B, W) and (nu_B, 0).  W = sum |nu|.
+// Node record written by every moment pass and read by the traversal, two
+// 16-byte halves per node (one 32-byte scalar load):
+//   [0] x_B.x, x_B.y, x_B.z, flags (int bits)
+//   [1] nu_B (3 floats; a scalar attribute in .x), skip (int bits)
+// flags = depth | leaf << 4 | single-point leaf << 5 | zero weight << 6.
+constexpr int kRecLeaf = 16;
+constexpr int kRecSingle = 32;
+constexpr int kRecZero = 64;
 
 enum Op { OP_A = WNNC_OP_A, OP_AT = WNNC_OP_AT, OP_G = WNNC_OP_G };
 
@@ -67,7 +74,8 @@ struct MomArgs {
     double *chunk_tot;       // 8 doubles per chunk
     double *head;            // 8 doubles per straddler
     double *tail;            // 8 doubles per straddler
-    float4 *mom;             // 2 float4 per node
+    float4 *mom;             // node records, 2 float4 per node
+    float *wout;             // optional: W = sum |nu| per node (inspection)
     int n;
     int n_strad;
 };
@@ -145,6 +153,7 @@ struct wnnc_ctx_s {
     DevBuf<double> chunk_tot;      // 8 per chunk
     DevBuf<double> head, tail;     // 8 per straddler
     DevBuf<float4> mom;            // 2 per node
+    DevBuf<float> wbuf;            // per-node W, filled on request
 
     // build scratch
     DevBuf<unsigned long long> keys_a, keys_b;

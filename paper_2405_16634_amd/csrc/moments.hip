@@ -19,18 +19,22 @@ namespace wnnc {
 
 constexpr int kMomVals = 7;  // |nu|, |nu| x (3), nu (3)
 
-__device__ inline void write_moment(float4 *__restrict__ mom, int node, const double *s) {
+// Node record: x_B = X / W and nu_B in FP32 with the node's topology (skip
+// pointer and flags) so that the traversal needs one 32-byte load per node.
+__device__ inline void write_moment(const MomArgs &a, int node, const int4 t, const double *s) {
     const double W = s[0];
-    float4 p, v;
+    int flags = t.w & 31;  // depth | leaf << 4
+    if ((flags & kRecLeaf) && t.z - t.y == 1) flags |= kRecSingle;
+    float4 p;
     if (W > 0.0) {
         p = make_float4((float)(s[1] / W), (float)(s[2] / W), (float)(s[3] / W),
-                        fmaxf((float)W, FLT_MIN));
+                        __int_as_float(flags));
     } else {
-        p = make_float4(0.f, 0.f, 0.f, 0.f);
+        p = make_float4(0.f, 0.f, 0.f, __int_as_float(flags | kRecZero));
     }
-    v = make_float4((float)s[4], (float)s[5], (float)s[6], 0.f);
-    mom[2 * node] = p;
-    mom[2 * node + 1] = v;
+    a.mom[2 * node] = p;
+    a.mom[2 * node + 1] = make_float4((float)s[4], (float)s[5], (float)s[6], __int_as_float(t.x));
+    if (a.wout) a.wout[node] = W > 0.0 ? fmaxf((float)W, FLT_MIN) : 0.f;
 }
 
 template <int MODE>
@@ -123,7 +127,7 @@ __global__ __launch_bounds__(kChunk) void k_moments_chunk(MomArgs a) {
             const int e = t.z - c0 - 1;
 #pragma unroll
             for (int k = 0; k < kMomVals; ++k) s[k] = P[k][e] - (b > 0 ? P[k][b - 1] : 0.0);
-            write_moment(a.mom, nd, s);
+            write_moment(a, nd, t, s);
         } else {
             const int sl = a.node_strad[nd];
 #pragma unroll
@@ -165,7 +169,7 @@ __global__ __launch_bounds__(256) void k_moments_strad(MomArgs a) {
         double tot[kMomVals];
 #pragma unroll
         for (int k = 0; k < kMomVals; ++k) tot[k] = (a.head[8 * sl + k] + s[k]) + a.tail[8 * sl + k];
-        write_moment(a.mom, nd, tot);
+        write_moment(a, nd, t, tot);
     }
 }
 

@@ -48,7 +48,9 @@ template <int OP>
 __device__ inline void pair_term(float dx, float dy, float dz, float r2, float4 v, float w2,
                                  float &s, float &gx, float &gy, float &gz) {
     const bool keep = (r2 >= w2) && (r2 > 0.0f);
-    const float ri = rsqrtf(r2);
+    // hardware reciprocal square root (about 1 ulp); r2 below the smallest
+    // normal only occurs for pairs that the cutoff removes when w > 0
+    const float ri = __builtin_amdgcn_rsqf(r2);
     const float ri2 = ri * ri;
     const float ri3 = ri2 * ri;
     if (OP == OP_A) {
@@ -116,35 +118,35 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
         int node = 0;
         const int m = a.m;
         while (node < m) {
-            const int4 tp = ldc_i4(a.topo + node);
             const float4 P = ldc_f4(a.mom + 2 * node);
-            if (P.w == 0.0f) {  // every attribute in the node is zero
-                node = tp.x;
+            const float4 V = ldc_f4(a.mom + 2 * node + 1);
+            const int flags = __float_as_int(P.w);
+            const int skip = __float_as_int(V.w);
+            if (flags & kRecZero) {  // every attribute in the node is zero
+                node = skip;
                 continue;
             }
-            const float4 V = ldc_f4(a.mom + 2 * node + 1);
-            const int depth = tp.w & 15;
-            const bool leaf = (tp.w >> 4) & 1;
+            const int depth = flags & 15;
             const unsigned long long act =
                 (unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)mlo, depth) |
                 ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)mhi, depth) << 32);
             const bool me = (act >> lane) & 1ull;
             const float dx = tx - P.x, dy = ty - P.y, dz = tz - P.z;
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            const bool single = leaf && (tp.z - tp.y == 1);
-            const bool far = me && (single || r2 > a.thr2[depth]);
+            const bool far = me && ((flags & kRecSingle) || r2 > a.thr2[depth]);
             if (far) {
                 pair_term<OP>(dx, dy, dz, r2, V, a.w2, s, gx, gy, gz);
                 if (COUNT) ++cnt;
             }
             const unsigned long long open = __ballot(me && !far);
             if (open == 0ull) {
-                node = tp.x;
+                node = skip;
                 continue;
             }
-            if (leaf) {
+            if (flags & kRecLeaf) {
                 // several points in a depth-D cell: direct sum for the lanes
                 // that did not accept the representative
+                const int4 tp = ldc_i4(a.topo + node);
                 const bool mine = (open >> lane) & 1ull;
                 for (int j = tp.y; j < tp.z; ++j) {
                     const float4 Q = ldc_f4(a.pts + j);
@@ -160,7 +162,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
                         if (COUNT) ++cnt;
                     }
                 }
-                node = tp.x;
+                node = skip;
             } else {
                 if (lane == depth + 1) {
                     mlo = (uint32_t)open;
