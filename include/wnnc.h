@@ -102,6 +102,8 @@ typedef struct {
                                (WNNC_FLAG_TIME_KERNELS) */
     double moments_ms;      /* summed moment-pass time (WNNC_FLAG_TIME_KERNELS) */
     double build_ms;        /* last wnnc_build, device time (always timed) */
+    int64_t n_clouds;       /* clouds in the current tree (1 for wnnc_build) */
+    int64_t tile;           /* targets per traversal lane (wnnc_set_tile) */
 } wnnc_stats_t;
 
 /* Create a context on HIP device `device`, enqueuing on `stream`
@@ -127,11 +129,40 @@ wnnc_status wnnc_set_flags(wnnc_ctx ctx, unsigned flags);
 wnnc_status wnnc_normalize(wnnc_ctx ctx, const float *P, int64_t N, float *P_norm,
                            double *center_scale);
 
+/* Batched normalization: B clouds stored one after another in P (cloud c =
+ * rows offsets[c] .. offsets[c+1]-1; offsets is a host array of B+1
+ * increasing values starting at 0, every cloud non-empty, 1 <= B <= 2^18),
+ * each normalized on its own as in wnnc_normalize.  center_scale (host):
+ * 4 doubles per cloud, or NULL.  Synchronizes. */
+wnnc_status wnnc_normalize_batched(wnnc_ctx ctx, const float *P, const int64_t *offsets, int B,
+                                   float *P_norm, double *center_scale);
+
 /* Build the octree over normalized points P (N,3), 1 <= N < 2^31.  Points
  * outside [-1,1]^3 are clamped into the boundary cells.  Replaces any
  * previous tree.  opts NULL = paper defaults.  Synchronizes (reads back the
  * node count). */
 wnnc_status wnnc_build(wnnc_ctx ctx, const float *P, int64_t N, const wnnc_tree_opts *opts);
+
+/* Build one octree per cloud for B independent clouds (layout as in
+ * wnnc_normalize_batched, each already normalized), as a single forest: one
+ * sort orders the points cloud by cloud.  Every later call on the context
+ * (operators, wnnc_orient) treats the clouds independently -- a point only
+ * interacts with its own cloud -- while each operator is one launch over all
+ * clouds.  Synchronizes. */
+wnnc_status wnnc_build_batched(wnnc_ctx ctx, const float *P, const int64_t *offsets, int B,
+                               const wnnc_tree_opts *opts);
+
+/* Traversal tile shape: each wavefront serves tpl groups of 64 sorted
+ * targets (tpl in {1, 2, 4}; default 1).  Results do not depend on it.
+ * Synchronizes when a tree exists (rebuilds the task list). */
+wnnc_status wnnc_set_tile(wnnc_ctx ctx, int tpl);
+wnnc_status wnnc_get_tile(wnnc_ctx ctx, int *tpl);
+
+/* Autotuner: times one adjoint-operator traversal at width w for every tile
+ * shape on the current tree and keeps the fastest.  ms_out (host, 3
+ * doubles, may be NULL) receives the times for tpl = 1, 2, 4.
+ * Synchronizes. */
+wnnc_status wnnc_autotune(wnnc_ctx ctx, float w, double *ms_out);
 
 /* Winding number at the points: s_out[i] = F(x_i; mu), mu_j = n_j sigma_j.
  * n: (N,3); sigma: (N) or NULL (then n already holds mu); w >= 0. */
@@ -147,7 +178,8 @@ wnnc_status wnnc_gradient(wnnc_ctx ctx, const float *n, const float *sigma, floa
  * |s|-weighted representatives). */
 wnnc_status wnnc_adjoint(wnnc_ctx ctx, const float *s, float w, float *out);
 
-/* Alg. 3 on the built tree.  mu0: (N,3) initial mu, or NULL for mu = 0 (the
+/* Alg. 3 on the built tree (on every cloud of a batched tree at once, each
+ * with its own step length).  mu0: (N,3) initial mu, or NULL for mu = 0 (the
  * paper's initialization).  mu_out: (N,3) final mu (oriented surface
  * elements in the normalized frame; normals are mu_i/|mu_i|).  mu_out may
  * alias mu0.  opts NULL = paper defaults. */
@@ -164,8 +196,9 @@ wnnc_status wnnc_normals(wnnc_ctx ctx, const float *mu, int64_t N, double scale,
                          float *area_out);
 
 /* Energies E = ||A_w mu - b||^2 of the mu entering each iteration of the
- * last wnnc_orient (host, at least `count` doubles; entry k is iteration
- * start_iter + k; count <= the number of iterations run).  Synchronizes. */
+ * last wnnc_orient, per cloud (host, count * n_clouds doubles; entry
+ * k * n_clouds + c is iteration start_iter + k of cloud c; count <= the
+ * number of iterations run).  Synchronizes. */
 wnnc_status wnnc_orient_energy(wnnc_ctx ctx, double *host_out, int count);
 
 /* Statistics since the last reset (host struct).  Synchronizes. */

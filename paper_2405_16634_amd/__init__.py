@@ -30,6 +30,8 @@ EXPORTED = [
     "wnnc_build", "wnnc_winding", "wnnc_gradient", "wnnc_adjoint", "wnnc_orient",
     "wnnc_orient_energy", "wnnc_stats", "wnnc_reset_stats", "wnnc_tree_export",
     "wnnc_moments_export", "wnnc_normals", "wnnc_last_error", "wnnc_version",
+    "wnnc_normalize_batched", "wnnc_build_batched", "wnnc_set_tile", "wnnc_get_tile",
+    "wnnc_autotune",
 ]
 
 
@@ -52,12 +54,14 @@ class Stats(ctypes.Structure):
     _fields_ = [("n_points", ctypes.c_int64), ("n_nodes", ctypes.c_int64),
                 ("calls", ctypes.c_int64 * 3), ("pairs", ctypes.c_int64 * 3),
                 ("traverse_ms", ctypes.c_double * 3), ("moments_ms", ctypes.c_double),
-                ("build_ms", ctypes.c_double)]
+                ("build_ms", ctypes.c_double), ("n_clouds", ctypes.c_int64),
+                ("tile", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return dict(n_points=self.n_points, n_nodes=self.n_nodes, calls=list(self.calls),
                     pairs=list(self.pairs), traverse_ms=list(self.traverse_ms),
-                    moments_ms=self.moments_ms, build_ms=self.build_ms)
+                    moments_ms=self.moments_ms, build_ms=self.build_ms,
+                    n_clouds=self.n_clouds, tile=self.tile)
 
 
 _lib = None
@@ -90,6 +94,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "wnnc_tree_export": [vp, vp, vp, vp, vp, vp],
         "wnnc_moments_export": [vp, vp, ctypes.c_int, vp, vp, vp],
         "wnnc_normals": [vp, vp, i64, dbl, vp, vp],
+        "wnnc_normalize_batched": [vp, vp, P(i64), ctypes.c_int, vp, P(dbl)],
+        "wnnc_build_batched": [vp, vp, P(i64), ctypes.c_int, P(TreeOpts)],
+        "wnnc_set_tile": [vp, ctypes.c_int],
+        "wnnc_get_tile": [vp, P(ctypes.c_int)],
+        "wnnc_autotune": [vp, f32, P(dbl)],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -165,6 +174,48 @@ def wnnc_normalize(ctx, P, P_norm):
     return (cs[0], cs[1], cs[2]), cs[3]
 
 
+def _offsets(offsets):
+    arr = (ctypes.c_int64 * len(offsets))(*[int(v) for v in offsets])
+    return arr, len(offsets) - 1
+
+
+def wnnc_normalize_batched(ctx, P, P_norm, offsets):
+    """Normalize each cloud (rows offsets[c]..offsets[c+1]) on its own.
+    Returns a list of (centre, scale) per cloud."""
+    n = P.shape[0]
+    off, B = _offsets(offsets)
+    cs = (ctypes.c_double * (4 * B))()
+    _check(load_library().wnnc_normalize_batched(ctx, _dev(P, "P", shape=(n, 3)), off, B,
+                                                 _dev(P_norm, "P_norm", shape=(n, 3)), cs))
+    return [((cs[4 * k], cs[4 * k + 1], cs[4 * k + 2]), cs[4 * k + 3]) for k in range(B)]
+
+
+def wnnc_build_batched(ctx, P, offsets, c: float = 2.0, max_depth: int = 15) -> None:
+    n = P.shape[0]
+    off, B = _offsets(offsets)
+    opts = TreeOpts(float(c), int(max_depth))
+    _check(load_library().wnnc_build_batched(ctx, _dev(P, "P", shape=(n, 3)), off, B,
+                                             ctypes.byref(opts)))
+
+
+def wnnc_set_tile(ctx, tpl: int) -> None:
+    _check(load_library().wnnc_set_tile(ctx, int(tpl)))
+
+
+def wnnc_get_tile(ctx) -> int:
+    v = ctypes.c_int()
+    _check(load_library().wnnc_get_tile(ctx, ctypes.byref(v)))
+    return v.value
+
+
+def wnnc_autotune(ctx, w: float = 0.002):
+    """Time every tile shape on the current tree and keep the fastest.
+    Returns {tpl: ms}."""
+    ms = (ctypes.c_double * 3)()
+    _check(load_library().wnnc_autotune(ctx, float(w), ms))
+    return {1: ms[0], 2: ms[1], 4: ms[2]}
+
+
 def wnnc_build(ctx, P, c: float = 2.0, max_depth: int = 15) -> None:
     n = P.shape[0]
     opts = TreeOpts(float(c), int(max_depth))
@@ -206,10 +257,14 @@ def wnnc_normals(ctx, mu, scale: float, n_out, area_out=None) -> None:
                                        _dev(area_out, "area_out", shape=(N,))))
 
 
-def wnnc_orient_energy(ctx, count: int):
-    buf = (ctypes.c_double * max(count, 1))()
+def wnnc_orient_energy(ctx, count: int, nclouds: int = 1):
+    """Energies of the last orientation run: a list of `count` values for one
+    cloud, or `count` lists of `nclouds` values."""
+    buf = (ctypes.c_double * max(count * nclouds, 1))()
     _check(load_library().wnnc_orient_energy(ctx, buf, int(count)))
-    return [buf[i] for i in range(count)]
+    if nclouds == 1:
+        return [buf[i] for i in range(count)]
+    return [[buf[i * nclouds + c] for c in range(nclouds)] for i in range(count)]
 
 
 def wnnc_stats(ctx) -> dict:
@@ -298,6 +353,26 @@ class Context:
     def build(self, P_norm, c: float = 2.0, max_depth: int = 15) -> None:
         wnnc_build(self._h, P_norm, c, max_depth)
         self.n = int(P_norm.shape[0])
+        self.nclouds = 1
+
+    def normalize_batched(self, P, offsets):
+        out = torch.empty_like(P)
+        cs = wnnc_normalize_batched(self._h, P, out, offsets)
+        return out, [Normalization(c, s) for c, s in cs]
+
+    def build_batched(self, P_norm, offsets, c: float = 2.0, max_depth: int = 15) -> None:
+        wnnc_build_batched(self._h, P_norm, offsets, c, max_depth)
+        self.n = int(P_norm.shape[0])
+        self.nclouds = len(offsets) - 1
+
+    def set_tile(self, tpl: int) -> None:
+        wnnc_set_tile(self._h, tpl)
+
+    def tile(self) -> int:
+        return wnnc_get_tile(self._h)
+
+    def autotune(self, w: float = 0.002):
+        return wnnc_autotune(self._h, w)
 
     def winding(self, mu, w: float, sigma=None):
         out = torch.empty(mu.shape[0], device=mu.device, dtype=torch.float32)
@@ -328,7 +403,7 @@ class Context:
         return (nrm, area) if with_area else nrm
 
     def energy(self, count: int):
-        return wnnc_orient_energy(self._h, count)
+        return wnnc_orient_energy(self._h, count, getattr(self, "nclouds", 1))
 
     def stats(self) -> dict:
         return wnnc_stats(self._h)

@@ -64,6 +64,7 @@ struct Timed {
 };
 
 MomArgs mom_args(wnnc_ctx_s *c) {
+    // (fields not set here are per-call inputs and outputs)
     MomArgs a;
     memset(&a, 0, sizeof(a));
     a.pts = c->pts.p;
@@ -78,6 +79,8 @@ MomArgs mom_args(wnnc_ctx_s *c) {
     a.head = c->head.p;
     a.tail = c->tail.p;
     a.mom = c->mom.p;
+    a.cloud = c->cloud_of.p;
+    a.alpha = c->scalars.p;
     a.n = (int)c->n;
     a.n_strad = c->n_strad;
     return a;
@@ -91,9 +94,12 @@ TravArgs trav_args(wnnc_ctx_s *c, float w) {
     a.mom = c->mom.p;
     a.perm = c->perm.p;
     a.pairs = c->pair_ctr.p;
+    a.tasks = c->tasks.p;
+    a.task_slot = c->task_slot.p;
+    a.ntasks = c->ntasks;
+    a.tpl = c->tpl;
     a.n = (int)c->n;
     a.m = (int)c->m;
-    a.nblocks = trav_blocks(c->n);
     a.w2 = (float)((double)w * (double)w);
     for (int d = 0; d < 16; ++d) {
         const double t = (double)c->c * ldexp(2.0, -d);
@@ -193,6 +199,13 @@ wnnc_status wnnc_destroy(wnnc_ctx ctx) {
     ctx->energy.release();
     ctx->pair_ctr.release();
     ctx->wbuf.release();
+    ctx->d_offsets.release();
+    ctx->d_roots.release();
+    ctx->norm_off.release();
+    ctx->cloud_of.release();
+    ctx->tasks.release();
+    ctx->task_slot.release();
+    ctx->task_lo.release();
     for (auto &t : ctx->pending) {
         (void)hipEventDestroy(t.a);
         (void)hipEventDestroy(t.b);
@@ -216,25 +229,55 @@ wnnc_status wnnc_set_flags(wnnc_ctx ctx, unsigned flags) {
     return WNNC_OK;
 }
 
-wnnc_status wnnc_normalize(wnnc_ctx ctx, const float *P, int64_t N, float *P_norm,
-                           double *center_scale) {
-    CHECK_CTX(ctx);
-    if (!P || !P_norm) return fail(WNNC_EINVAL, "null point pointer");
-    if (N < 1 || N > INT32_MAX) return fail(WNNC_EINVAL, "N = %lld out of range", (long long)N);
-    HIPCHK(ctx->norm_tmp.ensure(normalize_tmp_doubles(N)));
-    HIPCHK(launch_normalize(P, N, P_norm, ctx->norm_tmp.p, ctx->stream));
-    double cs[4];
-    HIPCHK(hipMemcpyAsync(cs, ctx->norm_tmp.p + normalize_tmp_doubles(N) - 8, 4 * sizeof(double),
-                          hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
-    if (center_scale) memcpy(center_scale, cs, sizeof(cs));
+static wnnc_status check_offsets(const int64_t *offsets, int B, int64_t *N) {
+    if (!offsets) return fail(WNNC_EINVAL, "null offsets");
+    if (B < 1 || B > (1 << 18)) return fail(WNNC_EINVAL, "cloud count %d out of range 1..2^18", B);
+    if (offsets[0] != 0) return fail(WNNC_EINVAL, "offsets[0] must be 0");
+    for (int c = 0; c < B; ++c)
+        if (offsets[c + 1] <= offsets[c]) return fail(WNNC_EINVAL, "cloud %d is empty", c);
+    *N = offsets[B];
+    if (*N > INT32_MAX - 1) return fail(WNNC_EINVAL, "N = %lld out of range", (long long)*N);
     return WNNC_OK;
 }
 
-wnnc_status wnnc_build(wnnc_ctx ctx, const float *P, int64_t N, const wnnc_tree_opts *opts) {
+static wnnc_status normalize_impl(wnnc_ctx ctx, const float *P, const int64_t *offsets, int B,
+                                  float *P_norm, double *center_scale) {
+    int64_t N = 0;
+    RETURN_IF(check_offsets(offsets, B, &N));
+    if (!P || !P_norm) return fail(WNNC_EINVAL, "null point pointer");
+    HIPCHK(ctx->norm_tmp.ensure(normalize_tmp_doubles(B)));
+    HIPCHK(ctx->norm_off.ensure(B + 1));
+    HIPCHK(hipMemcpyAsync(ctx->norm_off.p, offsets, (size_t)(B + 1) * sizeof(int64_t),
+                          hipMemcpyHostToDevice, ctx->stream));
+    const int64_t at = launch_normalize(P, N, ctx->norm_off.p, B, P_norm, ctx->norm_tmp.p, ctx->stream);
+    HIPCHK(hipGetLastError());
+    std::vector<double> cs((size_t)4 * B);
+    HIPCHK(hipMemcpyAsync(cs.data(), ctx->norm_tmp.p + at, cs.size() * sizeof(double),
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (center_scale) memcpy(center_scale, cs.data(), cs.size() * sizeof(double));
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_normalize(wnnc_ctx ctx, const float *P, int64_t N, float *P_norm,
+                           double *center_scale) {
     CHECK_CTX(ctx);
-    if (!P) return fail(WNNC_EINVAL, "null point pointer");
     if (N < 1 || N > INT32_MAX - 1) return fail(WNNC_EINVAL, "N = %lld out of range", (long long)N);
+    const int64_t off[2] = {0, N};
+    return normalize_impl(ctx, P, off, 1, P_norm, center_scale);
+}
+
+wnnc_status wnnc_normalize_batched(wnnc_ctx ctx, const float *P, const int64_t *offsets, int B,
+                                   float *P_norm, double *center_scale) {
+    CHECK_CTX(ctx);
+    return normalize_impl(ctx, P, offsets, B, P_norm, center_scale);
+}
+
+static wnnc_status build_impl(wnnc_ctx ctx, const float *P, const int64_t *offsets, int B,
+                              const wnnc_tree_opts *opts) {
+    int64_t N = 0;
+    RETURN_IF(check_offsets(offsets, B, &N));
+    if (!P) return fail(WNNC_EINVAL, "null point pointer");
     wnnc_tree_opts o = {2.0f, 15};
     if (opts) o = *opts;
     if (!(isfinite(o.c) && o.c > 0.0f)) return fail(WNNC_EINVAL, "c must be finite and > 0");
@@ -244,11 +287,17 @@ wnnc_status wnnc_build(wnnc_ctx ctx, const float *P, int64_t N, const wnnc_tree_
     ctx->n = N;
     ctx->c = o.c;
     ctx->depth = o.max_depth;
+    ctx->nclouds = B;
+    ctx->offsets.assign(offsets, offsets + B + 1);
+    HIPCHK(ctx->d_offsets.ensure(B + 1));
+    HIPCHK(hipMemcpyAsync(ctx->d_offsets.p, ctx->offsets.data(), (size_t)(B + 1) * sizeof(int64_t),
+                          hipMemcpyHostToDevice, ctx->stream));
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, ctx->stream));
     hipError_t e = build_tree(ctx, P);
+    if (e == hipSuccess) e = make_tasks(ctx, ctx->tpl);
     if (e != hipSuccess) {
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -263,6 +312,84 @@ wnnc_status wnnc_build(wnnc_ctx ctx, const float *P, int64_t N, const wnnc_tree_
     (void)hipEventDestroy(e1);
     ctx->build_ms = ms;
     ctx->built = true;
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_build(wnnc_ctx ctx, const float *P, int64_t N, const wnnc_tree_opts *opts) {
+    CHECK_CTX(ctx);
+    if (N < 1 || N > INT32_MAX - 1) return fail(WNNC_EINVAL, "N = %lld out of range", (long long)N);
+    const int64_t off[2] = {0, N};
+    return build_impl(ctx, P, off, 1, opts);
+}
+
+wnnc_status wnnc_build_batched(wnnc_ctx ctx, const float *P, const int64_t *offsets, int B,
+                               const wnnc_tree_opts *opts) {
+    CHECK_CTX(ctx);
+    return build_impl(ctx, P, offsets, B, opts);
+}
+
+wnnc_status wnnc_set_tile(wnnc_ctx ctx, int tpl) {
+    CHECK_CTX(ctx);
+    if (tpl != 1 && tpl != 2 && tpl != 4) return fail(WNNC_EINVAL, "tile must be 1, 2 or 4");
+    if (ctx->built) {
+        hipError_t e = make_tasks(ctx, tpl);
+        if (e != hipSuccess) return fail(WNNC_EDEVICE, "tasks: %s", hipGetErrorString(e));
+    } else {
+        ctx->tpl = tpl;
+    }
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_get_tile(wnnc_ctx ctx, int *tpl) {
+    CHECK_CTX(ctx);
+    if (!tpl) return fail(WNNC_EINVAL, "null output");
+    *tpl = ctx->tpl;
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_autotune(wnnc_ctx ctx, float w, double *ms_out) {
+    CHECK_CTX(ctx);
+    CHECK_BUILT(ctx);
+    if (!finite_nonneg(w)) return fail(WNNC_EINVAL, "w must be finite and >= 0");
+    // attribute: mu = 1/2 per point along a fixed direction would cancel in
+    // G; use the constant scalar 1/2 through A^T, whose traversal visits the
+    // same nodes as a smooth mu would (all weights positive)
+    MomArgs ma = mom_args(ctx);
+    ma.outs = ctx->rho.p;
+    RETURN_IF(run_moments(ctx, MOM_CONST_HALF, ma));
+    const int cand[3] = {1, 2, 4};
+    double best_ms = 1e300;
+    int best = ctx->tpl;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    for (int k = 0; k < 3; ++k) {
+        hipError_t e = make_tasks(ctx, cand[k]);
+        if (e != hipSuccess) return fail(WNNC_EDEVICE, "tasks: %s", hipGetErrorString(e));
+        TravArgs ta = trav_args(ctx, w);
+        ta.srcs = ctx->rho.p;
+        ta.out4 = ctx->vr.p;
+        ta.partial = ctx->partial.p + ctx->ntasks;
+        double t = 0.0;
+        for (int rep = 0; rep < 2; ++rep) {  // first launch warms the caches
+            HIPCHK(hipEventRecord(e0, ctx->stream));
+            HIPCHK(launch_traverse(ctx, OP_AT, TR_R, false, ta));
+            HIPCHK(hipEventRecord(e1, ctx->stream));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            t = ms;
+        }
+        if (ms_out) ms_out[k] = t;
+        if (t < best_ms) {
+            best_ms = t;
+            best = cand[k];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    hipError_t e = make_tasks(ctx, best);
+    if (e != hipSuccess) return fail(WNNC_EDEVICE, "tasks: %s", hipGetErrorString(e));
     return WNNC_OK;
 }
 
@@ -330,10 +457,10 @@ wnnc_status wnnc_orient(wnnc_ctx ctx, const wnnc_orient_opts *opts, const float 
     if (!finite_nonneg(o.w1) || !finite_nonneg(o.w2))
         return fail(WNNC_EINVAL, "widths must be finite and >= 0");
     const int64_t N = ctx->n;
-    const int nb = trav_blocks(N);
+    const int nt = ctx->ntasks;
     hipStream_t st = ctx->stream;
     const int count = stop - o.start_iter + 1;
-    HIPCHK(ctx->energy.ensure(count));
+    HIPCHK(ctx->energy.ensure((int64_t)count * ctx->nclouds));
 
     float4 *mu = ctx->va.p, *tmp = ctx->vb.p, *r = ctx->vr.p;
     float *rho = ctx->rho.p;
@@ -348,15 +475,14 @@ wnnc_status wnnc_orient(wnnc_ctx ctx, const wnnc_orient_opts *opts, const float 
         const double w = n <= 1 ? (double)o.w1
                                 : (double)o.w2 * (n - i) / (n - 1) + (double)o.w1 * (i - 1) / (n - 1);
         const float wf = (float)w;
-        double *eslot = ctx->energy.p + (i - o.start_iter);
+        double *erow = ctx->energy.p + (int64_t)(i - o.start_iter) * ctx->nclouds;
         // gradient step (Alg. 2): rho = b - A mu, r = A^T rho, t = A r
-        double e_const = -1.0;
-        if (zero && i == o.start_iter) {
+        const bool first = zero && i == o.start_iter;
+        if (first) {
             // mu = 0: A mu = 0 exactly, so rho = 1/2 everywhere
             MomArgs ma = mom_args(ctx);
             ma.outs = rho;
             RETURN_IF(run_moments(ctx, MOM_CONST_HALF, ma));
-            e_const = 0.25 * (double)N;
         } else {
             MomArgs ma = mom_args(ctx);
             ma.src4 = mu;
@@ -374,7 +500,7 @@ wnnc_status wnnc_orient(wnnc_ctx ctx, const wnnc_orient_opts *opts, const float 
             TravArgs ta = trav_args(ctx, wf);
             ta.srcs = rho;
             ta.out4 = r;
-            ta.partial = ctx->partial.p + nb;
+            ta.partial = ctx->partial.p + nt;
             RETURN_IF(run_traverse(ctx, OP_AT, TR_R, ta));
         }
         {
@@ -383,16 +509,15 @@ wnnc_status wnnc_orient(wnnc_ctx ctx, const wnnc_orient_opts *opts, const float 
             RETURN_IF(run_moments(ctx, MOM_VEC_SORTED, ma));
             TravArgs ta = trav_args(ctx, wf);
             ta.src4 = r;
-            ta.partial = ctx->partial.p + 2 * nb;
+            ta.partial = ctx->partial.p + 2 * nt;
             RETURN_IF(run_traverse(ctx, OP_A, TR_TSUM, ta));
         }
-        HIPCHK(launch_alpha(ctx, nb, e_const, eslot));
+        HIPCHK(launch_alpha(ctx, first, erow));
         // mu <- mu + alpha r, then the WNNC update and rescale
         {
             MomArgs ma = mom_args(ctx);
             ma.src4 = mu;
             ma.r4 = r;
-            ma.alpha = ctx->scalars.p;
             ma.out4 = tmp;
             RETURN_IF(run_moments(ctx, MOM_AXPY, ma));
             TravArgs ta = trav_args(ctx, wf);
@@ -422,7 +547,7 @@ wnnc_status wnnc_orient_energy(wnnc_ctx ctx, double *host_out, int count) {
     if (count > ctx->last_energy_count)
         return fail(WNNC_EINVAL, "only %d energies recorded", ctx->last_energy_count);
     if (count == 0) return WNNC_OK;
-    HIPCHK(hipMemcpyAsync(host_out, ctx->energy.p, (size_t)count * sizeof(double),
+    HIPCHK(hipMemcpyAsync(host_out, ctx->energy.p, (size_t)count * ctx->nclouds * sizeof(double),
                           hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return WNNC_OK;
@@ -457,6 +582,8 @@ wnnc_status wnnc_stats(wnnc_ctx ctx, wnnc_stats_t *out) {
     }
     out->moments_ms = ctx->mom_ms;
     out->build_ms = ctx->build_ms;
+    out->n_clouds = ctx->built ? ctx->nclouds : 0;
+    out->tile = ctx->tpl;
     return WNNC_OK;
 }
 

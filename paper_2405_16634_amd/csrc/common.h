@@ -44,6 +44,10 @@ enum MomMode {
     MOM_CONST_HALF = 5,    // nu = 1/2 (scalar); writes outs[i]
 };
 
+// Key layout: the cloud index sits above the 45 Morton bits, so one sort
+// groups the points cloud by cloud and each cloud gets its own root.
+constexpr int kMortonBits = 45;
+
 // Traversal epilogues.
 enum TravMode {
     TR_OUT_CALLER = 0,  // write the operator value to caller order (API calls)
@@ -65,7 +69,8 @@ struct MomArgs {
     const float4 *src4;      // sorted vector input
     const float *srcs;       // sorted scalar input
     const float4 *r4;        // axpy direction
-    const double *alpha;     // axpy step (device scalar)
+    const double *alpha;     // axpy step per cloud (device)
+    const int32_t *cloud;    // cloud index per sorted point (batched axpy)
     const float *cn;         // caller-order (N,3) input
     const float *csig;       // caller-order sigma (may be null)
     const float *cs;         // caller-order scalar input
@@ -90,10 +95,13 @@ struct TravArgs {
     float *out;              // TR_OUT_CALLER: caller-order output
     float *rho;              // TR_RHO output
     float4 *out4;            // TR_R / TR_RESCALE output
-    double *partial;         // per-block partial sums
+    double *partial;         // per-task partial sums (indexed by task_slot)
     unsigned long long *pairs;  // pair counter (counting variant)
+    const int4 *tasks;       // per wavefront: first, last target; root, end node
+    const int32_t *task_slot;
+    int ntasks;
+    int tpl;                 // target groups of 64 per wavefront (1, 2, 4)
     int n, m;
-    int nblocks;
     float w2;
     float thr2[16];          // (c * 2^(1-d))^2 per depth d
 };
@@ -163,12 +171,27 @@ struct wnnc_ctx_s {
     DevBuf<uint32_t> u32_tmp;      // n+1
     DevBuf<uint32_t> mflag, mslot; // m+1
     DevBuf<double> norm_tmp;
+    DevBuf<int64_t> norm_off;
+
+    // clouds (a single build is one cloud)
+    int nclouds = 1;
+    std::vector<int64_t> offsets;  // host, nclouds + 1 (caller = sorted ranges)
+    std::vector<int32_t> roots;    // host, nclouds + 1: first node of each cloud
+    DevBuf<int64_t> d_offsets;     // nclouds + 1
+    DevBuf<int32_t> d_roots;       // nclouds + 1
+    DevBuf<int32_t> cloud_of;      // n: cloud of each sorted point
+    // wavefront tasks for the current tile shape
+    int tpl = 1;
+    int ntasks = 0;
+    DevBuf<int4> tasks;
+    DevBuf<int32_t> task_slot;
+    DevBuf<int32_t> task_lo;       // nclouds + 1: task range of each cloud
 
     // iteration buffers (sorted order)
     DevBuf<float4> va, vb, vr;
     DevBuf<float> rho;
     DevBuf<double> partial;        // 3 * traversal blocks
-    DevBuf<double> scalars;        // [0] alpha
+    DevBuf<double> scalars;        // alpha per cloud
     DevBuf<double> energy;
     int last_energy_count = 0;
     DevBuf<unsigned long long> pair_ctr;  // 3 counters

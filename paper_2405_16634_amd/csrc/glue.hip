@@ -5,18 +5,23 @@
 
 namespace wnnc {
 
-// alpha = |r|^2 / |A r|^2 (Alg. 2), 0 when the denominator is 0.  The
-// per-block partial sums are reduced in a fixed order.  Also stores the
-// energy E = |rho|^2 of the iteration (or e_const when >= 0).
-__global__ __launch_bounds__(256) void k_alpha(const double *__restrict__ partial, int nb,
-                                               double e_const, double *__restrict__ scalars,
-                                               double *__restrict__ energy_slot) {
+// alpha = |r|^2 / |A r|^2 (Alg. 2) for each cloud (one workgroup per
+// cloud), 0 when the denominator is 0.  The cloud's per-task partial sums
+// are reduced in a fixed order.  Also stores the energy E = |rho|^2 of the
+// iteration (N_c / 4 for the iteration started from mu = 0).
+__global__ __launch_bounds__(256) void k_alpha(const double *__restrict__ partial, int ntasks,
+                                               const int32_t *__restrict__ task_lo,
+                                               const int64_t *__restrict__ off, int first,
+                                               double *__restrict__ alpha,
+                                               double *__restrict__ energy_row) {
     __shared__ double sh[3][256];
+    const int c = blockIdx.x;
+    const int lo = task_lo[c], hi = task_lo[c + 1];
     double acc[3] = {0.0, 0.0, 0.0};
-    for (int i = threadIdx.x; i < nb; i += 256) {
-        if (e_const < 0.0) acc[0] += partial[i];
-        acc[1] += partial[nb + i];
-        acc[2] += partial[2 * nb + i];
+    for (int i = lo + threadIdx.x; i < hi; i += 256) {
+        if (!first) acc[0] += partial[i];
+        acc[1] += partial[ntasks + i];
+        acc[2] += partial[2 * ntasks + i];
     }
     for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] = acc[k];
     __syncthreads();
@@ -27,14 +32,15 @@ __global__ __launch_bounds__(256) void k_alpha(const double *__restrict__ partia
     }
     if (threadIdx.x == 0) {
         const double r2 = sh[1][0], t2 = sh[2][0];
-        scalars[0] = t2 > 0.0 ? r2 / t2 : 0.0;
-        if (energy_slot) energy_slot[0] = e_const >= 0.0 ? e_const : sh[0][0];
+        alpha[c] = t2 > 0.0 ? r2 / t2 : 0.0;
+        if (energy_row) energy_row[c] = first ? 0.25 * (double)(off[c + 1] - off[c]) : sh[0][0];
     }
 }
 
-hipError_t launch_alpha(wnnc_ctx_s *ctx, int nb, double e_const, double *energy_slot) {
-    hipLaunchKernelGGL(k_alpha, dim3(1), dim3(256), 0, ctx->stream, ctx->partial.p, nb, e_const,
-                       ctx->scalars.p, energy_slot);
+hipError_t launch_alpha(wnnc_ctx_s *ctx, bool first, double *energy_row) {
+    hipLaunchKernelGGL(k_alpha, dim3(ctx->nclouds), dim3(256), 0, ctx->stream, ctx->partial.p,
+                       ctx->ntasks, ctx->task_lo.p, ctx->d_offsets.p, first ? 1 : 0,
+                       ctx->scalars.p, energy_row);
     return hipGetLastError();
 }
 

@@ -10,20 +10,27 @@ hipError_t exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint
                               hipStream_t st);
 
 // Tree build steps (tree.hip).
-hipError_t launch_normalize(const float *P, int64_t n, float *P_norm, double *dev_tmp,
-                            hipStream_t st);
-int64_t normalize_tmp_doubles(int64_t n);
+// Normalizes each cloud (rows d_off[c]..d_off[c+1]) of P into P_norm; tmp
+// holds normalize_tmp_doubles(nclouds) doubles.  Returns the offset in tmp
+// of the per-cloud (centre x, y, z, scale) quadruples.
+int64_t launch_normalize(const float *P, int64_t n, const int64_t *d_off, int nclouds,
+                         float *P_norm, double *tmp, hipStream_t st);
+int64_t normalize_tmp_doubles(int64_t nclouds);
 hipError_t build_tree(wnnc_ctx_s *ctx, const float *P);
+hipError_t make_tasks(wnnc_ctx_s *ctx, int tpl);
 
 // Moment pass (moments.hip): two launches, chunk pass then straddler pass.
 hipError_t launch_moments(wnnc_ctx_s *ctx, MomMode mode, const MomArgs &a);
 
 // Traversal (traverse.hip).
 hipError_t launch_traverse(wnnc_ctx_s *ctx, Op op, TravMode mode, bool count, const TravArgs &a);
-int trav_blocks(int64_t n);
+int trav_blocks(int64_t ntasks);
 
 // Glue (glue.hip).
-hipError_t launch_alpha(wnnc_ctx_s *ctx, int nblocks, double e_const, double *energy_slot);
+// Step length per cloud from the per-task partial sums; first = the
+// iteration started from mu = 0 (its energy is N_c / 4).  energy_row holds
+// one entry per cloud.
+hipError_t launch_alpha(wnnc_ctx_s *ctx, bool first, double *energy_row);
 hipError_t launch_zero_f4(float4 *p, int64_t n, hipStream_t st);
 hipError_t launch_gather_vec(const float *src, const uint32_t *perm, float4 *dst, int64_t n,
                              hipStream_t st);

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kChunk) void k_moments_chunk(MomArgs a) {
             a.outs[i] = nu0;
             scalar = true;
         } else if (MODE == MOM_AXPY) {
-            const float al = (float)a.alpha[0];
+            const float al = (float)a.alpha[a.cloud[i]];
             const float4 q = a.src4[i], r = a.r4[i];
             nu0 = fmaf(al, r.x, q.x), nu1 = fmaf(al, r.y, q.y), nu2 = fmaf(al, r.z, q.z);
             a.out4[i] = make_float4(nu0, nu1, nu2, 0.f);

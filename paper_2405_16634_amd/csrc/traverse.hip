@@ -1,7 +1,8 @@
 // Treecode traversal (Sec. 3.5, Alg. 4) for the three operators.
 //
-// One lane per target; a wavefront holds 64 Morton-consecutive targets and
-// walks the pre-order node array once.  Every lane keeps its own Alg. 4
+// A wavefront takes one task: 64 * TPL Morton-consecutive targets of one
+// cloud (TPL groups of 64, one target per lane in each group), and walks the
+// pre-order node range of that cloud once.  Every lane keeps its own Alg. 4
 // decisions: at node B, a lane that is still "inside" (has not replaced an
 // ancestor of B by its representative) tests |x - x_B| > c * width(B) and,
 // if so, adds the representative term; lanes that fail the test need B's
@@ -77,198 +78,206 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-// Block sum of one double per thread in a fixed order; valid in thread 0.
-__device__ inline double block_sum(double v) {
-    __shared__ double ws[kTravBlock / kWave];
-    __syncthreads();  // a previous call may still be reading ws
-    v = wave_sum(v);
-    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-    if (lane == 0) ws[wv] = v;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x == 0)
-        for (int k = 0; k < kTravBlock / kWave; ++k) t += ws[k];
-    return t;
+__device__ inline unsigned long long read_mask(uint32_t lo, uint32_t hi, int depth) {
+    return (unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)lo, depth) |
+           ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)hi, depth) << 32);
 }
 
-template <int OP, int MODE, bool COUNT>
+// One wavefront per task: TPL groups of 64 consecutive sorted targets
+// (group k holds targets first + 64k + lane) walk the node range
+// [root, end) of their cloud together.  Each group keeps its own mask stack
+// and Alg. 4 decisions; the groups share the node loads and the control.
+template <int OP, int MODE, bool COUNT, int TPL>
 __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
     // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
-    // contiguous range of Morton-ordered targets so its L2 sees one region.
+    // contiguous range of tasks (Morton-ordered targets) so its L2 sees one
+    // region of the tree.
     const int G = gridDim.x, b = blockIdx.x;
     const int q = G >> 3, r = G & 7, x = b & 7;
     const int lb = x * q + (x < r ? x : r) + (b >> 3);
-    const int t = (lb * (kTravBlock / kWave) + wv) * kWave + lane;
-    const bool valid = t < a.n;
+    const int wave = lb * (kTravBlock / kWave) + wv;
+    if (wave >= a.ntasks) return;
+    const int4 task = a.tasks[wave];
+    const int first = task.x, last = task.y, root = task.z, rend = task.w;
 
-    float tx = 0.f, ty = 0.f, tz = 0.f;
-    if (valid) {
-        const float4 p = a.pts[t];
-        tx = p.x, ty = p.y, tz = p.z;
-    }
-    float s = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+    float tx[TPL], ty[TPL], tz[TPL];
+    float s[TPL], gx[TPL], gy[TPL], gz[TPL];
+    bool valid[TPL];
+    uint32_t mlo[TPL], mhi[TPL];
     uint32_t cnt = 0;
-    const unsigned long long act0 = __ballot(valid);
-    if (act0 != 0ull) {
-        // mask stack: lane d holds the mask of lanes inside at depth d
-        uint32_t mlo = lane == 0 ? (uint32_t)act0 : 0u;
-        uint32_t mhi = lane == 0 ? (uint32_t)(act0 >> 32) : 0u;
-        int node = 0;
-        const int m = a.m;
-        while (node < m) {
-            const float4 P = ldc_f4(a.mom + 2 * node);
-            const float4 V = ldc_f4(a.mom + 2 * node + 1);
-            const int flags = __float_as_int(P.w);
-            const int skip = __float_as_int(V.w);
-            if (flags & kRecZero) {  // every attribute in the node is zero
-                node = skip;
-                continue;
-            }
-            const int depth = flags & 15;
-            const unsigned long long act =
-                (unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)mlo, depth) |
-                ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)mhi, depth) << 32);
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+        const int t = first + k * kWave + lane;
+        valid[k] = t < last;
+        tx[k] = ty[k] = tz[k] = 0.f;
+        if (valid[k]) {
+            const float4 p = a.pts[t];
+            tx[k] = p.x, ty[k] = p.y, tz[k] = p.z;
+        }
+        s[k] = gx[k] = gy[k] = gz[k] = 0.f;
+        // mask stack: lane d holds the mask of group-k lanes inside at depth d
+        const unsigned long long act0 = __ballot(valid[k]);
+        mlo[k] = lane == 0 ? (uint32_t)act0 : 0u;
+        mhi[k] = lane == 0 ? (uint32_t)(act0 >> 32) : 0u;
+    }
+    int node = root;
+    while (node < rend) {
+        const float4 P = ldc_f4(a.mom + 2 * node);
+        const float4 V = ldc_f4(a.mom + 2 * node + 1);
+        const int flags = __float_as_int(P.w);
+        const int skip = __float_as_int(V.w);
+        if (flags & kRecZero) {  // every attribute in the node is zero
+            node = skip;
+            continue;
+        }
+        const int depth = flags & 15;
+        const bool single = flags & kRecSingle;
+        const float thr2 = a.thr2[depth];
+        unsigned long long open[TPL];
+        unsigned long long any = 0ull;
+#pragma unroll
+        for (int k = 0; k < TPL; ++k) {
+            const unsigned long long act = read_mask(mlo[k], mhi[k], depth);
             const bool me = (act >> lane) & 1ull;
-            const float dx = tx - P.x, dy = ty - P.y, dz = tz - P.z;
+            const float dx = tx[k] - P.x, dy = ty[k] - P.y, dz = tz[k] - P.z;
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            const bool far = me && ((flags & kRecSingle) || r2 > a.thr2[depth]);
+            const bool far = me && (single || r2 > thr2);
             if (far) {
-                pair_term<OP>(dx, dy, dz, r2, V, a.w2, s, gx, gy, gz);
+                pair_term<OP>(dx, dy, dz, r2, V, a.w2, s[k], gx[k], gy[k], gz[k]);
                 if (COUNT) ++cnt;
             }
-            const unsigned long long open = __ballot(me && !far);
-            if (open == 0ull) {
-                node = skip;
-                continue;
-            }
-            if (flags & kRecLeaf) {
-                // several points in a depth-D cell: direct sum for the lanes
-                // that did not accept the representative
-                const int4 tp = ldc_i4(a.topo + node);
-                const bool mine = (open >> lane) & 1ull;
-                for (int j = tp.y; j < tp.z; ++j) {
-                    const float4 Q = ldc_f4(a.pts + j);
-                    float4 S;
-                    if (OP == OP_AT)
-                        S = make_float4(ldc_f(a.srcs + j), 0.f, 0.f, 0.f);
-                    else
-                        S = ldc_f4(a.src4 + j);
-                    if (mine) {
-                        const float ex = tx - Q.x, ey = ty - Q.y, ez = tz - Q.z;
+            open[k] = __ballot(me && !far);
+            any |= open[k];
+        }
+        if (any == 0ull) {
+            node = skip;
+            continue;
+        }
+        if (flags & kRecLeaf) {
+            // several points in a depth-D cell: direct sum for the lanes
+            // that did not accept the representative
+            const int4 tp = ldc_i4(a.topo + node);
+            for (int j = tp.y; j < tp.z; ++j) {
+                const float4 Q = ldc_f4(a.pts + j);
+                float4 S;
+                if (OP == OP_AT)
+                    S = make_float4(ldc_f(a.srcs + j), 0.f, 0.f, 0.f);
+                else
+                    S = ldc_f4(a.src4 + j);
+#pragma unroll
+                for (int k = 0; k < TPL; ++k) {
+                    if ((open[k] >> lane) & 1ull) {
+                        const float ex = tx[k] - Q.x, ey = ty[k] - Q.y, ez = tz[k] - Q.z;
                         const float e2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
-                        pair_term<OP>(ex, ey, ez, e2, S, a.w2, s, gx, gy, gz);
+                        pair_term<OP>(ex, ey, ez, e2, S, a.w2, s[k], gx[k], gy[k], gz[k]);
                         if (COUNT) ++cnt;
                     }
                 }
-                node = skip;
-            } else {
-                if (lane == depth + 1) {
-                    mlo = (uint32_t)open;
-                    mhi = (uint32_t)(open >> 32);
-                }
-                node = node + 1;
             }
+            node = skip;
+        } else {
+#pragma unroll
+            for (int k = 0; k < TPL; ++k) {
+                if (lane == depth + 1) {
+                    mlo[k] = (uint32_t)open[k];
+                    mhi[k] = (uint32_t)(open[k] >> 32);
+                }
+            }
+            node = node + 1;
         }
     }
 
     // epilogues
-    if (MODE == TR_OUT_CALLER) {
-        if (valid) {
+    double e = 0.0;
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+        const int t = first + k * kWave + lane;
+        if (!valid[k]) continue;
+        if (MODE == TR_OUT_CALLER) {
             const int64_t j = a.perm[t];
             if (OP == OP_A) {
-                a.out[j] = s * kInv4Pi;
+                a.out[j] = s[k] * kInv4Pi;
             } else {
                 const float sg = OP == OP_G ? -kInv4Pi : kInv4Pi;  // grad F = -G
-                a.out[3 * j] = gx * sg;
-                a.out[3 * j + 1] = gy * sg;
-                a.out[3 * j + 2] = gz * sg;
+                a.out[3 * j] = gx[k] * sg;
+                a.out[3 * j + 1] = gy[k] * sg;
+                a.out[3 * j + 2] = gz[k] * sg;
             }
-        }
-    } else if (MODE == TR_RHO) {
-        double e = 0.0;
-        if (valid) {
-            const float rho = 0.5f - s * kInv4Pi;
+        } else if (MODE == TR_RHO) {
+            const float rho = 0.5f - s[k] * kInv4Pi;
             a.rho[t] = rho;
-            e = (double)rho * (double)rho;
-        }
-        e = block_sum(e);
-        if (threadIdx.x == 0) a.partial[lb] = e;
-    } else if (MODE == TR_R) {
-        double e = 0.0;
-        if (valid) {
-            const float rx = gx * kInv4Pi, ry = gy * kInv4Pi, rz = gz * kInv4Pi;
+            e += (double)rho * (double)rho;
+        } else if (MODE == TR_R) {
+            const float rx = gx[k] * kInv4Pi, ry = gy[k] * kInv4Pi, rz = gz[k] * kInv4Pi;
             a.out4[t] = make_float4(rx, ry, rz, 0.f);
-            e = (double)rx * rx + (double)ry * ry + (double)rz * rz;
-        }
-        e = block_sum(e);
-        if (threadIdx.x == 0) a.partial[lb] = e;
-    } else if (MODE == TR_TSUM) {
-        double e = 0.0;
-        if (valid) {
-            const double tv = (double)(s * kInv4Pi);
-            e = tv * tv;
-        }
-        e = block_sum(e);
-        if (threadIdx.x == 0) a.partial[lb] = e;
-    } else if (MODE == TR_RESCALE) {
-        if (valid) {
+            e += (double)rx * rx + (double)ry * ry + (double)rz * rz;
+        } else if (MODE == TR_TSUM) {
+            const double tv = (double)(s[k] * kInv4Pi);
+            e += tv * tv;
+        } else if (MODE == TR_RESCALE) {
             const float4 mu = a.src4[t];
-            const double g2 = (double)gx * gx + (double)gy * gy + (double)gz * gz;
+            const double g2 = (double)gx[k] * gx[k] + (double)gy[k] * gy[k] + (double)gz[k] * gz[k];
             float4 o = mu;
             if (g2 > 0.0 && g2 <= DBL_MAX) {
                 const double mn = sqrt((double)mu.x * mu.x + (double)mu.y * mu.y + (double)mu.z * mu.z);
                 const double f = mn / sqrt(g2);
-                o = make_float4((float)(gx * f), (float)(gy * f), (float)(gz * f), 0.f);
+                o = make_float4((float)(gx[k] * f), (float)(gy[k] * f), (float)(gz[k] * f), 0.f);
             }
             a.out4[t] = o;
         }
     }
+    if (MODE == TR_RHO || MODE == TR_R || MODE == TR_TSUM) {
+        e = wave_sum(e);  // fixed butterfly order: reproducible
+        if (lane == 0) a.partial[a.task_slot[wave]] = e;
+    }
     if (COUNT) {
-        double c = block_sum((double)cnt);
-        if (threadIdx.x == 0) atomicAdd(a.pairs + OP, (unsigned long long)c);
+        const double c = wave_sum((double)cnt);
+        if (lane == 0) atomicAdd(a.pairs + OP, (unsigned long long)c);
     }
 }
 
-int trav_blocks(int64_t n) { return (int)((n + kTravBlock - 1) / kTravBlock); }
+int trav_blocks(int64_t ntasks) {
+    return (int)((ntasks + kTravBlock / kWave - 1) / (kTravBlock / kWave));
+}
+
+template <int OP, int MODE, int TPL>
+static void launch_tpl(bool count, const TravArgs &a, hipStream_t st) {
+    const dim3 grid((unsigned)trav_blocks(a.ntasks)), block(kTravBlock);
+    if (count)
+        hipLaunchKernelGGL((k_traverse<OP, MODE, true, TPL>), grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL((k_traverse<OP, MODE, false, TPL>), grid, block, 0, st, a);
+}
 
 template <int OP, int MODE>
-static void launch_one(bool count, const TravArgs &a, hipStream_t st) {
-    const dim3 grid((unsigned)trav_blocks(a.n)), block(kTravBlock);
-    if (count)
-        hipLaunchKernelGGL((k_traverse<OP, MODE, true>), grid, block, 0, st, a);
-    else
-        hipLaunchKernelGGL((k_traverse<OP, MODE, false>), grid, block, 0, st, a);
+static hipError_t launch_one(bool count, int tpl, const TravArgs &a, hipStream_t st) {
+    if (a.ntasks <= 0) return hipSuccess;
+    switch (tpl) {
+        case 1: launch_tpl<OP, MODE, 1>(count, a, st); break;
+        case 2: launch_tpl<OP, MODE, 2>(count, a, st); break;
+        case 4: launch_tpl<OP, MODE, 4>(count, a, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_traverse(wnnc_ctx_s *ctx, Op op, TravMode mode, bool count, const TravArgs &a) {
     hipStream_t st = ctx->stream;
+    const int tpl = a.tpl;
     if (op == OP_A) {
-        if (mode == TR_OUT_CALLER)
-            launch_one<OP_A, TR_OUT_CALLER>(count, a, st);
-        else if (mode == TR_RHO)
-            launch_one<OP_A, TR_RHO>(count, a, st);
-        else if (mode == TR_TSUM)
-            launch_one<OP_A, TR_TSUM>(count, a, st);
-        else
-            return hipErrorInvalidValue;
+        if (mode == TR_OUT_CALLER) return launch_one<OP_A, TR_OUT_CALLER>(count, tpl, a, st);
+        if (mode == TR_RHO) return launch_one<OP_A, TR_RHO>(count, tpl, a, st);
+        if (mode == TR_TSUM) return launch_one<OP_A, TR_TSUM>(count, tpl, a, st);
     } else if (op == OP_AT) {
-        if (mode == TR_OUT_CALLER)
-            launch_one<OP_AT, TR_OUT_CALLER>(count, a, st);
-        else if (mode == TR_R)
-            launch_one<OP_AT, TR_R>(count, a, st);
-        else
-            return hipErrorInvalidValue;
+        if (mode == TR_OUT_CALLER) return launch_one<OP_AT, TR_OUT_CALLER>(count, tpl, a, st);
+        if (mode == TR_R) return launch_one<OP_AT, TR_R>(count, tpl, a, st);
     } else {
-        if (mode == TR_OUT_CALLER)
-            launch_one<OP_G, TR_OUT_CALLER>(count, a, st);
-        else if (mode == TR_RESCALE)
-            launch_one<OP_G, TR_RESCALE>(count, a, st);
-        else
-            return hipErrorInvalidValue;
+        if (mode == TR_OUT_CALLER) return launch_one<OP_G, TR_OUT_CALLER>(count, tpl, a, st);
+        if (mode == TR_RESCALE) return launch_one<OP_G, TR_RESCALE>(count, tpl, a, st);
     }
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
 }  // namespace wnnc

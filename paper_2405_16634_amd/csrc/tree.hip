@@ -12,21 +12,43 @@
 // index range.
 #include <float.h>
 
+#include <utility>
+#include <vector>
+
 #include "common.h"
 #include "internal.h"
 
 namespace wnnc {
 
 // ------------------------------------------------------------ normalize --
+// Each cloud c (caller rows off[c] .. off[c+1]) is normalized on its own.
 
-constexpr int kNormBlocks = 256;
+constexpr int kNormBlocksPerCloud = 32;
 
-int64_t normalize_tmp_doubles(int64_t) { return kNormBlocks * 6 + 8; }
+int64_t normalize_tmp_doubles(int64_t nclouds) {
+    return nclouds * (kNormBlocksPerCloud * 6 + 4) + 8;
+}
 
-__global__ __launch_bounds__(256) void k_minmax(const float *__restrict__ P, int64_t n,
+__device__ inline int cloud_of_row(const int64_t *off, int nclouds, int64_t i) {
+    int lo = 0, hi = nclouds;  // off[lo] <= i < off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= i)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// grid (kNormBlocksPerCloud, nclouds): per-block extremes of one cloud
+__global__ __launch_bounds__(256) void k_minmax(const float *__restrict__ P,
+                                                const int64_t *__restrict__ off,
                                                 double *__restrict__ part) {
+    const int c = blockIdx.y;
+    const int64_t lo_i = off[c], hi_i = off[c + 1];
     float lo[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, hi[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+    for (int64_t i = lo_i + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi_i;
          i += (int64_t)gridDim.x * blockDim.x) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -52,49 +74,54 @@ __global__ __launch_bounds__(256) void k_minmax(const float *__restrict__ P, int
         }
         __syncthreads();
     }
-    if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = s[threadIdx.x][0];
+    if (threadIdx.x < 6)
+        part[((int64_t)c * kNormBlocksPerCloud + blockIdx.x) * 6 + threadIdx.x] = s[threadIdx.x][0];
 }
 
-// One thread: reduce the block extremes and derive centre and scale in FP64.
-__global__ void k_norm_finalize(double *__restrict__ part, int nb) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One thread per cloud: extremes -> centre and scale in FP64.
+__global__ void k_norm_finalize(const double *__restrict__ part, int nclouds,
+                                double *__restrict__ cs) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nclouds) return;
     double lo[3], hi[3];
     for (int k = 0; k < 3; ++k) {
-        lo[k] = part[k];
-        hi[k] = part[3 + k];
+        lo[k] = DBL_MAX;
+        hi[k] = -DBL_MAX;
     }
-    for (int b = 1; b < nb; ++b)
+    for (int b = 0; b < kNormBlocksPerCloud; ++b)
         for (int k = 0; k < 3; ++k) {
-            lo[k] = fmin(lo[k], part[b * 6 + k]);
-            hi[k] = fmax(hi[k], part[b * 6 + 3 + k]);
+            lo[k] = fmin(lo[k], part[((int64_t)c * kNormBlocksPerCloud + b) * 6 + k]);
+            hi[k] = fmax(hi[k], part[((int64_t)c * kNormBlocksPerCloud + b) * 6 + 3 + k]);
         }
     double half = 0.0;
-    double *out = part + kNormBlocks * 6;
     for (int k = 0; k < 3; ++k) {
-        out[k] = (lo[k] + hi[k]) / 2.0;
+        cs[4 * c + k] = (lo[k] + hi[k]) / 2.0;
         half = fmax(half, (hi[k] - lo[k]) / 2.0);
     }
-    out[3] = half > 0.0 ? (10.0 / 11.0) / half : 1.0;
+    cs[4 * c + 3] = half > 0.0 ? (10.0 / 11.0) / half : 1.0;
 }
 
 __global__ __launch_bounds__(256) void k_norm_apply(const float *P, int64_t n3, float *Q,
+                                                    const int64_t *__restrict__ off, int nclouds,
                                                     const double *__restrict__ cs) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n3) return;
     const int k = (int)(i % 3);
-    Q[i] = (float)(((double)P[i] - cs[k]) * cs[3]);
+    const int c = nclouds == 1 ? 0 : cloud_of_row(off, nclouds, i / 3);
+    Q[i] = (float)(((double)P[i] - cs[4 * c + k]) * cs[4 * c + 3]);
 }
 
-hipError_t launch_normalize(const float *P, int64_t n, float *P_norm, double *tmp,
-                            hipStream_t st) {
-    int nb = (int)((n + 255) / 256);
-    if (nb > kNormBlocks) nb = kNormBlocks;
-    hipLaunchKernelGGL(k_minmax, dim3(nb), dim3(256), 0, st, P, n, tmp);
-    hipLaunchKernelGGL(k_norm_finalize, dim3(1), dim3(64), 0, st, tmp, nb);
+// tmp layout: [partials | centre/scale (4 per cloud)]; returns the offset of
+// the centre/scale block in tmp.
+int64_t launch_normalize(const float *P, int64_t n, const int64_t *d_off, int nclouds,
+                         float *P_norm, double *tmp, hipStream_t st) {
+    double *cs = tmp + (int64_t)nclouds * kNormBlocksPerCloud * 6;
+    hipLaunchKernelGGL(k_minmax, dim3(kNormBlocksPerCloud, nclouds), dim3(256), 0, st, P, d_off, tmp);
+    hipLaunchKernelGGL(k_norm_finalize, dim3((nclouds + 63) / 64), dim3(64), 0, st, tmp, nclouds, cs);
     const int64_t n3 = 3 * n;
     hipLaunchKernelGGL(k_norm_apply, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, P, n3,
-                       P_norm, tmp + kNormBlocks * 6);
-    return hipGetLastError();
+                       P_norm, d_off, nclouds, cs);
+    return (int64_t)nclouds * kNormBlocksPerCloud * 6;
 }
 
 // ----------------------------------------------------------------- morton --
@@ -120,13 +147,22 @@ __device__ inline unsigned quantize15(float v) {
 }
 
 __global__ __launch_bounds__(256) void k_morton(const float *__restrict__ P, int64_t n,
+                                                const int64_t *__restrict__ off, int nclouds,
                                                 unsigned long long *__restrict__ keys,
                                                 uint32_t *__restrict__ vals) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     unsigned qx = quantize15(P[3 * i]), qy = quantize15(P[3 * i + 1]), qz = quantize15(P[3 * i + 2]);
-    keys[i] = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
+    const unsigned long long c = nclouds == 1 ? 0ull : (unsigned long long)cloud_of_row(off, nclouds, i);
+    keys[i] = (c << kMortonBits) | (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
     vals[i] = (uint32_t)i;
+}
+
+// Cloud index of every sorted point (clouds stay contiguous and in order).
+__global__ __launch_bounds__(256) void k_point_cloud(const unsigned long long *__restrict__ keys,
+                                                     int64_t n, int32_t *__restrict__ cloud) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) cloud[i] = (int32_t)(keys[i] >> kMortonBits);
 }
 
 // ------------------------------------------------------------ radix sort --
@@ -207,11 +243,13 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(
 
 // ----------------------------------------------------------------- nodes --
 
-// Number of leading octal digits (of 15) shared by two keys.
+// Number of leading octal digits (of 15) shared by two keys; -1 for keys of
+// different clouds.
 __device__ inline int lcp_digits(unsigned long long a, unsigned long long b) {
     unsigned long long x = a ^ b;
     if (x == 0ull) return 15;
-    return (__clzll(x) - 19) / 3;
+    if (x >> kMortonBits) return -1;
+    return (__clzll(x) - (64 - kMortonBits)) / 3;
 }
 
 __device__ inline void neighbour_lcp(const unsigned long long *keys, int64_t n, int64_t i, int D,
@@ -239,9 +277,9 @@ __global__ __launch_bounds__(256) void k_count_nodes(const unsigned long long *_
     counts[i] = L >= D ? 0u : (uint32_t)(hi - L);
 }
 
-// First sorted position after i whose key leaves the depth-d cell of key i.
+// First sorted position after i whose key leaves the depth-d cell of key i
+// (at depth 0 the cell is the cloud: the shift keeps only the cloud bits).
 __device__ inline int64_t run_end(const unsigned long long *keys, int64_t n, int64_t i, int d) {
-    if (d == 0) return n;
     const int shift = 3 * (15 - d);
     const unsigned long long pre = keys[i] >> shift;
     int64_t lo = i, step = 1;
@@ -280,6 +318,13 @@ __global__ __launch_bounds__(256) void k_emit_nodes(const unsigned long long *__
         topo[idx] = make_int4((int)node_off[end], (int)i, (int)end, d | (leaf << 4));
         strad_flag[idx] = ((i / kChunk) != ((end - 1) / kChunk)) ? 1u : 0u;
     }
+}
+
+__global__ __launch_bounds__(256) void k_gather_roots(const uint32_t *__restrict__ node_off,
+                                                      const int64_t *__restrict__ off, int nclouds,
+                                                      int32_t *__restrict__ roots) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c <= nclouds) roots[c] = (int32_t)node_off[off[c]];
 }
 
 __global__ __launch_bounds__(256) void k_gather_points(const float *__restrict__ P,
@@ -336,13 +381,19 @@ __global__ __launch_bounds__(256) void k_tail_fill(const int32_t *__restrict__ s
 
 static inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// Builds the forest over the normalized points P (caller order); the cloud
+// ranges are ctx->offsets (host) / ctx->d_offsets (device, already copied).
 hipError_t build_tree(wnnc_ctx_s *ctx, const float *P) {
     const int64_t n = ctx->n;
     const int D = ctx->depth;
+    const int nclouds = ctx->nclouds;
     hipStream_t st = ctx->stream;
     const int64_t nchunks = (n + kChunk - 1) / kChunk;
     const int ntiles = (int)((n + kRsTile - 1) / kRsTile);
     const int64_t hsize = (int64_t)256 * ntiles;
+    int cloud_bits = 0;
+    while ((1ll << cloud_bits) < nclouds) ++cloud_bits;
+    const int passes = (kMortonBits + cloud_bits + 7) / 8;
 
     TRY(ctx->pts.ensure(n));
     TRY(ctx->perm.ensure(n));
@@ -354,25 +405,26 @@ hipError_t build_tree(wnnc_ctx_s *ctx, const float *P) {
     TRY(ctx->hist.ensure(hsize));
     TRY(ctx->tail_off.ensure(nchunks + 1));
     TRY(ctx->chunk_tot.ensure(8 * nchunks));
+    TRY(ctx->cloud_of.ensure(n));
     TRY(ctx->va.ensure(n));
     TRY(ctx->vb.ensure(n));
     TRY(ctx->vr.ensure(n));
     TRY(ctx->rho.ensure(n));
-    TRY(ctx->partial.ensure(3 * (int64_t)trav_blocks(n)));
-    TRY(ctx->scalars.ensure(8));
+    TRY(ctx->scalars.ensure(nclouds));
     TRY(ctx->pair_ctr.ensure(4));
     {
         int64_t big = hsize > n + 1 ? hsize : n + 1;
         TRY(ctx->scan_tmp.ensure(scan_tmp_size(16 * big + 16)));
     }
 
-    // Morton keys and the stable sort: 6 passes of 8 bits cover the 45 key
-    // bits, and an even pass count leaves the result in keys_a / perm.
-    hipLaunchKernelGGL(k_morton, dim3(blocks_for(n, 256)), dim3(256), 0, st, P, n, ctx->keys_a.p,
-                       ctx->perm.p);
+    // Morton keys (cloud index above the 45 Morton bits) and a stable LSD
+    // sort, 8 bits per pass; an odd pass count leaves the result in the
+    // second buffer pair, which then becomes the first.
+    hipLaunchKernelGGL(k_morton, dim3(blocks_for(n, 256)), dim3(256), 0, st, P, n,
+                       ctx->d_offsets.p, nclouds, ctx->keys_a.p, ctx->perm.p);
     unsigned long long *kin = ctx->keys_a.p, *kout = ctx->keys_b.p;
     uint32_t *vin = ctx->perm.p, *vout = ctx->vals_b.p;
-    for (int pass = 0; pass < 6; ++pass) {
+    for (int pass = 0; pass < passes; ++pass) {
         const int shift = 8 * pass;
         hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(kRsThreads), 0, st, kin, n, shift,
                            ctx->hist.p, ntiles);
@@ -386,16 +438,28 @@ hipError_t build_tree(wnnc_ctx_s *ctx, const float *P) {
         vin = vout;
         vout = tv;
     }
+    if (passes & 1) {
+        std::swap(ctx->keys_a, ctx->keys_b);
+        std::swap(ctx->perm, ctx->vals_b);
+    }
     TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_point_cloud, dim3(blocks_for(n, 256)), dim3(256), 0, st, ctx->keys_a.p, n,
+                       ctx->cloud_of.p);
 
     // nodes started per point -> pre-order offsets; M is read back once
     hipLaunchKernelGGL(k_count_nodes, dim3(blocks_for(n + 1, 256)), dim3(256), 0, st,
                        ctx->keys_a.p, n, D, ctx->u32_tmp.p);
     TRY(exclusive_scan_u32(ctx->u32_tmp.p, ctx->node_off.p, n + 1, ctx->scan_tmp.p, st));
-    uint32_t m32 = 0;
-    TRY(hipMemcpyAsync(&m32, ctx->node_off.p + n, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    // first node of every cloud (node_off at the cloud starts); the last
+    // entry is M
+    TRY(ctx->d_roots.ensure(nclouds + 1));
+    hipLaunchKernelGGL(k_gather_roots, dim3((nclouds + 256) / 256), dim3(256), 0, st,
+                       ctx->node_off.p, ctx->d_offsets.p, nclouds, ctx->d_roots.p);
+    ctx->roots.resize(nclouds + 1);
+    TRY(hipMemcpyAsync(ctx->roots.data(), ctx->d_roots.p, (size_t)(nclouds + 1) * sizeof(int32_t),
+                       hipMemcpyDeviceToHost, st));
     TRY(hipStreamSynchronize(st));
-    const int64_t m = m32;
+    const int64_t m = ctx->roots[nclouds];
     ctx->m = m;
 
     TRY(ctx->topo.ensure(m));
@@ -436,6 +500,41 @@ hipError_t build_tree(wnnc_ctx_s *ctx, const float *P) {
                            ctx->strad_node.p, ctx->topo.p, (int)ns, cursor, ctx->tail_list.p);
     TRY(hipMemsetAsync(ctx->pair_ctr.p, 0, 4 * sizeof(unsigned long long), st));
     return hipGetLastError();
+}
+
+// Wavefront tasks for tile shape tpl: each cloud's sorted targets cut into
+// runs of 64 * tpl, in Morton order, cloud after cloud.  The partial-sum
+// slot of a task is its index, so a cloud's slots are contiguous.
+hipError_t make_tasks(wnnc_ctx_s *ctx, int tpl) {
+    const int per = kWave * tpl;
+    std::vector<int4> tk;
+    std::vector<int32_t> lo(ctx->nclouds + 1);
+    for (int c = 0; c < ctx->nclouds; ++c) {
+        lo[c] = (int32_t)tk.size();
+        const int64_t a = ctx->offsets[c], b = ctx->offsets[c + 1];
+        for (int64_t f = a; f < b; f += per)
+            tk.push_back(make_int4((int)f, (int)(f + per < b ? f + per : b), ctx->roots[c],
+                                   ctx->roots[c + 1]));
+    }
+    lo[ctx->nclouds] = (int32_t)tk.size();
+    const int64_t nt = (int64_t)tk.size();
+    std::vector<int32_t> slot((size_t)nt);
+    for (int64_t k = 0; k < nt; ++k) slot[k] = (int32_t)k;
+    TRY(ctx->tasks.ensure(nt));
+    TRY(ctx->task_slot.ensure(nt));
+    TRY(ctx->task_lo.ensure(ctx->nclouds + 1));
+    TRY(ctx->partial.ensure(3 * nt));
+    TRY(hipMemcpyAsync(ctx->tasks.p, tk.data(), (size_t)nt * sizeof(int4), hipMemcpyHostToDevice,
+                       ctx->stream));
+    TRY(hipMemcpyAsync(ctx->task_slot.p, slot.data(), (size_t)nt * sizeof(int32_t),
+                       hipMemcpyHostToDevice, ctx->stream));
+    TRY(hipMemcpyAsync(ctx->task_lo.p, lo.data(), lo.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice, ctx->stream));
+    // the host vectors are released on return: wait for the copies
+    TRY(hipStreamSynchronize(ctx->stream));
+    ctx->ntasks = (int)nt;
+    ctx->tpl = tpl;
+    return hipSuccess;
 }
 
 }  // namespace wnnc

@@ -1,0 +1,189 @@
+"""Batched clouds (one forest, one launch per operator) and traversal tile
+shapes.
+
+* every cloud of a batch has the octree its standalone build has (node sets
+  against the oracle's recursive partition of that cloud alone);
+* operators on a batch equal the oracle treecode of each cloud alone;
+* the 40-iteration orientation of a batch agrees with running each cloud
+  alone (per-cloud step lengths and energies);
+* the tile shape (targets per lane) does not change any result bit;
+* the 64-cloud workload (sizes log-uniform in [5k, 200k]) batched against
+  the clouds one by one.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2405_16634_amd as w
+    w.load_library()
+    return torch.device("cuda:0")
+
+
+def _batch():
+    rng = np.random.default_rng(40)
+    clouds = [
+        synth.ellipsoid_union(3077, 9, noise=0.001, with_init=False).points,
+        rng.uniform(-1, 1, (1, 3)).astype(np.float32),
+        np.repeat(rng.uniform(-1, 1, (3, 3)).astype(np.float32), 3, axis=0),
+        synth.fibonacci_sphere(2000, 0).points,
+        synth.torus_knot(20000, 5, with_init=False).points,
+        rng.uniform(-1, 1, (300, 3)).astype(np.float32),
+    ]
+    off = np.concatenate([[0], np.cumsum([len(c) for c in clouds])]).astype(np.int64)
+    return clouds, off
+
+
+def _sets(depth, begin, end, order, lo=0):
+    return {(int(d), tuple(sorted((order[b:e] - lo).tolist()))) for d, b, e in zip(depth, begin, end)}
+
+
+def test_batched_normalize_and_forest(dev, oracle_mod):
+    import torch
+    import paper_2405_16634_amd as w
+    clouds, off = _batch()
+    P = torch.from_numpy(np.concatenate(clouds)).to(dev)
+    ctx = w.Context(0)
+    x, norms = ctx.normalize_batched(P, off)
+    ctx.build_batched(x, off)
+    st = ctx.stats()
+    assert st["n_clouds"] == len(clouds)
+    xh = x.cpu().numpy()
+    d, leaf, b, e, perm = ctx.tree()
+    total = 0
+    for k, c in enumerate(clouds):
+        xo, _, sc = oracle_mod.normalize(c)
+        assert np.array_equal(xh[off[k]:off[k + 1]], xo)
+        assert norms[k].scale == pytest.approx(sc, rel=1e-15)
+        # nodes of cloud k: those whose points lie in its caller range
+        sel = (perm[b] >= off[k]) & (perm[b] < off[k + 1])
+        T = oracle_mod.Tree(xo.astype(np.float64))
+        od, ol, obg, oen, oo = T.export()
+        assert _sets(d[sel], b[sel], e[sel], perm, off[k]) == _sets(od, obg, oen, oo)
+        total += int(sel.sum())
+    assert total == len(d)
+    ctx.close()
+
+
+def test_batched_operators(dev, oracle_mod):
+    import torch
+    import paper_2405_16634_amd as w
+    clouds, off = _batch()
+    P = torch.from_numpy(np.concatenate(clouds)).to(dev)
+    ctx = w.Context(0)
+    x, _ = ctx.normalize_batched(P, off)
+    ctx.build_batched(x, off)
+    xh = x.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(5)
+    n = int(off[-1])
+    mu = (synth.random_unit(rng, n) * 1e-4).astype(np.float32)
+    rho = rng.standard_normal(n).astype(np.float32)
+    for w_ in (0.002, 0.016):
+        s = ctx.winding(torch.from_numpy(mu).to(dev), w_).cpu().numpy()
+        g = ctx.gradient(torch.from_numpy(mu).to(dev), w_).cpu().numpy()
+        at = ctx.adjoint(torch.from_numpy(rho).to(dev), w_).cpu().numpy()
+        for k in range(len(clouds)):
+            a, b_ = off[k], off[k + 1]
+            T = oracle_mod.Tree(xh[a:b_])
+            for op, got, nu, sign in (("A", s, mu, 1.0), ("G", g, mu, -1.0), ("AT", at, rho, 1.0)):
+                ref, mag, _ = T.apply(op, nu[a:b_].astype(np.float64), w_, 2.0, with_stats=True)
+                err = np.abs(got[a:b_] - sign * ref)
+                if err.ndim == 2:
+                    err = np.linalg.norm(err, axis=1)
+                ok = mag > 0
+                bad = (err[ok] / mag[ok] > TOL).mean() if ok.any() else 0.0
+                assert bad <= 2e-3, (k, op, w_, bad)
+                assert np.all(err[~ok] == 0.0)
+    ctx.close()
+
+
+def test_batched_orient_equals_single(dev):
+    import torch
+    import paper_2405_16634_amd as w
+    clouds, off = _batch()
+    P = torch.from_numpy(np.concatenate(clouds)).to(dev)
+    ctx = w.Context(0)
+    x, _ = ctx.normalize_batched(P, off)
+    ctx.build_batched(x, off)
+    mu_b = ctx.orient(40, 0.002, 0.016).cpu().numpy()
+    E_b = np.array(ctx.energy(40))  # (40, clouds)
+    ctx.close()
+    for k, c in enumerate(clouds):
+        ctx = w.Context(0)
+        xk, _ = ctx.normalize(torch.from_numpy(c).to(dev))
+        ctx.build(xk)
+        mu_s = ctx.orient(40, 0.002, 0.016).cpu().numpy()
+        E_s = np.array(ctx.energy(40))
+        ctx.close()
+        mb = mu_b[off[k]:off[k + 1]]
+        nz = np.linalg.norm(mu_s, axis=1) > 0
+        flip = ((mb[nz] * mu_s[nz]).sum(1) <= 0).mean() if nz.any() else 0.0
+        print(f"  cloud {k} n={len(c)} flip={flip:.2e} E39 batch={E_b[-1, k]:.6e} single={E_s[-1]:.6e}",
+              flush=True)
+        assert flip <= 1e-3
+        assert E_b[0, k] == pytest.approx(0.25 * len(c))
+        assert np.allclose(E_b[:, k], E_s, rtol=1e-3, atol=1e-9)
+
+
+def test_tile_shapes_give_identical_bits(dev):
+    import torch
+    import paper_2405_16634_amd as w
+    cloud = synth.torus_knot(20000, 5, with_init=False)
+    ctx = w.Context(0)
+    x, _ = ctx.normalize(torch.from_numpy(cloud.points).to(dev))
+    ctx.build(x)
+    rng = np.random.default_rng(2)
+    mu = torch.from_numpy((synth.random_unit(rng, cloud.n) * 1e-4).astype(np.float32)).to(dev)
+    ref = None
+    for tpl in (1, 2, 4):
+        ctx.set_tile(tpl)
+        assert ctx.tile() == tpl
+        out = (ctx.winding(mu, 0.002).clone(), ctx.gradient(mu, 0.002).clone(),
+               ctx.orient(5, 0.002, 0.016).clone())
+        if ref is None:
+            ref = out
+        else:
+            for a, b in zip(ref, out):
+                assert bool((a == b).all()), tpl
+    ms = ctx.autotune(0.002)
+    assert set(ms) == {1, 2, 4} and all(v > 0 for v in ms.values())
+    assert ctx.tile() == min(ms, key=ms.get)
+    ctx.close()
+
+
+def test_batched64_workload_matches_one_by_one(dev):
+    """The 64-cloud workload: sizes floor(exp(U[ln 5e3, ln 2e5])) (seed 1),
+    noise-free ellipsoid unions; one forest, one launch per operator."""
+    import torch
+    import paper_2405_16634_amd as w
+    sizes = synth.batched_sizes(64, 1)
+    clouds = synth.batched_clouds(64, 1, sizes)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    print(f"[case] batched64 N={off[-1]}", flush=True)
+    P = torch.from_numpy(np.concatenate([c.points for c in clouds])).to(dev)
+    ctx = w.Context(0)
+    x, _ = ctx.normalize_batched(P, off)
+    ctx.build_batched(x, off)
+    ctx.autotune(0.002)
+    mu_b = ctx.orient(40, 0.002, 0.016).cpu().numpy()
+    ctx.close()
+    flips = []
+    for k in range(0, 64, 9):
+        ctx = w.Context(0)
+        xk, _ = ctx.normalize(torch.from_numpy(clouds[k].points).to(dev))
+        ctx.build(xk)
+        mu_s = ctx.orient(40, 0.002, 0.016).cpu().numpy()
+        ctx.close()
+        flips.append(((mu_b[off[k]:off[k + 1]] * mu_s).sum(1) <= 0).mean())
+    print(f"  flips one-by-one vs batched: max={max(flips):.2e}", flush=True)
+    assert max(flips) <= 1e-3
