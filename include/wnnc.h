@@ -220,6 +220,65 @@ wnnc_status wnnc_tree_export(wnnc_ctx ctx, int32_t *depth, int32_t *leaf, int64_
 wnnc_status wnnc_moments_export(wnnc_ctx ctx, const float *nu, int dim, float *xB, float *nuB,
                                 float *W);
 
+/* ------------------------------------------------------- learned warm start
+ * A neighbourhood MLP predicts initial normals from the 16 nearest
+ * neighbours of each point; the WNNC iteration then starts from them.
+ * Network: 48 -> 64 -> 64 -> 3 with ReLU; BF16 operands, FP32 accumulation.
+ * Parameters are one device FP32 vector of WNNC_MLP_PARAMS values: W1
+ * [48][64], b1 [64], W2 [64][64], b2 [64], W3 [64][3], b3 [3] (row-major
+ * [in][out]). */
+#define WNNC_MLP_PARAMS 7491
+
+/* Features of every point of the built tree (all clouds), caller order:
+ * feat_out (N,48) = offsets to the 16 nearest other points of the same cloud,
+ * nearest first (ties by sorted position), divided by their RMS length;
+ * rows of clouds with fewer than 17 points are zero-padded.  nbr_out (N,16)
+ * int32 caller indices of the neighbours (-1 where missing), or NULL.
+ * Points must lie in [-1,1]^3 (normalized). */
+wnnc_status wnnc_knn_features(wnnc_ctx ctx, float *feat_out, int32_t *nbr_out);
+
+/* Unit normals predicted by the MLP: normals_out (N,3) from feat (N,48). */
+wnnc_status wnnc_mlp_forward(wnnc_ctx ctx, const float *params, const float *feat, int64_t N,
+                             float *normals_out);
+
+/* Loss mean_i (1 - cos(y_i, labels_i)) of the raw MLP outputs y and its
+ * gradient with respect to the parameters: grad_out (WNNC_MLP_PARAMS, device).
+ * loss_out (host, may be NULL; synchronizes when given). */
+wnnc_status wnnc_mlp_grad(wnnc_ctx ctx, const float *params, const float *feat,
+                          const float *labels, int64_t N, float *grad_out, double *loss_out);
+
+/* One Adam step (bias-corrected, step >= 1) on params with moments m, v
+ * (all WNNC_MLP_PARAMS device floats). */
+wnnc_status wnnc_mlp_adam(wnnc_ctx ctx, float *params, float *m, float *v, const float *grad,
+                          int step, float lr, float beta1, float beta2, float eps);
+
+/* Warm-started orientation options (defaults in brackets). */
+typedef struct {
+    int iters;            /* iterations of the warm schedule [8] */
+    float w1, w2;         /* warm schedule widths, w2 first [0.002, 0.004] */
+    float max_disagree;   /* self-check: largest tolerated fraction of points
+                             of a cloud whose final WNNC update points against
+                             mu [0.005]; above it the plain method reruns */
+    int fallback_iters;   /* plain method iterations on fallback [40] */
+    float fallback_w2;    /* plain method initial width on fallback [0.016];
+                             its final width is w1 */
+} wnnc_warm_opts;
+
+typedef struct {
+    int iterations;       /* iterations run (warm + fallback) */
+    int fallback;         /* 1 if the plain method was rerun */
+    double max_disagree;  /* worst per-cloud self-check fraction */
+} wnnc_warm_report;
+
+/* Learned warm start on the built tree (every cloud): neighbourhood
+ * features -> MLP unit normals n -> per cloud mu0 = beta n with the
+ * least-squares scale beta = <A n, 1/2> / |A n|^2 -> `iters` iterations of
+ * Alg. 3 with the warm schedule -> self-check; when it fails, the plain
+ * method from mu = 0.  mu_out (N,3) as wnnc_orient.  report (host) may be
+ * NULL.  Synchronizes once (the self-check). */
+wnnc_status wnnc_warm_orient(wnnc_ctx ctx, const float *params, const wnnc_warm_opts *opts,
+                             float *mu_out, wnnc_warm_report *report);
+
 /* Message of the last failing call on this thread. */
 const char *wnnc_last_error(void);
 

@@ -31,8 +31,10 @@ EXPORTED = [
     "wnnc_orient_energy", "wnnc_stats", "wnnc_reset_stats", "wnnc_tree_export",
     "wnnc_moments_export", "wnnc_normals", "wnnc_last_error", "wnnc_version",
     "wnnc_normalize_batched", "wnnc_build_batched", "wnnc_set_tile", "wnnc_get_tile",
-    "wnnc_autotune",
+    "wnnc_autotune", "wnnc_knn_features", "wnnc_mlp_forward", "wnnc_mlp_grad", "wnnc_mlp_adam",
+    "wnnc_warm_orient",
 ]
+MLP_PARAMS = 7491
 
 
 class WnncError(RuntimeError):
@@ -48,6 +50,17 @@ class TreeOpts(ctypes.Structure):
 class OrientOpts(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("w1", ctypes.c_float), ("w2", ctypes.c_float),
                 ("start_iter", ctypes.c_int), ("stop_iter", ctypes.c_int)]
+
+
+class WarmOpts(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("w1", ctypes.c_float), ("w2", ctypes.c_float),
+                ("max_disagree", ctypes.c_float), ("fallback_iters", ctypes.c_int),
+                ("fallback_w2", ctypes.c_float)]
+
+
+class WarmReport(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("fallback", ctypes.c_int),
+                ("max_disagree", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -99,6 +112,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "wnnc_set_tile": [vp, ctypes.c_int],
         "wnnc_get_tile": [vp, P(ctypes.c_int)],
         "wnnc_autotune": [vp, f32, P(dbl)],
+        "wnnc_knn_features": [vp, vp, vp],
+        "wnnc_mlp_forward": [vp, vp, vp, i64, vp],
+        "wnnc_mlp_grad": [vp, vp, vp, vp, i64, vp, P(dbl)],
+        "wnnc_mlp_adam": [vp, vp, vp, vp, vp, ctypes.c_int, f32, f32, f32, f32],
+        "wnnc_warm_orient": [vp, vp, P(WarmOpts), vp, P(WarmReport)],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -257,6 +275,54 @@ def wnnc_normals(ctx, mu, scale: float, n_out, area_out=None) -> None:
                                        _dev(area_out, "area_out", shape=(N,))))
 
 
+def wnnc_knn_features(ctx, feat_out, nbr_out=None) -> None:
+    N = feat_out.shape[0]
+    _check(load_library().wnnc_knn_features(ctx, _dev(feat_out, "feat_out", shape=(N, 48)),
+                                            _dev(nbr_out, "nbr_out", dtype=torch.int32,
+                                                 shape=(N, 16))))
+
+
+def wnnc_mlp_forward(ctx, params, feat, normals_out) -> None:
+    N = feat.shape[0]
+    _check(load_library().wnnc_mlp_forward(ctx, _dev(params, "params", shape=(MLP_PARAMS,)),
+                                           _dev(feat, "feat", shape=(N, 48)), N,
+                                           _dev(normals_out, "normals_out", shape=(N, 3))))
+
+
+def wnnc_mlp_grad(ctx, params, feat, labels, grad_out, with_loss: bool = True):
+    N = feat.shape[0]
+    loss = ctypes.c_double(0.0)
+    _check(load_library().wnnc_mlp_grad(ctx, _dev(params, "params", shape=(MLP_PARAMS,)),
+                                        _dev(feat, "feat", shape=(N, 48)),
+                                        _dev(labels, "labels", shape=(N, 3)), N,
+                                        _dev(grad_out, "grad_out", shape=(MLP_PARAMS,)),
+                                        ctypes.byref(loss) if with_loss else None))
+    return loss.value if with_loss else None
+
+
+def wnnc_mlp_adam(ctx, params, m, v, grad, step: int, lr: float = 1e-3, beta1: float = 0.9,
+                  beta2: float = 0.999, eps: float = 1e-8) -> None:
+    _check(load_library().wnnc_mlp_adam(ctx, _dev(params, "params", shape=(MLP_PARAMS,)),
+                                        _dev(m, "m", shape=(MLP_PARAMS,)),
+                                        _dev(v, "v", shape=(MLP_PARAMS,)),
+                                        _dev(grad, "grad", shape=(MLP_PARAMS,)), int(step),
+                                        float(lr), float(beta1), float(beta2), float(eps)))
+
+
+def wnnc_warm_orient(ctx, params, mu_out, iters: int = 8, w1: float = 0.002, w2: float = 0.004,
+                     max_disagree: float = 0.005, fallback_iters: int = 40,
+                     fallback_w2: float = 0.016) -> dict:
+    N = mu_out.shape[0]
+    opts = WarmOpts(int(iters), float(w1), float(w2), float(max_disagree), int(fallback_iters),
+                    float(fallback_w2))
+    rep = WarmReport()
+    _check(load_library().wnnc_warm_orient(ctx, _dev(params, "params", shape=(MLP_PARAMS,)),
+                                           ctypes.byref(opts), _dev(mu_out, "mu_out", shape=(N, 3)),
+                                           ctypes.byref(rep)))
+    return dict(iterations=rep.iterations, fallback=bool(rep.fallback),
+                max_disagree=rep.max_disagree)
+
+
 def wnnc_orient_energy(ctx, count: int, nclouds: int = 1):
     """Energies of the last orientation run: a list of `count` values for one
     cloud, or `count` lists of `nclouds` values."""
@@ -401,6 +467,19 @@ class Context:
         area = torch.empty(mu.shape[0], device=mu.device, dtype=torch.float32) if with_area else None
         wnnc_normals(self._h, mu, scale, nrm, area)
         return (nrm, area) if with_area else nrm
+
+    def warm_orient(self, params, out=None, **kw):
+        if out is None:
+            out = torch.empty(self.n, 3, device=f"cuda:{self.device}", dtype=torch.float32)
+        rep = wnnc_warm_orient(self._h, params, out, **kw)
+        return out, rep
+
+    def features(self, with_neighbours: bool = False):
+        feat = torch.empty(self.n, 48, device=f"cuda:{self.device}", dtype=torch.float32)
+        nbr = (torch.empty(self.n, 16, device=f"cuda:{self.device}", dtype=torch.int32)
+               if with_neighbours else None)
+        wnnc_knn_features(self._h, feat, nbr)
+        return (feat, nbr) if with_neighbours else feat
 
     def energy(self, count: int):
         return wnnc_orient_energy(self._h, count, getattr(self, "nclouds", 1))

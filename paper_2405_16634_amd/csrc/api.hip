@@ -94,6 +94,7 @@ TravArgs trav_args(wnnc_ctx_s *c, float w) {
     a.mom = c->mom.p;
     a.perm = c->perm.p;
     a.pairs = c->pair_ctr.p;
+    a.cloud = c->cloud_of.p;
     a.tasks = c->tasks.p;
     a.task_slot = c->task_slot.p;
     a.ntasks = c->ntasks;
@@ -206,6 +207,19 @@ wnnc_status wnnc_destroy(wnnc_ctx ctx) {
     ctx->tasks.release();
     ctx->task_slot.release();
     ctx->task_lo.release();
+    ctx->knn_idx.release();
+    ctx->knn_d2.release();
+    ctx->feat.release();
+    ctx->mlp_h1.release();
+    ctx->mlp_h2.release();
+    ctx->mlp_y.release();
+    ctx->mlp_dy.release();
+    ctx->mlp_d1.release();
+    ctx->mlp_d2.release();
+    ctx->mlp_part.release();
+    ctx->mlp_lpart.release();
+    ctx->flip_ctr.release();
+    ctx->nhat.release();
     for (auto &t : ctx->pending) {
         (void)hipEventDestroy(t.a);
         (void)hipEventDestroy(t.b);
@@ -441,43 +455,25 @@ wnnc_status wnnc_adjoint(wnnc_ctx ctx, const float *s, float w, float *out) {
     return run_traverse(ctx, OP_AT, TR_OUT_CALLER, ta);
 }
 
-wnnc_status wnnc_orient(wnnc_ctx ctx, const wnnc_orient_opts *opts, const float *mu0,
-                        float *mu_out) {
-    CHECK_CTX(ctx);
-    CHECK_BUILT(ctx);
-    if (!mu_out) return fail(WNNC_EINVAL, "null mu_out");
-    wnnc_orient_opts o = {40, 0.002f, 0.016f, 1, 0};
-    if (opts) o = *opts;
-    if (o.iters < 1) return fail(WNNC_EINVAL, "iters must be >= 1");
-    if (o.start_iter < 1 || o.start_iter > o.iters)
-        return fail(WNNC_EINVAL, "start_iter must be in 1..iters");
-    const int stop = o.stop_iter == 0 ? o.iters : o.stop_iter;
-    if (stop < o.start_iter || stop > o.iters)
-        return fail(WNNC_EINVAL, "stop_iter must be 0 or in start_iter..iters");
-    if (!finite_nonneg(o.w1) || !finite_nonneg(o.w2))
-        return fail(WNNC_EINVAL, "widths must be finite and >= 0");
-    const int64_t N = ctx->n;
+// Iterations start..stop of Alg. 3 (schedule over iters) on the sorted mu in
+// ctx->va.  zero: mu is 0 at the start (the first A(mu) is skipped).
+// flips (device, per cloud, may be null): in the last iteration, the number
+// of points whose WNNC update points against mu + alpha r.
+static wnnc_status run_iterations(wnnc_ctx ctx, int iters, float w1, float w2, int start, int stop,
+                                  bool zero, unsigned long long *flips) {
     const int nt = ctx->ntasks;
-    hipStream_t st = ctx->stream;
-    const int count = stop - o.start_iter + 1;
+    const int count = stop - start + 1;
     HIPCHK(ctx->energy.ensure((int64_t)count * ctx->nclouds));
-
     float4 *mu = ctx->va.p, *tmp = ctx->vb.p, *r = ctx->vr.p;
     float *rho = ctx->rho.p;
-    const bool zero = mu0 == nullptr;
-    if (zero)
-        HIPCHK(launch_zero_f4(mu, N, st));
-    else
-        HIPCHK(launch_gather_vec(mu0, ctx->perm.p, mu, N, st));
-
-    for (int i = o.start_iter; i <= stop; ++i) {
-        const int n = o.iters;
-        const double w = n <= 1 ? (double)o.w1
-                                : (double)o.w2 * (n - i) / (n - 1) + (double)o.w1 * (i - 1) / (n - 1);
+    for (int i = start; i <= stop; ++i) {
+        const int n = iters;
+        const double w = n <= 1 ? (double)w1
+                                : (double)w2 * (n - i) / (n - 1) + (double)w1 * (i - 1) / (n - 1);
         const float wf = (float)w;
-        double *erow = ctx->energy.p + (int64_t)(i - o.start_iter) * ctx->nclouds;
+        double *erow = ctx->energy.p + (int64_t)(i - start) * ctx->nclouds;
         // gradient step (Alg. 2): rho = b - A mu, r = A^T rho, t = A r
-        const bool first = zero && i == o.start_iter;
+        const bool first = zero && i == start;
         if (first) {
             // mu = 0: A mu = 0 exactly, so rho = 1/2 everywhere
             MomArgs ma = mom_args(ctx);
@@ -523,11 +519,102 @@ wnnc_status wnnc_orient(wnnc_ctx ctx, const wnnc_orient_opts *opts, const float 
             TravArgs ta = trav_args(ctx, wf);
             ta.src4 = tmp;
             ta.out4 = mu;
+            if (i == stop) ta.flips = flips;
             RETURN_IF(run_traverse(ctx, OP_G, TR_RESCALE, ta));
         }
     }
-    HIPCHK(launch_scatter_vec(mu, ctx->perm.p, mu_out, N, st));
     ctx->last_energy_count = count;
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_orient(wnnc_ctx ctx, const wnnc_orient_opts *opts, const float *mu0,
+                        float *mu_out) {
+    CHECK_CTX(ctx);
+    CHECK_BUILT(ctx);
+    if (!mu_out) return fail(WNNC_EINVAL, "null mu_out");
+    wnnc_orient_opts o = {40, 0.002f, 0.016f, 1, 0};
+    if (opts) o = *opts;
+    if (o.iters < 1) return fail(WNNC_EINVAL, "iters must be >= 1");
+    if (o.start_iter < 1 || o.start_iter > o.iters)
+        return fail(WNNC_EINVAL, "start_iter must be in 1..iters");
+    const int stop = o.stop_iter == 0 ? o.iters : o.stop_iter;
+    if (stop < o.start_iter || stop > o.iters)
+        return fail(WNNC_EINVAL, "stop_iter must be 0 or in start_iter..iters");
+    if (!finite_nonneg(o.w1) || !finite_nonneg(o.w2))
+        return fail(WNNC_EINVAL, "widths must be finite and >= 0");
+    const int64_t N = ctx->n;
+    hipStream_t st = ctx->stream;
+    const bool zero = mu0 == nullptr;
+    if (zero)
+        HIPCHK(launch_zero_f4(ctx->va.p, N, st));
+    else
+        HIPCHK(launch_gather_vec(mu0, ctx->perm.p, ctx->va.p, N, st));
+    RETURN_IF(run_iterations(ctx, o.iters, o.w1, o.w2, o.start_iter, stop, zero, nullptr));
+    HIPCHK(launch_scatter_vec(ctx->va.p, ctx->perm.p, mu_out, N, st));
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_warm_orient(wnnc_ctx ctx, const float *params, const wnnc_warm_opts *opts,
+                             float *mu_out, wnnc_warm_report *report) {
+    CHECK_CTX(ctx);
+    CHECK_BUILT(ctx);
+    if (!params || !mu_out) return fail(WNNC_EINVAL, "null pointer");
+    wnnc_warm_opts o = {8, 0.002f, 0.004f, 0.005f, 40, 0.016f};
+    if (opts) o = *opts;
+    if (o.iters < 1 || o.fallback_iters < 1) return fail(WNNC_EINVAL, "iteration counts must be >= 1");
+    if (!finite_nonneg(o.w1) || !finite_nonneg(o.w2) || !finite_nonneg(o.fallback_w2))
+        return fail(WNNC_EINVAL, "widths must be finite and >= 0");
+    if (!(o.max_disagree >= 0.0f && o.max_disagree <= 1.0f))
+        return fail(WNNC_EINVAL, "max_disagree must be in [0, 1]");
+    const int64_t N = ctx->n;
+    const int B = ctx->nclouds;
+    hipStream_t st = ctx->stream;
+    // 1. predicted unit normals (caller order, in vr reinterpreted as N*3)
+    HIPCHK(ctx->feat.ensure(N * kMlpIn));
+    HIPCHK(ctx->mlp_y.ensure(N * kMlpOut));
+    HIPCHK(ctx->nhat.ensure(N * 3));
+    HIPCHK(launch_knn_features(ctx, ctx->feat.p, nullptr));
+    HIPCHK(mlp_forward(ctx, params, ctx->feat.p, N, ctx->mlp_y.p));
+    HIPCHK(mlp_normals(ctx, ctx->mlp_y.p, N, ctx->nhat.p));
+    // 2. per-cloud least-squares scale beta = <A n, 1/2> / |A n|^2 at the
+    //    first width of the warm schedule; mu0 = beta n
+    {
+        MomArgs ma = mom_args(ctx);
+        ma.cn = ctx->nhat.p;
+        ma.out4 = ctx->vb.p;
+        RETURN_IF(run_moments(ctx, MOM_VEC_CALLER, ma));
+        TravArgs ta = trav_args(ctx, o.iters > 1 ? o.w2 : o.w1);
+        ta.src4 = ctx->vb.p;
+        ta.partial = ctx->partial.p;
+        RETURN_IF(run_traverse(ctx, OP_A, TR_SCALE, ta));
+        HIPCHK(launch_warm_scale(ctx, ctx->vb.p, ctx->va.p));
+    }
+    // 3. short schedule from mu0 with the self-check in its last iteration
+    HIPCHK(ctx->flip_ctr.ensure(B));
+    HIPCHK(hipMemsetAsync(ctx->flip_ctr.p, 0, (size_t)B * sizeof(unsigned long long), st));
+    RETURN_IF(run_iterations(ctx, o.iters, o.w1, o.w2, 1, o.iters, false, ctx->flip_ctr.p));
+    std::vector<unsigned long long> fl((size_t)B);
+    HIPCHK(hipMemcpyAsync(fl.data(), ctx->flip_ctr.p, (size_t)B * sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double worst = 0.0;
+    for (int c = 0; c < B; ++c) {
+        const double f = (double)fl[c] / (double)(ctx->offsets[c + 1] - ctx->offsets[c]);
+        worst = f > worst ? f : worst;
+    }
+    const bool fallback = worst > (double)o.max_disagree;
+    // 4. the plain method when the check fails
+    if (fallback) {
+        HIPCHK(launch_zero_f4(ctx->va.p, N, st));
+        RETURN_IF(run_iterations(ctx, o.fallback_iters, o.w1, o.fallback_w2, 1, o.fallback_iters,
+                                 true, nullptr));
+    }
+    HIPCHK(launch_scatter_vec(ctx->va.p, ctx->perm.p, mu_out, N, st));
+    if (report) {
+        report->iterations = o.iters + (fallback ? o.fallback_iters : 0);
+        report->fallback = fallback ? 1 : 0;
+        report->max_disagree = worst;
+    }
     return WNNC_OK;
 }
 
@@ -538,6 +625,45 @@ wnnc_status wnnc_normals(wnnc_ctx ctx, const float *mu, int64_t N, double scale,
     if (N < 1 || N > INT32_MAX) return fail(WNNC_EINVAL, "N = %lld out of range", (long long)N);
     if (!(isfinite(scale) && scale > 0.0)) return fail(WNNC_EINVAL, "scale must be finite and > 0");
     HIPCHK(launch_normals(mu, N, scale, n_out, area_out, ctx->stream));
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_knn_features(wnnc_ctx ctx, float *feat_out, int32_t *nbr_out) {
+    CHECK_CTX(ctx);
+    CHECK_BUILT(ctx);
+    if (!feat_out) return fail(WNNC_EINVAL, "null feat_out");
+    HIPCHK(launch_knn_features(ctx, feat_out, nbr_out));
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_mlp_forward(wnnc_ctx ctx, const float *params, const float *feat, int64_t N,
+                             float *normals_out) {
+    CHECK_CTX(ctx);
+    if (!params || !feat || !normals_out) return fail(WNNC_EINVAL, "null pointer");
+    if (N < 1 || N > INT32_MAX) return fail(WNNC_EINVAL, "N = %lld out of range", (long long)N);
+    HIPCHK(ctx->mlp_y.ensure(N * kMlpOut));
+    HIPCHK(mlp_forward(ctx, params, feat, N, ctx->mlp_y.p));
+    HIPCHK(mlp_normals(ctx, ctx->mlp_y.p, N, normals_out));
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_mlp_grad(wnnc_ctx ctx, const float *params, const float *feat,
+                          const float *labels, int64_t N, float *grad_out, double *loss_out) {
+    CHECK_CTX(ctx);
+    if (!params || !feat || !labels || !grad_out) return fail(WNNC_EINVAL, "null pointer");
+    if (N < 1 || N > INT32_MAX) return fail(WNNC_EINVAL, "N = %lld out of range", (long long)N);
+    HIPCHK(mlp_loss_grad(ctx, params, feat, labels, N, grad_out, loss_out));
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_mlp_adam(wnnc_ctx ctx, float *params, float *m, float *v, const float *grad,
+                          int step, float lr, float beta1, float beta2, float eps) {
+    CHECK_CTX(ctx);
+    if (!params || !m || !v || !grad) return fail(WNNC_EINVAL, "null pointer");
+    if (step < 1) return fail(WNNC_EINVAL, "step must be >= 1");
+    if (!(lr > 0.f && beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps > 0.f))
+        return fail(WNNC_EINVAL, "bad Adam hyperparameters");
+    HIPCHK(mlp_adam(ctx, params, m, v, grad, step, lr, beta1, beta2, eps));
     return WNNC_OK;
 }
 

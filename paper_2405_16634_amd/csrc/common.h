@@ -34,6 +34,18 @@ constexpr int kRecZero = 64;
 
 enum Op { OP_A = WNNC_OP_A, OP_AT = WNNC_OP_AT, OP_G = WNNC_OP_G };
 
+// Warm-start MLP: 48 -> 64 -> 64 -> 3; flat FP32 parameter vector, row-major
+// [in][out] weights each followed by its bias.
+constexpr int kMlpIn = 48, kMlpHidden = 64, kMlpOut = 3;
+constexpr int kOffW1 = 0;
+constexpr int kOffB1 = kOffW1 + kMlpIn * kMlpHidden;
+constexpr int kOffW2 = kOffB1 + kMlpHidden;
+constexpr int kOffB2 = kOffW2 + kMlpHidden * kMlpHidden;
+constexpr int kOffW3 = kOffB2 + kMlpHidden;
+constexpr int kOffB3 = kOffW3 + kMlpHidden * kMlpOut;
+constexpr int kMlpParams = kOffB3 + kMlpOut;  // 7491
+static_assert(kMlpParams == WNNC_MLP_PARAMS, "parameter count");
+
 // Moment-pass input modes.
 enum MomMode {
     MOM_VEC_SORTED = 0,    // nu = src4[i] (sorted float4)
@@ -55,6 +67,7 @@ enum TravMode {
     TR_R = 2,           // A^T: r (sorted float4), block partial of |r|^2
     TR_TSUM = 3,        // A: block partial of s^2 only
     TR_RESCALE = 4,     // G: mu <- G |mu| / |G| (sorted float4)
+    TR_SCALE = 5,       // A: block partials of s and s^2 (warm-start scale)
 };
 
 struct MomArgs {
@@ -97,6 +110,8 @@ struct TravArgs {
     float4 *out4;            // TR_R / TR_RESCALE output
     double *partial;         // per-task partial sums (indexed by task_slot)
     unsigned long long *pairs;  // pair counter (counting variant)
+    unsigned long long *flips;  // TR_RESCALE: per cloud, updates against mu (or null)
+    const int32_t *cloud;    // cloud of each sorted point (for flips)
     const int4 *tasks;       // per wavefront: first, last target; root, end node
     const int32_t *task_slot;
     int ntasks;
@@ -195,6 +210,15 @@ struct wnnc_ctx_s {
     DevBuf<double> energy;
     int last_energy_count = 0;
     DevBuf<unsigned long long> pair_ctr;  // 3 counters
+
+    // warm start: neighbours, features, MLP activations and scratch
+    DevBuf<int32_t> knn_idx;       // n * 16 sorted neighbour positions
+    DevBuf<float> knn_d2;          // n * 16 squared distances
+    DevBuf<float> feat;            // n * 48 features (caller order)
+    DevBuf<float> mlp_h1, mlp_h2, mlp_y, mlp_dy, mlp_d1, mlp_d2, mlp_part;
+    DevBuf<double> mlp_lpart;
+    DevBuf<unsigned long long> flip_ctr;  // per cloud
+    DevBuf<float> nhat;            // n * 3 predicted unit normals (caller order)
 
     // statistics
     int64_t calls[3] = {0, 0, 0};

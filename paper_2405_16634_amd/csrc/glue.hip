@@ -44,6 +44,50 @@ hipError_t launch_alpha(wnnc_ctx_s *ctx, bool first, double *energy_row) {
     return hipGetLastError();
 }
 
+// beta_c = (1/2) sum s / sum s^2 over cloud c (the least-squares uniform
+// scale of the predicted normals against b = 1/2), 0 if sum s^2 = 0.
+__global__ __launch_bounds__(256) void k_warm_beta(const double *__restrict__ partial, int ntasks,
+                                                   const int32_t *__restrict__ task_lo,
+                                                   double *__restrict__ beta) {
+    __shared__ double sh[2][256];
+    const int c = blockIdx.x;
+    double a = 0.0, b = 0.0;
+    for (int i = task_lo[c] + threadIdx.x; i < task_lo[c + 1]; i += 256) {
+        a += partial[i];
+        b += partial[ntasks + i];
+    }
+    sh[0][threadIdx.x] = a;
+    sh[1][threadIdx.x] = b;
+    __syncthreads();
+    for (int d = 128; d > 0; d >>= 1) {
+        if (threadIdx.x < d) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + d];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + d];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) beta[c] = sh[1][0] > 0.0 ? 0.5 * sh[0][0] / sh[1][0] : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_warm_apply(const float4 *__restrict__ nrm,
+                                                    const int32_t *__restrict__ cloud,
+                                                    const double *__restrict__ beta, int64_t n,
+                                                    float4 *__restrict__ mu) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float b = (float)beta[cloud[i]];
+    const float4 v = nrm[i];
+    mu[i] = make_float4(b * v.x, b * v.y, b * v.z, 0.f);
+}
+
+hipError_t launch_warm_scale(wnnc_ctx_s *ctx, const float4 *n_sorted, float4 *mu0) {
+    hipLaunchKernelGGL(k_warm_beta, dim3(ctx->nclouds), dim3(256), 0, ctx->stream, ctx->partial.p,
+                       ctx->ntasks, ctx->task_lo.p, ctx->scalars.p);
+    hipLaunchKernelGGL(k_warm_apply, dim3((unsigned)((ctx->n + 255) / 256)), dim3(256), 0,
+                       ctx->stream, n_sorted, ctx->cloud_of.p, ctx->scalars.p, ctx->n, mu0);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void k_zero_f4(float4 *p, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = make_float4(0.f, 0.f, 0.f, 0.f);

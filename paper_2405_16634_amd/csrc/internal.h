@@ -40,4 +40,16 @@ hipError_t launch_scatter_vec(const float4 *src, const uint32_t *perm, float *ds
 hipError_t launch_normals(const float *mu, int64_t n, double scale, float *nrm, float *area,
                           hipStream_t st);
 
+// Warm start (knn.hip, mlp.hip).
+hipError_t launch_knn_features(wnnc_ctx_s *ctx, float *feat, int32_t *nbr_caller);
+hipError_t mlp_forward(wnnc_ctx_s *ctx, const float *P, const float *X, int64_t n, float *Y);
+hipError_t mlp_normals(wnnc_ctx_s *ctx, const float *Y, int64_t n, float *out);
+hipError_t mlp_loss_grad(wnnc_ctx_s *ctx, const float *P, const float *X, const float *L,
+                         int64_t n, float *grad, double *loss);
+// mu0[i] = beta_c n[i] (sorted) with beta_c = (1/2) sum s / sum s^2 over
+// cloud c from the TR_SCALE partials.
+hipError_t launch_warm_scale(wnnc_ctx_s *ctx, const float4 *n_sorted, float4 *mu0);
+hipError_t mlp_adam(wnnc_ctx_s *ctx, float *P, float *m, float *v, const float *g, int step,
+                    float lr, float b1, float b2, float eps);
+
 }  // namespace wnnc

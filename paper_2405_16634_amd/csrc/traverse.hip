@@ -190,7 +190,8 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
     }
 
     // epilogues
-    double e = 0.0;
+    double e = 0.0, e2 = 0.0;
+    unsigned nflip = 0;
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
         const int t = first + k * kWave + lane;
@@ -216,6 +217,10 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
         } else if (MODE == TR_TSUM) {
             const double tv = (double)(s[k] * kInv4Pi);
             e += tv * tv;
+        } else if (MODE == TR_SCALE) {
+            const double tv = (double)(s[k] * kInv4Pi);
+            e += tv;
+            e2 += tv * tv;
         } else if (MODE == TR_RESCALE) {
             const float4 mu = a.src4[t];
             const double g2 = (double)gx[k] * gx[k] + (double)gy[k] * gy[k] + (double)gz[k] * gz[k];
@@ -226,6 +231,21 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
                 o = make_float4((float)(gx[k] * f), (float)(gy[k] * f), (float)(gz[k] * f), 0.f);
             }
             a.out4[t] = o;
+            if ((double)mu.x * gx[k] + (double)mu.y * gy[k] + (double)mu.z * gz[k] < 0.0) ++nflip;
+        }
+    }
+    if (MODE == TR_RESCALE && a.flips) {
+        unsigned tot = nflip;
+#pragma unroll
+        for (int d = kWave / 2; d > 0; d >>= 1) tot += __shfl_xor(tot, d, kWave);
+        if (lane == 0 && tot) atomicAdd(a.flips + a.cloud[first], (unsigned long long)tot);
+    }
+    if (MODE == TR_SCALE) {
+        e = wave_sum(e);
+        e2 = wave_sum(e2);
+        if (lane == 0) {
+            a.partial[a.task_slot[wave]] = e;
+            a.partial[a.ntasks + a.task_slot[wave]] = e2;
         }
     }
     if (MODE == TR_RHO || MODE == TR_R || MODE == TR_TSUM) {
@@ -270,6 +290,7 @@ hipError_t launch_traverse(wnnc_ctx_s *ctx, Op op, TravMode mode, bool count, co
         if (mode == TR_OUT_CALLER) return launch_one<OP_A, TR_OUT_CALLER>(count, tpl, a, st);
         if (mode == TR_RHO) return launch_one<OP_A, TR_RHO>(count, tpl, a, st);
         if (mode == TR_TSUM) return launch_one<OP_A, TR_TSUM>(count, tpl, a, st);
+        if (mode == TR_SCALE) return launch_one<OP_A, TR_SCALE>(count, tpl, a, st);
     } else if (op == OP_AT) {
         if (mode == TR_OUT_CALLER) return launch_one<OP_AT, TR_OUT_CALLER>(count, tpl, a, st);
         if (mode == TR_R) return launch_one<OP_AT, TR_R>(count, tpl, a, st);
