@@ -86,6 +86,38 @@ def cpu_baseline(cloud, w: float, c: float):
     }
 
 
+def warm_start_section(ctx, w, mu_plain, stream, iters, w1, w2):
+    """Warm-started orientation on the same cloud and tree against the plain
+    run (mu_plain), with the trained network in the package data."""
+    import torch
+    from paper_2405_16634_amd import warmstart as ws
+    if not os.path.exists(ws.DEFAULT_WEIGHTS):
+        return None
+    params = ws.load_params(ws.DEFAULT_WEIGHTS)
+    out = torch.empty_like(mu_plain)
+    w.wnnc_warm_orient(ctx.handle, params, out)  # warm-up
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e2 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    w.wnnc_orient(ctx.handle, mu_plain, None, iters, w1, w2)
+    e1.record(stream)
+    rep = w.wnnc_warm_orient(ctx.handle, params, out)
+    e2.record(stream)
+    torch.cuda.synchronize()
+    a = mu_plain.cpu().numpy().astype(np.float64)
+    b = out.cpu().numpy().astype(np.float64)
+    ok = (np.linalg.norm(a, axis=1) > 0) & (np.linalg.norm(b, axis=1) > 0)
+    flip = float(((a[ok] * b[ok]).sum(1) <= 0).mean())
+    t_plain, t_warm = e0.elapsed_time(e1), e1.elapsed_time(e2)
+    return {"plain_ms": round(t_plain, 3), "warm_ms": round(t_warm, 3),
+            "speedup": round(t_plain / t_warm, 3), "plain_iterations": iters,
+            "warm_iterations": rep["iterations"], "fallback": rep["fallback"],
+            "self_check_max_disagree": rep["max_disagree"], "flip_vs_plain": flip,
+            "equal_accuracy": flip <= 1e-3}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +154,12 @@ def main():
         w.wnnc_build(ctx.handle, Pn, c, depth)
         w.wnnc_orient(ctx.handle, mu, None, args.iters, w1, w2)
         w.wnnc_normals(ctx.handle, mu, cs[1], nrm)
+
+    # tile shape: the autotuner times each on this tree (results do not
+    # depend on it); later builds keep the choice
+    cs0 = w.wnnc_normalize(ctx.handle, P, Pn)
+    w.wnnc_build(ctx.handle, Pn, c, depth)
+    tile_ms = ctx.autotune(w1)
 
     # pair counts: one run with the counting kernels (same decisions)
     ctx.set_flags(w.FLAG_COUNT_PAIRS)
@@ -194,6 +232,8 @@ def main():
                 "avg_launch_ms": round(d["avg_ms"], 4),
                 "flop_per_launch": round(d["pairs_per_launch"] * FLOPS_PER_PAIR[{"A": 0, "AT": 1, "G": 2}[dom]])}
 
+    warm = warm_start_section(ctx, w, mu, stream, args.iters, w1, w2)
+
     nrm_h = nrm.cpu().numpy()
     ok = np.isfinite(cloud.normals).all(axis=1)
     pco = float(((nrm_h[ok] * cloud.normals[ok]).sum(1) > 0).mean())
@@ -222,11 +262,14 @@ def main():
         "pairs_per_kind": {KIND[k]: int(pairs[k]) for k in range(3)},
         "operator_calls": {KIND[k]: int(calls_per_run[k]) for k in range(3)},
         "traversal": per_kind,
+        "tile": ctx.tile(),
+        "tile_autotune_ms": {str(k): round(v, 4) for k, v in tile_ms.items()},
         "moments_ms_per_step": round(st["moments_ms"] / args.steps, 3),
         "host_wall_s_per_step": round((t_host1 - t_host0) / args.steps, 4),
         "accuracy_vs_generator": {"P_co": round(pco, 5), "AE_pcd": round(ae, 6)},
         "context_paper_rtx3090_s": {"N=50k": 1.25, "N=500k": 31.63},
         "roofline": roofline,
+        "warm_start": warm,
     }
     if rank == 0 and not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cloud, w1, c)

@@ -21,6 +21,9 @@ ARCH = os.environ.get("WNNC_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    # only the explicit fmaf() calls fuse: results then do not depend on how
+    # the compiler shapes each template instance (bit-identical tile shapes)
+    "-ffp-contract=off",
     # keep the compiler from emitting packed FP32 (v_pk_*_f32) instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function",

@@ -88,8 +88,9 @@ __global__ __launch_bounds__(256) void k_knn(const float4 *__restrict__ pts,
         cd.d[k] = FLT_MAX;
         cd.j[k] = -1;
     }
-    // seed with Morton-order neighbours
-    for (int j = max(lo, t - kK / 2 - 1); j <= min(hi - 1, t + kK / 2 + 1); ++j) {
+    // seed with Morton-order neighbours; the walk below skips them
+    const int s_lo = max(lo, t - kK / 2 - 1), s_hi = min(hi - 1, t + kK / 2 + 1);
+    for (int j = s_lo; j <= s_hi; ++j) {
         if (j == t) continue;
         const float4 q = pts[j];
         const float dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
@@ -107,7 +108,7 @@ __global__ __launch_bounds__(256) void k_knn(const float4 *__restrict__ pts,
         }
         if (tp.w & kRecLeaf) {
             for (int j = tp.y; j < tp.z; ++j) {
-                if (j == t) continue;
+                if (j >= s_lo && j <= s_hi) continue;  // seeded (or the target)
                 const float4 q = pts[j];
                 const float dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
                 offer(cd, fmaf(dx, dx, fmaf(dy, dy, dz * dz)), j);

@@ -38,16 +38,18 @@ __device__ inline float ldc_f(const float *p) {
     return *(const __attribute__((address_space(4))) float *)p;
 }
 
-constexpr float kInv4Pi = 0.0795774715459476678844f;
+constexpr double kInv4Pi = 0.0795774715459476678844;  // 1 / (4 pi)
 
 // Pair term without the 1/(4 pi) factor.  d = target - source, r2 = |d|^2.
 //   A  : -(d . nu) / r^3
 //   A^T: nu d / r^3                      (nu scalar, in v.x)
 //   G  : nu / r^3 - 3 (d . nu) d / r^5
-// Kept only when r >= w and r > 0 (Sec. 3.4).
+// Kept only when r >= w and r > 0 (Sec. 3.4).  The term is formed in FP32
+// and added to an FP64 per-target sum (FP64 adds issue at the FP32 rate on
+// this chip), so the sum's rounding does not grow with the number of terms.
 template <int OP>
 __device__ inline void pair_term(float dx, float dy, float dz, float r2, float4 v, float w2,
-                                 float &s, float &gx, float &gy, float &gz) {
+                                 double &s, double &gx, double &gy, double &gz) {
     const bool keep = (r2 >= w2) && (r2 > 0.0f);
     // hardware reciprocal square root (about 1 ulp); r2 below the smallest
     // normal only occurs for pairs that the cutoff removes when w > 0
@@ -57,18 +59,18 @@ __device__ inline void pair_term(float dx, float dy, float dz, float r2, float4 
     if (OP == OP_A) {
         const float dm = fmaf(dx, v.x, fmaf(dy, v.y, dz * v.z));
         const float t = -dm * ri3;
-        s += keep ? t : 0.0f;
+        s += keep ? (double)t : 0.0;
     } else if (OP == OP_AT) {
         const float f = v.x * ri3;
-        gx += keep ? f * dx : 0.0f;
-        gy += keep ? f * dy : 0.0f;
-        gz += keep ? f * dz : 0.0f;
+        gx += keep ? (double)(f * dx) : 0.0;
+        gy += keep ? (double)(f * dy) : 0.0;
+        gz += keep ? (double)(f * dz) : 0.0;
     } else {
         const float dm = fmaf(dx, v.x, fmaf(dy, v.y, dz * v.z));
         const float c5 = 3.0f * dm * (ri3 * ri2);
-        gx += keep ? fmaf(v.x, ri3, -c5 * dx) : 0.0f;
-        gy += keep ? fmaf(v.y, ri3, -c5 * dy) : 0.0f;
-        gz += keep ? fmaf(v.z, ri3, -c5 * dz) : 0.0f;
+        gx += keep ? (double)fmaf(v.x, ri3, -c5 * dx) : 0.0;
+        gy += keep ? (double)fmaf(v.y, ri3, -c5 * dy) : 0.0;
+        gz += keep ? (double)fmaf(v.z, ri3, -c5 * dz) : 0.0;
     }
 }
 
@@ -103,7 +105,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
     const int first = task.x, last = task.y, root = task.z, rend = task.w;
 
     float tx[TPL], ty[TPL], tz[TPL];
-    float s[TPL], gx[TPL], gy[TPL], gz[TPL];
+    double s[TPL], gx[TPL], gy[TPL], gz[TPL];
     bool valid[TPL];
     uint32_t mlo[TPL], mhi[TPL];
     uint32_t cnt = 0;
@@ -116,7 +118,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
             const float4 p = a.pts[t];
             tx[k] = p.x, ty[k] = p.y, tz[k] = p.z;
         }
-        s[k] = gx[k] = gy[k] = gz[k] = 0.f;
+        s[k] = gx[k] = gy[k] = gz[k] = 0.0;
         // mask stack: lane d holds the mask of group-k lanes inside at depth d
         const unsigned long long act0 = __ballot(valid[k]);
         mlo[k] = lane == 0 ? (uint32_t)act0 : 0u;
@@ -199,31 +201,32 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
         if (MODE == TR_OUT_CALLER) {
             const int64_t j = a.perm[t];
             if (OP == OP_A) {
-                a.out[j] = s[k] * kInv4Pi;
+                a.out[j] = (float)(s[k] * kInv4Pi);
             } else {
-                const float sg = OP == OP_G ? -kInv4Pi : kInv4Pi;  // grad F = -G
-                a.out[3 * j] = gx[k] * sg;
-                a.out[3 * j + 1] = gy[k] * sg;
-                a.out[3 * j + 2] = gz[k] * sg;
+                const double sg = OP == OP_G ? -kInv4Pi : kInv4Pi;  // grad F = -G
+                a.out[3 * j] = (float)(gx[k] * sg);
+                a.out[3 * j + 1] = (float)(gy[k] * sg);
+                a.out[3 * j + 2] = (float)(gz[k] * sg);
             }
         } else if (MODE == TR_RHO) {
-            const float rho = 0.5f - s[k] * kInv4Pi;
+            const float rho = (float)(0.5 - s[k] * kInv4Pi);
             a.rho[t] = rho;
             e += (double)rho * (double)rho;
         } else if (MODE == TR_R) {
-            const float rx = gx[k] * kInv4Pi, ry = gy[k] * kInv4Pi, rz = gz[k] * kInv4Pi;
+            const float rx = (float)(gx[k] * kInv4Pi), ry = (float)(gy[k] * kInv4Pi),
+                        rz = (float)(gz[k] * kInv4Pi);
             a.out4[t] = make_float4(rx, ry, rz, 0.f);
             e += (double)rx * rx + (double)ry * ry + (double)rz * rz;
         } else if (MODE == TR_TSUM) {
-            const double tv = (double)(s[k] * kInv4Pi);
+            const double tv = (double)(float)(s[k] * kInv4Pi);
             e += tv * tv;
         } else if (MODE == TR_SCALE) {
-            const double tv = (double)(s[k] * kInv4Pi);
+            const double tv = (double)(float)(s[k] * kInv4Pi);
             e += tv;
             e2 += tv * tv;
         } else if (MODE == TR_RESCALE) {
             const float4 mu = a.src4[t];
-            const double g2 = (double)gx[k] * gx[k] + (double)gy[k] * gy[k] + (double)gz[k] * gz[k];
+            const double g2 = gx[k] * gx[k] + gy[k] * gy[k] + gz[k] * gz[k];
             float4 o = mu;
             if (g2 > 0.0 && g2 <= DBL_MAX) {
                 const double mn = sqrt((double)mu.x * mu.x + (double)mu.y * mu.y + (double)mu.z * mu.z);
