@@ -262,8 +262,8 @@ def main():
         "pairs_per_kind": {KIND[k]: int(pairs[k]) for k in range(3)},
         "operator_calls": {KIND[k]: int(calls_per_run[k]) for k in range(3)},
         "traversal": per_kind,
-        "tile": ctx.tile(),
-        "tile_autotune_ms": {str(k): round(v, 4) for k, v in tile_ms.items()},
+        "tile": {"targets_per_lane": ctx.tile(), "prefetch": ctx.prefetch()},
+        "tile_autotune_ms": {f"tpl{k[0]}_pf{k[1]}": round(v, 4) for k, v in tile_ms.items()},
         "moments_ms_per_step": round(st["moments_ms"] / args.steps, 3),
         "host_wall_s_per_step": round((t_host1 - t_host0) / args.steps, 4),
         "accuracy_vs_generator": {"P_co": round(pco, 5), "AE_pcd": round(ae, 6)},

@@ -103,7 +103,7 @@ typedef struct {
     double moments_ms;      /* summed moment-pass time (WNNC_FLAG_TIME_KERNELS) */
     double build_ms;        /* last wnnc_build, device time (always timed) */
     int64_t n_clouds;       /* clouds in the current tree (1 for wnnc_build) */
-    int64_t tile;           /* targets per traversal lane (wnnc_set_tile) */
+    int64_t tile;           /* tile shape (wnnc_set_tile) | prefetch << 8 */
 } wnnc_stats_t;
 
 /* Create a context on HIP device `device`, enqueuing on `stream`
@@ -158,9 +158,14 @@ wnnc_status wnnc_build_batched(wnnc_ctx ctx, const float *P, const int64_t *offs
 wnnc_status wnnc_set_tile(wnnc_ctx ctx, int tpl);
 wnnc_status wnnc_get_tile(wnnc_ctx ctx, int *tpl);
 
+/* Software-pipelined node walk in the traversal (prefetch of both successor
+ * records); results do not depend on it.  Default off. */
+wnnc_status wnnc_set_prefetch(wnnc_ctx ctx, int on);
+
 /* Autotuner: times one adjoint-operator traversal at width w for every tile
- * shape on the current tree and keeps the fastest.  ms_out (host, 3
- * doubles, may be NULL) receives the times for tpl = 1, 2, 4.
+ * shape and prefetch setting on the current tree and keeps the fastest.
+ * ms_out (host, 6 doubles, may be NULL) receives the times for
+ * (tpl, prefetch) = (1,0), (1,1), (2,0), (2,1), (4,0), (4,1).
  * Synchronizes. */
 wnnc_status wnnc_autotune(wnnc_ctx ctx, float w, double *ms_out);
 

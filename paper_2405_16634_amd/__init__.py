@@ -32,7 +32,7 @@ EXPORTED = [
     "wnnc_moments_export", "wnnc_normals", "wnnc_last_error", "wnnc_version",
     "wnnc_normalize_batched", "wnnc_build_batched", "wnnc_set_tile", "wnnc_get_tile",
     "wnnc_autotune", "wnnc_knn_features", "wnnc_mlp_forward", "wnnc_mlp_grad", "wnnc_mlp_adam",
-    "wnnc_warm_orient",
+    "wnnc_warm_orient", "wnnc_set_prefetch",
 ]
 MLP_PARAMS = 7491
 
@@ -112,6 +112,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "wnnc_set_tile": [vp, ctypes.c_int],
         "wnnc_get_tile": [vp, P(ctypes.c_int)],
         "wnnc_autotune": [vp, f32, P(dbl)],
+        "wnnc_set_prefetch": [vp, ctypes.c_int],
         "wnnc_knn_features": [vp, vp, vp],
         "wnnc_mlp_forward": [vp, vp, vp, i64, vp],
         "wnnc_mlp_grad": [vp, vp, vp, vp, i64, vp, P(dbl)],
@@ -226,12 +227,16 @@ def wnnc_get_tile(ctx) -> int:
     return v.value
 
 
+def wnnc_set_prefetch(ctx, on: bool) -> None:
+    _check(load_library().wnnc_set_prefetch(ctx, 1 if on else 0))
+
+
 def wnnc_autotune(ctx, w: float = 0.002):
-    """Time every tile shape on the current tree and keep the fastest.
-    Returns {tpl: ms}."""
-    ms = (ctypes.c_double * 3)()
+    """Time every (tile shape, prefetch) on the current tree and keep the
+    fastest.  Returns {(tpl, prefetch): ms}."""
+    ms = (ctypes.c_double * 6)()
     _check(load_library().wnnc_autotune(ctx, float(w), ms))
-    return {1: ms[0], 2: ms[1], 4: ms[2]}
+    return {(t, p): ms[2 * k + p] for k, t in enumerate((1, 2, 4)) for p in (0, 1)}
 
 
 def wnnc_build(ctx, P, c: float = 2.0, max_depth: int = 15) -> None:
@@ -434,8 +439,14 @@ class Context:
     def set_tile(self, tpl: int) -> None:
         wnnc_set_tile(self._h, tpl)
 
+    def set_prefetch(self, on: bool) -> None:
+        wnnc_set_prefetch(self._h, on)
+
     def tile(self) -> int:
         return wnnc_get_tile(self._h)
+
+    def prefetch(self) -> bool:
+        return bool((wnnc_stats(self._h)["tile"] >> 8) & 1)
 
     def autotune(self, w: float = 0.002):
         return wnnc_autotune(self._h, w)

@@ -83,6 +83,10 @@ MomArgs mom_args(wnnc_ctx_s *c) {
     a.alpha = c->scalars.p;
     a.n = (int)c->n;
     a.n_strad = c->n_strad;
+    for (int d = 0; d < 16; ++d) {
+        const double t = (double)c->c * ldexp(2.0, -d);
+        a.thr2[d] = (float)(t * t);
+    }
     return a;
 }
 
@@ -99,6 +103,7 @@ TravArgs trav_args(wnnc_ctx_s *c, float w) {
     a.task_slot = c->task_slot.p;
     a.ntasks = c->ntasks;
     a.tpl = c->tpl;
+    a.prefetch = c->prefetch;
     a.n = (int)c->n;
     a.m = (int)c->m;
     a.w2 = (float)((double)w * (double)w);
@@ -361,47 +366,57 @@ wnnc_status wnnc_get_tile(wnnc_ctx ctx, int *tpl) {
     return WNNC_OK;
 }
 
+wnnc_status wnnc_set_prefetch(wnnc_ctx ctx, int on) {
+    CHECK_CTX(ctx);
+    ctx->prefetch = on ? 1 : 0;
+    return WNNC_OK;
+}
+
 wnnc_status wnnc_autotune(wnnc_ctx ctx, float w, double *ms_out) {
     CHECK_CTX(ctx);
     CHECK_BUILT(ctx);
     if (!finite_nonneg(w)) return fail(WNNC_EINVAL, "w must be finite and >= 0");
-    // attribute: mu = 1/2 per point along a fixed direction would cancel in
-    // G; use the constant scalar 1/2 through A^T, whose traversal visits the
-    // same nodes as a smooth mu would (all weights positive)
+    // the adjoint traversal with the constant scalar 1/2: every weight is
+    // positive, so it visits the nodes a smooth attribute would
     MomArgs ma = mom_args(ctx);
     ma.outs = ctx->rho.p;
     RETURN_IF(run_moments(ctx, MOM_CONST_HALF, ma));
     const int cand[3] = {1, 2, 4};
     double best_ms = 1e300;
-    int best = ctx->tpl;
+    int best = ctx->tpl, best_pf = ctx->prefetch;
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     for (int k = 0; k < 3; ++k) {
         hipError_t e = make_tasks(ctx, cand[k]);
         if (e != hipSuccess) return fail(WNNC_EDEVICE, "tasks: %s", hipGetErrorString(e));
-        TravArgs ta = trav_args(ctx, w);
-        ta.srcs = ctx->rho.p;
-        ta.out4 = ctx->vr.p;
-        ta.partial = ctx->partial.p + ctx->ntasks;
-        double t = 0.0;
-        for (int rep = 0; rep < 2; ++rep) {  // first launch warms the caches
-            HIPCHK(hipEventRecord(e0, ctx->stream));
-            HIPCHK(launch_traverse(ctx, OP_AT, TR_R, false, ta));
-            HIPCHK(hipEventRecord(e1, ctx->stream));
-            HIPCHK(hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-            t = ms;
-        }
-        if (ms_out) ms_out[k] = t;
-        if (t < best_ms) {
-            best_ms = t;
-            best = cand[k];
+        for (int pf = 0; pf < 2; ++pf) {
+            ctx->prefetch = pf;
+            TravArgs ta = trav_args(ctx, w);
+            ta.srcs = ctx->rho.p;
+            ta.out4 = ctx->vr.p;
+            ta.partial = ctx->partial.p + ctx->ntasks;
+            double t = 0.0;
+            for (int rep = 0; rep < 2; ++rep) {  // first launch warms the caches
+                HIPCHK(hipEventRecord(e0, ctx->stream));
+                HIPCHK(launch_traverse(ctx, OP_AT, TR_R, false, ta));
+                HIPCHK(hipEventRecord(e1, ctx->stream));
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                t = ms;
+            }
+            if (ms_out) ms_out[2 * k + pf] = t;
+            if (t < best_ms) {
+                best_ms = t;
+                best = cand[k];
+                best_pf = pf;
+            }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    ctx->prefetch = best_pf;
     hipError_t e = make_tasks(ctx, best);
     if (e != hipSuccess) return fail(WNNC_EDEVICE, "tasks: %s", hipGetErrorString(e));
     return WNNC_OK;
@@ -709,7 +724,7 @@ wnnc_status wnnc_stats(wnnc_ctx ctx, wnnc_stats_t *out) {
     out->moments_ms = ctx->mom_ms;
     out->build_ms = ctx->build_ms;
     out->n_clouds = ctx->built ? ctx->nclouds : 0;
-    out->tile = ctx->tpl;
+    out->tile = ctx->tpl | (ctx->prefetch << 8);
     return WNNC_OK;
 }
 
@@ -772,19 +787,20 @@ wnnc_status wnnc_moments_export(wnnc_ctx ctx, const float *nu, int dim, float *x
         ma.outs = ctx->rho.p;
         RETURN_IF(run_moments(ctx, MOM_SCALAR_CALLER, ma));
     }
-    std::vector<float4> mom((size_t)(2 * ctx->m));
+    std::vector<float4> mom((size_t)(kRecStride * ctx->m));
     std::vector<float> wv((size_t)ctx->m);
-    HIPCHK(hipMemcpyAsync(mom.data(), ctx->mom.p, (size_t)(2 * ctx->m) * sizeof(float4),
+    HIPCHK(hipMemcpyAsync(mom.data(), ctx->mom.p, (size_t)(kRecStride * ctx->m) * sizeof(float4),
                           hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipMemcpyAsync(wv.data(), ctx->wbuf.p, (size_t)ctx->m * sizeof(float),
                           hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     for (int64_t k = 0; k < ctx->m; ++k) {
-        const float4 p = mom[2 * k], v = mom[2 * k + 1];
+        const float4 p = mom[kRecStride * k], v = mom[kRecStride * k + 1];
+        const float4 lo = mom[kRecStride * k + 2];
         if (xB) {
-            xB[3 * k] = p.x;
-            xB[3 * k + 1] = p.y;
-            xB[3 * k + 2] = p.z;
+            xB[3 * k] = (float)((double)p.x + (double)lo.x);
+            xB[3 * k + 1] = (float)((double)p.y + (double)lo.y);
+            xB[3 * k + 2] = (float)((double)p.z + (double)lo.z);
         }
         if (W) W[k] = wv[k];
         if (nuB) {

@@ -23,11 +23,16 @@ constexpr int kMaxDepth = 15;    // 15 levels below the root: 45-bit Morton keys
 __host__ __device__ inline int topo_depth(int meta) { return meta & 15; }
 __host__ __device__ inline int topo_leaf(int meta) { return (meta >> 4) & 1; }
 
-// Node record written by every moment pass and read by the traversal, two
-// 16-byte halves per node (one 32-byte scalar load):
-//   [0] x_B.x, x_B.y, x_B.z, flags (int bits)
+// Node record written by every moment pass and read by the traversal, three
+// 16-byte parts per node (scalar loads):
+//   [0] hi(x_B).x, .y, .z, flags (int bits)
 //   [1] nu_B (3 floats; a scalar attribute in .x), skip (int bits)
+//   [2] lo(x_B).x, .y, .z, (c * width)^2 (the acceptance threshold)
+// with x_B = hi + lo to about 2^-48 (hi = FP32 rounding of the FP64 x_B,
+// lo = FP32 rounding of the rest), so that target - x_B keeps full FP32
+// precision when the target is close to the node.
 // flags = depth | leaf << 4 | single-point leaf << 5 | zero weight << 6.
+constexpr int kRecStride = 3;
 constexpr int kRecLeaf = 16;
 constexpr int kRecSingle = 32;
 constexpr int kRecZero = 64;
@@ -94,6 +99,7 @@ struct MomArgs {
     double *tail;            // 8 doubles per straddler
     float4 *mom;             // node records, 2 float4 per node
     float *wout;             // optional: W = sum |nu| per node (inspection)
+    float thr2[16];          // (c * 2^(1-d))^2 per depth d, copied into records
     int n;
     int n_strad;
 };
@@ -116,6 +122,7 @@ struct TravArgs {
     const int32_t *task_slot;
     int ntasks;
     int tpl;                 // target groups of 64 per wavefront (1, 2, 4)
+    int prefetch;            // software-pipelined node walk
     int n, m;
     float w2;
     float thr2[16];          // (c * 2^(1-d))^2 per depth d
@@ -197,6 +204,7 @@ struct wnnc_ctx_s {
     DevBuf<int32_t> cloud_of;      // n: cloud of each sorted point
     // wavefront tasks for the current tile shape
     int tpl = 1;
+    int prefetch = 0;
     int ntasks = 0;
     DevBuf<int4> tasks;
     DevBuf<int32_t> task_slot;

@@ -25,15 +25,20 @@ __device__ inline void write_moment(const MomArgs &a, int node, const int4 t, co
     const double W = s[0];
     int flags = t.w & 31;  // depth | leaf << 4
     if ((flags & kRecLeaf) && t.z - t.y == 1) flags |= kRecSingle;
-    float4 p;
+    float4 p, lo = make_float4(0.f, 0.f, 0.f, a.thr2[t.w & 15]);
     if (W > 0.0) {
-        p = make_float4((float)(s[1] / W), (float)(s[2] / W), (float)(s[3] / W),
-                        __int_as_float(flags));
+        const double x = s[1] / W, y = s[2] / W, z = s[3] / W;
+        const float hx = (float)x, hy = (float)y, hz = (float)z;
+        p = make_float4(hx, hy, hz, __int_as_float(flags));
+        lo = make_float4((float)(x - (double)hx), (float)(y - (double)hy), (float)(z - (double)hz),
+                         lo.w);
     } else {
         p = make_float4(0.f, 0.f, 0.f, __int_as_float(flags | kRecZero));
     }
-    a.mom[2 * node] = p;
-    a.mom[2 * node + 1] = make_float4((float)s[4], (float)s[5], (float)s[6], __int_as_float(t.x));
+    float4 *rec = a.mom + (int64_t)kRecStride * node;
+    rec[0] = p;
+    rec[1] = make_float4((float)s[4], (float)s[5], (float)s[6], __int_as_float(t.x));
+    rec[2] = lo;
     if (a.wout) a.wout[node] = W > 0.0 ? fmaxf((float)W, FLT_MIN) : 0.f;
 }
 

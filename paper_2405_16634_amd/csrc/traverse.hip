@@ -37,6 +37,9 @@ __device__ inline float4 ldc_f4(const float4 *p) {
 __device__ inline float ldc_f(const float *p) {
     return *(const __attribute__((address_space(4))) float *)p;
 }
+__device__ inline int ldc_i(const int *p) {
+    return *(const __attribute__((address_space(4))) int *)p;
+}
 
 constexpr double kInv4Pi = 0.0795774715459476678844;  // 1 / (4 pi)
 
@@ -89,10 +92,17 @@ __device__ inline unsigned long long read_mask(uint32_t lo, uint32_t hi, int dep
 // (group k holds targets first + 64k + lane) walk the node range
 // [root, end) of their cloud together.  Each group keeps its own mask stack
 // and Alg. 4 decisions; the groups share the node loads and the control.
-template <int OP, int MODE, bool COUNT, int TPL>
+// PF: software pipelining of the node walk.  The record of a node holds its
+// successors' indices (the first child is the next node, the subtree end is
+// the skip pointer), so both successor records are loaded as soon as the
+// current one is known and the loads overlap the work on the current node;
+// the one taken becomes the next current record.
+template <int OP, int MODE, bool COUNT, int TPL, bool PF>
 __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int wv = threadIdx.x / kWave;
+    // the wavefront index is uniform; say so, so that the node walk below is
+    // a scalar loop with scalar loads
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
     // contiguous range of tasks (Morton-ordered targets) so its L2 sees one
     // region of the tree.
@@ -101,7 +111,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
     const int lb = x * q + (x < r ? x : r) + (b >> 3);
     const int wave = lb * (kTravBlock / kWave) + wv;
     if (wave >= a.ntasks) return;
-    const int4 task = a.tasks[wave];
+    const int4 task = ldc_i4(a.tasks + wave);
     const int first = task.x, last = task.y, root = task.z, rend = task.w;
 
     float tx[TPL], ty[TPL], tz[TPL];
@@ -125,25 +135,49 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
         mhi[k] = lane == 0 ? (uint32_t)(act0 >> 32) : 0u;
     }
     int node = root;
+    const float4 *recs = a.mom;
+    float4 P = make_float4(0.f, 0.f, 0.f, 0.f), V = P, Lo = P;
+    if (PF && node < rend) {
+        P = ldc_f4(recs + kRecStride * node);
+        V = ldc_f4(recs + kRecStride * node + 1);
+        Lo = ldc_f4(recs + kRecStride * node + 2);
+    }
     while (node < rend) {
-        const float4 P = ldc_f4(a.mom + 2 * node);
-        const float4 V = ldc_f4(a.mom + 2 * node + 1);
+        if (!PF) {
+            P = ldc_f4(recs + kRecStride * node);
+            V = ldc_f4(recs + kRecStride * node + 1);
+            Lo = ldc_f4(recs + kRecStride * node + 2);
+        }
         const int flags = __float_as_int(P.w);
         const int skip = __float_as_int(V.w);
+        float4 P1 = P, V1 = V, L1 = Lo, P2 = P, V2 = V, L2 = Lo;
+        if (PF) {
+            // clamped to the cloud's last node: a load past it is never used
+            const int n1 = min(node + 1, rend - 1), n2 = min(skip, rend - 1);
+            P1 = ldc_f4(recs + kRecStride * n1);
+            V1 = ldc_f4(recs + kRecStride * n1 + 1);
+            L1 = ldc_f4(recs + kRecStride * n1 + 2);
+            P2 = ldc_f4(recs + kRecStride * n2);
+            V2 = ldc_f4(recs + kRecStride * n2 + 1);
+            L2 = ldc_f4(recs + kRecStride * n2 + 2);
+        }
         if (flags & kRecZero) {  // every attribute in the node is zero
             node = skip;
+            P = P2, V = V2, Lo = L2;
             continue;
         }
         const int depth = flags & 15;
         const bool single = flags & kRecSingle;
-        const float thr2 = a.thr2[depth];
+        const float thr2 = Lo.w;
         unsigned long long open[TPL];
         unsigned long long any = 0ull;
 #pragma unroll
         for (int k = 0; k < TPL; ++k) {
             const unsigned long long act = read_mask(mlo[k], mhi[k], depth);
             const bool me = (act >> lane) & 1ull;
-            const float dx = tx[k] - P.x, dy = ty[k] - P.y, dz = tz[k] - P.z;
+            // (x - hi) is exact for a target near the node; then the low part
+            const float dx = (tx[k] - P.x) - Lo.x, dy = (ty[k] - P.y) - Lo.y,
+                        dz = (tz[k] - P.z) - Lo.z;
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
             const bool far = me && (single || r2 > thr2);
             if (far) {
@@ -155,6 +189,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
         }
         if (any == 0ull) {
             node = skip;
+            P = P2, V = V2, Lo = L2;
             continue;
         }
         if (flags & kRecLeaf) {
@@ -179,6 +214,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
                 }
             }
             node = skip;
+            P = P2, V = V2, Lo = L2;
         } else {
 #pragma unroll
             for (int k = 0; k < TPL; ++k) {
@@ -188,6 +224,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
                 }
             }
             node = node + 1;
+            P = P1, V = V1, Lo = L1;
         }
     }
 
@@ -241,19 +278,20 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
         unsigned tot = nflip;
 #pragma unroll
         for (int d = kWave / 2; d > 0; d >>= 1) tot += __shfl_xor(tot, d, kWave);
-        if (lane == 0 && tot) atomicAdd(a.flips + a.cloud[first], (unsigned long long)tot);
+        if (lane == 0 && tot) atomicAdd(a.flips + ldc_i(a.cloud + first), (unsigned long long)tot);
     }
     if (MODE == TR_SCALE) {
         e = wave_sum(e);
         e2 = wave_sum(e2);
         if (lane == 0) {
-            a.partial[a.task_slot[wave]] = e;
-            a.partial[a.ntasks + a.task_slot[wave]] = e2;
+            const int sl = ldc_i(a.task_slot + wave);
+            a.partial[sl] = e;
+            a.partial[a.ntasks + sl] = e2;
         }
     }
     if (MODE == TR_RHO || MODE == TR_R || MODE == TR_TSUM) {
         e = wave_sum(e);  // fixed butterfly order: reproducible
-        if (lane == 0) a.partial[a.task_slot[wave]] = e;
+        if (lane == 0) a.partial[ldc_i(a.task_slot + wave)] = e;
     }
     if (COUNT) {
         const double c = wave_sum((double)cnt);
@@ -268,10 +306,17 @@ int trav_blocks(int64_t ntasks) {
 template <int OP, int MODE, int TPL>
 static void launch_tpl(bool count, const TravArgs &a, hipStream_t st) {
     const dim3 grid((unsigned)trav_blocks(a.ntasks)), block(kTravBlock);
-    if (count)
-        hipLaunchKernelGGL((k_traverse<OP, MODE, true, TPL>), grid, block, 0, st, a);
-    else
-        hipLaunchKernelGGL((k_traverse<OP, MODE, false, TPL>), grid, block, 0, st, a);
+    if (a.prefetch) {
+        if (count)
+            hipLaunchKernelGGL((k_traverse<OP, MODE, true, TPL, true>), grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL((k_traverse<OP, MODE, false, TPL, true>), grid, block, 0, st, a);
+    } else {
+        if (count)
+            hipLaunchKernelGGL((k_traverse<OP, MODE, true, TPL, false>), grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL((k_traverse<OP, MODE, false, TPL, false>), grid, block, 0, st, a);
+    }
 }
 
 template <int OP, int MODE>

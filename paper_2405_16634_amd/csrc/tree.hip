@@ -464,7 +464,7 @@ hipError_t build_tree(wnnc_ctx_s *ctx, const float *P) {
 
     TRY(ctx->topo.ensure(m));
     TRY(ctx->node_strad.ensure(m));
-    TRY(ctx->mom.ensure(2 * m));
+    TRY(ctx->mom.ensure(kRecStride * m));
     TRY(ctx->mflag.ensure(m + 1));
     TRY(ctx->mslot.ensure(m + 1));
 

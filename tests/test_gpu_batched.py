@@ -146,18 +146,20 @@ def test_tile_shapes_give_identical_bits(dev):
     mu = torch.from_numpy((synth.random_unit(rng, cloud.n) * 1e-4).astype(np.float32)).to(dev)
     ref = None
     for tpl in (1, 2, 4):
-        ctx.set_tile(tpl)
-        assert ctx.tile() == tpl
-        out = (ctx.winding(mu, 0.002).clone(), ctx.gradient(mu, 0.002).clone(),
-               ctx.orient(5, 0.002, 0.016).clone())
-        if ref is None:
-            ref = out
-        else:
-            for a, b in zip(ref, out):
-                assert bool((a == b).all()), tpl
+        for pf in (False, True):
+            ctx.set_tile(tpl)
+            ctx.set_prefetch(pf)
+            assert ctx.tile() == tpl and ctx.prefetch() == pf
+            out = (ctx.winding(mu, 0.002).clone(), ctx.gradient(mu, 0.002).clone(),
+                   ctx.orient(5, 0.002, 0.016).clone())
+            if ref is None:
+                ref = out
+            else:
+                for a, b in zip(ref, out):
+                    assert bool((a == b).all()), (tpl, pf)
     ms = ctx.autotune(0.002)
-    assert set(ms) == {1, 2, 4} and all(v > 0 for v in ms.values())
-    assert ctx.tile() == min(ms, key=ms.get)
+    assert len(ms) == 6 and all(v > 0 for v in ms.values())
+    assert (ctx.tile(), int(ctx.prefetch())) == min(ms, key=ms.get)
     ctx.close()
 
 
