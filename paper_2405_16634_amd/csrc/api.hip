@@ -1,5 +1,6 @@
 // The C ABI (include/wnnc.h): argument checks, buffers, and the order of
 // kernel launches for the operators and for the WNNC iteration (Alg. 3).
+#include <float.h>
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -106,7 +107,8 @@ TravArgs trav_args(wnnc_ctx_s *c, float w) {
     a.prefetch = c->prefetch;
     a.n = (int)c->n;
     a.m = (int)c->m;
-    a.w2 = (float)((double)w * (double)w);
+    // pairs closer than w, and coincident pairs, contribute nothing
+    a.w2 = fmaxf((float)((double)w * (double)w), FLT_MIN);
     for (int d = 0; d < 16; ++d) {
         const double t = (double)c->c * ldexp(2.0, -d);
         a.thr2[d] = (float)(t * t);

@@ -25,7 +25,9 @@ __device__ inline void write_moment(const MomArgs &a, int node, const int4 t, co
     const double W = s[0];
     int flags = t.w & 31;  // depth | leaf << 4
     if ((flags & kRecLeaf) && t.z - t.y == 1) flags |= kRecSingle;
-    float4 p, lo = make_float4(0.f, 0.f, 0.f, a.thr2[t.w & 15]);
+    // a single-point leaf's representative is its point: threshold -1 makes
+    // every target take it as a representative
+    float4 p, lo = make_float4(0.f, 0.f, 0.f, (flags & kRecSingle) ? -1.0f : a.thr2[t.w & 15]);
     if (W > 0.0) {
         const double x = s[1] / W, y = s[2] / W, z = s[3] / W;
         const float hx = (float)x, hy = (float)y, hz = (float)z;

@@ -53,27 +53,30 @@ constexpr double kInv4Pi = 0.0795774715459476678844;  // 1 / (4 pi)
 template <int OP>
 __device__ inline void pair_term(float dx, float dy, float dz, float r2, float4 v, float w2,
                                  double &s, double &gx, double &gy, double &gz) {
-    const bool keep = (r2 >= w2) && (r2 > 0.0f);
-    // hardware reciprocal square root (about 1 ulp); r2 below the smallest
-    // normal only occurs for pairs that the cutoff removes when w > 0
-    const float ri = __builtin_amdgcn_rsqf(r2);
+    // w2 >= the smallest normal float, so this also drops r = 0 (and keeps
+    // denormal arguments away from the hardware reciprocal square root)
+    const bool keep = r2 >= w2;
+    const float ri = __builtin_amdgcn_rsqf(r2);  // about 1 ulp
     const float ri2 = ri * ri;
     const float ri3 = ri2 * ri;
     if (OP == OP_A) {
         const float dm = fmaf(dx, v.x, fmaf(dy, v.y, dz * v.z));
-        const float t = -dm * ri3;
-        s += keep ? (double)t : 0.0;
+        const float t = keep ? -dm * ri3 : 0.0f;
+        s += (double)t;
     } else if (OP == OP_AT) {
-        const float f = v.x * ri3;
-        gx += keep ? (double)(f * dx) : 0.0;
-        gy += keep ? (double)(f * dy) : 0.0;
-        gz += keep ? (double)(f * dz) : 0.0;
+        const float f = keep ? v.x * ri3 : 0.0f;
+        gx += (double)(f * dx);
+        gy += (double)(f * dy);
+        gz += (double)(f * dz);
     } else {
         const float dm = fmaf(dx, v.x, fmaf(dy, v.y, dz * v.z));
-        const float c5 = 3.0f * dm * (ri3 * ri2);
-        gx += keep ? (double)fmaf(v.x, ri3, -c5 * dx) : 0.0;
-        gy += keep ? (double)fmaf(v.y, ri3, -c5 * dy) : 0.0;
-        gz += keep ? (double)fmaf(v.z, ri3, -c5 * dz) : 0.0;
+        // both factors masked: at r = 0, ri is infinite
+        const float a3 = keep ? ri3 : 0.0f;
+        const float b5 = keep ? ri3 * ri2 : 0.0f;
+        const float c5 = 3.0f * dm * b5;
+        gx += (double)fmaf(v.x, a3, -c5 * dx);
+        gy += (double)fmaf(v.y, a3, -c5 * dy);
+        gz += (double)fmaf(v.z, a3, -c5 * dz);
     }
 }
 
@@ -167,8 +170,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
             continue;
         }
         const int depth = flags & 15;
-        const bool single = flags & kRecSingle;
-        const float thr2 = Lo.w;
+        const float thr2 = Lo.w;  // -1 for a single-point leaf: always taken
         unsigned long long open[TPL];
         unsigned long long any = 0ull;
 #pragma unroll
@@ -179,7 +181,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
             const float dx = (tx[k] - P.x) - Lo.x, dy = (ty[k] - P.y) - Lo.y,
                         dz = (tz[k] - P.z) - Lo.z;
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            const bool far = me && (single || r2 > thr2);
+            const bool far = me && r2 > thr2;
             if (far) {
                 pair_term<OP>(dx, dy, dz, r2, V, a.w2, s[k], gx[k], gy[k], gz[k]);
                 if (COUNT) ++cnt;
