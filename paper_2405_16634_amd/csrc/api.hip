@@ -322,6 +322,8 @@ static wnnc_status build_impl(wnnc_ctx ctx, const float *P, const int64_t *offse
     if (e != hipSuccess) {
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
+        if (e == hipErrorNotSupported)
+            return fail(WNNC_EINVAL, "tree build: more than %lld nodes", (long long)kMaxNodes);
         return fail(e == hipErrorOutOfMemory ? WNNC_ENOMEM : WNNC_EDEVICE, "tree build: %s",
                     hipGetErrorString(e));
     }

@@ -23,16 +23,20 @@ constexpr int kMaxDepth = 15;    // 15 levels below the root: 45-bit Morton keys
 __host__ __device__ inline int topo_depth(int meta) { return meta & 15; }
 __host__ __device__ inline int topo_leaf(int meta) { return (meta >> 4) & 1; }
 
-// Node record written by every moment pass and read by the traversal, three
-// 16-byte parts per node (scalar loads):
+// Node record written by every moment pass and read by the traversal, 64
+// bytes per node (one 16-dword scalar load):
 //   [0] hi(x_B).x, .y, .z, flags (int bits)
 //   [1] nu_B (3 floats; a scalar attribute in .x), skip (int bits)
 //   [2] lo(x_B).x, .y, .z, (c * width)^2 (the acceptance threshold)
+//   [3] first point, end point (int bits), 0, 0
 // with x_B = hi + lo to about 2^-48 (hi = FP32 rounding of the FP64 x_B,
 // lo = FP32 rounding of the rest), so that target - x_B keeps full FP32
 // precision when the target is close to the node.
 // flags = depth | leaf << 4 | single-point leaf << 5 | zero weight << 6.
-constexpr int kRecStride = 3;
+// The traversal addresses records with 32-bit byte offsets: at most
+// kMaxNodes nodes.
+constexpr int kRecStride = 4;
+constexpr int64_t kMaxNodes = int64_t(1) << 26;
 constexpr int kRecLeaf = 16;
 constexpr int kRecSingle = 32;
 constexpr int kRecZero = 64;

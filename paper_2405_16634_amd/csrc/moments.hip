@@ -41,6 +41,7 @@ __device__ inline void write_moment(const MomArgs &a, int node, const int4 t, co
     rec[0] = p;
     rec[1] = make_float4((float)s[4], (float)s[5], (float)s[6], __int_as_float(t.x));
     rec[2] = lo;
+    rec[3] = make_float4(__int_as_float(t.y), __int_as_float(t.z), 0.f, 0.f);
     if (a.wout) a.wout[node] = W > 0.0 ? fmaxf((float)W, FLT_MIN) : 0.f;
 }
 

@@ -23,22 +23,27 @@ namespace wnnc {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+#define WNNC_AS4 __attribute__((address_space(4)))
 
 // Loads through the constant address space: uniform addresses become SMEM
 // loads (the arrays are not written during the kernel).
 __device__ inline int4 ldc_i4(const int4 *p) {
-    v4i v = *(const __attribute__((address_space(4))) v4i *)p;
+    v4i v = *(const WNNC_AS4 v4i *)p;
     return make_int4(v.x, v.y, v.z, v.w);
 }
 __device__ inline float4 ldc_f4(const float4 *p) {
-    v4f v = *(const __attribute__((address_space(4))) v4f *)p;
+    v4f v = *(const WNNC_AS4 v4f *)p;
     return make_float4(v.x, v.y, v.z, v.w);
 }
-__device__ inline float ldc_f(const float *p) {
-    return *(const __attribute__((address_space(4))) float *)p;
-}
-__device__ inline int ldc_i(const int *p) {
-    return *(const __attribute__((address_space(4))) int *)p;
+__device__ inline float ldc_f(const float *p) { return *(const WNNC_AS4 float *)p; }
+__device__ inline int ldc_i(const int *p) { return *(const WNNC_AS4 int *)p; }
+
+// The 64-byte record of a node: one 16-dword scalar load at a 32-bit byte
+// offset from the base (the address needs one shift).
+__device__ inline v16f ld_rec(const float4 *base, int node) {
+    const WNNC_AS4 char *b = (const WNNC_AS4 char *)base;
+    return *(const WNNC_AS4 v16f *)(b + ((unsigned)node << 6));
 }
 
 constexpr double kInv4Pi = 0.0795774715459476678844;  // 1 / (4 pi)
@@ -47,37 +52,43 @@ constexpr double kInv4Pi = 0.0795774715459476678844;  // 1 / (4 pi)
 //   A  : -(d . nu) / r^3
 //   A^T: nu d / r^3                      (nu scalar, in v.x)
 //   G  : nu / r^3 - 3 (d . nu) d / r^5
-// Kept only when r >= w and r > 0 (Sec. 3.4).  The term is formed in FP32
-// and added to an FP64 per-target sum (FP64 adds issue at the FP32 rate on
-// this chip), so the sum's rounding does not grow with the number of terms.
+// `take` is false for lanes whose pair does not count: not selected by the
+// traversal, or cut off (r < w, Sec. 3.4).  Their term is an exact zero, so
+// that the unconditional add below leaves the sum unchanged.  The term is
+// formed in FP32 and added to an FP64 per-target sum (FP64 adds issue at the
+// FP32 rate on this chip), so the sum's rounding does not grow with the
+// number of terms.
 template <int OP>
-__device__ inline void pair_term(float dx, float dy, float dz, float r2, float4 v, float w2,
+__device__ inline void pair_term(float dx, float dy, float dz, float r2, float4 v, bool take,
                                  double &s, double &gx, double &gy, double &gz) {
-    // w2 >= the smallest normal float, so this also drops r = 0 (and keeps
-    // denormal arguments away from the hardware reciprocal square root)
-    const bool keep = r2 >= w2;
     const float ri = __builtin_amdgcn_rsqf(r2);  // about 1 ulp
     const float ri2 = ri * ri;
     const float ri3 = ri2 * ri;
     if (OP == OP_A) {
         const float dm = fmaf(dx, v.x, fmaf(dy, v.y, dz * v.z));
-        const float t = keep ? -dm * ri3 : 0.0f;
+        const float t = take ? -dm * ri3 : 0.0f;
         s += (double)t;
     } else if (OP == OP_AT) {
-        const float f = keep ? v.x * ri3 : 0.0f;
+        const float f = take ? v.x * ri3 : 0.0f;
         gx += (double)(f * dx);
         gy += (double)(f * dy);
         gz += (double)(f * dz);
     } else {
         const float dm = fmaf(dx, v.x, fmaf(dy, v.y, dz * v.z));
         // both factors masked: at r = 0, ri is infinite
-        const float a3 = keep ? ri3 : 0.0f;
-        const float b5 = keep ? ri3 * ri2 : 0.0f;
+        const float a3 = take ? ri3 : 0.0f;
+        const float b5 = take ? ri3 * ri2 : 0.0f;
         const float c5 = 3.0f * dm * b5;
         gx += (double)fmaf(v.x, a3, -c5 * dx);
         gy += (double)fmaf(v.y, a3, -c5 * dy);
         gz += (double)fmaf(v.z, a3, -c5 * dz);
     }
+}
+
+// The calling lane's bit of a wave-uniform lane mask (the mask is used as a
+// condition directly, with no per-lane shift).
+__device__ inline bool lane_in(unsigned long long mask) {
+    return __builtin_amdgcn_inverse_ballot_w64(mask);
 }
 
 __device__ inline double wave_sum(double v) {
@@ -95,11 +106,10 @@ __device__ inline unsigned long long read_mask(uint32_t lo, uint32_t hi, int dep
 // (group k holds targets first + 64k + lane) walk the node range
 // [root, end) of their cloud together.  Each group keeps its own mask stack
 // and Alg. 4 decisions; the groups share the node loads and the control.
-// PF: software pipelining of the node walk.  The record of a node holds its
-// successors' indices (the first child is the next node, the subtree end is
-// the skip pointer), so both successor records are loaded as soon as the
-// current one is known and the loads overlap the work on the current node;
-// the one taken becomes the next current record.
+// PF: software pipelining of the node walk.  A node's successor is its skip
+// pointer (subtree done) or the next node (descend); the skip successor's
+// record is loaded while the node is visited, so that load overlaps the
+// work on the node.
 template <int OP, int MODE, bool COUNT, int TPL, bool PF>
 __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -137,68 +147,41 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
         mlo[k] = lane == 0 ? (uint32_t)act0 : 0u;
         mhi[k] = lane == 0 ? (uint32_t)(act0 >> 32) : 0u;
     }
-    int node = root;
-    const float4 *recs = a.mom;
-    float4 P = make_float4(0.f, 0.f, 0.f, 0.f), V = P, Lo = P;
-    if (PF && node < rend) {
-        P = ldc_f4(recs + kRecStride * node);
-        V = ldc_f4(recs + kRecStride * node + 1);
-        Lo = ldc_f4(recs + kRecStride * node + 2);
-    }
-    while (node < rend) {
-        if (!PF) {
-            P = ldc_f4(recs + kRecStride * node);
-            V = ldc_f4(recs + kRecStride * node + 1);
-            Lo = ldc_f4(recs + kRecStride * node + 2);
-        }
-        const int flags = __float_as_int(P.w);
-        const int skip = __float_as_int(V.w);
-        float4 P1 = P, V1 = V, L1 = Lo, P2 = P, V2 = V, L2 = Lo;
-        if (PF) {
-            // clamped to the cloud's last node: a load past it is never used
-            const int n1 = min(node + 1, rend - 1), n2 = min(skip, rend - 1);
-            P1 = ldc_f4(recs + kRecStride * n1);
-            V1 = ldc_f4(recs + kRecStride * n1 + 1);
-            L1 = ldc_f4(recs + kRecStride * n1 + 2);
-            P2 = ldc_f4(recs + kRecStride * n2);
-            V2 = ldc_f4(recs + kRecStride * n2 + 1);
-            L2 = ldc_f4(recs + kRecStride * n2 + 2);
-        }
-        if (flags & kRecZero) {  // every attribute in the node is zero
-            node = skip;
-            P = P2, V = V2, Lo = L2;
-            continue;
-        }
+    // One node visit for all groups; returns the next node in pre-order.
+    auto visit = [&](const v16f &R, int node) -> int {
+        const int flags = __float_as_int(R[3]);
+        const int skip = __float_as_int(R[7]);
+        if (flags & kRecZero) return skip;  // every attribute in the node is zero
         const int depth = flags & 15;
-        const float thr2 = Lo.w;  // -1 for a single-point leaf: always taken
+        const float thr2 = R[11];  // -1 for a single-point leaf: always taken
+        const float4 V = make_float4(R[4], R[5], R[6], 0.f);
         unsigned long long open[TPL];
         unsigned long long any = 0ull;
 #pragma unroll
         for (int k = 0; k < TPL; ++k) {
+            // lanes of group k inside at this depth; of those, the ones that
+            // accept the representative (far) and the ones that need B's
+            // children (open), all as wave-uniform lane masks
             const unsigned long long act = read_mask(mlo[k], mhi[k], depth);
-            const bool me = (act >> lane) & 1ull;
             // (x - hi) is exact for a target near the node; then the low part
-            const float dx = (tx[k] - P.x) - Lo.x, dy = (ty[k] - P.y) - Lo.y,
-                        dz = (tz[k] - P.z) - Lo.z;
+            const float dx = (tx[k] - R[0]) - R[8], dy = (ty[k] - R[1]) - R[9],
+                        dz = (tz[k] - R[2]) - R[10];
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            const bool far = me && r2 > thr2;
-            if (far) {
-                pair_term<OP>(dx, dy, dz, r2, V, a.w2, s[k], gx[k], gy[k], gz[k]);
-                if (COUNT) ++cnt;
-            }
-            open[k] = __ballot(me && !far);
+            const unsigned long long far = act & __ballot(r2 > thr2);
+            // w2 >= the smallest normal float, so the cutoff also drops r = 0
+            // (and keeps denormal arguments away from the hardware rsq)
+            const unsigned long long take = far & __ballot(r2 >= a.w2);
+            pair_term<OP>(dx, dy, dz, r2, V, lane_in(take), s[k], gx[k], gy[k], gz[k]);
+            if (COUNT) cnt += (uint32_t)__popcll(far);
+            open[k] = act & ~far;
             any |= open[k];
         }
-        if (any == 0ull) {
-            node = skip;
-            P = P2, V = V2, Lo = L2;
-            continue;
-        }
+        if (any == 0ull) return skip;
         if (flags & kRecLeaf) {
             // several points in a depth-D cell: direct sum for the lanes
             // that did not accept the representative
-            const int4 tp = ldc_i4(a.topo + node);
-            for (int j = tp.y; j < tp.z; ++j) {
+            const int jb = __float_as_int(R[12]), je = __float_as_int(R[13]);
+            for (int j = jb; j < je; ++j) {
                 const float4 Q = ldc_f4(a.pts + j);
                 float4 S;
                 if (OP == OP_AT)
@@ -207,26 +190,47 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
                     S = ldc_f4(a.src4 + j);
 #pragma unroll
                 for (int k = 0; k < TPL; ++k) {
-                    if ((open[k] >> lane) & 1ull) {
-                        const float ex = tx[k] - Q.x, ey = ty[k] - Q.y, ez = tz[k] - Q.z;
-                        const float e2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
-                        pair_term<OP>(ex, ey, ez, e2, S, a.w2, s[k], gx[k], gy[k], gz[k]);
-                        if (COUNT) ++cnt;
-                    }
+                    const float ex = tx[k] - Q.x, ey = ty[k] - Q.y, ez = tz[k] - Q.z;
+                    const float e2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
+                    const unsigned long long take = open[k] & __ballot(e2 >= a.w2);
+                    pair_term<OP>(ex, ey, ez, e2, S, lane_in(take), s[k], gx[k], gy[k], gz[k]);
+                    if (COUNT) cnt += (uint32_t)__popcll(open[k]);
                 }
             }
-            node = skip;
-            P = P2, V = V2, Lo = L2;
-        } else {
+            return skip;
+        }
 #pragma unroll
-            for (int k = 0; k < TPL; ++k) {
-                if (lane == depth + 1) {
-                    mlo[k] = (uint32_t)open[k];
-                    mhi[k] = (uint32_t)(open[k] >> 32);
-                }
+        for (int k = 0; k < TPL; ++k) {
+            if (lane == depth + 1) {
+                mlo[k] = (uint32_t)open[k];
+                mhi[k] = (uint32_t)(open[k] >> 32);
             }
-            node = node + 1;
-            P = P1, V = V1, Lo = L1;
+        }
+        return node + 1;
+    };
+
+    if (!PF) {
+        for (int node = root; node < rend;) node = visit(ld_rec(a.mom, node), node);
+    } else if (root < rend) {
+        // Two record buffers used in turn.  While a node is visited, the
+        // record of its skip successor is loaded into the other buffer; when
+        // the walk descends instead, that buffer is reloaded with the first
+        // child.  (Loads past the cloud's last node are clamped to it.)
+        int node = root;
+        v16f RA = ld_rec(a.mom, node), RB;
+        for (;;) {
+            int sk = __float_as_int(RA[7]);
+            RB = ld_rec(a.mom, min(sk, rend - 1));
+            int nx = visit(RA, node);
+            if (nx >= rend) break;
+            if (nx != sk) RB = ld_rec(a.mom, nx);
+            node = nx;
+            sk = __float_as_int(RB[7]);
+            RA = ld_rec(a.mom, min(sk, rend - 1));
+            nx = visit(RB, node);
+            if (nx >= rend) break;
+            if (nx != sk) RA = ld_rec(a.mom, nx);
+            node = nx;
         }
     }
 
@@ -295,9 +299,8 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
         e = wave_sum(e);  // fixed butterfly order: reproducible
         if (lane == 0) a.partial[ldc_i(a.task_slot + wave)] = e;
     }
-    if (COUNT) {
-        const double c = wave_sum((double)cnt);
-        if (lane == 0) atomicAdd(a.pairs + OP, (unsigned long long)c);
+    if (COUNT) {  // cnt is wave-uniform: the pairs of all lanes
+        if (lane == 0) atomicAdd(a.pairs + OP, (unsigned long long)cnt);
     }
 }
 

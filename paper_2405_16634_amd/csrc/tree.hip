@@ -460,6 +460,7 @@ hipError_t build_tree(wnnc_ctx_s *ctx, const float *P) {
                        hipMemcpyDeviceToHost, st));
     TRY(hipStreamSynchronize(st));
     const int64_t m = ctx->roots[nclouds];
+    if (m > kMaxNodes) return hipErrorNotSupported;  // beyond 32-bit record offsets
     ctx->m = m;
 
     TRY(ctx->topo.ensure(m));
