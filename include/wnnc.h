@@ -103,7 +103,11 @@ typedef struct {
     double moments_ms;      /* summed moment-pass time (WNNC_FLAG_TIME_KERNELS) */
     double build_ms;        /* last wnnc_build, device time (always timed) */
     int64_t n_clouds;       /* clouds in the current tree (1 for wnnc_build) */
-    int64_t tile;           /* tile shape (wnnc_set_tile) | prefetch << 8 */
+    int64_t tile;           /* tile shape (wnnc_set_tile) | prefetch << 8 |
+                               split (wnnc_set_split) << 16 */
+    int64_t n_groups;       /* target groups (64 * tile shape targets) */
+    int64_t n_tasks;        /* wavefronts per traversal launch (groups, or
+                               parts of split walks) */
 } wnnc_stats_t;
 
 /* Create a context on HIP device `device`, enqueuing on `stream`
@@ -158,16 +162,37 @@ wnnc_status wnnc_build_batched(wnnc_ctx ctx, const float *P, const int64_t *offs
 wnnc_status wnnc_set_tile(wnnc_ctx ctx, int tpl);
 wnnc_status wnnc_get_tile(wnnc_ctx ctx, int *tpl);
 
-/* Software-pipelined node walk in the traversal (prefetch of both successor
- * records); results do not depend on it.  Default off. */
+/* Load balance of the traversal: with visits > 0 and tile shape 1, the
+ * walk of a 64-target group that takes more than `visits` node visits (as
+ * recorded by wnnc_build) runs as several wavefronts over consecutive
+ * node ranges, each rebuilding its lanes' decisions at the range's
+ * ancestors, and a combining pass adds their FP64 sums in range order.
+ * The decisions and terms are those of the whole walk (Alg. 4); only the
+ * FP64 summation order changes.  0 = whole walks (default).  visits in
+ * 0..WNNC_MAX_SPLIT.  Synchronizes when a tree exists. */
+#define WNNC_MAX_SPLIT (1 << 20)
+wnnc_status wnnc_set_split(wnnc_ctx ctx, int visits);
+wnnc_status wnnc_get_split(wnnc_ctx ctx, int *visits);
+
+/* Software-pipelined node walk in the traversal (the skip successor's
+ * record is loaded during the visit); results do not depend on it.
+ * Default off. */
 wnnc_status wnnc_set_prefetch(wnnc_ctx ctx, int on);
 
-/* Autotuner: times one adjoint-operator traversal at width w for every tile
- * shape and prefetch setting on the current tree and keeps the fastest.
- * ms_out (host, 6 doubles, may be NULL) receives the times for
- * (tpl, prefetch) = (1,0), (1,1), (2,0), (2,1), (4,0), (4,1).
- * Synchronizes. */
-wnnc_status wnnc_autotune(wnnc_ctx ctx, float w, double *ms_out);
+/* Autotuner: times one adjoint-operator traversal at width w for each of
+ * WNNC_AUTOTUNE_CONFIGS settings on the current tree and keeps the fastest:
+ * (tpl, split) = (1, 0), (2, 0), (4, 0), (1, 1024), (1, 512), each with
+ * prefetch off and on (in that order).  times_out (host,
+ * WNNC_AUTOTUNE_CONFIGS entries, may be NULL) receives the settings and
+ * their times.  Overwrites the context's iteration buffers.  Synchronizes. */
+#define WNNC_AUTOTUNE_CONFIGS 10
+typedef struct {
+    int tpl;
+    int prefetch;
+    int split;
+    double ms;
+} wnnc_tile_time;
+wnnc_status wnnc_autotune(wnnc_ctx ctx, float w, wnnc_tile_time *times_out);
 
 /* Winding number at the points: s_out[i] = F(x_i; mu), mu_j = n_j sigma_j.
  * n: (N,3); sigma: (N) or NULL (then n already holds mu); w >= 0. */
@@ -260,25 +285,34 @@ wnnc_status wnnc_mlp_adam(wnnc_ctx ctx, float *params, float *m, float *v, const
 /* Warm-started orientation options (defaults in brackets). */
 typedef struct {
     int iters;            /* iterations of the warm schedule [8] */
-    float w1, w2;         /* warm schedule widths, w2 first [0.002, 0.004] */
+    float w1, w2;         /* warm schedule widths, w2 first [0.002, 0.016]:
+                             the plain schedule compressed into `iters` */
     float max_disagree;   /* self-check: largest tolerated fraction of points
                              of a cloud whose final WNNC update points against
                              mu [0.005]; above it the plain method reruns */
     int fallback_iters;   /* plain method iterations on fallback [40] */
     float fallback_w2;    /* plain method initial width on fallback [0.016];
                              its final width is w1 */
+    float max_pred_disagree; /* self-check: largest tolerated fraction of
+                             points of a cloud whose result points against
+                             the prediction [0.4]; near 1/2 the prediction
+                             carried no information and the result is
+                             not trusted */
 } wnnc_warm_opts;
 
 typedef struct {
     int iterations;       /* iterations run (warm + fallback) */
     int fallback;         /* 1 if the plain method was rerun */
-    double max_disagree;  /* worst per-cloud self-check fraction */
+    double max_disagree;  /* worst per-cloud update self-check fraction */
+    double max_pred_disagree; /* worst per-cloud fraction of results against
+                             the prediction (before any fallback) */
 } wnnc_warm_report;
 
 /* Learned warm start on the built tree (every cloud): neighbourhood
  * features -> MLP unit normals n -> per cloud mu0 = beta n with the
  * least-squares scale beta = <A n, 1/2> / |A n|^2 -> `iters` iterations of
- * Alg. 3 with the warm schedule -> self-check; when it fails, the plain
+ * Alg. 3 with the warm schedule -> self-checks (the last update and the
+ * agreement with the prediction, per cloud); when either fails, the plain
  * method from mu = 0.  mu_out (N,3) as wnnc_orient.  report (host) may be
  * NULL.  Synchronizes once (the self-check). */
 wnnc_status wnnc_warm_orient(wnnc_ctx ctx, const float *params, const wnnc_warm_opts *opts,

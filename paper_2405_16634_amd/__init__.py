@@ -32,9 +32,11 @@ EXPORTED = [
     "wnnc_moments_export", "wnnc_normals", "wnnc_last_error", "wnnc_version",
     "wnnc_normalize_batched", "wnnc_build_batched", "wnnc_set_tile", "wnnc_get_tile",
     "wnnc_autotune", "wnnc_knn_features", "wnnc_mlp_forward", "wnnc_mlp_grad", "wnnc_mlp_adam",
-    "wnnc_warm_orient", "wnnc_set_prefetch",
+    "wnnc_warm_orient", "wnnc_set_prefetch", "wnnc_set_split", "wnnc_get_split",
 ]
 MLP_PARAMS = 7491
+AUTOTUNE_CONFIGS = 10
+MAX_SPLIT = 1 << 20
 
 
 class WnncError(RuntimeError):
@@ -55,12 +57,17 @@ class OrientOpts(ctypes.Structure):
 class WarmOpts(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("w1", ctypes.c_float), ("w2", ctypes.c_float),
                 ("max_disagree", ctypes.c_float), ("fallback_iters", ctypes.c_int),
-                ("fallback_w2", ctypes.c_float)]
+                ("fallback_w2", ctypes.c_float), ("max_pred_disagree", ctypes.c_float)]
 
 
 class WarmReport(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("fallback", ctypes.c_int),
-                ("max_disagree", ctypes.c_double)]
+                ("max_disagree", ctypes.c_double), ("max_pred_disagree", ctypes.c_double)]
+
+
+class TileTime(ctypes.Structure):
+    _fields_ = [("tpl", ctypes.c_int), ("prefetch", ctypes.c_int), ("split", ctypes.c_int),
+                ("ms", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -68,13 +75,15 @@ class Stats(ctypes.Structure):
                 ("calls", ctypes.c_int64 * 3), ("pairs", ctypes.c_int64 * 3),
                 ("traverse_ms", ctypes.c_double * 3), ("moments_ms", ctypes.c_double),
                 ("build_ms", ctypes.c_double), ("n_clouds", ctypes.c_int64),
-                ("tile", ctypes.c_int64)]
+                ("tile", ctypes.c_int64), ("n_groups", ctypes.c_int64),
+                ("n_tasks", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return dict(n_points=self.n_points, n_nodes=self.n_nodes, calls=list(self.calls),
                     pairs=list(self.pairs), traverse_ms=list(self.traverse_ms),
                     moments_ms=self.moments_ms, build_ms=self.build_ms,
-                    n_clouds=self.n_clouds, tile=self.tile)
+                    n_clouds=self.n_clouds, tile=self.tile, n_groups=self.n_groups,
+                    n_tasks=self.n_tasks)
 
 
 _lib = None
@@ -111,8 +120,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "wnnc_build_batched": [vp, vp, P(i64), ctypes.c_int, P(TreeOpts)],
         "wnnc_set_tile": [vp, ctypes.c_int],
         "wnnc_get_tile": [vp, P(ctypes.c_int)],
-        "wnnc_autotune": [vp, f32, P(dbl)],
+        "wnnc_autotune": [vp, f32, P(TileTime)],
         "wnnc_set_prefetch": [vp, ctypes.c_int],
+        "wnnc_set_split": [vp, ctypes.c_int],
+        "wnnc_get_split": [vp, P(ctypes.c_int)],
         "wnnc_knn_features": [vp, vp, vp],
         "wnnc_mlp_forward": [vp, vp, vp, i64, vp],
         "wnnc_mlp_grad": [vp, vp, vp, vp, i64, vp, P(dbl)],
@@ -231,12 +242,22 @@ def wnnc_set_prefetch(ctx, on: bool) -> None:
     _check(load_library().wnnc_set_prefetch(ctx, 1 if on else 0))
 
 
+def wnnc_set_split(ctx, visits: int) -> None:
+    _check(load_library().wnnc_set_split(ctx, int(visits)))
+
+
+def wnnc_get_split(ctx) -> int:
+    v = ctypes.c_int()
+    _check(load_library().wnnc_get_split(ctx, ctypes.byref(v)))
+    return v.value
+
+
 def wnnc_autotune(ctx, w: float = 0.002):
-    """Time every (tile shape, prefetch) on the current tree and keep the
-    fastest.  Returns {(tpl, prefetch): ms}."""
-    ms = (ctypes.c_double * 6)()
-    _check(load_library().wnnc_autotune(ctx, float(w), ms))
-    return {(t, p): ms[2 * k + p] for k, t in enumerate((1, 2, 4)) for p in (0, 1)}
+    """Time every tuned (tile shape, prefetch, split) setting on the current
+    tree and keep the fastest.  Returns {(tpl, prefetch, split): ms}."""
+    out = (TileTime * AUTOTUNE_CONFIGS)()
+    _check(load_library().wnnc_autotune(ctx, float(w), out))
+    return {(r.tpl, r.prefetch, r.split): r.ms for r in out}
 
 
 def wnnc_build(ctx, P, c: float = 2.0, max_depth: int = 15) -> None:
@@ -314,18 +335,18 @@ def wnnc_mlp_adam(ctx, params, m, v, grad, step: int, lr: float = 1e-3, beta1: f
                                         float(lr), float(beta1), float(beta2), float(eps)))
 
 
-def wnnc_warm_orient(ctx, params, mu_out, iters: int = 8, w1: float = 0.002, w2: float = 0.004,
+def wnnc_warm_orient(ctx, params, mu_out, iters: int = 8, w1: float = 0.002, w2: float = 0.016,
                      max_disagree: float = 0.005, fallback_iters: int = 40,
-                     fallback_w2: float = 0.016) -> dict:
+                     fallback_w2: float = 0.016, max_pred_disagree: float = 0.4) -> dict:
     N = mu_out.shape[0]
     opts = WarmOpts(int(iters), float(w1), float(w2), float(max_disagree), int(fallback_iters),
-                    float(fallback_w2))
+                    float(fallback_w2), float(max_pred_disagree))
     rep = WarmReport()
     _check(load_library().wnnc_warm_orient(ctx, _dev(params, "params", shape=(MLP_PARAMS,)),
                                            ctypes.byref(opts), _dev(mu_out, "mu_out", shape=(N, 3)),
                                            ctypes.byref(rep)))
     return dict(iterations=rep.iterations, fallback=bool(rep.fallback),
-                max_disagree=rep.max_disagree)
+                max_disagree=rep.max_disagree, max_pred_disagree=rep.max_pred_disagree)
 
 
 def wnnc_orient_energy(ctx, count: int, nclouds: int = 1):
@@ -447,6 +468,12 @@ class Context:
 
     def prefetch(self) -> bool:
         return bool((wnnc_stats(self._h)["tile"] >> 8) & 1)
+
+    def set_split(self, visits: int) -> None:
+        wnnc_set_split(self._h, visits)
+
+    def split(self) -> int:
+        return wnnc_get_split(self._h)
 
     def autotune(self, w: float = 0.002):
         return wnnc_autotune(self._h, w)

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 
 #include "common.h"
@@ -102,7 +103,10 @@ TravArgs trav_args(wnnc_ctx_s *c, float w) {
     a.cloud = c->cloud_of.p;
     a.tasks = c->tasks.p;
     a.task_slot = c->task_slot.p;
+    a.roots = c->d_roots.p;
+    a.parts = c->parts.p;
     a.ntasks = c->ntasks;
+    a.nslots = c->ngroups;
     a.tpl = c->tpl;
     a.prefetch = c->prefetch;
     a.n = (int)c->n;
@@ -294,6 +298,30 @@ wnnc_status wnnc_normalize_batched(wnnc_ctx ctx, const float *P, const int64_t *
     return normalize_impl(ctx, P, offsets, B, P_norm, center_scale);
 }
 
+// Records the walk of every 64-target group (node visits of the adjoint
+// traversal with the constant attribute 1/2: every weight is positive, so
+// it visits the nodes a smooth attribute would) for splitting long walks.
+static hipError_t plan_walks(wnnc_ctx_s *ctx) {
+    ctx->plan.clear();
+    TRY(make_tasks(ctx, 1, 0));
+    const int64_t len = (int64_t)ctx->ngroups * kPlanStride;
+    TRY(ctx->d_plan.ensure(len));
+    TRY(hipMemsetAsync(ctx->d_plan.p, 0, (size_t)len * sizeof(int32_t), ctx->stream));
+    MomArgs ma = mom_args(ctx);
+    ma.outs = ctx->rho.p;
+    TRY(launch_moments(ctx, MOM_CONST_HALF, ma));
+    TravArgs ta = trav_args(ctx, 0.0f);
+    ta.srcs = ctx->rho.p;
+    ta.plan = ctx->d_plan.p;
+    TRY(record_plan(ctx, ta));
+    std::vector<int32_t> pl((size_t)len);
+    TRY(hipMemcpyAsync(pl.data(), ctx->d_plan.p, (size_t)len * sizeof(int32_t),
+                       hipMemcpyDeviceToHost, ctx->stream));
+    TRY(hipStreamSynchronize(ctx->stream));
+    ctx->plan.swap(pl);
+    return hipSuccess;
+}
+
 static wnnc_status build_impl(wnnc_ctx ctx, const float *P, const int64_t *offsets, int B,
                               const wnnc_tree_opts *opts) {
     int64_t N = 0;
@@ -317,8 +345,10 @@ static wnnc_status build_impl(wnnc_ctx ctx, const float *P, const int64_t *offse
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, ctx->stream));
+    const int tpl = ctx->tpl, split = ctx->split;  // planning uses its own tasks
     hipError_t e = build_tree(ctx, P);
-    if (e == hipSuccess) e = make_tasks(ctx, ctx->tpl);
+    if (e == hipSuccess) e = plan_walks(ctx);
+    if (e == hipSuccess) e = make_tasks(ctx, tpl, split);
     if (e != hipSuccess) {
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -355,11 +385,31 @@ wnnc_status wnnc_set_tile(wnnc_ctx ctx, int tpl) {
     CHECK_CTX(ctx);
     if (tpl != 1 && tpl != 2 && tpl != 4) return fail(WNNC_EINVAL, "tile must be 1, 2 or 4");
     if (ctx->built) {
-        hipError_t e = make_tasks(ctx, tpl);
+        hipError_t e = make_tasks(ctx, tpl, ctx->split);
         if (e != hipSuccess) return fail(WNNC_EDEVICE, "tasks: %s", hipGetErrorString(e));
     } else {
         ctx->tpl = tpl;
     }
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_set_split(wnnc_ctx ctx, int visits) {
+    CHECK_CTX(ctx);
+    if (visits < 0 || visits > WNNC_MAX_SPLIT)
+        return fail(WNNC_EINVAL, "split must be in 0..%d", WNNC_MAX_SPLIT);
+    if (ctx->built) {
+        hipError_t e = make_tasks(ctx, ctx->tpl, visits);
+        if (e != hipSuccess) return fail(WNNC_EDEVICE, "tasks: %s", hipGetErrorString(e));
+    } else {
+        ctx->split = visits;
+    }
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_get_split(wnnc_ctx ctx, int *visits) {
+    CHECK_CTX(ctx);
+    if (!visits) return fail(WNNC_EINVAL, "null output");
+    *visits = ctx->split;
     return WNNC_OK;
 }
 
@@ -376,7 +426,7 @@ wnnc_status wnnc_set_prefetch(wnnc_ctx ctx, int on) {
     return WNNC_OK;
 }
 
-wnnc_status wnnc_autotune(wnnc_ctx ctx, float w, double *ms_out) {
+wnnc_status wnnc_autotune(wnnc_ctx ctx, float w, wnnc_tile_time *times_out) {
     CHECK_CTX(ctx);
     CHECK_BUILT(ctx);
     if (!finite_nonneg(w)) return fail(WNNC_EINVAL, "w must be finite and >= 0");
@@ -385,21 +435,23 @@ wnnc_status wnnc_autotune(wnnc_ctx ctx, float w, double *ms_out) {
     MomArgs ma = mom_args(ctx);
     ma.outs = ctx->rho.p;
     RETURN_IF(run_moments(ctx, MOM_CONST_HALF, ma));
-    const int cand[3] = {1, 2, 4};
+    // (tpl, split) pairs, each with and without prefetch
+    static const int cand[WNNC_AUTOTUNE_CONFIGS / 2][2] = {
+        {1, 0}, {2, 0}, {4, 0}, {1, 1024}, {1, 512}};
     double best_ms = 1e300;
-    int best = ctx->tpl, best_pf = ctx->prefetch;
+    int best = ctx->tpl, best_pf = ctx->prefetch, best_split = ctx->split;
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    for (int k = 0; k < 3; ++k) {
-        hipError_t e = make_tasks(ctx, cand[k]);
+    for (int k = 0; k < WNNC_AUTOTUNE_CONFIGS / 2; ++k) {
+        hipError_t e = make_tasks(ctx, cand[k][0], cand[k][1]);
         if (e != hipSuccess) return fail(WNNC_EDEVICE, "tasks: %s", hipGetErrorString(e));
         for (int pf = 0; pf < 2; ++pf) {
             ctx->prefetch = pf;
             TravArgs ta = trav_args(ctx, w);
             ta.srcs = ctx->rho.p;
             ta.out4 = ctx->vr.p;
-            ta.partial = ctx->partial.p + ctx->ntasks;
+            ta.partial = ctx->partial.p + ctx->ngroups;
             double t = 0.0;
             for (int rep = 0; rep < 2; ++rep) {  // first launch warms the caches
                 HIPCHK(hipEventRecord(e0, ctx->stream));
@@ -410,18 +462,25 @@ wnnc_status wnnc_autotune(wnnc_ctx ctx, float w, double *ms_out) {
                 HIPCHK(hipEventElapsedTime(&ms, e0, e1));
                 t = ms;
             }
-            if (ms_out) ms_out[2 * k + pf] = t;
+            if (times_out) {
+                wnnc_tile_time &o = times_out[2 * k + pf];
+                o.tpl = cand[k][0];
+                o.prefetch = pf;
+                o.split = cand[k][1];
+                o.ms = t;
+            }
             if (t < best_ms) {
                 best_ms = t;
-                best = cand[k];
+                best = cand[k][0];
                 best_pf = pf;
+                best_split = cand[k][1];
             }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     ctx->prefetch = best_pf;
-    hipError_t e = make_tasks(ctx, best);
+    hipError_t e = make_tasks(ctx, best, best_split);
     if (e != hipSuccess) return fail(WNNC_EDEVICE, "tasks: %s", hipGetErrorString(e));
     return WNNC_OK;
 }
@@ -480,7 +539,7 @@ wnnc_status wnnc_adjoint(wnnc_ctx ctx, const float *s, float w, float *out) {
 // of points whose WNNC update points against mu + alpha r.
 static wnnc_status run_iterations(wnnc_ctx ctx, int iters, float w1, float w2, int start, int stop,
                                   bool zero, unsigned long long *flips) {
-    const int nt = ctx->ntasks;
+    const int nt = ctx->ngroups;  // row stride of the per-group sums
     const int count = stop - start + 1;
     HIPCHK(ctx->energy.ensure((int64_t)count * ctx->nclouds));
     float4 *mu = ctx->va.p, *tmp = ctx->vb.p, *r = ctx->vr.p;
@@ -578,13 +637,15 @@ wnnc_status wnnc_warm_orient(wnnc_ctx ctx, const float *params, const wnnc_warm_
     CHECK_CTX(ctx);
     CHECK_BUILT(ctx);
     if (!params || !mu_out) return fail(WNNC_EINVAL, "null pointer");
-    wnnc_warm_opts o = {8, 0.002f, 0.004f, 0.005f, 40, 0.016f};
+    wnnc_warm_opts o = {8, 0.002f, 0.016f, 0.005f, 40, 0.016f, 0.4f};
     if (opts) o = *opts;
     if (o.iters < 1 || o.fallback_iters < 1) return fail(WNNC_EINVAL, "iteration counts must be >= 1");
     if (!finite_nonneg(o.w1) || !finite_nonneg(o.w2) || !finite_nonneg(o.fallback_w2))
         return fail(WNNC_EINVAL, "widths must be finite and >= 0");
     if (!(o.max_disagree >= 0.0f && o.max_disagree <= 1.0f))
         return fail(WNNC_EINVAL, "max_disagree must be in [0, 1]");
+    if (!(o.max_pred_disagree >= 0.0f && o.max_pred_disagree <= 1.0f))
+        return fail(WNNC_EINVAL, "max_pred_disagree must be in [0, 1]");
     const int64_t N = ctx->n;
     const int B = ctx->nclouds;
     hipStream_t st = ctx->stream;
@@ -608,20 +669,25 @@ wnnc_status wnnc_warm_orient(wnnc_ctx ctx, const float *params, const wnnc_warm_
         RETURN_IF(run_traverse(ctx, OP_A, TR_SCALE, ta));
         HIPCHK(launch_warm_scale(ctx, ctx->vb.p, ctx->va.p));
     }
-    // 3. short schedule from mu0 with the self-check in its last iteration
-    HIPCHK(ctx->flip_ctr.ensure(B));
-    HIPCHK(hipMemsetAsync(ctx->flip_ctr.p, 0, (size_t)B * sizeof(unsigned long long), st));
+    // 3. short schedule from mu0; self-checks: the last update against mu
+    //    (flip_ctr[0..B)) and the result against the prediction
+    //    (flip_ctr[B..2B))
+    HIPCHK(ctx->flip_ctr.ensure(2 * B));
+    HIPCHK(hipMemsetAsync(ctx->flip_ctr.p, 0, (size_t)(2 * B) * sizeof(unsigned long long), st));
     RETURN_IF(run_iterations(ctx, o.iters, o.w1, o.w2, 1, o.iters, false, ctx->flip_ctr.p));
-    std::vector<unsigned long long> fl((size_t)B);
-    HIPCHK(hipMemcpyAsync(fl.data(), ctx->flip_ctr.p, (size_t)B * sizeof(unsigned long long),
+    HIPCHK(launch_pred_disagree(ctx, ctx->va.p, ctx->nhat.p, ctx->flip_ctr.p + B));
+    std::vector<unsigned long long> fl((size_t)(2 * B));
+    HIPCHK(hipMemcpyAsync(fl.data(), ctx->flip_ctr.p, (size_t)(2 * B) * sizeof(unsigned long long),
                           hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    double worst = 0.0;
+    double worst = 0.0, worst_pred = 0.0;
     for (int c = 0; c < B; ++c) {
-        const double f = (double)fl[c] / (double)(ctx->offsets[c + 1] - ctx->offsets[c]);
-        worst = f > worst ? f : worst;
+        const double nc = (double)(ctx->offsets[c + 1] - ctx->offsets[c]);
+        worst = std::max(worst, (double)fl[c] / nc);
+        worst_pred = std::max(worst_pred, (double)fl[B + c] / nc);
     }
-    const bool fallback = worst > (double)o.max_disagree;
+    const bool fallback =
+        worst > (double)o.max_disagree || worst_pred > (double)o.max_pred_disagree;
     // 4. the plain method when the check fails
     if (fallback) {
         HIPCHK(launch_zero_f4(ctx->va.p, N, st));
@@ -633,6 +699,7 @@ wnnc_status wnnc_warm_orient(wnnc_ctx ctx, const float *params, const wnnc_warm_
         report->iterations = o.iters + (fallback ? o.fallback_iters : 0);
         report->fallback = fallback ? 1 : 0;
         report->max_disagree = worst;
+        report->max_pred_disagree = worst_pred;
     }
     return WNNC_OK;
 }
@@ -728,7 +795,9 @@ wnnc_status wnnc_stats(wnnc_ctx ctx, wnnc_stats_t *out) {
     out->moments_ms = ctx->mom_ms;
     out->build_ms = ctx->build_ms;
     out->n_clouds = ctx->built ? ctx->nclouds : 0;
-    out->tile = ctx->tpl | (ctx->prefetch << 8);
+    out->tile = ctx->tpl | (ctx->prefetch << 8) | ((int64_t)ctx->split << 16);
+    out->n_groups = ctx->built ? ctx->ngroups : 0;
+    out->n_tasks = ctx->built ? ctx->ntasks : 0;
     return WNNC_OK;
 }
 

@@ -77,7 +77,15 @@ enum TravMode {
     TR_TSUM = 3,        // A: block partial of s^2 only
     TR_RESCALE = 4,     // G: mu <- G |mu| / |G| (sorted float4)
     TR_SCALE = 5,       // A: block partials of s and s^2 (warm-start scale)
+    TR_PLAN = 6,        // no output: record the walk of each group (split planning)
 };
+
+// Split planning: the walk of every 64-target group is recorded as its node
+// visit count and the node at every kPlanStep-th visit (up to kPlanCap of
+// them), kPlanStride ints per group.
+constexpr int kPlanStep = 64;
+constexpr int kPlanCap = 63;
+constexpr int kPlanStride = kPlanCap + 1;
 
 struct MomArgs {
     const float4 *pts;       // sorted points
@@ -101,7 +109,7 @@ struct MomArgs {
     double *chunk_tot;       // 8 doubles per chunk
     double *head;            // 8 doubles per straddler
     double *tail;            // 8 doubles per straddler
-    float4 *mom;             // node records, 2 float4 per node
+    float4 *mom;             // node records, kRecStride float4 per node
     float *wout;             // optional: W = sum |nu| per node (inspection)
     float thr2[16];          // (c * 2^(1-d))^2 per depth d, copied into records
     int n;
@@ -122,9 +130,13 @@ struct TravArgs {
     unsigned long long *pairs;  // pair counter (counting variant)
     unsigned long long *flips;  // TR_RESCALE: per cloud, updates against mu (or null)
     const int32_t *cloud;    // cloud of each sorted point (for flips)
-    const int4 *tasks;       // per wavefront: first, last target; root, end node
-    const int32_t *task_slot;
-    int ntasks;
+    const int4 *tasks;       // per wavefront: first, last target; first, end node
+    const int32_t *task_slot;  // >= 0: group slot (whole walk); < 0: -1 - part slot
+    const int32_t *roots;    // first node of each cloud (nclouds + 1)
+    double *parts;           // per part slot: 3 x 64 FP64 sums (component-major)
+    int32_t *plan;           // TR_PLAN output, kPlanStride ints per group
+    int ntasks;              // wavefronts launched
+    int nslots;              // groups: row stride of the per-group partial sums
     int tpl;                 // target groups of 64 per wavefront (1, 2, 4)
     int prefetch;            // software-pipelined node walk
     int n, m;
@@ -186,7 +198,7 @@ struct wnnc_ctx_s {
     DevBuf<int32_t> tail_list;     // n_strad
     DevBuf<double> chunk_tot;      // 8 per chunk
     DevBuf<double> head, tail;     // 8 per straddler
-    DevBuf<float4> mom;            // 2 per node
+    DevBuf<float4> mom;            // kRecStride per node
     DevBuf<float> wbuf;            // per-node W, filled on request
 
     // build scratch
@@ -206,18 +218,30 @@ struct wnnc_ctx_s {
     DevBuf<int64_t> d_offsets;     // nclouds + 1
     DevBuf<int32_t> d_roots;       // nclouds + 1
     DevBuf<int32_t> cloud_of;      // n: cloud of each sorted point
-    // wavefront tasks for the current tile shape
+    // wavefront tasks for the current tile shape.  A group is 64 * tpl
+    // consecutive targets of one cloud; its walk runs as one task, or, split
+    // into parts of about `split` node visits, as one task per part plus a
+    // combining pass (only for tpl = 1).
     int tpl = 1;
     int prefetch = 0;
-    int ntasks = 0;
+    int split = 0;
+    int ntasks = 0;                // tasks launched per traversal
+    int ngroups = 0;               // groups (per-group partial sums)
+    int nparts = 0;                // part slots
+    int nsplit = 0;                // groups walked in parts
     DevBuf<int4> tasks;
     DevBuf<int32_t> task_slot;
-    DevBuf<int32_t> task_lo;       // nclouds + 1: task range of each cloud
+    DevBuf<int32_t> task_lo;       // nclouds + 1: group range of each cloud
+    DevBuf<int4> split_groups;     // nsplit: first, last target; first, end part slot
+    DevBuf<int32_t> split_slot;    // nsplit: group slot
+    DevBuf<double> parts;          // nparts * 3 * 64
+    std::vector<int32_t> plan;     // host: recorded walks of the 64-target groups
+    DevBuf<int32_t> d_plan;
 
     // iteration buffers (sorted order)
     DevBuf<float4> va, vb, vr;
     DevBuf<float> rho;
-    DevBuf<double> partial;        // 3 * traversal blocks
+    DevBuf<double> partial;        // 3 rows of ngroups per-group sums
     DevBuf<double> scalars;        // alpha per cloud
     DevBuf<double> energy;
     int last_energy_count = 0;

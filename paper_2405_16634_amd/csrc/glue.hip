@@ -9,7 +9,7 @@ namespace wnnc {
 // cloud), 0 when the denominator is 0.  The cloud's per-task partial sums
 // are reduced in a fixed order.  Also stores the energy E = |rho|^2 of the
 // iteration (N_c / 4 for the iteration started from mu = 0).
-__global__ __launch_bounds__(256) void k_alpha(const double *__restrict__ partial, int ntasks,
+__global__ __launch_bounds__(256) void k_alpha(const double *__restrict__ partial, int nslots,
                                                const int32_t *__restrict__ task_lo,
                                                const int64_t *__restrict__ off, int first,
                                                double *__restrict__ alpha,
@@ -20,8 +20,8 @@ __global__ __launch_bounds__(256) void k_alpha(const double *__restrict__ partia
     double acc[3] = {0.0, 0.0, 0.0};
     for (int i = lo + threadIdx.x; i < hi; i += 256) {
         if (!first) acc[0] += partial[i];
-        acc[1] += partial[ntasks + i];
-        acc[2] += partial[2 * ntasks + i];
+        acc[1] += partial[nslots + i];
+        acc[2] += partial[2 * nslots + i];
     }
     for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] = acc[k];
     __syncthreads();
@@ -39,14 +39,14 @@ __global__ __launch_bounds__(256) void k_alpha(const double *__restrict__ partia
 
 hipError_t launch_alpha(wnnc_ctx_s *ctx, bool first, double *energy_row) {
     hipLaunchKernelGGL(k_alpha, dim3(ctx->nclouds), dim3(256), 0, ctx->stream, ctx->partial.p,
-                       ctx->ntasks, ctx->task_lo.p, ctx->d_offsets.p, first ? 1 : 0,
+                       ctx->ngroups, ctx->task_lo.p, ctx->d_offsets.p, first ? 1 : 0,
                        ctx->scalars.p, energy_row);
     return hipGetLastError();
 }
 
 // beta_c = (1/2) sum s / sum s^2 over cloud c (the least-squares uniform
 // scale of the predicted normals against b = 1/2), 0 if sum s^2 = 0.
-__global__ __launch_bounds__(256) void k_warm_beta(const double *__restrict__ partial, int ntasks,
+__global__ __launch_bounds__(256) void k_warm_beta(const double *__restrict__ partial, int nslots,
                                                    const int32_t *__restrict__ task_lo,
                                                    double *__restrict__ beta) {
     __shared__ double sh[2][256];
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void k_warm_beta(const double *__restrict__ pa
     double a = 0.0, b = 0.0;
     for (int i = task_lo[c] + threadIdx.x; i < task_lo[c + 1]; i += 256) {
         a += partial[i];
-        b += partial[ntasks + i];
+        b += partial[nslots + i];
     }
     sh[0][threadIdx.x] = a;
     sh[1][threadIdx.x] = b;
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void k_warm_apply(const float4 *__restrict__ n
 
 hipError_t launch_warm_scale(wnnc_ctx_s *ctx, const float4 *n_sorted, float4 *mu0) {
     hipLaunchKernelGGL(k_warm_beta, dim3(ctx->nclouds), dim3(256), 0, ctx->stream, ctx->partial.p,
-                       ctx->ntasks, ctx->task_lo.p, ctx->scalars.p);
+                       ctx->ngroups, ctx->task_lo.p, ctx->scalars.p);
     hipLaunchKernelGGL(k_warm_apply, dim3((unsigned)((ctx->n + 255) / 256)), dim3(256), 0,
                        ctx->stream, n_sorted, ctx->cloud_of.p, ctx->scalars.p, ctx->n, mu0);
     return hipGetLastError();
@@ -128,7 +128,43 @@ __global__ __launch_bounds__(256) void k_normals(const float *mu, int64_t n, flo
     if (area) area[i] = (float)(l * inv_s2);
 }
 
+// Per cloud, the number of points whose sorted mu points against the
+// prediction nhat (caller order): mu . nhat <= 0 with mu nonzero.  One atomic
+// per wavefront when its points share a cloud.
+__global__ __launch_bounds__(256) void k_pred_disagree(const float4 *__restrict__ mu,
+                                                       const float *__restrict__ nhat,
+                                                       const uint32_t *__restrict__ perm,
+                                                       const int32_t *__restrict__ cloud, int64_t n,
+                                                       unsigned long long *__restrict__ count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = false;
+    int c = -1;
+    if (i < n) {
+        const float4 m = mu[i];
+        const int64_t j = perm[i];
+        const double d = (double)m.x * nhat[3 * j] + (double)m.y * nhat[3 * j + 1] +
+                         (double)m.z * nhat[3 * j + 2];
+        bad = (m.x != 0.f || m.y != 0.f || m.z != 0.f) && d <= 0.0;
+        c = cloud[i];
+    }
+    const int c0 = __shfl(c, 0, 64);
+    const bool same = __all(c == c0 || c < 0);
+    if (same) {
+        const unsigned long long k = __popcll(__ballot(bad));
+        if ((threadIdx.x & 63) == 0 && k) atomicAdd(count + c0, k);
+    } else if (bad) {
+        atomicAdd(count + c, 1ull);
+    }
+}
+
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t launch_pred_disagree(wnnc_ctx_s *ctx, const float4 *mu, const float *nhat,
+                                unsigned long long *count) {
+    hipLaunchKernelGGL(k_pred_disagree, dim3(nblk(ctx->n)), dim3(256), 0, ctx->stream, mu, nhat,
+                       ctx->perm.p, ctx->cloud_of.p, ctx->n, count);
+    return hipGetLastError();
+}
 
 hipError_t launch_zero_f4(float4 *p, int64_t n, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_f4, dim3(nblk(n)), dim3(256), 0, st, p, n);

@@ -5,6 +5,13 @@
 
 namespace wnnc {
 
+// Returns a HIP error from the enclosing function (host code).
+#define TRY(x)                           \
+    do {                                 \
+        hipError_t _e = (x);             \
+        if (_e != hipSuccess) return _e; \
+    } while (0)
+
 int64_t scan_tmp_size(int64_t n);
 hipError_t exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp,
                               hipStream_t st);
@@ -17,7 +24,9 @@ int64_t launch_normalize(const float *P, int64_t n, const int64_t *d_off, int nc
                          float *P_norm, double *tmp, hipStream_t st);
 int64_t normalize_tmp_doubles(int64_t nclouds);
 hipError_t build_tree(wnnc_ctx_s *ctx, const float *P);
-hipError_t make_tasks(wnnc_ctx_s *ctx, int tpl);
+// Wavefront tasks for tile shape tpl and split size `split` (node visits per
+// part, 0 = whole walks; used only with tpl = 1 and a recorded plan).
+hipError_t make_tasks(wnnc_ctx_s *ctx, int tpl, int split);
 
 // Moment pass (moments.hip): two launches, chunk pass then straddler pass.
 hipError_t launch_moments(wnnc_ctx_s *ctx, MomMode mode, const MomArgs &a);
@@ -25,9 +34,12 @@ hipError_t launch_moments(wnnc_ctx_s *ctx, MomMode mode, const MomArgs &a);
 // Traversal (traverse.hip).
 hipError_t launch_traverse(wnnc_ctx_s *ctx, Op op, TravMode mode, bool count, const TravArgs &a);
 int trav_blocks(int64_t ntasks);
+// Records the walk of every 64-target group (ctx->plan) for split planning;
+// the tasks must be whole walks of single 64-target groups.
+hipError_t record_plan(wnnc_ctx_s *ctx, const TravArgs &a);
 
 // Glue (glue.hip).
-// Step length per cloud from the per-task partial sums; first = the
+// Step length per cloud from the per-group partial sums; first = the
 // iteration started from mu = 0 (its energy is N_c / 4).  energy_row holds
 // one entry per cloud.
 hipError_t launch_alpha(wnnc_ctx_s *ctx, bool first, double *energy_row);
@@ -49,6 +61,10 @@ hipError_t mlp_loss_grad(wnnc_ctx_s *ctx, const float *P, const float *X, const 
 // mu0[i] = beta_c n[i] (sorted) with beta_c = (1/2) sum s / sum s^2 over
 // cloud c from the TR_SCALE partials.
 hipError_t launch_warm_scale(wnnc_ctx_s *ctx, const float4 *n_sorted, float4 *mu0);
+// count[c] += points of cloud c whose sorted mu points against the caller-
+// order prediction nhat (N,3).
+hipError_t launch_pred_disagree(wnnc_ctx_s *ctx, const float4 *mu, const float *nhat,
+                                unsigned long long *count);
 hipError_t mlp_adam(wnnc_ctx_s *ctx, float *P, float *m, float *v, const float *g, int step,
                     float lr, float b1, float b2, float eps);
 

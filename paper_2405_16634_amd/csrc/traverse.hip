@@ -102,10 +102,88 @@ __device__ inline unsigned long long read_mask(uint32_t lo, uint32_t hi, int dep
            ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)hi, depth) << 32);
 }
 
+// Per-target epilogue from the FP64 sums of target t (sorted position);
+// accumulates the target's share of the per-group reductions.
+template <int OP, int MODE>
+__device__ inline void finish_target(const TravArgs &a, int t, double s, double gx, double gy,
+                                     double gz, double &e, double &e2, unsigned &nflip) {
+    if (MODE == TR_OUT_CALLER) {
+        const int64_t j = a.perm[t];
+        if (OP == OP_A) {
+            a.out[j] = (float)(s * kInv4Pi);
+        } else {
+            const double sg = OP == OP_G ? -kInv4Pi : kInv4Pi;  // grad F = -G
+            a.out[3 * j] = (float)(gx * sg);
+            a.out[3 * j + 1] = (float)(gy * sg);
+            a.out[3 * j + 2] = (float)(gz * sg);
+        }
+    } else if (MODE == TR_RHO) {
+        const float rho = (float)(0.5 - s * kInv4Pi);
+        a.rho[t] = rho;
+        e += (double)rho * (double)rho;
+    } else if (MODE == TR_R) {
+        const float rx = (float)(gx * kInv4Pi), ry = (float)(gy * kInv4Pi),
+                    rz = (float)(gz * kInv4Pi);
+        a.out4[t] = make_float4(rx, ry, rz, 0.f);
+        e += (double)rx * rx + (double)ry * ry + (double)rz * rz;
+    } else if (MODE == TR_TSUM) {
+        const double tv = (double)(float)(s * kInv4Pi);
+        e += tv * tv;
+    } else if (MODE == TR_SCALE) {
+        const double tv = (double)(float)(s * kInv4Pi);
+        e += tv;
+        e2 += tv * tv;
+    } else if (MODE == TR_RESCALE) {
+        const float4 mu = a.src4[t];
+        const double g2 = gx * gx + gy * gy + gz * gz;
+        float4 o = mu;
+        if (g2 > 0.0 && g2 <= DBL_MAX) {
+            const double mn = sqrt((double)mu.x * mu.x + (double)mu.y * mu.y + (double)mu.z * mu.z);
+            const double f = mn / sqrt(g2);
+            o = make_float4((float)(gx * f), (float)(gy * f), (float)(gz * f), 0.f);
+        }
+        a.out4[t] = o;
+        if ((double)mu.x * gx + (double)mu.y * gy + (double)mu.z * gz < 0.0) ++nflip;
+    }
+}
+
+// Per-group reductions of a wavefront (one group slot), in a fixed order.
+template <int MODE>
+__device__ inline void finish_group(const TravArgs &a, int sl, int first, int lane, double e,
+                                    double e2, unsigned nflip) {
+    if (MODE == TR_RESCALE && a.flips) {
+        unsigned tot = nflip;
+#pragma unroll
+        for (int d = kWave / 2; d > 0; d >>= 1) tot += __shfl_xor(tot, d, kWave);
+        if (lane == 0 && tot) atomicAdd(a.flips + a.cloud[first], (unsigned long long)tot);
+    }
+    if (MODE == TR_SCALE) {
+        e = wave_sum(e);
+        e2 = wave_sum(e2);
+        if (lane == 0) {
+            a.partial[sl] = e;
+            a.partial[a.nslots + sl] = e2;
+        }
+    }
+    if (MODE == TR_RHO || MODE == TR_R || MODE == TR_TSUM) {
+        e = wave_sum(e);  // fixed butterfly order: reproducible
+        if (lane == 0) a.partial[sl] = e;
+    }
+}
+
 // One wavefront per task: TPL groups of 64 consecutive sorted targets
-// (group k holds targets first + 64k + lane) walk the node range
-// [root, end) of their cloud together.  Each group keeps its own mask stack
-// and Alg. 4 decisions; the groups share the node loads and the control.
+// (group k holds targets first + 64k + lane) walk the pre-order node range
+// [first node, end node) of their cloud together.  Each group keeps its own
+// mask stack and Alg. 4 decisions; the groups share the node loads and the
+// control.
+//
+// A task whose range starts below the cloud's root is one part of a walk
+// split for load balance (TPL = 1 only): the lanes' decisions at the
+// ancestors of its first node are evaluated again (without their terms) to
+// rebuild the mask stack, so the part makes exactly the decisions, and adds
+// exactly the terms, that the whole walk makes over that node range.  The
+// part's FP64 sums go to its part slot; k_combine adds the parts in order.
+//
 // PF: software pipelining of the node walk.  A node's successor is its skip
 // pointer (subtree done) or the next node (descend); the skip successor's
 // record is loaded while the node is visited, so that load overlaps the
@@ -125,13 +203,15 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
     const int wave = lb * (kTravBlock / kWave) + wv;
     if (wave >= a.ntasks) return;
     const int4 task = ldc_i4(a.tasks + wave);
-    const int first = task.x, last = task.y, root = task.z, rend = task.w;
+    const int first = task.x, last = task.y, nbeg = task.z, nend = task.w;
+    const int tslot = ldc_i(a.task_slot + wave);
 
     float tx[TPL], ty[TPL], tz[TPL];
     double s[TPL], gx[TPL], gy[TPL], gz[TPL];
     bool valid[TPL];
     uint32_t mlo[TPL], mhi[TPL];
     uint32_t cnt = 0;
+    int visits = 0;
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
         const int t = first + k * kWave + lane;
@@ -147,8 +227,50 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
         mlo[k] = lane == 0 ? (uint32_t)act0 : 0u;
         mhi[k] = lane == 0 ? (uint32_t)(act0 >> 32) : 0u;
     }
+
+    // A part: the decisions at the ancestors of its first node, from the
+    // cloud's root down (at most one ancestor per depth, at most 8 children
+    // per node, so both loops end on any input).
+    {
+        int node = ldc_i(a.roots + ldc_i(a.cloud + first));
+        for (int d = 0; d < kMaxDepth && node < nbeg; ++d) {
+            const v16f R = ld_rec(a.mom, node);
+            const int flags = __float_as_int(R[3]);
+            const int depth = flags & 15;
+#pragma unroll
+            for (int k = 0; k < TPL; ++k) {
+                unsigned long long open = 0ull;  // a zero-weight node is not descended
+                if (!(flags & kRecZero)) {
+                    const unsigned long long act = read_mask(mlo[k], mhi[k], depth);
+                    const float dx = (tx[k] - R[0]) - R[8], dy = (ty[k] - R[1]) - R[9],
+                                dz = (tz[k] - R[2]) - R[10];
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    open = act & ~__ballot(r2 > R[11]);
+                }
+                if (lane == depth + 1) {
+                    mlo[k] = (uint32_t)open;
+                    mhi[k] = (uint32_t)(open >> 32);
+                }
+            }
+            // the child whose subtree holds the first node
+            int ch = node + 1;
+            for (int c = 0; c < 8; ++c) {
+                const int sk = ldc_i((const int *)(a.mom + kRecStride * ch + 1) + 3);
+                if (sk > nbeg) break;
+                ch = sk;
+            }
+            node = ch;
+        }
+    }
+
     // One node visit for all groups; returns the next node in pre-order.
     auto visit = [&](const v16f &R, int node) -> int {
+        if (MODE == TR_PLAN) {
+            if (visits > 0 && visits % kPlanStep == 0 && visits / kPlanStep <= kPlanCap &&
+                lane == 0)
+                a.plan[(int64_t)tslot * kPlanStride + visits / kPlanStep] = node;
+            ++visits;
+        }
         const int flags = __float_as_int(R[3]);
         const int skip = __float_as_int(R[7]);
         if (flags & kRecZero) return skip;  // every attribute in the node is zero
@@ -210,98 +332,81 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
     };
 
     if (!PF) {
-        for (int node = root; node < rend;) node = visit(ld_rec(a.mom, node), node);
-    } else if (root < rend) {
+        for (int node = nbeg; node < nend;) node = visit(ld_rec(a.mom, node), node);
+    } else if (nbeg < nend) {
         // Two record buffers used in turn.  While a node is visited, the
         // record of its skip successor is loaded into the other buffer; when
         // the walk descends instead, that buffer is reloaded with the first
-        // child.  (Loads past the cloud's last node are clamped to it.)
-        int node = root;
+        // child.  (Loads past the range's last node are clamped to it.)
+        int node = nbeg;
         v16f RA = ld_rec(a.mom, node), RB;
         for (;;) {
             int sk = __float_as_int(RA[7]);
-            RB = ld_rec(a.mom, min(sk, rend - 1));
+            RB = ld_rec(a.mom, min(sk, nend - 1));
             int nx = visit(RA, node);
-            if (nx >= rend) break;
+            if (nx >= nend) break;
             if (nx != sk) RB = ld_rec(a.mom, nx);
             node = nx;
             sk = __float_as_int(RB[7]);
-            RA = ld_rec(a.mom, min(sk, rend - 1));
+            RA = ld_rec(a.mom, min(sk, nend - 1));
             nx = visit(RB, node);
-            if (nx >= rend) break;
+            if (nx >= nend) break;
             if (nx != sk) RA = ld_rec(a.mom, nx);
             node = nx;
         }
     }
 
-    // epilogues
-    double e = 0.0, e2 = 0.0;
-    unsigned nflip = 0;
-#pragma unroll
-    for (int k = 0; k < TPL; ++k) {
-        const int t = first + k * kWave + lane;
-        if (!valid[k]) continue;
-        if (MODE == TR_OUT_CALLER) {
-            const int64_t j = a.perm[t];
-            if (OP == OP_A) {
-                a.out[j] = (float)(s[k] * kInv4Pi);
-            } else {
-                const double sg = OP == OP_G ? -kInv4Pi : kInv4Pi;  // grad F = -G
-                a.out[3 * j] = (float)(gx[k] * sg);
-                a.out[3 * j + 1] = (float)(gy[k] * sg);
-                a.out[3 * j + 2] = (float)(gz[k] * sg);
-            }
-        } else if (MODE == TR_RHO) {
-            const float rho = (float)(0.5 - s[k] * kInv4Pi);
-            a.rho[t] = rho;
-            e += (double)rho * (double)rho;
-        } else if (MODE == TR_R) {
-            const float rx = (float)(gx[k] * kInv4Pi), ry = (float)(gy[k] * kInv4Pi),
-                        rz = (float)(gz[k] * kInv4Pi);
-            a.out4[t] = make_float4(rx, ry, rz, 0.f);
-            e += (double)rx * rx + (double)ry * ry + (double)rz * rz;
-        } else if (MODE == TR_TSUM) {
-            const double tv = (double)(float)(s[k] * kInv4Pi);
-            e += tv * tv;
-        } else if (MODE == TR_SCALE) {
-            const double tv = (double)(float)(s[k] * kInv4Pi);
-            e += tv;
-            e2 += tv * tv;
-        } else if (MODE == TR_RESCALE) {
-            const float4 mu = a.src4[t];
-            const double g2 = gx[k] * gx[k] + gy[k] * gy[k] + gz[k] * gz[k];
-            float4 o = mu;
-            if (g2 > 0.0 && g2 <= DBL_MAX) {
-                const double mn = sqrt((double)mu.x * mu.x + (double)mu.y * mu.y + (double)mu.z * mu.z);
-                const double f = mn / sqrt(g2);
-                o = make_float4((float)(gx[k] * f), (float)(gy[k] * f), (float)(gz[k] * f), 0.f);
-            }
-            a.out4[t] = o;
-            if ((double)mu.x * gx[k] + (double)mu.y * gy[k] + (double)mu.z * gz[k] < 0.0) ++nflip;
-        }
-    }
-    if (MODE == TR_RESCALE && a.flips) {
-        unsigned tot = nflip;
-#pragma unroll
-        for (int d = kWave / 2; d > 0; d >>= 1) tot += __shfl_xor(tot, d, kWave);
-        if (lane == 0 && tot) atomicAdd(a.flips + ldc_i(a.cloud + first), (unsigned long long)tot);
-    }
-    if (MODE == TR_SCALE) {
-        e = wave_sum(e);
-        e2 = wave_sum(e2);
-        if (lane == 0) {
-            const int sl = ldc_i(a.task_slot + wave);
-            a.partial[sl] = e;
-            a.partial[a.ntasks + sl] = e2;
-        }
-    }
-    if (MODE == TR_RHO || MODE == TR_R || MODE == TR_TSUM) {
-        e = wave_sum(e);  // fixed butterfly order: reproducible
-        if (lane == 0) a.partial[ldc_i(a.task_slot + wave)] = e;
-    }
     if (COUNT) {  // cnt is wave-uniform: the pairs of all lanes
         if (lane == 0) atomicAdd(a.pairs + OP, (unsigned long long)cnt);
     }
+    if (MODE == TR_PLAN) {
+        if (lane == 0) a.plan[(int64_t)tslot * kPlanStride] = visits;
+        return;
+    }
+    if (tslot < 0) {  // one part of a split walk (TPL = 1): its sums
+        double *qp = a.parts + (int64_t)(-1 - tslot) * (3 * kWave);
+        if (OP == OP_A) {
+            qp[lane] = s[0];
+        } else {
+            qp[lane] = gx[0];
+            qp[kWave + lane] = gy[0];
+            qp[2 * kWave + lane] = gz[0];
+        }
+        return;
+    }
+    double e = 0.0, e2 = 0.0;
+    unsigned nflip = 0;
+#pragma unroll
+    for (int k = 0; k < TPL; ++k)
+        if (valid[k])
+            finish_target<OP, MODE>(a, first + k * kWave + lane, s[k], gx[k], gy[k], gz[k], e, e2,
+                                    nflip);
+    finish_group<MODE>(a, tslot, first, lane, e, e2, nflip);
+}
+
+// Groups walked in parts: one wavefront per group adds its parts' sums in
+// part order and runs the epilogue.
+template <int OP, int MODE>
+__global__ __launch_bounds__(kWave) void k_combine(TravArgs a, const int4 *__restrict__ groups,
+                                                   const int32_t *__restrict__ gslot) {
+    const int lane = threadIdx.x;
+    const int4 g = ldc_i4(groups + blockIdx.x);
+    double s = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int p = g.z; p < g.w; ++p) {
+        const double *qp = a.parts + (int64_t)p * (3 * kWave);
+        if (OP == OP_A) {
+            s += qp[lane];
+        } else {
+            gx += qp[lane];
+            gy += qp[kWave + lane];
+            gz += qp[2 * kWave + lane];
+        }
+    }
+    double e = 0.0, e2 = 0.0;
+    unsigned nflip = 0;
+    const int t = g.x + lane;
+    if (t < g.y) finish_target<OP, MODE>(a, t, s, gx, gy, gz, e, e2, nflip);
+    finish_group<MODE>(a, ldc_i(gslot + blockIdx.x), g.x, lane, e, e2, nflip);
 }
 
 int trav_blocks(int64_t ntasks) {
@@ -325,33 +430,44 @@ static void launch_tpl(bool count, const TravArgs &a, hipStream_t st) {
 }
 
 template <int OP, int MODE>
-static hipError_t launch_one(bool count, int tpl, const TravArgs &a, hipStream_t st) {
+static hipError_t launch_one(wnnc_ctx_s *ctx, bool count, const TravArgs &a) {
+    hipStream_t st = ctx->stream;
     if (a.ntasks <= 0) return hipSuccess;
-    switch (tpl) {
+    switch (a.tpl) {
         case 1: launch_tpl<OP, MODE, 1>(count, a, st); break;
         case 2: launch_tpl<OP, MODE, 2>(count, a, st); break;
         case 4: launch_tpl<OP, MODE, 4>(count, a, st); break;
         default: return hipErrorInvalidValue;
     }
+    if (ctx->nsplit > 0)
+        hipLaunchKernelGGL((k_combine<OP, MODE>), dim3((unsigned)ctx->nsplit), dim3(kWave), 0, st,
+                           a, ctx->split_groups.p, ctx->split_slot.p);
     return hipGetLastError();
 }
 
 hipError_t launch_traverse(wnnc_ctx_s *ctx, Op op, TravMode mode, bool count, const TravArgs &a) {
-    hipStream_t st = ctx->stream;
-    const int tpl = a.tpl;
     if (op == OP_A) {
-        if (mode == TR_OUT_CALLER) return launch_one<OP_A, TR_OUT_CALLER>(count, tpl, a, st);
-        if (mode == TR_RHO) return launch_one<OP_A, TR_RHO>(count, tpl, a, st);
-        if (mode == TR_TSUM) return launch_one<OP_A, TR_TSUM>(count, tpl, a, st);
-        if (mode == TR_SCALE) return launch_one<OP_A, TR_SCALE>(count, tpl, a, st);
+        if (mode == TR_OUT_CALLER) return launch_one<OP_A, TR_OUT_CALLER>(ctx, count, a);
+        if (mode == TR_RHO) return launch_one<OP_A, TR_RHO>(ctx, count, a);
+        if (mode == TR_TSUM) return launch_one<OP_A, TR_TSUM>(ctx, count, a);
+        if (mode == TR_SCALE) return launch_one<OP_A, TR_SCALE>(ctx, count, a);
     } else if (op == OP_AT) {
-        if (mode == TR_OUT_CALLER) return launch_one<OP_AT, TR_OUT_CALLER>(count, tpl, a, st);
-        if (mode == TR_R) return launch_one<OP_AT, TR_R>(count, tpl, a, st);
+        if (mode == TR_OUT_CALLER) return launch_one<OP_AT, TR_OUT_CALLER>(ctx, count, a);
+        if (mode == TR_R) return launch_one<OP_AT, TR_R>(ctx, count, a);
     } else {
-        if (mode == TR_OUT_CALLER) return launch_one<OP_G, TR_OUT_CALLER>(count, tpl, a, st);
-        if (mode == TR_RESCALE) return launch_one<OP_G, TR_RESCALE>(count, tpl, a, st);
+        if (mode == TR_OUT_CALLER) return launch_one<OP_G, TR_OUT_CALLER>(ctx, count, a);
+        if (mode == TR_RESCALE) return launch_one<OP_G, TR_RESCALE>(ctx, count, a);
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t record_plan(wnnc_ctx_s *ctx, const TravArgs &a) {
+    if (a.ntasks <= 0) return hipSuccess;
+    if (a.tpl != 1 || ctx->nsplit != 0) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)trav_blocks(a.ntasks)), block(kTravBlock);
+    hipLaunchKernelGGL((k_traverse<OP_AT, TR_PLAN, false, 1, false>), grid, block, 0, ctx->stream,
+                       a);
+    return hipGetLastError();
 }
 
 }  // namespace wnnc

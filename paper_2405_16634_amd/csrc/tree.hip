@@ -12,6 +12,7 @@
 // index range.
 #include <float.h>
 
+#include <algorithm>
 #include <utility>
 #include <vector>
 
@@ -373,12 +374,6 @@ __global__ __launch_bounds__(256) void k_tail_fill(const int32_t *__restrict__ s
 
 // ------------------------------------------------------------------- host --
 
-#define TRY(x)                           \
-    do {                                 \
-        hipError_t _e = (x);             \
-        if (_e != hipSuccess) return _e; \
-    } while (0)
-
 static inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 // Builds the forest over the normalized points P (caller order); the cloud
@@ -506,35 +501,89 @@ hipError_t build_tree(wnnc_ctx_s *ctx, const float *P) {
 // Wavefront tasks for tile shape tpl: each cloud's sorted targets cut into
 // runs of 64 * tpl, in Morton order, cloud after cloud.  The partial-sum
 // slot of a task is its index, so a cloud's slots are contiguous.
-hipError_t make_tasks(wnnc_ctx_s *ctx, int tpl) {
+hipError_t make_tasks(wnnc_ctx_s *ctx, int tpl, int split) {
     const int per = kWave * tpl;
-    std::vector<int4> tk;
+    const bool use_plan = split > 0 && tpl == 1 && !ctx->plan.empty();
+    std::vector<int4> tk, sg;
+    std::vector<int32_t> slot, sslot;
     std::vector<int32_t> lo(ctx->nclouds + 1);
+    std::vector<int32_t> cut;
+    int32_t g = 0, nparts = 0;
     for (int c = 0; c < ctx->nclouds; ++c) {
-        lo[c] = (int32_t)tk.size();
+        lo[c] = g;
         const int64_t a = ctx->offsets[c], b = ctx->offsets[c + 1];
-        for (int64_t f = a; f < b; f += per)
-            tk.push_back(make_int4((int)f, (int)(f + per < b ? f + per : b), ctx->roots[c],
-                                   ctx->roots[c + 1]));
+        const int root = ctx->roots[c], rend = ctx->roots[c + 1];
+        for (int64_t f = a; f < b; f += per, ++g) {
+            const int l = (int)(f + per < b ? f + per : b);
+            // cut points: nodes the recorded walk reaches near every
+            // split-th visit (the walk moves forward in pre-order, so they
+            // increase)
+            cut.clear();
+            if (use_plan) {
+                const int32_t *pl = ctx->plan.data() + (size_t)g * kPlanStride;
+                const int64_t V = pl[0];
+                const int P = (int)((V + split - 1) / split);
+                const int kmax = (int)std::min<int64_t>(kPlanCap, V > 0 ? (V - 1) / kPlanStep : 0);
+                int prev = root;
+                for (int q = 1; q < P; ++q) {
+                    const int64_t v = V * q / P;
+                    int k = (int)((v + kPlanStep / 2) / kPlanStep);
+                    k = std::min(std::max(k, 1), kmax);
+                    if (k < 1) continue;
+                    const int nd = pl[k];
+                    if (nd > prev && nd < rend) {
+                        cut.push_back(nd);
+                        prev = nd;
+                    }
+                }
+            }
+            if (cut.empty()) {
+                tk.push_back(make_int4((int)f, l, root, rend));
+                slot.push_back(g);
+                continue;
+            }
+            const int P = (int)cut.size() + 1;
+            sg.push_back(make_int4((int)f, l, nparts, nparts + P));
+            sslot.push_back(g);
+            int s0 = root;
+            for (int q = 0; q < P; ++q) {
+                const int e = q + 1 < P ? cut[q] : rend;
+                tk.push_back(make_int4((int)f, l, s0, e));
+                slot.push_back(-1 - (nparts + q));
+                s0 = e;
+            }
+            nparts += P;
+        }
     }
-    lo[ctx->nclouds] = (int32_t)tk.size();
-    const int64_t nt = (int64_t)tk.size();
-    std::vector<int32_t> slot((size_t)nt);
-    for (int64_t k = 0; k < nt; ++k) slot[k] = (int32_t)k;
+    lo[ctx->nclouds] = g;
+    const int64_t nt = (int64_t)tk.size(), ns = (int64_t)sg.size();
     TRY(ctx->tasks.ensure(nt));
     TRY(ctx->task_slot.ensure(nt));
     TRY(ctx->task_lo.ensure(ctx->nclouds + 1));
-    TRY(ctx->partial.ensure(3 * nt));
+    TRY(ctx->partial.ensure(3 * (int64_t)g));
+    TRY(ctx->split_groups.ensure(ns > 0 ? ns : 1));
+    TRY(ctx->split_slot.ensure(ns > 0 ? ns : 1));
+    TRY(ctx->parts.ensure(nparts > 0 ? (int64_t)nparts * 3 * kWave : 1));
     TRY(hipMemcpyAsync(ctx->tasks.p, tk.data(), (size_t)nt * sizeof(int4), hipMemcpyHostToDevice,
                        ctx->stream));
     TRY(hipMemcpyAsync(ctx->task_slot.p, slot.data(), (size_t)nt * sizeof(int32_t),
                        hipMemcpyHostToDevice, ctx->stream));
     TRY(hipMemcpyAsync(ctx->task_lo.p, lo.data(), lo.size() * sizeof(int32_t),
                        hipMemcpyHostToDevice, ctx->stream));
+    if (ns > 0) {
+        TRY(hipMemcpyAsync(ctx->split_groups.p, sg.data(), (size_t)ns * sizeof(int4),
+                           hipMemcpyHostToDevice, ctx->stream));
+        TRY(hipMemcpyAsync(ctx->split_slot.p, sslot.data(), (size_t)ns * sizeof(int32_t),
+                           hipMemcpyHostToDevice, ctx->stream));
+    }
     // the host vectors are released on return: wait for the copies
     TRY(hipStreamSynchronize(ctx->stream));
     ctx->ntasks = (int)nt;
+    ctx->ngroups = g;
+    ctx->nparts = nparts;
+    ctx->nsplit = (int)ns;
     ctx->tpl = tpl;
+    ctx->split = split;
     return hipSuccess;
 }
 

@@ -7,6 +7,7 @@ shapes.
 * the 40-iteration orientation of a batch agrees with running each cloud
   alone (per-cloud step lengths and energies);
 * the tile shape (targets per lane) does not change any result bit;
+* walks split into node-range parts make the same decisions as whole walks;
 * the 64-cloud workload (sizes log-uniform in [5k, 200k]) batched against
   the clouds one by one.
 """
@@ -75,7 +76,10 @@ def test_batched_normalize_and_forest(dev, oracle_mod):
     ctx.close()
 
 
-def test_batched_operators(dev, oracle_mod):
+@pytest.mark.parametrize("split", [0, 48])
+def test_batched_operators(dev, oracle_mod, split):
+    """Every cloud against the oracle; with split = 48 the walks run as many
+    short parts that start deep in the tree."""
     import torch
     import paper_2405_16634_amd as w
     clouds, off = _batch()
@@ -83,6 +87,9 @@ def test_batched_operators(dev, oracle_mod):
     ctx = w.Context(0)
     x, _ = ctx.normalize_batched(P, off)
     ctx.build_batched(x, off)
+    ctx.set_split(split)
+    st = ctx.stats()
+    assert (st["n_tasks"] > st["n_groups"]) == (split > 0)
     xh = x.cpu().numpy().astype(np.float64)
     rng = np.random.default_rng(5)
     n = int(off[-1])
@@ -157,9 +164,75 @@ def test_tile_shapes_give_identical_bits(dev):
             else:
                 for a, b in zip(ref, out):
                     assert bool((a == b).all()), (tpl, pf)
+    ctx.close()
+
+
+def _max_ulps(a, b):
+    a = a.cpu().numpy().astype(np.float32).view(np.int32).astype(np.int64)
+    b = b.cpu().numpy().astype(np.float32).view(np.int32).astype(np.int64)
+    return int(np.abs(a - b).max())
+
+
+def test_split_walks_make_the_same_decisions(dev):
+    """Walks split into node-range parts (down to 32 visits, so that parts
+    start deep in the tree and rebuild long ancestor chains) count exactly
+    the pairs of whole walks, agree with them to FP64 summation order (a few
+    FP32 ulps), and are bit-identical across prefetch settings."""
+    import torch
+    import paper_2405_16634_amd as w
+    cloud = synth.torus_knot(20000, 5, with_init=False)
+    ctx = w.Context(0)
+    x, _ = ctx.normalize(torch.from_numpy(cloud.points).to(dev))
+    ctx.build(x)
+    ngroups = (cloud.n + 63) // 64
+    rng = np.random.default_rng(2)
+    mu = torch.from_numpy((synth.random_unit(rng, cloud.n) * 1e-4).astype(np.float32)).to(dev)
+    rho = torch.from_numpy(rng.standard_normal(cloud.n).astype(np.float32)).to(dev)
+    res = {}
+    for split in (0, 32, 256):
+        for pf in (False, True):
+            ctx.set_tile(1)
+            ctx.set_split(split)
+            ctx.set_prefetch(pf)
+            assert ctx.split() == split
+            ctx.set_flags(w.FLAG_COUNT_PAIRS)
+            ctx.reset_stats()
+            out = (ctx.winding(mu, 0.002).clone(), ctx.gradient(mu, 0.002).clone(),
+                   ctx.adjoint(rho, 0.002).clone())
+            st = ctx.stats()
+            ctx.set_flags(0)
+            assert st["n_groups"] == ngroups
+            if split == 0:
+                assert st["n_tasks"] == ngroups
+            else:
+                assert st["n_tasks"] > ngroups, (split, st["n_tasks"])
+            o5 = ctx.orient(5, 0.002, 0.016).clone()
+            res[(split, pf)] = (out, list(st["pairs"]), o5)
+            print(f"  split={split} pf={int(pf)} tasks={st['n_tasks']} pairs={st['pairs']}", flush=True)
+    ref_out, ref_pairs, ref_o5 = res[(0, False)]
+    for (split, pf), (out, pairs, o5) in res.items():
+        assert pairs == ref_pairs, (split, pf)
+        other = res[(split, not pf)]
+        for a, b in zip(out, other[0]):
+            assert bool((a == b).all()), (split, pf)
+        for a, b in zip(out, ref_out):
+            assert _max_ulps(a, b) <= 4, (split, pf)
+        flip = ((o5 * ref_o5).sum(1) <= 0).float().mean().item()
+        assert flip == 0.0, (split, pf)
+    ctx.close()
+
+
+def test_autotune_keeps_the_fastest(dev):
+    import torch
+    import paper_2405_16634_amd as w
+    cloud = synth.torus_knot(20000, 5, with_init=False)
+    ctx = w.Context(0)
+    x, _ = ctx.normalize(torch.from_numpy(cloud.points).to(dev))
+    ctx.build(x)
     ms = ctx.autotune(0.002)
-    assert len(ms) == 6 and all(v > 0 for v in ms.values())
-    assert (ctx.tile(), int(ctx.prefetch())) == min(ms, key=ms.get)
+    assert len(ms) == w.AUTOTUNE_CONFIGS and all(v > 0 for v in ms.values())
+    assert {k[:2] for k in ms} == {(t, p) for t in (1, 2, 4) for p in (0, 1)}
+    assert (ctx.tile(), int(ctx.prefetch()), ctx.split()) == min(ms, key=ms.get)
     ctx.close()
 
 
