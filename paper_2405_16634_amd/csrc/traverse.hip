@@ -66,8 +66,8 @@ __device__ inline void pair_term(float dx, float dy, float dz, float r2, float4 
     const float ri3 = ri2 * ri;
     if (OP == OP_A) {
         const float dm = fmaf(dx, v.x, fmaf(dy, v.y, dz * v.z));
-        const float t = take ? -dm * ri3 : 0.0f;
-        s += (double)t;
+        const float m3 = take ? -ri3 : 0.0f;
+        s += (double)(dm * m3);
     } else if (OP == OP_AT) {
         const float f = take ? v.x * ri3 : 0.0f;
         gx += (double)(f * dx);
@@ -210,6 +210,11 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
     double s[TPL], gx[TPL], gy[TPL], gz[TPL];
     bool valid[TPL];
     uint32_t mlo[TPL], mhi[TPL];
+    // the mask of the depth visited last (equal to its stack entry), so that
+    // a visit at the same depth (a sibling, or a child after a descent)
+    // needs no read of the stack
+    unsigned long long cur[TPL];
+    int cur_depth = -1;
     uint32_t cnt = 0;
     int visits = 0;
 #pragma unroll
@@ -277,6 +282,11 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
         const int depth = flags & 15;
         const float thr2 = R[11];  // -1 for a single-point leaf: always taken
         const float4 V = make_float4(R[4], R[5], R[6], 0.f);
+        if (depth != cur_depth) {
+#pragma unroll
+            for (int k = 0; k < TPL; ++k) cur[k] = read_mask(mlo[k], mhi[k], depth);
+            cur_depth = depth;
+        }
         unsigned long long open[TPL];
         unsigned long long any = 0ull;
 #pragma unroll
@@ -284,7 +294,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
             // lanes of group k inside at this depth; of those, the ones that
             // accept the representative (far) and the ones that need B's
             // children (open), all as wave-uniform lane masks
-            const unsigned long long act = read_mask(mlo[k], mhi[k], depth);
+            const unsigned long long act = cur[k];
             // (x - hi) is exact for a target near the node; then the low part
             const float dx = (tx[k] - R[0]) - R[8], dy = (ty[k] - R[1]) - R[9],
                         dz = (tz[k] - R[2]) - R[10];
@@ -327,7 +337,9 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
                 mlo[k] = (uint32_t)open[k];
                 mhi[k] = (uint32_t)(open[k] >> 32);
             }
+            cur[k] = open[k];
         }
+        cur_depth = depth + 1;
         return node + 1;
     };
 
