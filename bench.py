@@ -16,7 +16,6 @@ of the same workload on the host cores.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -31,26 +30,22 @@ METRIC = "WNNC 40-iter time & Gpair-interactions/s at N=500k; warm-start vs plai
 FLOPS_PER_PAIR = {0: 18, 1: 18, 2: 31}  # A, A^T, G (FMA = 2, rsqrt = 1)
 KIND = {0: "A", 1: "AT", 2: "G"}
 PEAK_FP32_TFLOPS = 157.3
-TRAVERSE_SRC = os.path.join(ROOT, "paper_2405_16634_amd", "csrc", "traverse.hip")
 
 
-def source_digest(path: str) -> str:
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
-
-
-def load_traffic(kind: str):
-    """HBM bytes per launch from a committed rocprofv3 PMC summary, if it was
-    taken on the current traversal source."""
-    path = os.path.join(ROOT, "profiles", f"traffic_traverse_{kind}_torusknot500k.json")
+def load_profile(name: str):
+    """A committed rocprofv3 summary (profiles/NAME.json), if it was taken on
+    the current traversal sources."""
+    path = os.path.join(ROOT, "profiles", name + ".json")
     if not os.path.exists(path):
         return None
     try:
         d = json.load(open(path))
     except Exception:
         return None
-    if d.get("source_sha") != source_digest(TRAVERSE_SRC):
+    from paper_2405_16634_amd.profiling import traversal_digest
+    if d.get("source_sha") != traversal_digest():
         return None
-    return d.get("bytes_per_launch")
+    return d
 
 
 def cpu_baseline(cloud, w: float, c: float):
@@ -252,12 +247,21 @@ def main():
                                  gpairs_per_s=pairs_per_launch / (avg_ms * 1e-3) / 1e9)
     dom = max(per_kind, key=lambda k: per_kind[k]["total_ms"])
     d = per_kind[dom]
-    traffic = load_traffic(dom)
+    tr = load_profile(f"traffic_traverse_{dom}_torusknot500k")
     roofline = {"bound": "alu", "achieved": round(d["tflops"], 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(d["tflops"] / PEAK_FP32_TFLOPS, 4),
-                "traffic": traffic, "kernel": f"k_traverse<{dom}>",
+                "traffic": tr["bytes_per_launch"] if tr else None,
+                "kernel": f"k_traverse<{dom}>",
                 "avg_launch_ms": round(d["avg_ms"], 4),
                 "flop_per_launch": round(d["pairs_per_launch"] * FLOPS_PER_PAIR[{"A": 0, "AT": 1, "G": 2}[dom]])}
+    sq = load_profile(f"sq_traverse_{dom}_torusknot500k")
+    if sq and "SQ_INSTS_VALU" in sq["per_dispatch"]:
+        # the instruction-issue view: wave64 vector instructions per launch
+        # (committed counters) over this run's launch time
+        vi = sq["per_dispatch"]["SQ_INSTS_VALU"]
+        roofline["valu_issue"] = {"insts_per_launch": vi,
+                                  "frac": round(vi / (d["avg_ms"] * 1e-3) / sq["valu_issue_peak_per_s"], 4),
+                                  "peak_per_s": sq["valu_issue_peak_per_s"]}
 
     warm = warm_start_section(ctx, w, mu, stream, args.iters, w1, w2, cloud.normals)
 
@@ -295,6 +299,7 @@ def main():
         "tile_autotune_ms": {f"tpl{k[0]}_pf{k[1]}_split{k[2]}": round(v, 4)
                              for k, v in tile_ms.items()},
         "moments_ms_per_step": round(st["moments_ms"] / args.steps, 3),
+        "combine_ms_per_step": round(st["combine_ms"] / args.steps, 3),
         "host_wall_s_per_step": round((t_host1 - t_host0) / args.steps, 4),
         "accuracy_vs_generator": {"P_co": round(pco, 5), "AE_pcd": round(ae, 6)},
         "context_paper_rtx3090_s": {"N=50k": 1.25, "N=500k": 31.63},

@@ -108,6 +108,9 @@ typedef struct {
     int64_t n_groups;       /* target groups (64 * tile shape targets) */
     int64_t n_tasks;        /* wavefronts per traversal launch (groups, or
                                parts of split walks) */
+    double combine_ms;      /* summed time of the passes that add the parts of
+                               split walks (WNNC_FLAG_TIME_KERNELS); not in
+                               traverse_ms */
 } wnnc_stats_t;
 
 /* Create a context on HIP device `device`, enqueuing on `stream`
@@ -181,11 +184,11 @@ wnnc_status wnnc_set_prefetch(wnnc_ctx ctx, int on);
 
 /* Autotuner: times one adjoint-operator traversal at width w for each of
  * WNNC_AUTOTUNE_CONFIGS settings on the current tree and keeps the fastest:
- * (tpl, split) = (1, 0), (2, 0), (4, 0), (1, 1024), (1, 512), each with
- * prefetch off and on (in that order).  times_out (host,
+ * (tpl, split) = (1, 0), (2, 0), (4, 0), (1, 1024), (1, 512), (1, 256),
+ * each with prefetch off and on (in that order).  times_out (host,
  * WNNC_AUTOTUNE_CONFIGS entries, may be NULL) receives the settings and
  * their times.  Overwrites the context's iteration buffers.  Synchronizes. */
-#define WNNC_AUTOTUNE_CONFIGS 10
+#define WNNC_AUTOTUNE_CONFIGS 12
 typedef struct {
     int tpl;
     int prefetch;

@@ -131,6 +131,9 @@ wnnc_status run_traverse(wnnc_ctx_s *c, Op op, TravMode mode, const TravArgs &a)
     Timed tm(c, (int)op);
     HIPCHK(launch_traverse(c, op, mode, (c->flags & WNNC_FLAG_COUNT_PAIRS) != 0, a));
     tm.done();
+    Timed tc(c, 4);
+    HIPCHK(launch_combine(c, op, mode, a));
+    tc.done();
     c->calls[op] += 1;
     return WNNC_OK;
 }
@@ -437,7 +440,7 @@ wnnc_status wnnc_autotune(wnnc_ctx ctx, float w, wnnc_tile_time *times_out) {
     RETURN_IF(run_moments(ctx, MOM_CONST_HALF, ma));
     // (tpl, split) pairs, each with and without prefetch
     static const int cand[WNNC_AUTOTUNE_CONFIGS / 2][2] = {
-        {1, 0}, {2, 0}, {4, 0}, {1, 1024}, {1, 512}};
+        {1, 0}, {2, 0}, {4, 0}, {1, 1024}, {1, 512}, {1, 256}};
     double best_ms = 1e300;
     int best = ctx->tpl, best_pf = ctx->prefetch, best_split = ctx->split;
     hipEvent_t e0, e1;
@@ -455,7 +458,7 @@ wnnc_status wnnc_autotune(wnnc_ctx ctx, float w, wnnc_tile_time *times_out) {
             double t = 0.0;
             for (int rep = 0; rep < 2; ++rep) {  // first launch warms the caches
                 HIPCHK(hipEventRecord(e0, ctx->stream));
-                HIPCHK(launch_traverse(ctx, OP_AT, TR_R, false, ta));
+                HIPCHK(launch_traverse_all(ctx, OP_AT, TR_R, false, ta));
                 HIPCHK(hipEventRecord(e1, ctx->stream));
                 HIPCHK(hipEventSynchronize(e1));
                 float ms = 0.f;
@@ -774,8 +777,10 @@ wnnc_status wnnc_stats(wnnc_ctx ctx, wnnc_stats_t *out) {
         HIPCHK(hipEventElapsedTime(&ms, t.a, t.b));
         if (t.kind < 3)
             ctx->trav_ms[t.kind] += ms;
-        else
+        else if (t.kind == 3)
             ctx->mom_ms += ms;
+        else
+            ctx->comb_ms += ms;
         ctx->event_pool.push_back(t.a);
         ctx->event_pool.push_back(t.b);
     }
@@ -793,6 +798,7 @@ wnnc_status wnnc_stats(wnnc_ctx ctx, wnnc_stats_t *out) {
         out->traverse_ms[k] = ctx->trav_ms[k];
     }
     out->moments_ms = ctx->mom_ms;
+    out->combine_ms = ctx->comb_ms;
     out->build_ms = ctx->build_ms;
     out->n_clouds = ctx->built ? ctx->nclouds : 0;
     out->tile = ctx->tpl | (ctx->prefetch << 8) | ((int64_t)ctx->split << 16);
@@ -814,6 +820,7 @@ wnnc_status wnnc_reset_stats(wnnc_ctx ctx) {
         ctx->trav_ms[k] = 0;
     }
     ctx->mom_ms = 0;
+    ctx->comb_ms = 0;
     HIPCHK(ctx->pair_ctr.ensure(4));
     HIPCHK(hipMemsetAsync(ctx->pair_ctr.p, 0, 4 * sizeof(unsigned long long), ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));

@@ -260,12 +260,13 @@ struct wnnc_ctx_s {
     int64_t calls[3] = {0, 0, 0};
     double trav_ms[3] = {0, 0, 0};
     double mom_ms = 0;
+    double comb_ms = 0;
     double build_ms = 0;
 
     // event pairs of timed launches, resolved by wnnc_stats
     struct Timed {
         hipEvent_t a, b;
-        int kind;  // 0..2 traversal of an operator kind, 3 moment pass
+        int kind;  // 0..2 traversal of an operator kind, 3 moment pass, 4 combining pass
     };
     std::vector<Timed> pending;
     std::vector<hipEvent_t> event_pool;

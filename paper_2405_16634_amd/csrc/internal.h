@@ -32,7 +32,15 @@ hipError_t make_tasks(wnnc_ctx_s *ctx, int tpl, int split);
 hipError_t launch_moments(wnnc_ctx_s *ctx, MomMode mode, const MomArgs &a);
 
 // Traversal (traverse.hip).
+// The walk kernel, then (when walks are split) the combining pass that adds
+// the parts and runs the epilogue; launch_traverse_all issues both.
 hipError_t launch_traverse(wnnc_ctx_s *ctx, Op op, TravMode mode, bool count, const TravArgs &a);
+hipError_t launch_combine(wnnc_ctx_s *ctx, Op op, TravMode mode, const TravArgs &a);
+inline hipError_t launch_traverse_all(wnnc_ctx_s *ctx, Op op, TravMode mode, bool count,
+                                      const TravArgs &a) {
+    const hipError_t e = launch_traverse(ctx, op, mode, count, a);
+    return e != hipSuccess ? e : launch_combine(ctx, op, mode, a);
+}
 int trav_blocks(int64_t ntasks);
 // Records the walk of every 64-target group (ctx->plan) for split planning;
 // the tasks must be whole walks of single 64-target groups.

@@ -451,9 +451,14 @@ static hipError_t launch_one(wnnc_ctx_s *ctx, bool count, const TravArgs &a) {
         case 4: launch_tpl<OP, MODE, 4>(count, a, st); break;
         default: return hipErrorInvalidValue;
     }
-    if (ctx->nsplit > 0)
-        hipLaunchKernelGGL((k_combine<OP, MODE>), dim3((unsigned)ctx->nsplit), dim3(kWave), 0, st,
-                           a, ctx->split_groups.p, ctx->split_slot.p);
+    return hipGetLastError();
+}
+
+template <int OP, int MODE>
+static hipError_t launch_comb(wnnc_ctx_s *ctx, const TravArgs &a) {
+    if (a.ntasks <= 0 || ctx->nsplit <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_combine<OP, MODE>), dim3((unsigned)ctx->nsplit), dim3(kWave), 0,
+                       ctx->stream, a, ctx->split_groups.p, ctx->split_slot.p);
     return hipGetLastError();
 }
 
@@ -469,6 +474,22 @@ hipError_t launch_traverse(wnnc_ctx_s *ctx, Op op, TravMode mode, bool count, co
     } else {
         if (mode == TR_OUT_CALLER) return launch_one<OP_G, TR_OUT_CALLER>(ctx, count, a);
         if (mode == TR_RESCALE) return launch_one<OP_G, TR_RESCALE>(ctx, count, a);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_combine(wnnc_ctx_s *ctx, Op op, TravMode mode, const TravArgs &a) {
+    if (op == OP_A) {
+        if (mode == TR_OUT_CALLER) return launch_comb<OP_A, TR_OUT_CALLER>(ctx, a);
+        if (mode == TR_RHO) return launch_comb<OP_A, TR_RHO>(ctx, a);
+        if (mode == TR_TSUM) return launch_comb<OP_A, TR_TSUM>(ctx, a);
+        if (mode == TR_SCALE) return launch_comb<OP_A, TR_SCALE>(ctx, a);
+    } else if (op == OP_AT) {
+        if (mode == TR_OUT_CALLER) return launch_comb<OP_AT, TR_OUT_CALLER>(ctx, a);
+        if (mode == TR_R) return launch_comb<OP_AT, TR_R>(ctx, a);
+    } else {
+        if (mode == TR_OUT_CALLER) return launch_comb<OP_G, TR_OUT_CALLER>(ctx, a);
+        if (mode == TR_RESCALE) return launch_comb<OP_G, TR_RESCALE>(ctx, a);
     }
     return hipErrorInvalidValue;
 }

@@ -1,0 +1,194 @@
+"""Summaries of rocprofv3 output for the committed profiles.
+
+Three summaries, all from CSV output (``rocprofv3 ... -f csv -d DIR -o NAME``):
+
+* ``trace``: the per-kernel statistics of a ``--kernel-trace --stats`` run
+  (``NAME_kernel_stats.csv``) as a Markdown table.
+* ``traffic``: HBM bytes per dispatch of one kernel from two PMC runs
+  (``--pmc FETCH_SIZE``, then ``--pmc WRITE_SIZE``; KiB per dispatch),
+  each scaled by what the same counter reads for a plain copy kernel of
+  known size (``python -m paper_2405_16634_amd.profile_copy``, which copies
+  ``--mb`` MiB per dispatch): factor = bytes the copy must move / bytes the
+  counter reports.  Written as JSON with the digest of the traversal sources
+  the counters were taken on; bench.py reports the figure only while the
+  digest matches.
+* ``sq``: instruction counters (SQ_INSTS_VALU, ...) per dispatch of one
+  kernel, and the fraction of the chip's wave64 vector-issue ceiling they
+  take over the kernel's traced duration.
+
+``python -m paper_2405_16634_amd.profiling trace --csv F --cmd "..." --out F``
+``python -m paper_2405_16634_amd.profiling traffic --fetch F --write F
+    --cal-fetch F --cal-write F --mb 512 --kernel REGEX --cmd "..." --out F``
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRAVERSAL_SOURCES = [os.path.join(HERE, "csrc", "traverse.hip"),
+                     os.path.join(HERE, "csrc", "common.h")]
+
+
+def traversal_digest() -> str:
+    """Digest of the sources that define the traversal kernel."""
+    h = hashlib.sha256()
+    for p in TRAVERSAL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _rows(path):
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def counter_per_dispatch(path: str, counter: str, kernel: str) -> tuple[float, int]:
+    """Mean value of `counter` over the dispatches of kernels matching the
+    regex `kernel` (one row per dispatch and counter), and the count."""
+    rx = re.compile(kernel)
+    vals = [float(r["Counter_Value"]) for r in _rows(path)
+            if r["Counter_Name"] == counter and rx.search(r["Kernel_Name"])]
+    if not vals:
+        raise ValueError(f"{path}: no {counter} rows for kernels matching {kernel!r}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def traffic(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, mb, kernel, cmd):
+    copy_kib = mb * 1024.0  # each copy dispatch reads and writes this much
+    cal = "copyBuffer|elementwise_kernel|copy"
+    cf, ncf = counter_per_dispatch(cal_fetch_csv, "FETCH_SIZE", cal)
+    cw, ncw = counter_per_dispatch(cal_write_csv, "WRITE_SIZE", cal)
+    # the calibration CSV may hold a small setup kernel too: use the
+    # dispatches that moved about the copy's size
+    rx = re.compile(cal)
+    big_f = [float(r["Counter_Value"]) for r in _rows(cal_fetch_csv)
+             if r["Counter_Name"] == "FETCH_SIZE" and rx.search(r["Kernel_Name"])
+             and float(r["Counter_Value"]) > 0.1 * copy_kib]
+    big_w = [float(r["Counter_Value"]) for r in _rows(cal_write_csv)
+             if r["Counter_Name"] == "WRITE_SIZE" and rx.search(r["Kernel_Name"])
+             and float(r["Counter_Value"]) > 0.1 * copy_kib]
+    if big_f:
+        cf, ncf = sum(big_f) / len(big_f), len(big_f)
+    if big_w:
+        cw, ncw = sum(big_w) / len(big_w), len(big_w)
+    f_fetch = copy_kib / cf
+    f_write = copy_kib / cw
+    kf, nf = counter_per_dispatch(fetch_csv, "FETCH_SIZE", kernel)
+    kw, nw = counter_per_dispatch(write_csv, "WRITE_SIZE", kernel)
+    read_b = kf * 1024.0 * f_fetch
+    write_b = kw * 1024.0 * f_write
+    return {
+        "kernel": kernel,
+        "source_sha": traversal_digest(),
+        "bytes_per_launch": round(read_b + write_b),
+        "read_bytes_per_launch": round(read_b),
+        "write_bytes_per_launch": round(write_b),
+        "fetch_kib_per_dispatch": round(kf, 3), "fetch_dispatches": nf,
+        "write_kib_per_dispatch": round(kw, 3), "write_dispatches": nw,
+        "calibration": {"copy_mib_per_dispatch": mb,
+                        "fetch_kib_per_copy": round(cf, 3), "fetch_factor": round(f_fetch, 4),
+                        "write_kib_per_copy": round(cw, 3), "write_factor": round(f_write, 4),
+                        "copy_dispatches": [ncf, ncw]},
+        "command": cmd,
+    }
+
+
+# Issue ceiling of one MI355X for wave64 vector instructions: 256 CUs x 4
+# SIMDs, each issuing one wave64 instruction per 4 cycles (16 lanes), 2.4 GHz.
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
+
+
+def sq(csv_path: str, kernel: str, trace_csv: str, cmd: str) -> dict:
+    """Instruction counters per dispatch of the kernels matching `kernel`
+    (one --pmc run with SQ_* counters), with the kernels' average duration
+    from a kernel trace of the same command (kernel_trace CSV)."""
+    rx = re.compile(kernel)
+    per = {}
+    for r in _rows(csv_path):
+        if rx.search(r["Kernel_Name"]):
+            per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    out = {k: round(sum(v) / len(v), 1) for k, v in per.items()}
+    durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+            for r in _rows(trace_csv) if rx.search(r["Kernel_Name"])]
+    avg = sum(durs) / len(durs)
+    d = {"kernel": kernel, "source_sha": traversal_digest(), "per_dispatch": out,
+         "dispatches": len(next(iter(per.values()))), "trace_avg_s": avg,
+         "valu_issue_peak_per_s": VALU_ISSUE_PEAK, "command": cmd}
+    if "SQ_INSTS_VALU" in out:
+        d["valu_issue_frac"] = round(out["SQ_INSTS_VALU"] / avg / VALU_ISSUE_PEAK, 4)
+    return d
+
+
+def trace_markdown(stats_csv: str, title: str, cmd: str, groups=(), top: int = 25) -> str:
+    """groups: (label, regex) pairs; each gets the call-weighted average
+    duration of the kernels whose names match."""
+    rows = _rows(stats_csv)
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = [f"# {title}", "", "Command (run from the repository root on one MI355X):", "",
+           "```", cmd, "```", "",
+           "Kernel statistics (rocprofv3 --kernel-trace --stats; durations in microseconds):", "",
+           "| kernel | calls | total us | average us | % |", "|---|---|---|---|---|"]
+    for r in rows[:top]:
+        out.append(f"| `{r['Name']}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e3:.1f} | "
+                   f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    if groups:
+        out += ["", "Kernel groups (all template instances whose names match):", "",
+                "| group | regex | calls | average us |", "|---|---|---|---|"]
+        for label, rx in groups:
+            m = [r for r in rows if re.search(rx, r["Name"])]
+            calls = sum(int(r["Calls"]) for r in m)
+            tot = sum(float(r["TotalDurationNs"]) for r in m)
+            avg = tot / calls / 1e3 if calls else float("nan")
+            out.append(f"| {label} | `{rx}` | {calls} | {avg:.2f} |")
+    return "\n".join(out) + "\n"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("--csv", required=True)
+    t.add_argument("--title", default="Kernel trace")
+    t.add_argument("--cmd", required=True)
+    t.add_argument("--out", required=True)
+    t.add_argument("--group", action="append", default=[], metavar="LABEL=REGEX")
+    q = sub.add_parser("traffic")
+    for k in ("fetch", "write", "cal_fetch", "cal_write"):
+        q.add_argument("--" + k.replace("_", "-"), required=True)
+    q.add_argument("--mb", type=int, default=512)
+    q.add_argument("--kernel", required=True)
+    q.add_argument("--cmd", required=True)
+    q.add_argument("--out", required=True)
+    c = sub.add_parser("sq")
+    c.add_argument("--csv", required=True)
+    c.add_argument("--trace", required=True, help="kernel_trace CSV of the same workload")
+    c.add_argument("--kernel", required=True)
+    c.add_argument("--cmd", required=True)
+    c.add_argument("--out", required=True)
+    a = ap.parse_args()
+    if a.what == "trace":
+        text = trace_markdown(a.csv, a.title, a.cmd,
+                              [tuple(g.split("=", 1)) for g in a.group])
+        with open(a.out, "w") as f:
+            f.write(text)
+    elif a.what == "sq":
+        d = sq(a.csv, a.kernel, a.trace, a.cmd)
+        with open(a.out, "w") as f:
+            json.dump(d, f, indent=1)
+            f.write("\n")
+    else:
+        d = traffic(a.fetch, a.write, a.cal_fetch, a.cal_write, a.mb, a.kernel, a.cmd)
+        with open(a.out, "w") as f:
+            json.dump(d, f, indent=1)
+            f.write("\n")
+    print(f"wrote {a.out}")
+
+
+if __name__ == "__main__":
+    main()
