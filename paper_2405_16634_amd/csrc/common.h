@@ -190,6 +190,7 @@ struct wnnc_ctx_s {
     DevBuf<float4> pts;            // n sorted normalized points
     DevBuf<uint32_t> perm;         // n: sorted position -> caller index
     DevBuf<int4> topo;             // m
+    DevBuf<float4> cells;          // m: node cell box, or the point of a single-point leaf
     DevBuf<uint32_t> node_off;     // n+1: first node started by each point
     DevBuf<int32_t> node_strad;    // m: straddler slot or -1
     DevBuf<int32_t> strad_node;    // n_strad
@@ -248,6 +249,8 @@ struct wnnc_ctx_s {
     DevBuf<unsigned long long> pair_ctr;  // 3 counters
 
     // warm start: neighbours, features, MLP activations and scratch
+    DevBuf<int4> knn_groups;       // 64-point groups of every cloud (first, last; root, end)
+    int knn_ngroups = 0;
     DevBuf<int32_t> knn_idx;       // n * 16 sorted neighbour positions
     DevBuf<float> knn_d2;          // n * 16 squared distances
     DevBuf<float> feat;            // n * 48 features (caller order)

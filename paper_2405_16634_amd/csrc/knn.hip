@@ -2,14 +2,16 @@
 // and the neighbourhood features of the learned warm start: the offsets to
 // the 16 neighbours in increasing distance, divided by their RMS length.
 //
-// One lane per target.  The candidate list (squared distance, sorted index)
-// lives in registers, sorted ascending; it is seeded with the target's
-// Morton-order neighbours, which gives a tight radius from the start.  Each
-// lane then walks its cloud's pre-order node range on its own, skipping a
-// subtree whenever the box of its cell is farther than the current 16th
-// candidate (cells come from the Morton key of the node's first point), and
-// testing the points of the leaves it reaches.  Ties are broken by sorted
-// index.  Requires points inside [-1,1]^3 (normalized clouds).
+// One wavefront per group of 64 Morton-consecutive points of one cloud, one
+// point per lane.  Each lane keeps a candidate list (squared distance, sorted
+// index) in registers, sorted ascending, seeded with its Morton-order
+// neighbours on both sides (a tight radius from the start).  The wavefront then walks the
+// cloud's pre-order node range as one scalar loop: a subtree is skipped when
+// its cell (built with the tree) is farther than every lane's current 16th
+// candidate; the points of the leaves reached are offered to every lane
+// that needs them.  Ties are broken by sorted index,
+// so the result does not depend on the order in which points are offered.
+// Requires points inside [-1,1]^3 (normalized clouds).
 #include <float.h>
 
 #include "common.h"
@@ -19,109 +21,160 @@ namespace wnnc {
 
 constexpr int kK = 16;
 
-__device__ inline unsigned compact3(unsigned long long x) {
-    x &= 0x1249249249249ull;
-    x = (x ^ (x >> 2)) & 0x10c30c30c30c3ull;
-    x = (x ^ (x >> 4)) & 0x100f00f00f00full;
-    x = (x ^ (x >> 8)) & 0x1f0000ff0000ffull;
-    x = (x ^ (x >> 16)) & 0x1f00000000ffffull;
-    x = (x ^ (x >> 32)) & 0x7fffull;
-    return (unsigned)x;
-}
-
 struct Cand {
     float d[kK];
     int j[kK];
 };
 
+// (d, j) sorts before (dd, jj).  Bitwise operators: no short-circuit
+// branches, so the callers compile to compares and selects.
 __device__ inline bool better(float d, int j, float dd, int jj) {
-    return d < dd || (d == dd && j < jj);
+    return (d < dd) | ((d == dd) & (j < jj));
 }
 
-// insert (d, j) into the sorted list if it beats the last entry
-__device__ inline void offer(Cand &c, float d, int j) {
-    if (!better(d, j, c.d[kK - 1], c.j[kK - 1])) return;
-    c.d[kK - 1] = d;
-    c.j[kK - 1] = j;
+// Inserts (d, j) into the sorted list where `take` holds and (d, j) beats
+// the last entry: every entry the new one beats moves down one place.
+// Branch-free (selects only), so the list stays in the same registers.
+__device__ inline void offer(Cand &c, float d, int j, bool take = true) {
+    take = take & better(d, j, c.d[kK - 1], c.j[kK - 1]);
 #pragma unroll
     for (int k = kK - 1; k > 0; --k) {
-        if (better(c.d[k], c.j[k], c.d[k - 1], c.j[k - 1])) {
-            const float td = c.d[k];
-            const int tj = c.j[k];
-            c.d[k] = c.d[k - 1];
-            c.j[k] = c.j[k - 1];
-            c.d[k - 1] = td;
-            c.j[k - 1] = tj;
-        }
+        const bool shift = take & better(d, j, c.d[k - 1], c.j[k - 1]);
+        // beats entry k but not entry k-1
+        const bool put = take & !shift & better(d, j, c.d[k], c.j[k]);
+        c.d[k] = shift ? c.d[k - 1] : (put ? d : c.d[k]);
+        c.j[k] = shift ? c.j[k - 1] : (put ? j : c.j[k]);
     }
+    const bool first = take & better(d, j, c.d[0], c.j[0]);
+    c.d[0] = first ? d : c.d[0];
+    c.j[0] = first ? j : c.j[0];
 }
 
-// squared distance from p to the depth-d cell of key (FP32 box)
-__device__ inline float cell_dist2(unsigned long long key, int d, float px, float py, float pz) {
-    const int sh = kMaxDepth - d;
-    const float w = ldexpf(1.0f, 1 - d);
-    const unsigned long long mk = key & ((1ull << kMortonBits) - 1ull);
-    const float lx = -1.0f + (float)(compact3(mk >> 2) >> sh) * w;
-    const float ly = -1.0f + (float)(compact3(mk >> 1) >> sh) * w;
-    const float lz = -1.0f + (float)(compact3(mk) >> sh) * w;
-    const float dx = fmaxf(fmaxf(lx - px, px - (lx + w)), 0.0f);
-    const float dy = fmaxf(fmaxf(ly - py, py - (ly + w)), 0.0f);
-    const float dz = fmaxf(fmaxf(lz - pz, pz - (lz + w)), 0.0f);
-    return dx * dx + dy * dy + dz * dz;
-}
+typedef int v4i_knn __attribute__((ext_vector_type(4)));
+typedef float v4f_knn __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void k_knn(const float4 *__restrict__ pts,
-                                             const unsigned long long *__restrict__ keys,
-                                             const int4 *__restrict__ topo,
-                                             const int32_t *__restrict__ cloud,
-                                             const int64_t *__restrict__ off,
-                                             const int32_t *__restrict__ roots, int n,
-                                             int32_t *__restrict__ nbr, float *__restrict__ nd2) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const int c = cloud[t];
+// Wave-uniform loads through the constant address space (scalar loads).
+__device__ inline int4 knn_ld_i4(const int4 *p) {
+    const v4i_knn v = *(const __attribute__((address_space(4))) v4i_knn *)p;
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+__device__ inline float4 knn_ld_f4(const float4 *p) {
+    const v4f_knn v = *(const __attribute__((address_space(4))) v4f_knn *)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+// groups: per wavefront (first, last point; first, end node of the cloud),
+// the 64-point groups of every cloud.
+__global__ __launch_bounds__(kWave) void k_knn(const float4 *__restrict__ pts,
+                                               const float4 *__restrict__ cells,
+                                               const int4 *__restrict__ topo,
+                                               const int4 *__restrict__ groups,
+                                               const int64_t *__restrict__ off,
+                                               const int32_t *__restrict__ cloud, int ngroups,
+                                               int32_t *__restrict__ nbr,
+                                               float *__restrict__ nd2) {
+    const int g = blockIdx.x;
+    if (g >= ngroups) return;
+    const int lane = threadIdx.x;
+    const int4 G = knn_ld_i4(groups + g);
+    const int c = *(const __attribute__((address_space(4))) int *)(cloud + G.x);
     const int lo = (int)off[c], hi = (int)off[c + 1];
-    const float4 p = pts[t];
+    const int t = G.x + lane;
+    const bool valid = t < G.y;
+    float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (valid) p = pts[t];
     Cand cd;
 #pragma unroll
     for (int k = 0; k < kK; ++k) {
         cd.d[k] = FLT_MAX;
         cd.j[k] = -1;
     }
-    // seed with Morton-order neighbours; the walk below skips them
-    const int s_lo = max(lo, t - kK / 2 - 1), s_hi = min(hi - 1, t + kK / 2 + 1);
-    for (int j = s_lo; j <= s_hi; ++j) {
-        if (j == t) continue;
-        const float4 q = pts[j];
-        const float dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
-        offer(cd, fmaf(dx, dx, fmaf(dy, dy, dz * dz)), j);
+    // seed with the kK Morton-order neighbours on each side (one side alone
+    // fills the list, which bounds the radius also where the curve jumps);
+    // the walk below skips them
+    const int s_lo = max(lo, t - kK), s_hi = min(hi - 1, t + kK);
+#pragma unroll 1
+    for (int q = -kK; q <= kK; ++q) {
+        const int j = t + q;
+        const bool in = valid && q != 0 && j >= s_lo && j <= s_hi;
+        float4 r = p;
+        if (in) r = pts[j];
+        const float dx = r.x - p.x, dy = r.y - p.y, dz = r.z - p.z;
+        offer(cd, fmaf(dx, dx, fmaf(dy, dy, dz * dz)), j, in);
     }
-    int node = roots[c];
-    const int rend = roots[c + 1];
-    while (node < rend) {
-        const int4 tp = topo[node];
-        const int depth = tp.w & 15;
-        const float bd = cell_dist2(keys[tp.y], depth, p.x, p.y, p.z);
-        if (bd > cd.d[kK - 1]) {
-            node = tp.x;
-            continue;
-        }
-        if (tp.w & kRecLeaf) {
-            for (int j = tp.y; j < tp.z; ++j) {
-                if (j >= s_lo && j <= s_hi) continue;  // seeded (or the target)
-                const float4 q = pts[j];
-                const float dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
-                offer(cd, fmaf(dx, dx, fmaf(dy, dy, dz * dz)), j);
+    // One pruned walk over the pre-order range [nb, ne), skipping the
+    // subtree [hole, hole_end) (hole = -1: none).
+    auto walk = [&](int nb, int ne, int hole, int hole_end) {
+        int node = nb;
+        while (node < ne) {
+            if (node == hole) {
+                node = hole_end;
+                continue;
             }
-            node = tp.x;
-        } else {
-            node = node + 1;
+            // the node and its geometry: two independent scalar loads
+            const int4 tp = knn_ld_i4(topo + node);
+            const float4 cb = knn_ld_f4(cells + node);
+            if (cb.w < 0.0f) {  // a single-point leaf: its point directly
+                const int j = tp.y;
+                const float dx = cb.x - p.x, dy = cb.y - p.y, dz = cb.z - p.z;
+                const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                const bool take = valid & ((j < s_lo) | (j > s_hi)) &
+                                  better(d2, j, cd.d[kK - 1], cd.j[kK - 1]);
+                if (__ballot(take)) offer(cd, d2, j, take);
+                node = tp.x;
+                continue;
+            }
+            // each lane's distance to the node's cell
+            const float bx = fmaxf(fmaxf(cb.x - p.x, p.x - (cb.x + cb.w)), 0.0f);
+            const float by = fmaxf(fmaxf(cb.y - p.y, p.y - (cb.y + cb.w)), 0.0f);
+            const float bz = fmaxf(fmaxf(cb.z - p.z, p.z - (cb.z + cb.w)), 0.0f);
+            const bool need = valid & (bx * bx + by * by + bz * bz <= cd.d[kK - 1]);
+            if (__ballot(need) == 0ull) {
+                node = tp.x;
+                continue;
+            }
+            if (tp.w & kRecLeaf) {
+#pragma unroll 1
+                for (int j = tp.y; j < tp.z; ++j) {
+                    const float4 r = knn_ld_f4(pts + j);
+                    const float dx = r.x - p.x, dy = r.y - p.y, dz = r.z - p.z;
+                    const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    // seeded (or the target itself) points were offered already
+                    const bool take = need & ((j < s_lo) | (j > s_hi)) &
+                                      better(d2, j, cd.d[kK - 1], cd.j[kK - 1]);
+                    if (__ballot(take)) offer(cd, d2, j, take);
+                }
+                node = tp.x;
+            } else {
+                node = node + 1;
+            }
         }
+    };
+    // Nearest first: the deepest node holding the whole group (its home),
+    // whose points give every lane a tight radius, then the rest of the
+    // cloud's tree with that radius.  At most one node per depth and 8
+    // children per node are examined, so the search ends on any input.
+    int home = G.z;
+    for (int d = 0; d < kMaxDepth; ++d) {
+        const int4 th = knn_ld_i4(topo + home);
+        if (th.w & kRecLeaf) break;
+        int ch = home + 1;
+        for (int q = 0; q < 7; ++q) {  // the child whose point range holds `first`
+            const int4 tc = knn_ld_i4(topo + ch);
+            if (tc.z > G.x) break;
+            ch = tc.x;
+        }
+        if (knn_ld_i4(topo + ch).z < G.y) break;  // it does not hold the whole group
+        home = ch;
     }
+    const int home_end = knn_ld_i4(topo + home).x;
+    walk(home, home_end, -1, 0);
+    walk(G.z, G.w, home, home_end);
+    if (valid) {
 #pragma unroll
-    for (int k = 0; k < kK; ++k) {
-        nbr[(int64_t)t * kK + k] = cd.j[k];
-        nd2[(int64_t)t * kK + k] = cd.d[k];
+        for (int k = 0; k < kK; ++k) {
+            nbr[(int64_t)t * kK + k] = cd.j[k];
+            nd2[(int64_t)t * kK + k] = cd.d[k];
+        }
     }
 }
 
@@ -174,9 +227,10 @@ hipError_t launch_knn_features(wnnc_ctx_s *ctx, float *feat, int32_t *nbr_caller
     e = ctx->knn_d2.ensure((int64_t)n * kK);
     if (e != hipSuccess) return e;
     const unsigned nb = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_knn, dim3(nb), dim3(256), 0, st, ctx->pts.p, ctx->keys_a.p, ctx->topo.p,
-                       ctx->cloud_of.p, ctx->d_offsets.p, ctx->d_roots.p, n, ctx->knn_idx.p,
-                       ctx->knn_d2.p);
+    if (ctx->knn_ngroups > 0)
+        hipLaunchKernelGGL(k_knn, dim3((unsigned)ctx->knn_ngroups), dim3(kWave), 0, st, ctx->pts.p,
+                           ctx->cells.p, ctx->topo.p, ctx->knn_groups.p, ctx->d_offsets.p,
+                           ctx->cloud_of.p, ctx->knn_ngroups, ctx->knn_idx.p, ctx->knn_d2.p);
     hipLaunchKernelGGL(k_features, dim3(nb), dim3(256), 0, st, ctx->pts.p, ctx->perm.p,
                        ctx->knn_idx.p, n, feat, nbr_caller);
     return hipGetLastError();

@@ -328,6 +328,41 @@ __global__ __launch_bounds__(256) void k_gather_roots(const uint32_t *__restrict
     if (c <= nclouds) roots[c] = (int32_t)node_off[off[c]];
 }
 
+// Extract every third bit (bit 3b of x -> bit b), 15 bits.
+__device__ inline unsigned compact3_15(unsigned long long x) {
+    x &= 0x1249249249249ull;
+    x = (x ^ (x >> 2)) & 0x10c30c30c30c3ull;
+    x = (x ^ (x >> 4)) & 0x100f00f00f00full;
+    x = (x ^ (x >> 8)) & 0x1f0000ff0000ffull;
+    x = (x ^ (x >> 16)) & 0x1f00000000ffffull;
+    x = (x ^ (x >> 32)) & 0x7fffull;
+    return (unsigned)x;
+}
+
+// Geometry of every node for searches by distance (the neighbour search):
+// a single-point leaf holds its point (x, y, z, -1); any other node its
+// cell (lower corner x, y, z, side), from the Morton key of its first point.
+__global__ __launch_bounds__(256) void k_node_cells(const int4 *__restrict__ topo,
+                                                    const unsigned long long *__restrict__ keys,
+                                                    const float4 *__restrict__ pts, int64_t m,
+                                                    float4 *__restrict__ cells) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    const int4 t = topo[k];
+    if ((t.w & kRecLeaf) && t.z - t.y == 1) {
+        const float4 q = pts[t.y];
+        cells[k] = make_float4(q.x, q.y, q.z, -1.0f);
+        return;
+    }
+    const int depth = t.w & 15;
+    const int sh = kMaxDepth - depth;
+    const float w = ldexpf(1.0f, 1 - depth);
+    const unsigned long long mk = keys[t.y] & ((1ull << kMortonBits) - 1ull);
+    cells[k] = make_float4(-1.0f + (float)(compact3_15(mk >> 2) >> sh) * w,
+                           -1.0f + (float)(compact3_15(mk >> 1) >> sh) * w,
+                           -1.0f + (float)(compact3_15(mk) >> sh) * w, w);
+}
+
 __global__ __launch_bounds__(256) void k_gather_points(const float *__restrict__ P,
                                                        const uint32_t *__restrict__ perm,
                                                        int64_t n, float4 *__restrict__ pts) {
@@ -469,6 +504,9 @@ hipError_t build_tree(wnnc_ctx_s *ctx, const float *P) {
                        n, D, ctx->node_off.p, ctx->topo.p, ctx->mflag.p);
     hipLaunchKernelGGL(k_gather_points, dim3(blocks_for(n, 256)), dim3(256), 0, st, P,
                        ctx->perm.p, n, ctx->pts.p);
+    TRY(ctx->cells.ensure(m));
+    hipLaunchKernelGGL(k_node_cells, dim3(blocks_for(m, 256)), dim3(256), 0, st, ctx->topo.p,
+                       ctx->keys_a.p, ctx->pts.p, m, ctx->cells.p);
     TRY(exclusive_scan_u32(ctx->mflag.p, ctx->mslot.p, m + 1, ctx->scan_tmp.p, st));
     uint32_t ns32 = 0;
     TRY(hipMemcpyAsync(&ns32, ctx->mslot.p + m, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
