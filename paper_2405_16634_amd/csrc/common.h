@@ -7,144 +7,7 @@
 #include <vector>
 
 #include "../../include/wnnc.h"
-
-namespace wnnc {
-
-constexpr int kWave = 64;
-constexpr int kChunk = 256;      // points per moment-pass chunk (one workgroup)
-constexpr int kTravBlock = 64;  // traversal workgroup: one wave (finest dispatch)
-constexpr int kMaxDepth = 15;    // 15 levels below the root: 45-bit Morton keys
-
-// Node topology, one int4 per node in depth-first pre-order:
-//   x = skip: index of the first node after this node's subtree
-//   y = begin, z = end: the node's points are sorted positions [begin, end)
-//   w = depth | (leaf << 4)
-// The first child of an internal node is the next node (index + 1).
-__host__ __device__ inline int topo_depth(int meta) { return meta & 15; }
-__host__ __device__ inline int topo_leaf(int meta) { return (meta >> 4) & 1; }
-
-// Node record written by every moment pass and read by the traversal, 64
-// bytes per node (one 16-dword scalar load):
-//   [0] hi(x_B).x, .y, .z, flags (int bits)
-//   [1] nu_B (3 floats; a scalar attribute in .x), skip (int bits)
-//   [2] lo(x_B).x, .y, .z, (c * width)^2 (the acceptance threshold)
-//   [3] first point, end point (int bits), 0, 0
-// with x_B = hi + lo to about 2^-48 (hi = FP32 rounding of the FP64 x_B,
-// lo = FP32 rounding of the rest), so that target - x_B keeps full FP32
-// precision when the target is close to the node.
-// flags = depth | leaf << 4 | single-point leaf << 5 | zero weight << 6.
-// The traversal addresses records with 32-bit byte offsets: at most
-// kMaxNodes nodes.
-constexpr int kRecStride = 4;
-constexpr int64_t kMaxNodes = int64_t(1) << 26;
-constexpr int kRecLeaf = 16;
-constexpr int kRecSingle = 32;
-constexpr int kRecZero = 64;
-
-enum Op { OP_A = WNNC_OP_A, OP_AT = WNNC_OP_AT, OP_G = WNNC_OP_G };
-
-// Warm-start MLP: 48 -> 64 -> 64 -> 3; flat FP32 parameter vector, row-major
-// [in][out] weights each followed by its bias.
-constexpr int kMlpIn = 48, kMlpHidden = 64, kMlpOut = 3;
-constexpr int kOffW1 = 0;
-constexpr int kOffB1 = kOffW1 + kMlpIn * kMlpHidden;
-constexpr int kOffW2 = kOffB1 + kMlpHidden;
-constexpr int kOffB2 = kOffW2 + kMlpHidden * kMlpHidden;
-constexpr int kOffW3 = kOffB2 + kMlpHidden;
-constexpr int kOffB3 = kOffW3 + kMlpHidden * kMlpOut;
-constexpr int kMlpParams = kOffB3 + kMlpOut;  // 7491
-static_assert(kMlpParams == WNNC_MLP_PARAMS, "parameter count");
-
-// Moment-pass input modes.
-enum MomMode {
-    MOM_VEC_SORTED = 0,    // nu = src4[i] (sorted float4)
-    MOM_SCALAR_SORTED = 1, // nu = srcs[i] (sorted float)
-    MOM_VEC_CALLER = 2,    // nu = n[perm[i]] * (sigma ? sigma[perm[i]] : 1); writes out4[i]
-    MOM_SCALAR_CALLER = 3, // nu = s[perm[i]]; writes outs[i]
-    MOM_AXPY = 4,          // nu = src4[i] + alpha * r4[i]; writes out4[i]
-    MOM_CONST_HALF = 5,    // nu = 1/2 (scalar); writes outs[i]
-};
-
-// Key layout: the cloud index sits above the 45 Morton bits, so one sort
-// groups the points cloud by cloud and each cloud gets its own root.
-constexpr int kMortonBits = 45;
-
-// Traversal epilogues.
-enum TravMode {
-    TR_OUT_CALLER = 0,  // write the operator value to caller order (API calls)
-    TR_RHO = 1,         // A: rho = 1/2 - s (sorted), block partial of rho^2
-    TR_R = 2,           // A^T: r (sorted float4), block partial of |r|^2
-    TR_TSUM = 3,        // A: block partial of s^2 only
-    TR_RESCALE = 4,     // G: mu <- G |mu| / |G| (sorted float4)
-    TR_SCALE = 5,       // A: block partials of s and s^2 (warm-start scale)
-    TR_PLAN = 6,        // no output: record the walk of each group (split planning)
-};
-
-// Split planning: the walk of every 64-target group is recorded as its node
-// visit count and the node at every kPlanStep-th visit (up to kPlanCap of
-// them), kPlanStride ints per group.
-constexpr int kPlanStep = 64;
-constexpr int kPlanCap = 63;
-constexpr int kPlanStride = kPlanCap + 1;
-
-struct MomArgs {
-    const float4 *pts;       // sorted points
-    const int4 *topo;
-    const uint32_t *node_off;
-    const int32_t *node_strad;
-    const uint32_t *tail_off;
-    const int32_t *tail_list;
-    const int32_t *strad_node;
-    const uint32_t *perm;
-    const float4 *src4;      // sorted vector input
-    const float *srcs;       // sorted scalar input
-    const float4 *r4;        // axpy direction
-    const double *alpha;     // axpy step per cloud (device)
-    const int32_t *cloud;    // cloud index per sorted point (batched axpy)
-    const float *cn;         // caller-order (N,3) input
-    const float *csig;       // caller-order sigma (may be null)
-    const float *cs;         // caller-order scalar input
-    float4 *out4;
-    float *outs;
-    double *chunk_tot;       // 8 doubles per chunk
-    double *head;            // 8 doubles per straddler
-    double *tail;            // 8 doubles per straddler
-    float4 *mom;             // node records, kRecStride float4 per node
-    float *wout;             // optional: W = sum |nu| per node (inspection)
-    float thr2[16];          // (c * 2^(1-d))^2 per depth d, copied into records
-    int n;
-    int n_strad;
-};
-
-struct TravArgs {
-    const float4 *pts;
-    const int4 *topo;
-    const float4 *mom;
-    const float4 *src4;      // sorted vector attributes (A, G)
-    const float *srcs;       // sorted scalar attributes (A^T)
-    const uint32_t *perm;
-    float *out;              // TR_OUT_CALLER: caller-order output
-    float *rho;              // TR_RHO output
-    float4 *out4;            // TR_R / TR_RESCALE output
-    double *partial;         // per-task partial sums (indexed by task_slot)
-    unsigned long long *pairs;  // pair counter (counting variant)
-    unsigned long long *flips;  // TR_RESCALE: per cloud, updates against mu (or null)
-    const int32_t *cloud;    // cloud of each sorted point (for flips)
-    const int4 *tasks;       // per wavefront: first, last target; first, end node
-    const int32_t *task_slot;  // >= 0: group slot (whole walk); < 0: -1 - part slot
-    const int32_t *roots;    // first node of each cloud (nclouds + 1)
-    double *parts;           // per part slot: 3 x 64 FP64 sums (component-major)
-    int32_t *plan;           // TR_PLAN output, kPlanStride ints per group
-    int ntasks;              // wavefronts launched
-    int nslots;              // groups: row stride of the per-group partial sums
-    int tpl;                 // target groups of 64 per wavefront (1, 2, 4)
-    int prefetch;            // software-pipelined node walk
-    int n, m;
-    float w2;
-    float thr2[16];          // (c * 2^(1-d))^2 per depth d
-};
-
-}  // namespace wnnc
+#include "layout.h"
 
 // A device array that only grows.
 template <typename T>

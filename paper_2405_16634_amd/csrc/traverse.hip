@@ -301,7 +301,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
             const unsigned long long far = act & __ballot(r2 > thr2);
             // w2 >= the smallest normal float, so the cutoff also drops r = 0
-            // (and keeps denormal arguments away from the hardware rsq)
+            // (and keeps denormal arguments away from the hardware rsq).
             const unsigned long long take = far & __ballot(r2 >= a.w2);
             pair_term<OP>(dx, dy, dz, r2, V, lane_in(take), s[k], gx[k], gy[k], gz[k]);
             if (COUNT) cnt += (uint32_t)__popcll(far);
@@ -331,12 +331,12 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
             }
             return skip;
         }
+        // push: lane depth + 1 takes the mask (selected by a scalar lane mask)
+        const bool at = lane_in(1ull << (depth + 1));
 #pragma unroll
         for (int k = 0; k < TPL; ++k) {
-            if (lane == depth + 1) {
-                mlo[k] = (uint32_t)open[k];
-                mhi[k] = (uint32_t)(open[k] >> 32);
-            }
+            mlo[k] = at ? (uint32_t)open[k] : mlo[k];
+            mhi[k] = at ? (uint32_t)(open[k] >> 32) : mhi[k];
             cur[k] = open[k];
         }
         cur_depth = depth + 1;

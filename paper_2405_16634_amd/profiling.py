@@ -31,7 +31,7 @@ import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TRAVERSAL_SOURCES = [os.path.join(HERE, "csrc", "traverse.hip"),
-                     os.path.join(HERE, "csrc", "common.h")]
+                     os.path.join(HERE, "csrc", "layout.h")]
 
 
 def traversal_digest() -> str:
