@@ -250,6 +250,8 @@ def main():
     tr = load_profile(f"traffic_traverse_{dom}_torusknot500k")
     roofline = {"bound": "alu", "achieved": round(d["tflops"], 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(d["tflops"] / PEAK_FP32_TFLOPS, 4),
+                # without packed FP32 (disabled in this build) the ceiling is half
+                "frac_nonpacked": round(d["tflops"] / (PEAK_FP32_TFLOPS / 2), 4),
                 "traffic": tr["bytes_per_launch"] if tr else None,
                 "kernel": f"k_traverse<{dom}>",
                 "avg_launch_ms": round(d["avg_ms"], 4),
@@ -262,6 +264,9 @@ def main():
         roofline["valu_issue"] = {"insts_per_launch": vi,
                                   "frac": round(vi / (d["avg_ms"] * 1e-3) / sq["valu_issue_peak_per_s"], 4),
                                   "peak_per_s": sq["valu_issue_peak_per_s"]}
+        for k in ("VALUBusy", "VALUUtilization"):
+            if k in sq["per_dispatch"]:
+                roofline["valu_issue"][k] = sq["per_dispatch"][k]
 
     warm = warm_start_section(ctx, w, mu, stream, args.iters, w1, w2, cloud.normals)
 

@@ -171,7 +171,7 @@ wnnc_status wnnc_get_tile(wnnc_ctx ctx, int *tpl);
  * node ranges, each rebuilding its lanes' decisions at the range's
  * ancestors, and a combining pass adds their FP64 sums in range order.
  * The decisions and terms are those of the whole walk (Alg. 4); only the
- * FP64 summation order changes.  0 = whole walks (default).  visits in
+ * FP64 summation order changes.  0 = whole walks; default 256.  visits in
  * 0..WNNC_MAX_SPLIT.  Synchronizes when a tree exists. */
 #define WNNC_MAX_SPLIT (1 << 20)
 wnnc_status wnnc_set_split(wnnc_ctx ctx, int visits);

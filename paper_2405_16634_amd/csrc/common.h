@@ -88,7 +88,7 @@ struct wnnc_ctx_s {
     // combining pass (only for tpl = 1).
     int tpl = 1;
     int prefetch = 0;
-    int split = 0;
+    int split = 256;               // node visits per part of a split walk (0: whole walks)
     int ntasks = 0;                // tasks launched per traversal
     int ngroups = 0;               // groups (per-group partial sums)
     int nparts = 0;                // part slots

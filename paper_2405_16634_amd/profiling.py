@@ -104,16 +104,18 @@ def traffic(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, mb, kernel, cmd)
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
-def sq(csv_path: str, kernel: str, trace_csv: str, cmd: str) -> dict:
-    """Instruction counters per dispatch of the kernels matching `kernel`
-    (one --pmc run with SQ_* counters), with the kernels' average duration
-    from a kernel trace of the same command (kernel_trace CSV)."""
+def sq(csv_paths, kernel: str, trace_csv: str, cmd: str) -> dict:
+    """Instruction counters (and derived metrics such as VALUBusy) per
+    dispatch of the kernels matching `kernel`, from one or more --pmc runs,
+    with the kernels' average duration from a kernel trace of the same
+    command (kernel_trace CSV)."""
     rx = re.compile(kernel)
     per = {}
-    for r in _rows(csv_path):
-        if rx.search(r["Kernel_Name"]):
-            per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
-    out = {k: round(sum(v) / len(v), 1) for k, v in per.items()}
+    for path in ([csv_paths] if isinstance(csv_paths, str) else csv_paths):
+        for r in _rows(path):
+            if rx.search(r["Kernel_Name"]):
+                per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    out = {k: round(sum(v) / len(v), 3) for k, v in per.items()}
     durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
             for r in _rows(trace_csv) if rx.search(r["Kernel_Name"])]
     avg = sum(durs) / len(durs)
@@ -166,7 +168,7 @@ def main():
     q.add_argument("--cmd", required=True)
     q.add_argument("--out", required=True)
     c = sub.add_parser("sq")
-    c.add_argument("--csv", required=True)
+    c.add_argument("--csv", required=True, action="append")
     c.add_argument("--trace", required=True, help="kernel_trace CSV of the same workload")
     c.add_argument("--kernel", required=True)
     c.add_argument("--cmd", required=True)
