@@ -45,6 +45,30 @@ __device__ inline void write_moment(const MomArgs &a, int node, const int4 t, co
     if (a.wout) a.wout[node] = W > 0.0 ? fmaxf((float)W, FLT_MIN) : 0.f;
 }
 
+// One DPP step on an FP64 value: each lane receives the value of the lane
+// selected by CTRL (as its two 32-bit halves), 0 where that lane is outside
+// the row or the lane's row is not in ROW_MASK.
+template <int CTRL, int ROW_MASK>
+__device__ inline double dpp_f64(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Inclusive scan over the 64 lanes: within rows of 16 (row shifts 1, 2, 4,
+// 8), then lane 15 of rows 0 and 2 into rows 1 and 3, then lane 31 into rows
+// 2 and 3.  Fixed order: reproducible.
+__device__ inline double wave_scan(double x) {
+    x += dpp_f64<0x111, 0xf>(x);
+    x += dpp_f64<0x112, 0xf>(x);
+    x += dpp_f64<0x114, 0xf>(x);
+    x += dpp_f64<0x118, 0xf>(x);
+    x += dpp_f64<0x142, 0xa>(x);
+    x += dpp_f64<0x143, 0xc>(x);
+    return x;
+}
+
 template <int MODE>
 __global__ __launch_bounds__(kChunk) void k_moments_chunk(MomArgs a) {
     __shared__ double P[kMomVals][kChunk];
@@ -100,15 +124,9 @@ __global__ __launch_bounds__(kChunk) void k_moments_chunk(MomArgs a) {
         v[5] = d1;
         v[6] = d2;
     }
-    // inclusive scan over the chunk: wavefront shuffles, then wave totals
+    // inclusive scan over the chunk: within each wavefront, then wave totals
 #pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-#pragma unroll
-        for (int k = 0; k < kMomVals; ++k) {
-            const double o = __shfl_up(v[k], d, kWave);
-            if (lane >= d) v[k] += o;
-        }
-    }
+    for (int k = 0; k < kMomVals; ++k) v[k] = wave_scan(v[k]);
     if (lane == kWave - 1) {
 #pragma unroll
         for (int k = 0; k < kMomVals; ++k) wtot[k][wv] = v[k];

@@ -263,3 +263,42 @@ def test_batched64_workload_matches_one_by_one(dev):
         flips.append(((mu_b[off[k]:off[k + 1]] * mu_s).sum(1) <= 0).mean())
     print(f"  flips one-by-one vs batched: max={max(flips):.2e}", flush=True)
     assert max(flips) <= 1e-3
+
+
+def test_split_walks_with_zero_weight_regions(dev, oracle_mod):
+    """Attributes zero on whole regions (zero-weight subtrees, which are not
+    descended): parts that start below such ancestors must add nothing there.
+    Split and whole walks against the oracle, and against each other."""
+    import torch
+    import paper_2405_16634_amd as w
+    cloud = synth.torus_knot(20000, 11, with_init=False)
+    ctx = w.Context(0)
+    x, _ = ctx.normalize(torch.from_numpy(cloud.points).to(dev))
+    ctx.build(x)
+    xh = x.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(12)
+    mu = (synth.random_unit(rng, cloud.n) * 1e-4).astype(np.float32)
+    rho = rng.standard_normal(cloud.n).astype(np.float32)
+    dead = xh[:, 0] > 0.1  # a slab of zero attributes
+    mu[dead] = 0.0
+    rho[dead] = 0.0
+    T = oracle_mod.Tree(xh)
+    outs = {}
+    for split in (0, 64):
+        ctx.set_split(split)
+        outs[split] = (ctx.winding(torch.from_numpy(mu).to(dev), 0.002).cpu().numpy(),
+                       ctx.gradient(torch.from_numpy(mu).to(dev), 0.002).cpu().numpy(),
+                       ctx.adjoint(torch.from_numpy(rho).to(dev), 0.002).cpu().numpy())
+        for op, got, nu, sign in (("A", outs[split][0], mu, 1.0), ("G", outs[split][1], mu, -1.0),
+                                  ("AT", outs[split][2], rho, 1.0)):
+            ref, mag, _ = T.apply(op, nu.astype(np.float64), 0.002, 2.0, with_stats=True)
+            err = np.abs(got - sign * ref)
+            if err.ndim == 2:
+                err = np.linalg.norm(err, axis=1)
+            ok = mag > 0
+            bad = (err[ok] / mag[ok] > TOL).mean()
+            assert bad <= 2e-3, (split, op, bad)
+            assert np.all(err[~ok] == 0.0), (split, op)
+    for a, b in zip(outs[0], outs[64]):
+        assert np.allclose(a, b, rtol=1e-6, atol=0.0), float(np.abs(a - b).max())
+    ctx.close()
