@@ -23,8 +23,8 @@ constexpr int kMaxDepth = 15;    // 15 levels below the root: 45-bit Morton keys
 __host__ __device__ inline int topo_depth(int meta) { return meta & 15; }
 __host__ __device__ inline int topo_leaf(int meta) { return (meta >> 4) & 1; }
 
-// Node record written by every moment pass and read by the traversal, 64
-// bytes per node (one 16-dword scalar load):
+// Node record read by the traversal, 64 bytes per node (one 16-dword scalar
+// load); parts [0..2] are written by every moment pass, [3] with the tree:
 //   [0] hi(x_B).x, .y, .z, flags (int bits)
 //   [1] nu_B (3 floats; a scalar attribute in .x), skip (int bits)
 //   [2] lo(x_B).x, .y, .z, (c * width)^2 (the acceptance threshold)

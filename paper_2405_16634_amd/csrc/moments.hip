@@ -40,8 +40,7 @@ __device__ inline void write_moment(const MomArgs &a, int node, const int4 t, co
     float4 *rec = a.mom + (int64_t)kRecStride * node;
     rec[0] = p;
     rec[1] = make_float4((float)s[4], (float)s[5], (float)s[6], __int_as_float(t.x));
-    rec[2] = lo;
-    rec[3] = make_float4(__int_as_float(t.y), __int_as_float(t.z), 0.f, 0.f);
+    rec[2] = lo;  // rec[3] (the point range) is written once, with the tree
     if (a.wout) a.wout[node] = W > 0.0 ? fmaxf((float)W, FLT_MIN) : 0.f;
 }
 
@@ -182,6 +181,9 @@ __global__ __launch_bounds__(256) void k_moments_strad(MomArgs a) {
     double s[kMomVals];
 #pragma unroll
     for (int k = 0; k < kMomVals; ++k) s[k] = 0.0;
+    // (unrolled so that several chunks' loads are in flight; the additions
+    // keep their order)
+#pragma unroll 4
     for (int c = cb + 1 + lane; c < ce; c += kWave) {
 #pragma unroll
         for (int k = 0; k < kMomVals; ++k) s[k] += a.chunk_tot[8 * c + k];

@@ -339,16 +339,20 @@ __device__ inline unsigned compact3_15(unsigned long long x) {
     return (unsigned)x;
 }
 
-// Geometry of every node for searches by distance (the neighbour search):
-// a single-point leaf holds its point (x, y, z, -1); any other node its
-// cell (lower corner x, y, z, side), from the Morton key of its first point.
+// Static parts of the node records: the point range of every record (the
+// moment passes write the rest), and the geometry of every node for
+// searches by distance (the neighbour search): a single-point leaf holds its
+// point (x, y, z, -1); any other node its cell (lower corner x, y, z, side),
+// from the Morton key of its first point.
 __global__ __launch_bounds__(256) void k_node_cells(const int4 *__restrict__ topo,
                                                     const unsigned long long *__restrict__ keys,
                                                     const float4 *__restrict__ pts, int64_t m,
-                                                    float4 *__restrict__ cells) {
+                                                    float4 *__restrict__ cells,
+                                                    float4 *__restrict__ mom) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= m) return;
     const int4 t = topo[k];
+    mom[kRecStride * k + 3] = make_float4(__int_as_float(t.y), __int_as_float(t.z), 0.f, 0.f);
     if ((t.w & kRecLeaf) && t.z - t.y == 1) {
         const float4 q = pts[t.y];
         cells[k] = make_float4(q.x, q.y, q.z, -1.0f);
@@ -506,7 +510,7 @@ hipError_t build_tree(wnnc_ctx_s *ctx, const float *P) {
                        ctx->perm.p, n, ctx->pts.p);
     TRY(ctx->cells.ensure(m));
     hipLaunchKernelGGL(k_node_cells, dim3(blocks_for(m, 256)), dim3(256), 0, st, ctx->topo.p,
-                       ctx->keys_a.p, ctx->pts.p, m, ctx->cells.p);
+                       ctx->keys_a.p, ctx->pts.p, m, ctx->cells.p, ctx->mom.p);
     TRY(exclusive_scan_u32(ctx->mflag.p, ctx->mslot.p, m + 1, ctx->scan_tmp.p, st));
     uint32_t ns32 = 0;
     TRY(hipMemcpyAsync(&ns32, ctx->mslot.p + m, sizeof(uint32_t), hipMemcpyDeviceToHost, st));

@@ -34,12 +34,21 @@ TRAVERSAL_SOURCES = [os.path.join(HERE, "csrc", "traverse.hip"),
                      os.path.join(HERE, "csrc", "layout.h")]
 
 
+def _code_only(text: str) -> str:
+    """C++ source without comments and with whitespace runs collapsed (string
+    literals in these sources hold no comment markers)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def traversal_digest() -> str:
-    """Digest of the sources that define the traversal kernel."""
+    """Digest of the code (comments and layout ignored) of the sources that
+    define the traversal kernel."""
     h = hashlib.sha256()
     for p in TRAVERSAL_SOURCES:
-        with open(p, "rb") as f:
-            h.update(f.read())
+        with open(p, encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 
