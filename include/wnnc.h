@@ -201,6 +201,17 @@ wnnc_status wnnc_autotune(wnnc_ctx ctx, float w, wnnc_tile_time *times_out);
  * n: (N,3); sigma: (N) or NULL (then n already holds mu); w >= 0. */
 wnnc_status wnnc_winding(wnnc_ctx ctx, const float *n, const float *sigma, float w, float *s_out);
 
+/* Winding number at query points anywhere in space (the field F of Sec. 3.1,
+ * eq. of the winding number; e.g. on a grid, for the indicator function of
+ * the oriented surface): s_out[k] = F(Q_k; mu), mu_j = n_j sigma_j over the
+ * points of the built tree, which must be one cloud.  Q: (M,3) device, in
+ * the frame of the points given to wnnc_build (normalized); M >= 1.  Each
+ * query makes its own Alg. 4 decisions on the tree (c and D of the build),
+ * with the cutoff w as for the points.  n, sigma, w as wnnc_winding.
+ * Synchronizes.  EINVAL for a batched tree. */
+wnnc_status wnnc_winding_at(wnnc_ctx ctx, const float *n, const float *sigma, float w,
+                            const float *Q, int64_t M, float *s_out);
+
 /* Gradient of the winding number at the points: grad_out (N,3) =
  * grad F(x_i; mu) = -G(mu)_i.  Arguments as wnnc_winding. */
 wnnc_status wnnc_gradient(wnnc_ctx ctx, const float *n, const float *sigma, float w,

@@ -33,6 +33,7 @@ EXPORTED = [
     "wnnc_normalize_batched", "wnnc_build_batched", "wnnc_set_tile", "wnnc_get_tile",
     "wnnc_autotune", "wnnc_knn_features", "wnnc_mlp_forward", "wnnc_mlp_grad", "wnnc_mlp_adam",
     "wnnc_warm_orient", "wnnc_set_prefetch", "wnnc_set_split", "wnnc_get_split",
+    "wnnc_winding_at",
 ]
 MLP_PARAMS = 7491
 AUTOTUNE_CONFIGS = 12
@@ -107,6 +108,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "wnnc_normalize": [vp, vp, i64, vp, P(dbl)],
         "wnnc_build": [vp, vp, i64, P(TreeOpts)],
         "wnnc_winding": [vp, vp, vp, f32, vp],
+        "wnnc_winding_at": [vp, vp, vp, f32, vp, i64, vp],
         "wnnc_gradient": [vp, vp, vp, f32, vp],
         "wnnc_adjoint": [vp, vp, f32, vp],
         "wnnc_orient": [vp, P(OrientOpts), vp, vp],
@@ -271,6 +273,15 @@ def wnnc_winding(ctx, n, sigma, w: float, s_out) -> None:
     _check(load_library().wnnc_winding(ctx, _dev(n, "n", shape=(N, 3)),
                                        _dev(sigma, "sigma", shape=(N,)), float(w),
                                        _dev(s_out, "s_out", shape=(N,))))
+
+
+def wnnc_winding_at(ctx, n, sigma, w: float, Q, s_out) -> None:
+    N = n.shape[0]
+    M = Q.shape[0]
+    _check(load_library().wnnc_winding_at(ctx, _dev(n, "n", shape=(N, 3)),
+                                          _dev(sigma, "sigma", shape=(N,)), float(w),
+                                          _dev(Q, "Q", shape=(M, 3)), M,
+                                          _dev(s_out, "s_out", shape=(M,))))
 
 
 def wnnc_gradient(ctx, n, sigma, w: float, grad_out) -> None:
@@ -481,6 +492,12 @@ class Context:
     def winding(self, mu, w: float, sigma=None):
         out = torch.empty(mu.shape[0], device=mu.device, dtype=torch.float32)
         wnnc_winding(self._h, mu, sigma, w, out)
+        return out
+
+    def winding_at(self, mu, w: float, Q, sigma=None):
+        """F(Q_k; mu) at query points Q (M,3) in the normalized frame."""
+        out = torch.empty(Q.shape[0], device=Q.device, dtype=torch.float32)
+        wnnc_winding_at(self._h, mu, sigma, w, Q, out)
         return out
 
     def gradient(self, mu, w: float, sigma=None):

@@ -95,6 +95,9 @@ MomArgs mom_args(wnnc_ctx_s *c) {
 TravArgs trav_args(wnnc_ctx_s *c, float w) {
     TravArgs a;
     memset(&a, 0, sizeof(a));
+    a.tpts = c->pts.p;
+    a.tperm = c->perm.p;
+    a.tcloud = c->cloud_of.p;
     a.pts = c->pts.p;
     a.topo = c->topo.p;
     a.mom = c->mom.p;
@@ -222,6 +225,14 @@ wnnc_status wnnc_destroy(wnnc_ctx ctx) {
     ctx->task_slot.release();
     ctx->task_lo.release();
     ctx->knn_groups.release();
+    ctx->qkeys_a.release();
+    ctx->qkeys_b.release();
+    ctx->qperm.release();
+    ctx->qvals_b.release();
+    ctx->qpts.release();
+    ctx->qtasks.release();
+    ctx->qslot.release();
+    ctx->qcloud.release();
     ctx->cells.release();
     ctx->knn_idx.release();
     ctx->knn_d2.release();
@@ -509,6 +520,59 @@ wnnc_status wnnc_winding(wnnc_ctx ctx, const float *n, const float *sigma, float
     ta.src4 = ctx->va.p;
     ta.out = s_out;
     return run_traverse(ctx, OP_A, TR_OUT_CALLER, ta);
+}
+
+wnnc_status wnnc_winding_at(wnnc_ctx ctx, const float *n, const float *sigma, float w,
+                            const float *Q, int64_t M, float *s_out) {
+    CHECK_CTX(ctx);
+    CHECK_BUILT(ctx);
+    if (!n || !Q || !s_out) return fail(WNNC_EINVAL, "null pointer");
+    if (M < 1 || M > INT32_MAX - 1) return fail(WNNC_EINVAL, "M = %lld out of range", (long long)M);
+    if (!finite_nonneg(w)) return fail(WNNC_EINVAL, "w must be finite and >= 0");
+    if (ctx->nclouds != 1) return fail(WNNC_EINVAL, "queries need a tree of one cloud");
+    hipStream_t st = ctx->stream;
+    MomArgs ma = mom_args(ctx);
+    ma.cn = n;
+    ma.csig = sigma;
+    ma.out4 = ctx->va.p;
+    RETURN_IF(run_moments(ctx, MOM_VEC_CALLER, ma));
+    // queries in Morton order, 64 per wavefront, whole walks of the tree
+    HIPCHK(sort_queries(ctx, Q, M));
+    const int ng = (int)((M + kWave - 1) / kWave);
+    std::vector<int4> tk((size_t)ng);
+    std::vector<int32_t> slot((size_t)ng);
+    for (int g = 0; g < ng; ++g) {
+        const int64_t f = (int64_t)g * kWave;
+        tk[g] = make_int4((int)f, (int)(f + kWave < M ? f + kWave : M), ctx->roots[0], ctx->roots[1]);
+        slot[g] = g;
+    }
+    HIPCHK(ctx->qtasks.ensure(ng));
+    HIPCHK(ctx->qslot.ensure(ng));
+    HIPCHK(ctx->qcloud.ensure(M));
+    HIPCHK(hipMemcpyAsync(ctx->qtasks.p, tk.data(), (size_t)ng * sizeof(int4), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ctx->qslot.p, slot.data(), (size_t)ng * sizeof(int32_t),
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(ctx->qcloud.p, 0, (size_t)M * sizeof(int32_t), st));
+    TravArgs ta = trav_args(ctx, w);
+    ta.src4 = ctx->va.p;
+    ta.out = s_out;
+    ta.tpts = ctx->qpts.p;
+    ta.tperm = ctx->qperm.p;
+    ta.tcloud = ctx->qcloud.p;
+    ta.tasks = ctx->qtasks.p;
+    ta.task_slot = ctx->qslot.p;
+    ta.ntasks = ng;
+    ta.nslots = ng;
+    ta.tpl = 1;
+    {
+        Timed tm(ctx, (int)OP_A);
+        HIPCHK(launch_traverse(ctx, OP_A, TR_OUT_CALLER, (ctx->flags & WNNC_FLAG_COUNT_PAIRS) != 0, ta));
+        tm.done();
+        ctx->calls[OP_A] += 1;
+    }
+    // the host task list is released on return
+    HIPCHK(hipStreamSynchronize(st));
+    return WNNC_OK;
 }
 
 wnnc_status wnnc_gradient(wnnc_ctx ctx, const float *n, const float *sigma, float w,

@@ -102,6 +102,13 @@ struct wnnc_ctx_s {
     std::vector<int32_t> plan;     // host: recorded walks of the 64-target groups
     DevBuf<int32_t> d_plan;
 
+    // off-surface queries (wnnc_winding_at): sorted copies and their tasks
+    DevBuf<unsigned long long> qkeys_a, qkeys_b;
+    DevBuf<uint32_t> qperm, qvals_b;
+    DevBuf<float4> qpts;
+    DevBuf<int4> qtasks;
+    DevBuf<int32_t> qslot, qcloud;
+
     // iteration buffers (sorted order)
     DevBuf<float4> va, vb, vr;
     DevBuf<float> rho;

@@ -24,6 +24,9 @@ int64_t launch_normalize(const float *P, int64_t n, const int64_t *d_off, int nc
                          float *P_norm, double *tmp, hipStream_t st);
 int64_t normalize_tmp_doubles(int64_t nclouds);
 hipError_t build_tree(wnnc_ctx_s *ctx, const float *P);
+// Sorts M caller-order query points (M,3) by Morton key into ctx->qpts, with
+// their caller rows in ctx->qperm.
+hipError_t sort_queries(wnnc_ctx_s *ctx, const float *Q, int64_t M);
 // Wavefront tasks for tile shape tpl and split size `split` (node visits per
 // part, 0 = whole walks; used only with tpl = 1 and a recorded plan).
 hipError_t make_tasks(wnnc_ctx_s *ctx, int tpl, int split);

@@ -117,6 +117,9 @@ struct MomArgs {
 };
 
 struct TravArgs {
+    const float4 *tpts;      // targets (sorted), their caller rows and clouds;
+    const uint32_t *tperm;   // the points themselves, or sorted query points
+    const int32_t *tcloud;
     const float4 *pts;
     const int4 *topo;
     const float4 *mom;

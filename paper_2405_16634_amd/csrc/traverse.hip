@@ -108,7 +108,7 @@ template <int OP, int MODE>
 __device__ inline void finish_target(const TravArgs &a, int t, double s, double gx, double gy,
                                      double gz, double &e, double &e2, unsigned &nflip) {
     if (MODE == TR_OUT_CALLER) {
-        const int64_t j = a.perm[t];
+        const int64_t j = a.tperm[t];
         if (OP == OP_A) {
             a.out[j] = (float)(s * kInv4Pi);
         } else {
@@ -155,7 +155,7 @@ __device__ inline void finish_group(const TravArgs &a, int sl, int first, int la
         unsigned tot = nflip;
 #pragma unroll
         for (int d = kWave / 2; d > 0; d >>= 1) tot += __shfl_xor(tot, d, kWave);
-        if (lane == 0 && tot) atomicAdd(a.flips + a.cloud[first], (unsigned long long)tot);
+        if (lane == 0 && tot) atomicAdd(a.flips + a.tcloud[first], (unsigned long long)tot);
     }
     if (MODE == TR_SCALE) {
         e = wave_sum(e);
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
         valid[k] = t < last;
         tx[k] = ty[k] = tz[k] = 0.f;
         if (valid[k]) {
-            const float4 p = a.pts[t];
+            const float4 p = a.tpts[t];
             tx[k] = p.x, ty[k] = p.y, tz[k] = p.z;
         }
         s[k] = gx[k] = gy[k] = gz[k] = 0.0;
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
     // cloud's root down (at most one ancestor per depth, at most 8 children
     // per node, so both loops end on any input).
     {
-        int node = ldc_i(a.roots + ldc_i(a.cloud + first));
+        int node = ldc_i(a.roots + ldc_i(a.tcloud + first));
         for (int d = 0; d < kMaxDepth && node < nbeg; ++d) {
             const v16f R = ld_rec(a.mom, node);
             const int flags = __float_as_int(R[3]);

@@ -417,6 +417,48 @@ static inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t -
 
 // Builds the forest over the normalized points P (caller order); the cloud
 // ranges are ctx->offsets (host) / ctx->d_offsets (device, already copied).
+// Morton keys of the n caller-order points P (cloud index above the 45
+// Morton bits when nclouds > 1) and a stable LSD sort, 8 bits per pass: on
+// return ka holds the sorted keys and va the caller index of each.  An odd
+// pass count leaves the result in the second buffer pair, which then becomes
+// the first.  Uses ctx->hist and ctx->scan_tmp (sized here for n).
+hipError_t morton_sort(wnnc_ctx_s *ctx, const float *P, int64_t n, int nclouds, int passes,
+                       DevBuf<unsigned long long> &ka, DevBuf<unsigned long long> &kb,
+                       DevBuf<uint32_t> &va, DevBuf<uint32_t> &vb) {
+    hipStream_t st = ctx->stream;
+    const int ntiles = (int)((n + kRsTile - 1) / kRsTile);
+    const int64_t hsize = (int64_t)256 * ntiles;
+    TRY(ka.ensure(n));
+    TRY(kb.ensure(n));
+    TRY(va.ensure(n));
+    TRY(vb.ensure(n));
+    TRY(ctx->hist.ensure(hsize));
+    TRY(ctx->scan_tmp.ensure(scan_tmp_size(16 * (hsize > n + 1 ? hsize : n + 1) + 16)));
+    hipLaunchKernelGGL(k_morton, dim3(blocks_for(n, 256)), dim3(256), 0, st, P, n,
+                       ctx->d_offsets.p, nclouds, ka.p, va.p);
+    unsigned long long *kin = ka.p, *kout = kb.p;
+    uint32_t *vin = va.p, *vout = vb.p;
+    for (int pass = 0; pass < passes; ++pass) {
+        const int shift = 8 * pass;
+        hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(kRsThreads), 0, st, kin, n, shift,
+                           ctx->hist.p, ntiles);
+        TRY(exclusive_scan_u32(ctx->hist.p, ctx->hist.p, hsize, ctx->scan_tmp.p, st));
+        hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(kRsThreads), 0, st, kin, vin, kout,
+                           vout, n, shift, ctx->hist.p, ntiles);
+        unsigned long long *tk = kin;
+        kin = kout;
+        kout = tk;
+        uint32_t *tv = vin;
+        vin = vout;
+        vout = tv;
+    }
+    if (passes & 1) {
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    return hipGetLastError();
+}
+
 hipError_t build_tree(wnnc_ctx_s *ctx, const float *P) {
     const int64_t n = ctx->n;
     const int D = ctx->depth;
@@ -451,32 +493,8 @@ hipError_t build_tree(wnnc_ctx_s *ctx, const float *P) {
         TRY(ctx->scan_tmp.ensure(scan_tmp_size(16 * big + 16)));
     }
 
-    // Morton keys (cloud index above the 45 Morton bits) and a stable LSD
-    // sort, 8 bits per pass; an odd pass count leaves the result in the
-    // second buffer pair, which then becomes the first.
-    hipLaunchKernelGGL(k_morton, dim3(blocks_for(n, 256)), dim3(256), 0, st, P, n,
-                       ctx->d_offsets.p, nclouds, ctx->keys_a.p, ctx->perm.p);
-    unsigned long long *kin = ctx->keys_a.p, *kout = ctx->keys_b.p;
-    uint32_t *vin = ctx->perm.p, *vout = ctx->vals_b.p;
-    for (int pass = 0; pass < passes; ++pass) {
-        const int shift = 8 * pass;
-        hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(kRsThreads), 0, st, kin, n, shift,
-                           ctx->hist.p, ntiles);
-        TRY(exclusive_scan_u32(ctx->hist.p, ctx->hist.p, hsize, ctx->scan_tmp.p, st));
-        hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(kRsThreads), 0, st, kin, vin, kout,
-                           vout, n, shift, ctx->hist.p, ntiles);
-        unsigned long long *tk = kin;
-        kin = kout;
-        kout = tk;
-        uint32_t *tv = vin;
-        vin = vout;
-        vout = tv;
-    }
-    if (passes & 1) {
-        std::swap(ctx->keys_a, ctx->keys_b);
-        std::swap(ctx->perm, ctx->vals_b);
-    }
-    TRY(hipGetLastError());
+    TRY(morton_sort(ctx, P, n, nclouds, passes, ctx->keys_a, ctx->keys_b, ctx->perm,
+                    ctx->vals_b));
     hipLaunchKernelGGL(k_point_cloud, dim3(blocks_for(n, 256)), dim3(256), 0, st, ctx->keys_a.p, n,
                        ctx->cloud_of.p);
 
@@ -627,6 +645,15 @@ hipError_t make_tasks(wnnc_ctx_s *ctx, int tpl, int split) {
     ctx->tpl = tpl;
     ctx->split = split;
     return hipSuccess;
+}
+
+hipError_t sort_queries(wnnc_ctx_s *ctx, const float *Q, int64_t M) {
+    TRY(morton_sort(ctx, Q, M, 1, (kMortonBits + 7) / 8, ctx->qkeys_a, ctx->qkeys_b, ctx->qperm,
+                    ctx->qvals_b));
+    TRY(ctx->qpts.ensure(M));
+    hipLaunchKernelGGL(k_gather_points, dim3(blocks_for(M, 256)), dim3(256), 0, ctx->stream, Q,
+                       ctx->qperm.p, M, ctx->qpts.p);
+    return hipGetLastError();
 }
 
 }  // namespace wnnc
