@@ -22,26 +22,46 @@ Readings (where the paper leaves a choice):
 * rescale keeps mu_i unchanged when |mu^_i| is 0 or not finite, and a zero
   mu_i stays zero.
 * n = 1 uses w = w1.
+
+Variants (Sec. 5: other width schedules, and fixed areas, Sec. 6.1.1):
+* the paper reports cosine and exponential schedules behaving like the
+  linear one, without formulas; read as the smooth decreasing curves from w2
+  (i = 1) to w1 (i = n):
+    cosine      w = w1 + (w2 - w1) (1 + cos(pi t)) / 2
+    exponential w = w2 (w1 / w2)^t          (w1, w2 > 0)
+  with t = (i - 1) / (n - 1);
+* with given areas sigma, the rescale sets |mu_i| = sigma_i:
+  mu_i <- mu^_i sigma_i / |mu^_i| (kept when |mu^_i| is 0 or not finite).
 """
 from __future__ import annotations
 
 import numpy as np
 
 
-def width_schedule(i: int, n: int, w1: float, w2: float) -> float:
-    """Linear width schedule of Alg. 3 (i is 1-based)."""
+def width_schedule(i: int, n: int, w1: float, w2: float, mode: str = "linear") -> float:
+    """Width of iteration i (1-based) of n: the linear schedule of Alg. 3, or
+    the cosine / exponential variants (module docstring)."""
     if n <= 1:
         return float(w1)
-    return w2 * (n - i) / (n - 1) + w1 * (i - 1) / (n - 1)
+    t = (i - 1) / (n - 1)
+    if mode == "linear":
+        return w2 * (n - i) / (n - 1) + w1 * (i - 1) / (n - 1)
+    if mode == "cosine":
+        return w1 + (w2 - w1) * (1.0 + np.cos(np.pi * t)) / 2.0
+    if mode == "exponential":
+        if not (w1 > 0 and w2 > 0):
+            raise ValueError("the exponential schedule needs w1, w2 > 0")
+        return w2 * (w1 / w2) ** t
+    raise ValueError(mode)
 
 
-def rescale(mu, mu_hat):
-    """mu_i <- mu^_i |mu_i| / |mu^_i| (Alg. 3); kept when |mu^_i| is 0 or
-    not finite."""
+def rescale(mu, mu_hat, areas=None):
+    """mu_i <- mu^_i |mu_i| / |mu^_i| (Alg. 3), or mu^_i sigma_i / |mu^_i|
+    with given areas (Sec. 6.1.1); kept when |mu^_i| is 0 or not finite."""
     mu = np.asarray(mu, dtype=np.float64)
     mu_hat = np.asarray(mu_hat, dtype=np.float64)
     nh = np.linalg.norm(mu_hat, axis=1)
-    nm = np.linalg.norm(mu, axis=1)
+    nm = np.linalg.norm(mu, axis=1) if areas is None else np.asarray(areas, dtype=np.float64)
     ok = np.isfinite(nh) & (nh > 0)
     out = mu.copy()
     out[ok] = mu_hat[ok] * (nm[ok] / nh[ok])[:, None]
@@ -88,25 +108,26 @@ def grad_step(ops, mu, w, b=0.5):
 
 def orient(x, iters=40, w1=0.002, w2=0.016, mu0=None, backend="tree", c=2.0,
            max_depth=15, leaf_cap=1, start_iter=1, grad=True, wnnc=True,
-           do_rescale=True, callback=None):
+           do_rescale=True, callback=None, schedule="linear", areas=None):
     """Alg. 3 on normalized points x (n,3).  Returns mu (n,3) in FP64.
 
     grad / wnnc / do_rescale switch the three steps off for the ablations of
-    Sec. 4.7 (defaults: the full method).  callback(i, mu, info) is called
-    after every iteration.
+    Sec. 4.7 (defaults: the full method).  schedule and areas select the
+    variants of the module docstring.  callback(i, mu, info) is called after
+    every iteration.
     """
     x = np.asarray(x, dtype=np.float64)
     ops = _Ops(x, backend, c, max_depth, leaf_cap)
     mu = np.zeros_like(x) if mu0 is None else np.array(mu0, dtype=np.float64)
     for i in range(start_iter, iters + 1):
-        w = width_schedule(i, iters, w1, w2)
+        w = width_schedule(i, iters, w1, w2, schedule)
         info = {"w": w}
         if grad:
             mu, alpha, _, E = grad_step(ops, mu, w)
             info.update(alpha=alpha, E=E)
         if wnnc:
             mu_hat = ops("G", mu, w)
-            mu = rescale(mu, mu_hat) if do_rescale else mu_hat
+            mu = rescale(mu, mu_hat, areas) if do_rescale else mu_hat
         if callback is not None:
             callback(i, mu, info)
     return mu

@@ -341,3 +341,49 @@ def test_table5_sphere_areas(oracle_mod):
     assert abs(a.max() / rows["max"] - 1) < 0.05
     n = mu / np.linalg.norm(mu, axis=1, keepdims=True)
     assert np.all((n * s.normals).sum(1) > 0)
+
+
+# ------------------------------------------------- method variants (Sec. 5)
+
+def test_width_schedules_end_points_and_shape(oracle_mod):
+    """Every schedule starts at w2, ends at w1 and decreases; the cosine
+    midpoint is the mean and the exponential midpoint the geometric mean;
+    the linear one is Alg. 3's formula."""
+    from oracle.iterate import width_schedule
+    w1, w2 = 0.002, 0.016
+    for mode in ("linear", "cosine", "exponential"):
+        ws = [width_schedule(i, 41, w1, w2, mode) for i in range(1, 42)]
+        assert ws[0] == pytest.approx(w2, rel=1e-15)
+        assert ws[-1] == pytest.approx(w1, rel=1e-15)
+        assert all(a >= b for a, b in zip(ws, ws[1:]))
+        assert width_schedule(1, 1, w1, w2, mode) == w1
+    assert width_schedule(21, 41, w1, w2, "cosine") == pytest.approx((w1 + w2) / 2, rel=1e-14)
+    assert width_schedule(21, 41, w1, w2, "exponential") == pytest.approx(np.sqrt(w1 * w2), rel=1e-14)
+    assert width_schedule(11, 41, w1, w2, "linear") == pytest.approx(w2 - 0.25 * (w2 - w1), rel=1e-14)
+    with pytest.raises(ValueError):
+        width_schedule(2, 5, 0.0, w2, "exponential")
+
+
+def test_fixed_area_rescale_sets_the_lengths(oracle_mod):
+    """Sec. 6.1.1: |mu_i| = sigma_i with the direction of G(mu)_i; a zero
+    G keeps mu_i.  On the sphere with sigma = 4 pi / N the run orients every
+    point outward and ends with exactly those lengths."""
+    from oracle import iterate
+    rng = np.random.default_rng(4)
+    mu = rng.standard_normal((6, 3))
+    g = rng.standard_normal((6, 3))
+    g[2] = 0.0
+    sig = rng.uniform(0.5, 2.0, 6)
+    out = iterate.rescale(mu, g, sig)
+    ok = np.arange(6) != 2
+    assert np.allclose(np.linalg.norm(out[ok], axis=1), sig[ok], rtol=1e-14)
+    assert np.allclose(out[ok] / np.linalg.norm(out[ok], axis=1)[:, None],
+                       g[ok] / np.linalg.norm(g[ok], axis=1)[:, None], rtol=1e-14)
+    assert np.array_equal(out[2], mu[2])
+    c = synth.fibonacci_sphere(2000, 0)
+    x, _, _ = oracle_mod.normalize(c.points)
+    x = x.astype(np.float64)
+    area = np.full(len(x), 4.0 * np.pi * (np.linalg.norm(x, axis=1).mean() ** 2) / len(x))
+    mu = iterate.orient(x, iters=10, backend="direct", areas=area)
+    assert np.allclose(np.linalg.norm(mu, axis=1), area, rtol=1e-12)
+    assert np.all((mu * x).sum(1) > 0)
