@@ -13,7 +13,10 @@ Contents (paper: Lin, Shi, Liu 2024, WNNC normal orientation):
 * ``direct_np``            -- the same sums in vectorized numpy for small N
                               (a second, independent transcription).
 * ``Tree``                 -- the paper's treecode (Sec. 3.5, Alg. 4) in C.
-* ``grad_step``/``orient`` -- Alg. 2 and Alg. 3 (``iterate.py``).
+* ``grad_step``/``orient`` -- Alg. 2 and Alg. 3 (``iterate.py``), with the
+                              width-schedule and fixed-area variants.
+* ``areas.knn_areas``      -- the kNN local-area estimate of Sec. 6.1 and
+                              Table 5 (``areas.py``).
 
 Parity pins: see the module docstrings of ``direct_np`` and ``iterate`` and
 the ``tests/test_oracle_*.py`` files.

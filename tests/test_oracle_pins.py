@@ -387,3 +387,78 @@ def test_fixed_area_rescale_sets_the_lengths(oracle_mod):
     mu = iterate.orient(x, iters=10, backend="direct", areas=area)
     assert np.allclose(np.linalg.norm(mu, axis=1), area, rtol=1e-12)
     assert np.all((mu * x).sum(1) > 0)
+
+
+# ---------------------------------------- kNN local areas (Sec. 6.1, Table 5)
+
+def _areas_part(args):
+    from oracle.areas import knn_areas
+    x, nbr, rows = args
+    return knn_areas(x, rows=rows, nbr=nbr)
+
+
+def test_knn_areas_reproduce_table5():
+    """Table 5, kNN column: the estimate on the 163,842-vertex unit sphere
+    has the printed min, max, mean and total (4 significant digits)."""
+    import os
+    from concurrent.futures import ProcessPoolExecutor
+    from oracle.areas import knn
+    path = os.path.join(os.path.dirname(__file__), "golden", "table5_sphere_areas.txt")
+    rows = {}
+    for line in open(path):
+        if line.startswith("#") or line.startswith("stat") or not line.strip():
+            continue
+        k, gt, kn, solved = line.split()
+        rows[k] = float(kn)
+    x = synth.icosphere(7).points.astype(np.float64)
+    nbr = knn(x, 16)
+    parts = np.array_split(np.arange(len(x)), 8)
+    with ProcessPoolExecutor(8) as ex:
+        a = np.concatenate(list(ex.map(_areas_part, [(x, nbr, p) for p in parts])))
+    for stat, v in (("min", a.min()), ("max", a.max()), ("mean", a.mean()), ("total", a.sum())):
+        assert abs(v / rows[stat] - 1) < 1e-3, (stat, v, rows[stat])
+
+
+def _rotation(seed):
+    q, _ = np.linalg.qr(np.random.default_rng(seed).standard_normal((3, 3)))
+    return q
+
+
+def test_knn_areas_lattices_by_hand():
+    """Planar lattices, rotated and shifted: an interior point of a square
+    lattice of spacing a has the cell a^2, of a triangular lattice
+    (sqrt(3)/2) a^2; the corner of a 5 x 5 square grid of spacing 1 has the
+    quadrant cell [-R, 1/2]^2 with R = 4 (its 16th neighbour is at (4, 0)):
+    area 4.5^2."""
+    from oracle.areas import knn_areas
+    a = 0.03
+    R = _rotation(4)
+    shift = np.array([0.1, -0.2, 0.05])
+    g = np.arange(-4, 5)
+    sq = np.array([(i, j, 0.0) for i in g for j in g]) * a
+    centre = int(np.where((sq == 0).all(1))[0][0])
+    out = knn_areas(sq @ R.T + shift)
+    assert abs(out[centre] / a ** 2 - 1) < 1e-9
+    tri = np.array([(i + 0.5 * (j % 2), j * np.sqrt(3) / 2, 0.0) for i in g for j in g]) * a
+    c2 = int(np.argmin(np.linalg.norm(tri - tri.mean(0), axis=1)))
+    out = knn_areas(tri @ R.T + shift)
+    assert abs(out[c2] / (np.sqrt(3) / 2 * a * a) - 1) < 1e-9
+    g5 = np.arange(5)
+    grid = np.array([(i, j, 0.0) for i in g5 for j in g5])
+    out = knn_areas(grid @ R.T)
+    assert abs(out[0] - 4.5 ** 2) < 1e-9
+
+
+def test_knn_areas_tiny_clouds():
+    """Three points (0,0), (1,0), (0,2): the first has the cell
+    {x <= 1/2, y <= 1} clipped to [-2, 2]^2 (R = 2, e1 along (1,0)), area
+    2.5 * 3; clouds of one or two points have no plane and get 0; the
+    estimate scales with the square of a uniform scale."""
+    from oracle.areas import knn_areas
+    P = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.0, 2.0, 0.0]])
+    out = knn_areas(P @ _rotation(7).T)
+    assert abs(out[0] - 7.5) < 1e-9
+    assert np.all(knn_areas(P[:2]) == 0) and np.all(knn_areas(P[:1]) == 0)
+    x = synth.fibonacci_sphere(400, 2).points.astype(np.float64)
+    assert np.allclose(knn_areas(3.0 * x), 9.0 * knn_areas(x), rtol=1e-9)
+    assert np.all(knn_areas(x) > 0)
