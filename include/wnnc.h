@@ -8,17 +8,17 @@
  *   winding number  s_i    = F(x_i; mu)  = sum_j gradPhi(x_i - x_j) . mu_j
  *                                                  (eq. wnf-discretization)
  *   gradient        grad F(x_i; mu)      = sum_j HPhi(x_i - x_j) mu_j
- *                                                  (Sec. 3.2; G = -grad F)
+ *                                                  (Sec. 4.2; G = -grad F)
  *   adjoint         (A^T s)_j            = sum_i s_i gradPhi(x_i - x_j)
  *                                                  (Alg. 2)
  *   orientation     Alg. 3 (Alg. 2 gradient step, WNNC update, rescale)
  *
  * with gradPhi(y) = -y/(4 pi |y|^3) and HPhi(y) = -I/(4 pi |y|^3) +
  * 3 y y^T/(4 pi |y|^5); every pair closer than the smoothing width w (and
- * every coincident pair) contributes zero (Sec. 3.4).  mu_j = n_j sigma_j is
- * the oriented surface element: unit normal times area weight (Sec. 2).
+ * every coincident pair) contributes zero (Sec. 4.4).  mu_j = n_j sigma_j is
+ * the oriented surface element: unit normal times area weight (Sec. 3).
  *
- * Treecode (Sec. 3.5, Alg. 4): an octree over [-1,1]^3 split while a node
+ * Treecode (Sec. 4.5, Alg. 4): an octree over [-1,1]^3 split while a node
  * holds more than one point and is shallower than the maximum depth D; per
  * call, nu-representatives x_B = sum |nu_i| x_i / sum |nu_i|, nu_B = sum nu_i;
  * per target, a node is replaced by its representative when
@@ -62,13 +62,13 @@ typedef enum {
     WNNC_ESTATE = -4,   /* no tree built yet (call wnnc_build first) */
 } wnnc_status;
 
-/* Treecode options (Sec. 4.1.1 defaults in brackets). */
+/* Treecode options (Sec. 5.1.1 defaults in brackets). */
 typedef struct {
     float c;        /* acceptance threshold c > 0 [2] */
     int max_depth;  /* maximum octree depth D, 1..15 [15] */
 } wnnc_tree_opts;
 
-/* Alg. 3 options (Sec. 4.1.1 defaults in brackets). */
+/* Alg. 3 options (Sec. 5.1.1 defaults in brackets). */
 typedef struct {
     int iters;       /* n >= 1 [40] */
     float w1, w2;    /* final and initial smoothing widths, normalized frame
@@ -80,7 +80,20 @@ typedef struct {
                         [0]; (mu, i) is the whole state, so stopping at k and
                         resuming at k+1 with the returned mu reproduces an
                         uninterrupted run bit for bit */
+    int schedule;    /* width schedule [WNNC_SCHEDULE_LINEAR, the above];
+                        the variants named in Sec. 5.5.1, both from w2 at
+                        i = 1 to w1 at i = n, t = (i-1)/(n-1):
+                        COSINE w = w1 + (w2 - w1)(1 + cos(pi t))/2,
+                        EXPONENTIAL w = w2 (w1/w2)^t (w1, w2 > 0) */
+    const float *areas; /* NULL [the method], or (N) caller-order device
+                        areas sigma_i >= 0 in the normalized frame: the
+                        rescale of Alg. 3 becomes mu_i <- G_i sigma_i/|G_i|
+                        (Sec. 6.1.1), so |mu_i| = sigma_i */
 } wnnc_orient_opts;
+
+#define WNNC_SCHEDULE_LINEAR 0
+#define WNNC_SCHEDULE_COSINE 1
+#define WNNC_SCHEDULE_EXPONENTIAL 2
 
 /* Instrumentation flags (wnnc_set_flags). */
 #define WNNC_FLAG_COUNT_PAIRS 1u  /* count pair evaluations (slower kernels) */
@@ -127,7 +140,7 @@ wnnc_status wnnc_set_stream(wnnc_ctx ctx, void *stream);
 /* Instrumentation flags, see WNNC_FLAG_*. */
 wnnc_status wnnc_set_flags(wnnc_ctx ctx, unsigned flags);
 
-/* Sec. 4.1.1 normalization: centre the bounding box at the origin and scale
+/* Sec. 5.1.1 normalization: centre the bounding box at the origin and scale
  * uniformly so that the largest half-extent is 10/11 ([-1,1]^3 with a margin
  * of 1/11).  P, P_norm: (N,3), may alias.  center_scale (host, 4 doubles):
  * centre x,y,z and scale s, so P_norm = (P - centre) * s computed in FP64
@@ -201,7 +214,7 @@ wnnc_status wnnc_autotune(wnnc_ctx ctx, float w, wnnc_tile_time *times_out);
  * n: (N,3); sigma: (N) or NULL (then n already holds mu); w >= 0. */
 wnnc_status wnnc_winding(wnnc_ctx ctx, const float *n, const float *sigma, float w, float *s_out);
 
-/* Winding number at query points anywhere in space (the field F of Sec. 3.1,
+/* Winding number at query points anywhere in space (the field F of Sec. 3,
  * eq. of the winding number; e.g. on a grid, for the indicator function of
  * the oriented surface): s_out[k] = F(Q_k; mu), mu_j = n_j sigma_j over the
  * points of the built tree, which must be one cloud.  Q: (M,3) device, in
@@ -221,6 +234,23 @@ wnnc_status wnnc_gradient(wnnc_ctx ctx, const float *n, const float *sigma, floa
  * out_j = sum_i s_i gradPhi(x_i - x_j) (with the treecode, using the
  * |s|-weighted representatives). */
 wnnc_status wnnc_adjoint(wnnc_ctx ctx, const float *s, float w, float *out);
+
+/* Parameter sets of the paper's experiments, for wnnc_orient_preset.  All
+ * keep the linear schedule and c = 2, D = 15; widths in the normalized
+ * frame. */
+#define WNNC_PRESET_DEFAULT 0    /* Sec. 5.1.1: 40 iterations, w1 0.002, w2 0.016 */
+#define WNNC_PRESET_NOISE_025 1  /* Sec. 5.2.5, Gaussian noise of 0.25 % of the
+                                    bounding-box diagonal: w1 0.02, w2 = 4 w1 */
+#define WNNC_PRESET_NOISE_05 2   /* Sec. 5.2.5, 0.5 %: w1 0.03, w2 = 4 w1 */
+#define WNNC_PRESET_NOISE_1 3    /* Sec. 5.2.5, 1 %: w1 0.04, w2 = 4 w1 */
+#define WNNC_PRESET_SCAN 4       /* Sec. 5.2.6, raw range scans: w1 0.01, w2 0.04 */
+#define WNNC_PRESET_HIGH_GENUS 5 /* Sec. 5.2.3, high-genus surfaces: 300
+                                    iterations, default widths */
+
+/* Fill *out (host) with preset `preset` (WNNC_PRESET_*): iters, w1, w2 as
+ * listed, start_iter 1, stop_iter 0, the linear schedule, no fixed areas.
+ * Host only; needs no device. */
+wnnc_status wnnc_orient_preset(int preset, wnnc_orient_opts *out);
 
 /* Alg. 3 on the built tree (on every cloud of a batched tree at once, each
  * with its own step length).  mu0: (N,3) initial mu, or NULL for mu = 0 (the
@@ -280,6 +310,20 @@ wnnc_status wnnc_moments_export(wnnc_ctx ctx, const float *nu, int dim, float *x
  * int32 caller indices of the neighbours (-1 where missing), or NULL.
  * Points must lie in [-1,1]^3 (normalized). */
 wnnc_status wnnc_knn_features(wnnc_ctx ctx, float *feat_out, int32_t *nbr_out);
+
+/* kNN local areas (Sec. 6.1; the estimate Table 5 compares the solved areas
+ * with, and a source of fixed areas for wnnc_orient_opts.areas).  For every
+ * point of the built tree (all clouds), from its k nearest other points of
+ * the same cloud (2 <= k <= 16): the tangent plane of the point and its
+ * neighbours by principal components (normal = eigenvector of the smallest
+ * eigenvalue of their covariance), the neighbours projected onto it in the
+ * basis e1 = the nearest neighbour's projected direction, e2 = n x e1, and
+ * the area of the point's Voronoi cell among the projections, clipped to the
+ * square [-R,R]^2 (R = the largest projected distance) so that cells at the
+ * edge of an open surface stay bounded.  areas_out (N) device, caller order,
+ * in the normalized frame (divide by scale^2 for the input frame).  A point
+ * with fewer than 2 neighbours gets 0.  FP64 inside, rounded once. */
+wnnc_status wnnc_knn_areas(wnnc_ctx ctx, int k, float *areas_out);
 
 /* Unit normals predicted by the MLP: normals_out (N,3) from feat (N,48). */
 wnnc_status wnnc_mlp_forward(wnnc_ctx ctx, const float *params, const float *feat, int64_t N,

@@ -6,13 +6,13 @@ and never imports it.
 
 Contents (paper: Lin, Shi, Liu 2024, WNNC normal orientation):
 
-* ``normalize``            -- the input normalization of Sec. 4.1.1.
+* ``normalize``            -- the input normalization of Sec. 5.1.1.
 * ``direct``               -- exact O(N^2) FP64 sums of A, A^T, G with the
-                              smoothing cutoff (Thm. 1, Sec. 3.2, Sec. 3.4),
+                              smoothing cutoff (Thm. 1, Sec. 4.2, Sec. 4.4),
                               in C (``liboracle.so``).
 * ``direct_np``            -- the same sums in vectorized numpy for small N
                               (a second, independent transcription).
-* ``Tree``                 -- the paper's treecode (Sec. 3.5, Alg. 4) in C.
+* ``Tree``                 -- the paper's treecode (Sec. 4.5, Alg. 4) in C.
 * ``grad_step``/``orient`` -- Alg. 2 and Alg. 3 (``iterate.py``), with the
                               width-schedule and fixed-area variants.
 * ``areas.knn_areas``      -- the kNN local-area estimate of Sec. 6.1 and
@@ -83,7 +83,7 @@ def set_threads(n: int) -> None:
 
 
 def normalize(points):
-    """Sec. 4.1.1: fit the cloud into [-1,1]^3 with a margin of 1/11.
+    """Sec. 5.1.1: fit the cloud into [-1,1]^3 with a margin of 1/11.
 
     Reading: centre = midpoint of the bounding box; one uniform scale so that
     the largest half-extent becomes 1 - 1/11 = 10/11.  Computed in FP64 from
@@ -118,7 +118,7 @@ def direct(op: str, x, nu, w: float, targets=None, with_mag: bool = False):
 
 
 class Tree:
-    """The paper's octree and treecode (Sec. 3.5, Alg. 4), FP64, in C."""
+    """The paper's octree and treecode (Sec. 4.5, Alg. 4), FP64, in C."""
 
     def __init__(self, x, max_depth: int = 15, leaf_cap: int = 1):
         lib = _load()

@@ -3,13 +3,13 @@
 A second transcription of the operators, independent of the C file, used on
 clouds of at most a few thousand points:
 
-  A  (Sec. 3.3):  s_i  = sum_j gradPhi(x_i - x_j) . mu_j
+  A  (Sec. 4.3):  s_i  = sum_j gradPhi(x_i - x_j) . mu_j
   A^T (Alg. 2):   v_j  = sum_i rho_i gradPhi(x_i - x_j)
-  G  (Sec. 3.2):  mu^_i = -sum_j HPhi(x_i - x_j) mu_j
+  G  (Sec. 4.2):  mu^_i = -sum_j HPhi(x_i - x_j) mu_j
 
 with gradPhi(y) = -y/(4 pi |y|^3) (Thm. 1), HPhi(y) = -I/(4 pi |y|^3) +
-3 y y^T / (4 pi |y|^5) (Sec. 3.2), and every term with |y| < w (or y = 0)
-set to zero (Sec. 3.4).
+3 y y^T / (4 pi |y|^5) (Sec. 4.2), and every term with |y| < w (or y = 0)
+set to zero (Sec. 4.4).
 """
 from __future__ import annotations
 

@@ -8,7 +8,7 @@ Alg. 3, per iteration i = 1..n:
   mu <- grad_step(mu; A_w, b),  b = (1/2, ..., 1/2)  (Alg. 2)
   mu^ <- G_w(mu)                                     (WNNC update)
   mu_i <- mu^_i |mu_i| / |mu^_i|                     (rescale)
-starting from mu = 0 (Sec. 3.3).
+starting from mu = 0 (Sec. 4.3).
 
 Alg. 2 for E(mu) = ||A mu - b||^2:
   r <- A^T b - A^T A mu,  alpha <- r^T r / (r^T A^T A r),  mu <- mu + alpha r
@@ -23,7 +23,7 @@ Readings (where the paper leaves a choice):
   mu_i stays zero.
 * n = 1 uses w = w1.
 
-Variants (Sec. 5: other width schedules, and fixed areas, Sec. 6.1.1):
+Variants (other width schedules, Sec. 5.5.1; fixed areas, Sec. 6.1.1):
 * the paper reports cosine and exponential schedules behaving like the
   linear one, without formulas; read as the smooth decreasing curves from w2
   (i = 1) to w1 (i = n):
@@ -112,7 +112,7 @@ def orient(x, iters=40, w1=0.002, w2=0.016, mu0=None, backend="tree", c=2.0,
     """Alg. 3 on normalized points x (n,3).  Returns mu (n,3) in FP64.
 
     grad / wnnc / do_rescale switch the three steps off for the ablations of
-    Sec. 4.7 (defaults: the full method).  schedule and areas select the
+    Sec. 5.5 (defaults: the full method).  schedule and areas select the
     variants of the module docstring.  callback(i, mu, info) is called after
     every iteration.
     """

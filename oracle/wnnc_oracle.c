@@ -13,17 +13,17 @@
  *
  *   Phi(y)      = 1 / (4 pi |y|)                       (Thm. 1)
  *   grad Phi(y) = -y / (4 pi |y|^3)                    (Thm. 1)
- *   H Phi(y)    = -I/(4 pi |y|^3) + 3 y y^T/(4 pi |y|^5)  (Sec. 3.2)
+ *   H Phi(y)    = -I/(4 pi |y|^3) + 3 y y^T/(4 pi |y|^5)  (Sec. 4.2)
  *
- *   A  : mu -> s,     s_i   = sum_j gradPhi(x_i - x_j) . mu_j     (Sec. 3.3, E)
+ *   A  : mu -> s,     s_i   = sum_j gradPhi(x_i - x_j) . mu_j     (Sec. 4.3, E)
  *   A^T: rho -> v,    v_j   = sum_i rho_i gradPhi(x_i - x_j)      (Alg. 2)
  *   G  : mu -> mu^,   mu^_i = -grad F(x_i; mu)
- *                            = -sum_j HPhi(x_i - x_j) mu_j        (Sec. 3.2)
+ *                            = -sum_j HPhi(x_i - x_j) mu_j        (Sec. 4.2)
  *
- * Smoothing (Sec. 3.4): a pair term is set to 0 when |x_i - x_j| < w.  The
+ * Smoothing (Sec. 4.4): a pair term is set to 0 when |x_i - x_j| < w.  The
  * coincident pair |y| = 0 is also 0 (it is excluded for every w > 0 anyway).
  *
- * Treecode (Sec. 3.5, Alg. 4): an octree over [-1,1]^3 is built by recursive
+ * Treecode (Sec. 4.5, Alg. 4): an octree over [-1,1]^3 is built by recursive
  * partition; a node is split while it holds more than `leaf_cap` points
  * (1 in the paper) and its depth is below the maximum depth D (15 in the
  * paper).  Child membership: a coordinate equal to the split plane goes to

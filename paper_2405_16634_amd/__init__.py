@@ -31,7 +31,8 @@ EXPORTED = [
     "wnnc_orient_energy", "wnnc_stats", "wnnc_reset_stats", "wnnc_tree_export",
     "wnnc_moments_export", "wnnc_normals", "wnnc_last_error", "wnnc_version",
     "wnnc_normalize_batched", "wnnc_build_batched", "wnnc_set_tile", "wnnc_get_tile",
-    "wnnc_autotune", "wnnc_knn_features", "wnnc_mlp_forward", "wnnc_mlp_grad", "wnnc_mlp_adam",
+    "wnnc_autotune", "wnnc_orient_preset", "wnnc_knn_features", "wnnc_knn_areas",
+    "wnnc_mlp_forward", "wnnc_mlp_grad", "wnnc_mlp_adam",
     "wnnc_warm_orient", "wnnc_set_prefetch", "wnnc_set_split", "wnnc_get_split",
     "wnnc_winding_at",
 ]
@@ -52,7 +53,13 @@ class TreeOpts(ctypes.Structure):
 
 class OrientOpts(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("w1", ctypes.c_float), ("w2", ctypes.c_float),
-                ("start_iter", ctypes.c_int), ("stop_iter", ctypes.c_int)]
+                ("start_iter", ctypes.c_int), ("stop_iter", ctypes.c_int),
+                ("schedule", ctypes.c_int), ("areas", ctypes.c_void_p)]
+
+
+SCHEDULES = {"linear": 0, "cosine": 1, "exponential": 2}
+PRESETS = {"default": 0, "noise_0.25": 1, "noise_0.5": 2, "noise_1": 3, "scan": 4,
+           "high_genus": 5}
 
 
 class WarmOpts(ctypes.Structure):
@@ -127,6 +134,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "wnnc_set_split": [vp, ctypes.c_int],
         "wnnc_get_split": [vp, P(ctypes.c_int)],
         "wnnc_knn_features": [vp, vp, vp],
+        "wnnc_knn_areas": [vp, ctypes.c_int, vp],
+        "wnnc_orient_preset": [ctypes.c_int, P(OrientOpts)],
         "wnnc_mlp_forward": [vp, vp, vp, i64, vp],
         "wnnc_mlp_grad": [vp, vp, vp, vp, i64, vp, P(dbl)],
         "wnnc_mlp_adam": [vp, vp, vp, vp, vp, ctypes.c_int, f32, f32, f32, f32],
@@ -298,9 +307,12 @@ def wnnc_adjoint(ctx, s, w: float, out) -> None:
 
 
 def wnnc_orient(ctx, mu_out, mu0=None, iters: int = 40, w1: float = 0.002, w2: float = 0.016,
-                start_iter: int = 1, stop_iter: int = 0) -> None:
+                start_iter: int = 1, stop_iter: int = 0, schedule: str = "linear",
+                areas=None) -> None:
     N = mu_out.shape[0]
-    opts = OrientOpts(int(iters), float(w1), float(w2), int(start_iter), int(stop_iter))
+    ar = _dev(areas, "areas", shape=(N,))
+    opts = OrientOpts(int(iters), float(w1), float(w2), int(start_iter), int(stop_iter),
+                      SCHEDULES[schedule], ar.value if ar is not None else None)
     _check(load_library().wnnc_orient(ctx, ctypes.byref(opts), _dev(mu0, "mu0", shape=(N, 3)),
                                       _dev(mu_out, "mu_out", shape=(N, 3))))
 
@@ -317,6 +329,18 @@ def wnnc_knn_features(ctx, feat_out, nbr_out=None) -> None:
     _check(load_library().wnnc_knn_features(ctx, _dev(feat_out, "feat_out", shape=(N, 48)),
                                             _dev(nbr_out, "nbr_out", dtype=torch.int32,
                                                  shape=(N, 16))))
+
+
+def wnnc_orient_preset(preset: str) -> dict:
+    """iters, w1, w2 of one of the paper's parameter sets (PRESETS)."""
+    o = OrientOpts()
+    _check(load_library().wnnc_orient_preset(PRESETS[preset], ctypes.byref(o)))
+    return {"iters": o.iters, "w1": o.w1, "w2": o.w2}
+
+
+def wnnc_knn_areas(ctx, areas_out, k: int = 16) -> None:
+    N = areas_out.shape[0]
+    _check(load_library().wnnc_knn_areas(ctx, int(k), _dev(areas_out, "areas_out", shape=(N,))))
 
 
 def wnnc_mlp_forward(ctx, params, feat, normals_out) -> None:
@@ -511,10 +535,15 @@ class Context:
         return out
 
     def orient(self, iters: int = 40, w1: float = 0.002, w2: float = 0.016, mu0=None,
-               start_iter: int = 1, stop_iter: int = 0, out=None):
+               start_iter: int = 1, stop_iter: int = 0, out=None, schedule: str = "linear",
+               areas=None, preset: str | None = None):
+        """Alg. 3; `preset` (a PRESETS name) replaces iters, w1 and w2."""
+        if preset is not None:
+            p = wnnc_orient_preset(preset)
+            iters, w1, w2 = p["iters"], p["w1"], p["w2"]
         if out is None:
             out = torch.empty(self.n, 3, device=f"cuda:{self.device}", dtype=torch.float32)
-        wnnc_orient(self._h, out, mu0, iters, w1, w2, start_iter, stop_iter)
+        wnnc_orient(self._h, out, mu0, iters, w1, w2, start_iter, stop_iter, schedule, areas)
         return out
 
     def normals(self, mu, scale: float = 1.0, with_area: bool = False):
@@ -535,6 +564,14 @@ class Context:
                if with_neighbours else None)
         wnnc_knn_features(self._h, feat, nbr)
         return (feat, nbr) if with_neighbours else feat
+
+    def knn_areas(self, k: int = 16, out=None):
+        """kNN local areas of every point (normalized frame, caller order)."""
+        if out is None:
+            out = torch.empty(self.n, device=f"cuda:{self.device}", dtype=torch.float32)
+        _dev(out, "out", shape=(self.n,))
+        wnnc_knn_areas(self._h, out, k)
+        return out
 
     def energy(self, count: int):
         return wnnc_orient_energy(self._h, count, getattr(self, "nclouds", 1))

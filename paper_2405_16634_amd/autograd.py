@@ -1,7 +1,7 @@
 """Differentiable winding numbers: autograd Functions over the C ABI.
 
 The adjoint operator is the backward of the winding-number operator
-(Sec. 3.5, last paragraph: A^T is exactly the backward function of A):
+(Sec. 4.5, last paragraph: A^T is exactly the backward function of A):
 
 * ``winding(ctx, mu, w)``   s = A_w(mu)          backward: g -> A_w^T g
 * ``adjoint(ctx, s, w)``    v = A_w^T s          backward: g -> A_w g

@@ -225,6 +225,7 @@ wnnc_status wnnc_destroy(wnnc_ctx ctx) {
     ctx->task_slot.release();
     ctx->task_lo.release();
     ctx->knn_groups.release();
+    ctx->areas.release();
     ctx->qkeys_a.release();
     ctx->qkeys_b.release();
     ctx->qperm.release();
@@ -611,18 +612,27 @@ wnnc_status wnnc_adjoint(wnnc_ctx ctx, const float *s, float w, float *out) {
 // ctx->va.  zero: mu is 0 at the start (the first A(mu) is skipped).
 // flips (device, per cloud, may be null): in the last iteration, the number
 // of points whose WNNC update points against mu + alpha r.
+// Width of iteration i of n (1-based) under schedule `sched`
+// (wnnc_orient_opts; FP64 on the host, rounded once to FP32).
+static double schedule_width(int sched, int i, int n, float w1, float w2) {
+    if (n <= 1) return (double)w1;
+    const double t = (double)(i - 1) / (n - 1);
+    if (sched == WNNC_SCHEDULE_COSINE)
+        return (double)w1 + ((double)w2 - (double)w1) * (1.0 + cos(M_PI * t)) / 2.0;
+    if (sched == WNNC_SCHEDULE_EXPONENTIAL) return (double)w2 * pow((double)w1 / (double)w2, t);
+    return (double)w2 * (n - i) / (n - 1) + (double)w1 * (i - 1) / (n - 1);
+}
+
 static wnnc_status run_iterations(wnnc_ctx ctx, int iters, float w1, float w2, int start, int stop,
-                                  bool zero, unsigned long long *flips) {
+                                  bool zero, unsigned long long *flips,
+                                  int sched = WNNC_SCHEDULE_LINEAR, const float *areas = nullptr) {
     const int nt = ctx->ngroups;  // row stride of the per-group sums
     const int count = stop - start + 1;
     HIPCHK(ctx->energy.ensure((int64_t)count * ctx->nclouds));
     float4 *mu = ctx->va.p, *tmp = ctx->vb.p, *r = ctx->vr.p;
     float *rho = ctx->rho.p;
     for (int i = start; i <= stop; ++i) {
-        const int n = iters;
-        const double w = n <= 1 ? (double)w1
-                                : (double)w2 * (n - i) / (n - 1) + (double)w1 * (i - 1) / (n - 1);
-        const float wf = (float)w;
+        const float wf = (float)schedule_width(sched, i, iters, w1, w2);
         double *erow = ctx->energy.p + (int64_t)(i - start) * ctx->nclouds;
         // gradient step (Alg. 2): rho = b - A mu, r = A^T rho, t = A r
         const bool first = zero && i == start;
@@ -671,6 +681,7 @@ static wnnc_status run_iterations(wnnc_ctx ctx, int iters, float w1, float w2, i
             TravArgs ta = trav_args(ctx, wf);
             ta.src4 = tmp;
             ta.out4 = mu;
+            ta.areas = areas;
             if (i == stop) ta.flips = flips;
             RETURN_IF(run_traverse(ctx, OP_G, TR_RESCALE, ta));
         }
@@ -679,14 +690,34 @@ static wnnc_status run_iterations(wnnc_ctx ctx, int iters, float w1, float w2, i
     return WNNC_OK;
 }
 
+wnnc_status wnnc_orient_preset(int preset, wnnc_orient_opts *out) {
+    if (!out) return fail(WNNC_EINVAL, "null out");
+    wnnc_orient_opts o = {40, 0.002f, 0.016f, 1, 0, WNNC_SCHEDULE_LINEAR, nullptr};
+    switch (preset) {
+    case WNNC_PRESET_DEFAULT: break;
+    case WNNC_PRESET_NOISE_025: o.w1 = 0.02f, o.w2 = 0.08f; break;
+    case WNNC_PRESET_NOISE_05: o.w1 = 0.03f, o.w2 = 0.12f; break;
+    case WNNC_PRESET_NOISE_1: o.w1 = 0.04f, o.w2 = 0.16f; break;
+    case WNNC_PRESET_SCAN: o.w1 = 0.01f, o.w2 = 0.04f; break;
+    case WNNC_PRESET_HIGH_GENUS: o.iters = 300; break;
+    default: return fail(WNNC_EINVAL, "unknown preset %d", preset);
+    }
+    *out = o;
+    return WNNC_OK;
+}
+
 wnnc_status wnnc_orient(wnnc_ctx ctx, const wnnc_orient_opts *opts, const float *mu0,
                         float *mu_out) {
     CHECK_CTX(ctx);
     CHECK_BUILT(ctx);
     if (!mu_out) return fail(WNNC_EINVAL, "null mu_out");
-    wnnc_orient_opts o = {40, 0.002f, 0.016f, 1, 0};
+    wnnc_orient_opts o = {40, 0.002f, 0.016f, 1, 0, WNNC_SCHEDULE_LINEAR, nullptr};
     if (opts) o = *opts;
     if (o.iters < 1) return fail(WNNC_EINVAL, "iters must be >= 1");
+    if (o.schedule < WNNC_SCHEDULE_LINEAR || o.schedule > WNNC_SCHEDULE_EXPONENTIAL)
+        return fail(WNNC_EINVAL, "unknown width schedule %d", o.schedule);
+    if (o.schedule == WNNC_SCHEDULE_EXPONENTIAL && !(o.w1 > 0.0f && o.w2 > 0.0f))
+        return fail(WNNC_EINVAL, "the exponential schedule needs w1, w2 > 0");
     if (o.start_iter < 1 || o.start_iter > o.iters)
         return fail(WNNC_EINVAL, "start_iter must be in 1..iters");
     const int stop = o.stop_iter == 0 ? o.iters : o.stop_iter;
@@ -701,7 +732,14 @@ wnnc_status wnnc_orient(wnnc_ctx ctx, const wnnc_orient_opts *opts, const float 
         HIPCHK(launch_zero_f4(ctx->va.p, N, st));
     else
         HIPCHK(launch_gather_vec(mu0, ctx->perm.p, ctx->va.p, N, st));
-    RETURN_IF(run_iterations(ctx, o.iters, o.w1, o.w2, o.start_iter, stop, zero, nullptr));
+    const float *areas = nullptr;
+    if (o.areas) {
+        HIPCHK(ctx->areas.ensure(N));
+        HIPCHK(launch_gather_scalar(o.areas, ctx->perm.p, ctx->areas.p, N, st));
+        areas = ctx->areas.p;
+    }
+    RETURN_IF(run_iterations(ctx, o.iters, o.w1, o.w2, o.start_iter, stop, zero, nullptr,
+                             o.schedule, areas));
     HIPCHK(launch_scatter_vec(ctx->va.p, ctx->perm.p, mu_out, N, st));
     return WNNC_OK;
 }
@@ -793,6 +831,16 @@ wnnc_status wnnc_knn_features(wnnc_ctx ctx, float *feat_out, int32_t *nbr_out) {
     CHECK_BUILT(ctx);
     if (!feat_out) return fail(WNNC_EINVAL, "null feat_out");
     HIPCHK(launch_knn_features(ctx, feat_out, nbr_out));
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_knn_areas(wnnc_ctx ctx, int k, float *areas_out) {
+    CHECK_CTX(ctx);
+    CHECK_BUILT(ctx);
+    if (!areas_out) return fail(WNNC_EINVAL, "null areas_out");
+    if (k < 2 || k > 16) return fail(WNNC_EINVAL, "k = %d out of range 2..16", k);
+    HIPCHK(launch_knn(ctx));
+    HIPCHK(launch_knn_areas(ctx, k, areas_out));
     return WNNC_OK;
 }
 

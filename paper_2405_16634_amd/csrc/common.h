@@ -112,6 +112,7 @@ struct wnnc_ctx_s {
     // iteration buffers (sorted order)
     DevBuf<float4> va, vb, vr;
     DevBuf<float> rho;
+    DevBuf<float> areas;           // fixed areas (sorted), when an orientation uses them
     DevBuf<double> partial;        // 3 rows of ngroups per-group sums
     DevBuf<double> scalars;        // alpha per cloud
     DevBuf<double> energy;

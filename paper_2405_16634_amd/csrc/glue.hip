@@ -159,6 +159,19 @@ __global__ __launch_bounds__(256) void k_pred_disagree(const float4 *__restrict_
 
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+__global__ __launch_bounds__(256) void k_gather_scalar(const float *__restrict__ src,
+                                                       const uint32_t *__restrict__ perm, int64_t n,
+                                                       float *__restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[perm[i]];
+}
+
+hipError_t launch_gather_scalar(const float *src, const uint32_t *perm, float *dst, int64_t n,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_scalar, dim3(nblk(n)), dim3(256), 0, st, src, perm, n, dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_pred_disagree(wnnc_ctx_s *ctx, const float4 *mu, const float *nhat,
                                 unsigned long long *count) {
     hipLaunchKernelGGL(k_pred_disagree, dim3(nblk(ctx->n)), dim3(256), 0, ctx->stream, mu, nhat,

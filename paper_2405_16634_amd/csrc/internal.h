@@ -57,6 +57,9 @@ hipError_t launch_alpha(wnnc_ctx_s *ctx, bool first, double *energy_row);
 hipError_t launch_zero_f4(float4 *p, int64_t n, hipStream_t st);
 hipError_t launch_gather_vec(const float *src, const uint32_t *perm, float4 *dst, int64_t n,
                              hipStream_t st);
+// dst[i] = src[perm[i]] (caller order to sorted order)
+hipError_t launch_gather_scalar(const float *src, const uint32_t *perm, float *dst, int64_t n,
+                                hipStream_t st);
 hipError_t launch_scatter_vec(const float4 *src, const uint32_t *perm, float *dst, int64_t n,
                               hipStream_t st);
 
@@ -64,7 +67,12 @@ hipError_t launch_normals(const float *mu, int64_t n, double scale, float *nrm, 
                           hipStream_t st);
 
 // Warm start (knn.hip, mlp.hip).
+// k = 16 nearest neighbours of every point within its cloud (sorted
+// indices, nearest first, -1 where missing) into ctx->knn_idx.
+hipError_t launch_knn(wnnc_ctx_s *ctx);
 hipError_t launch_knn_features(wnnc_ctx_s *ctx, float *feat, int32_t *nbr_caller);
+// kNN local areas from ctx->knn_idx (launch_knn first), caller order.
+hipError_t launch_knn_areas(wnnc_ctx_s *ctx, int k, float *areas_out);
 hipError_t mlp_forward(wnnc_ctx_s *ctx, const float *P, const float *X, int64_t n, float *Y);
 hipError_t mlp_normals(wnnc_ctx_s *ctx, const float *Y, int64_t n, float *out);
 hipError_t mlp_loss_grad(wnnc_ctx_s *ctx, const float *P, const float *X, const float *L,

@@ -219,19 +219,26 @@ __global__ __launch_bounds__(256) void k_features(const float4 *__restrict__ pts
     }
 }
 
-hipError_t launch_knn_features(wnnc_ctx_s *ctx, float *feat, int32_t *nbr_caller) {
+hipError_t launch_knn(wnnc_ctx_s *ctx) {
     const int n = (int)ctx->n;
-    hipStream_t st = ctx->stream;
     hipError_t e = ctx->knn_idx.ensure((int64_t)n * kK);
     if (e != hipSuccess) return e;
     e = ctx->knn_d2.ensure((int64_t)n * kK);
     if (e != hipSuccess) return e;
-    const unsigned nb = (unsigned)((n + 255) / 256);
     if (ctx->knn_ngroups > 0)
-        hipLaunchKernelGGL(k_knn, dim3((unsigned)ctx->knn_ngroups), dim3(kWave), 0, st, ctx->pts.p,
-                           ctx->cells.p, ctx->topo.p, ctx->knn_groups.p, ctx->d_offsets.p,
-                           ctx->cloud_of.p, ctx->knn_ngroups, ctx->knn_idx.p, ctx->knn_d2.p);
-    hipLaunchKernelGGL(k_features, dim3(nb), dim3(256), 0, st, ctx->pts.p, ctx->perm.p,
+        hipLaunchKernelGGL(k_knn, dim3((unsigned)ctx->knn_ngroups), dim3(kWave), 0, ctx->stream,
+                           ctx->pts.p, ctx->cells.p, ctx->topo.p, ctx->knn_groups.p,
+                           ctx->d_offsets.p, ctx->cloud_of.p, ctx->knn_ngroups, ctx->knn_idx.p,
+                           ctx->knn_d2.p);
+    return hipGetLastError();
+}
+
+hipError_t launch_knn_features(wnnc_ctx_s *ctx, float *feat, int32_t *nbr_caller) {
+    const int n = (int)ctx->n;
+    hipError_t e = launch_knn(ctx);
+    if (e != hipSuccess) return e;
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_features, dim3(nb), dim3(256), 0, ctx->stream, ctx->pts.p, ctx->perm.p,
                        ctx->knn_idx.p, n, feat, nbr_caller);
     return hipGetLastError();
 }

@@ -132,6 +132,7 @@ struct TravArgs {
     double *partial;         // per-task partial sums (indexed by task_slot)
     unsigned long long *pairs;  // pair counter (counting variant)
     unsigned long long *flips;  // TR_RESCALE: per cloud, updates against mu (or null)
+    const float *areas;      // TR_RESCALE: sorted fixed areas (or null: keep |mu|)
     const int32_t *cloud;    // cloud of each sorted point (for flips)
     const int4 *tasks;       // per wavefront: first, last target; first, end node
     const int32_t *task_slot;  // >= 0: group slot (whole walk); < 0: -1 - part slot

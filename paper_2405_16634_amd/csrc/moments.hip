@@ -1,5 +1,5 @@
 // The per-call moment pass: nu-representatives of every octree node
-// (Sec. 3.5, eqs. for the node representative location and vector):
+// (Sec. 4.5, eqs. for the node representative location and vector):
 //   W_B = sum_{i in B} |nu_i|,  x_B = sum |nu_i| x_i / W_B,  nu_B = sum nu_i.
 //
 // Nodes are contiguous ranges of the Morton-sorted points.  The points are

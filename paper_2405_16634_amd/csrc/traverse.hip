@@ -1,4 +1,4 @@
-// Treecode traversal (Sec. 3.5, Alg. 4) for the three operators.
+// Treecode traversal (Sec. 4.5, Alg. 4) for the three operators.
 //
 // A wavefront takes one task: 64 * TPL Morton-consecutive targets of one
 // cloud (TPL groups of 64, one target per lane in each group), and walks the
@@ -53,7 +53,7 @@ constexpr double kInv4Pi = 0.0795774715459476678844;  // 1 / (4 pi)
 //   A^T: nu d / r^3                      (nu scalar, in v.x)
 //   G  : nu / r^3 - 3 (d . nu) d / r^5
 // `take` is false for lanes whose pair does not count: not selected by the
-// traversal, or cut off (r < w, Sec. 3.4).  Their term is an exact zero, so
+// traversal, or cut off (r < w, Sec. 4.4).  Their term is an exact zero, so
 // that the unconditional add below leaves the sum unchanged.  The term is
 // formed in FP32 and added to an FP64 per-target sum (FP64 adds issue at the
 // FP32 rate on this chip), so the sum's rounding does not grow with the
@@ -138,7 +138,10 @@ __device__ inline void finish_target(const TravArgs &a, int t, double s, double 
         const double g2 = gx * gx + gy * gy + gz * gz;
         float4 o = mu;
         if (g2 > 0.0 && g2 <= DBL_MAX) {
-            const double mn = sqrt((double)mu.x * mu.x + (double)mu.y * mu.y + (double)mu.z * mu.z);
+            // the length kept: |mu| (Alg. 3), or a given area (Sec. 6.1.1)
+            const double mn = a.areas ? (double)a.areas[t]
+                                      : sqrt((double)mu.x * mu.x + (double)mu.y * mu.y +
+                                             (double)mu.z * mu.z);
             const double f = mn / sqrt(g2);
             o = make_float4((float)(gx * f), (float)(gy * f), (float)(gz * f), 0.f);
         }

@@ -1,4 +1,4 @@
-// Normalization (Sec. 4.1.1) and the octree build (Sec. 3.5) on the device.
+// Normalization (Sec. 5.1.1) and the octree build (Sec. 4.5) on the device.
 //
 // The octree over [-1,1]^3 with maximum depth D is the tree of Morton-code
 // prefixes: quantize each coordinate to 15 bits, interleave into a 45-bit

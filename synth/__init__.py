@@ -10,16 +10,16 @@ Every generator takes an explicit seed and uses ``numpy.random.default_rng``
 
 Workloads (stand-ins for the paper's scanned and benchmark models, which are
 not available; the paper's inputs are 1e4..2.4e6 points, uniform or noisy,
-Sec. 4):
+Sec. 5):
 
 * ``fibonacci_sphere``  -- a jittered Fibonacci lattice on the unit sphere,
   the sphere sanity case of Thm. 1.
 * ``ellipsoid_union``   -- points uniform by area on the boundary of a union
   of random ellipsoids inside the unit cube, with optional Gaussian noise of
-  a fraction of the bounding-box diagonal (the noise model of Sec. 4.4).
+  a fraction of the bounding-box diagonal (the noise model of Sec. 5.2.5).
 * ``torus_knot``        -- a (2,3) torus-knot tube with a 10:1 sampling
   density variation along the curve plus uniform outliers (non-uniform raw
-  scans with outliers, Sec. 4.5).
+  scans with outliers, Sec. 5.2.6).
 * ``batched_sizes``     -- the log-uniform cloud sizes of the batched case.
 * ``icosphere``         -- vertices of a subdivided icosahedron projected on
   the unit sphere (163,842 vertices at level 7: the sphere of Table 5).
@@ -353,9 +353,9 @@ def config(name: str) -> dict:
     """The workloads with their method settings (widths in the normalized
     frame, iteration count, treecode threshold c and depth D).
 
-    The defaults of Sec. 4.1: w1 = 0.002, w2 = 0.016, c = 2, D = 15, 40
+    The defaults of Sec. 5.1: w1 = 0.002, w2 = 0.016, c = 2, D = 15, 40
     iterations; the noisy case uses the 0.25 % noise widths w1 = 0.02,
-    w2 = 4 w1 of Sec. 4.4.
+    w2 = 4 w1 of Sec. 5.2.5.
     """
     if name == "sphere2k":
         return dict(make=lambda: fibonacci_sphere(2000, 0), w1=0.002, w2=0.016,

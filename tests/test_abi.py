@@ -48,3 +48,22 @@ def test_errors_are_reported_without_a_device():
     assert st == w.WNNC_EINVAL
     assert "null" in w.wnnc_last_error()
     assert lib.wnnc_build(None, None, 0, None) == w.WNNC_EINVAL
+
+
+def test_orient_presets_are_the_papers_parameter_sets():
+    """Host-only: the experiment presets (Sec. 5.1.1 defaults, Sec. 5.2.5
+    noise levels with w2 = 4 w1, Sec. 5.2.6 scans, Sec. 5.2.3 high genus)."""
+    import numpy as np
+    import paper_2405_16634_amd as w
+    want = {"default": (40, 0.002, 0.016), "noise_0.25": (40, 0.02, 0.08),
+            "noise_0.5": (40, 0.03, 0.12), "noise_1": (40, 0.04, 0.16),
+            "scan": (40, 0.01, 0.04), "high_genus": (300, 0.002, 0.016)}
+    assert set(want) == set(w.PRESETS)
+    for name, (it, w1, w2) in want.items():
+        p = w.wnnc_orient_preset(name)
+        assert p["iters"] == it
+        # the widths are FP32 in the options struct
+        assert p["w1"] == float(np.float32(w1)) and p["w2"] == float(np.float32(w2))
+    o = w.OrientOpts()
+    assert w.load_library().wnnc_orient_preset(6, ctypes.byref(o)) == w.WNNC_EINVAL
+    assert "preset" in w.wnnc_last_error()

@@ -1,4 +1,4 @@
-"""The adjoint kernel behind torch.autograd (Sec. 3.5: A^T is the backward
+"""The adjoint kernel behind torch.autograd (Sec. 4.5: A^T is the backward
 of A), checked against central finite differences and the FP64 oracle.
 
 Workload: a 5,000-point subset of the torus-knot cloud (the first 5,000 of a

@@ -1,4 +1,4 @@
-"""Winding number at query points off the surface (the field F of Sec. 3.1).
+"""Winding number at query points off the surface (the field F of Sec. 3).
 
 * every query matches the oracle's treecode at the same targets (Alg. 4 per
   query on the points' tree) within the per-target FP32 bound;

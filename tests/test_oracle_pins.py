@@ -70,7 +70,7 @@ def test_on_surface_coulomb_identity(oracle_mod):
 
 
 def test_sphere_normals_are_a_wnnc_fixed_point(oracle_mod):
-    """Sec. 3.2, eq. (wnnc-property-v2): outward sphere normals satisfy
+    """Sec. 4.2, eq. (wnnc-property-v2): outward sphere normals satisfy
     mu_i = lambda_i G(mu)_i with lambda_i > 0.  On the unit sphere with
     mu_j = sigma x_j the gradient operator reduces to the closed form
     G_i = (sigma/4pi) sum_{j != i} [(3/2) x_i - (1/2) x_j] / r_ij^3."""
@@ -109,13 +109,13 @@ def test_two_point_hand_values(oracle_mod):
         assert np.allclose(G[1], [0, 0, 0], atol=1e-15)
         assert np.allclose(AT[1], [1 / np.pi, 0, 0], rtol=0, atol=1e-15)
         assert np.allclose(AT[0], [0, 0, 0], atol=1e-15)
-    # the smoothing width removes the pair (Sec. 3.4: zero when |y| < w)
+    # the smoothing width removes the pair (Sec. 4.4: zero when |y| < w)
     assert np.all(oracle_mod.direct("A", x, mu, 0.5000001) == 0.0)
     assert np.any(oracle_mod.direct("A", x, mu, 0.5) != 0.0)
 
 
 def test_gradient_is_minus_grad_of_winding_number(oracle_mod):
-    """G(mu)_i = -grad F(x_i; mu) (Sec. 3.2): central differences of the
+    """G(mu)_i = -grad F(x_i; mu) (Sec. 4.2): central differences of the
     winding number queried off the points; the self term stays cut off on
     both sides since h < w."""
     rng = np.random.default_rng(11)
@@ -175,7 +175,7 @@ def tree_sets(T):
 
 
 def test_tree_hand_cases(oracle_mod):
-    """Sec. 3.5: partition until one point or depth D; the cube is [-1,1]^3."""
+    """Sec. 4.5: partition until one point or depth D; the cube is [-1,1]^3."""
     # opposite octants: root + two depth-1 leaves
     T = oracle_mod.Tree(np.array([[-0.5, -0.5, -0.5], [0.5, 0.5, 0.5]]))
     sets = tree_sets(T)[0]
@@ -271,7 +271,7 @@ def test_treecode_error_shrinks_with_c(oracle_mod):
 # ---------------------------------------------------------------- Alg. 3 --
 
 def test_iteration_ablations(oracle_mod):
-    """Sec. 4.7.2: without the gradient step mu stays exactly 0; without the
+    """Sec. 5.5.2: without the gradient step mu stays exactly 0; without the
     rescale one WNNC update changes the lengths by a large factor that grows
     with the point density (10^4..10^10 on the paper's data)."""
     factors = []
@@ -300,7 +300,7 @@ def test_flipping_mu_flips_every_operator(oracle_mod):
 
 def test_sphere_end_to_end_direct(oracle_mod):
     """Alg. 3 from mu = 0 on the 2k jittered sphere orients every normal
-    outward (Sec. 3.3: zero initialisation and the PGR energy resolve the
+    outward (Sec. 4.3: zero initialisation and the PGR energy resolve the
     inside/outside ambiguity)."""
     s = synth.fibonacci_sphere(2000, 0)
     x, _, sc = oracle_mod.normalize(s.points)
@@ -309,7 +309,7 @@ def test_sphere_end_to_end_direct(oracle_mod):
     dots = (n * s.normals).sum(1)
     assert np.all(dots > 0)
     assert ((1 - dots) / 2).mean() < 2e-4
-    # unscaled unit random initial vectors break it (Sec. 5.1.3)
+    # unscaled unit random initial vectors break it (Sec. 6.1.3)
     mu_r = oracle_mod.orient(x, backend="direct", iters=10, mu0=s.mu0.astype(np.float64))
     assert ((mu_r * s.normals).sum(1) > 0).mean() < 0.9
 
@@ -343,7 +343,7 @@ def test_table5_sphere_areas(oracle_mod):
     assert np.all((n * s.normals).sum(1) > 0)
 
 
-# ------------------------------------------------- method variants (Sec. 5)
+# ------------------------------- method variants (Sec. 5.5.1, Sec. 6.1.1)
 
 def test_width_schedules_end_points_and_shape(oracle_mod):
     """Every schedule starts at w2, ends at w1 and decreases; the cosine
