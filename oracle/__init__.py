@@ -57,6 +57,9 @@ def _load():
     lib.or_tree_reps.argtypes = [ctypes.c_void_p, d, ctypes.c_int, d, d, d]
     lib.or_tree_apply.argtypes = [ctypes.c_void_p, ctypes.c_int, d, ctypes.c_double,
                                   ctypes.c_double, d, i64, d, d, p64]
+    lib.or_tree_apply_order.argtypes = [ctypes.c_void_p, ctypes.c_int, d, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_int, ctypes.c_int, d, i64, d,
+                                        d, p64]
     lib.or_num_threads.restype = ctypes.c_int
     lib.or_set_threads.argtypes = [ctypes.c_int]
     _lib = lib
@@ -168,9 +171,12 @@ class Tree:
         _load().or_tree_reps(self._h, _dp(nu), dim, _dp(xB), _dp(nuB), _dp(W))
         return xB, (nuB[:, 0] if dim == 1 else nuB), W
 
-    def apply(self, op: str, nu, w: float, c: float = 2.0, targets=None, with_stats: bool = False):
+    def apply(self, op: str, nu, w: float, c: float = 2.0, targets=None, with_stats: bool = False,
+              order: int = 0, wsafe: bool = False):
         """Treecode operator; returns out (and per-target magnitude sums and
-        pair counts with with_stats)."""
+        pair counts with with_stats).  order 1 or 2 replaces each accepted
+        node's representative term by the Taylor expansion of the pair term
+        about x_B to that order (the higher-order far field; 0 is Alg. 4)."""
         lib = _load()
         o = _OPS[op]
         nu = _f64(nu, (self.n, 3) if o != OP_AT else (self.n,))
@@ -179,8 +185,12 @@ class Tree:
         out = np.zeros((t.shape[0], dout))
         mag = np.zeros(t.shape[0])
         pairs = np.zeros(t.shape[0], np.int64)
-        lib.or_tree_apply(self._h, o, _dp(nu), float(w), float(c), _dp(t), t.shape[0],
-                          _dp(out), _dp(mag), pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+        if order not in (0, 1, 2):
+            raise ValueError("order must be 0, 1 or 2")
+        lib.or_tree_apply_order(self._h, o, _dp(nu), float(w), float(c), int(order),
+                                int(bool(wsafe)), _dp(t),
+                                t.shape[0], _dp(out), _dp(mag),
+                                pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
         out = out[:, 0] if dout == 1 else out
         return (out, mag, pairs) if with_stats else out
 

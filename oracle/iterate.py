@@ -71,11 +71,13 @@ def rescale(mu, mu_hat, areas=None):
 class _Ops:
     """A, A^T, G at width w through the chosen backend."""
 
-    def __init__(self, x, backend, c=2.0, max_depth=15, leaf_cap=1):
+    def __init__(self, x, backend, c=2.0, max_depth=15, leaf_cap=1, order=0, wsafe=False):
         from . import Tree, direct
         self.x = np.asarray(x, dtype=np.float64)
         self.backend = backend
         self.c = c
+        self.order = order
+        self.wsafe = wsafe
         if backend == "tree":
             self.tree = Tree(self.x, max_depth=max_depth, leaf_cap=leaf_cap)
         elif backend == "direct":
@@ -88,7 +90,7 @@ class _Ops:
 
     def __call__(self, op, nu, w):
         if self.backend == "tree":
-            return self.tree.apply(op, nu, w, self.c)
+            return self.tree.apply(op, nu, w, self.c, order=self.order, wsafe=self.wsafe)
         if self.backend == "direct":
             return self._direct(op, self.x, nu, w)
         return getattr(self._np, op)(self.x, nu, w)
@@ -108,16 +110,18 @@ def grad_step(ops, mu, w, b=0.5):
 
 def orient(x, iters=40, w1=0.002, w2=0.016, mu0=None, backend="tree", c=2.0,
            max_depth=15, leaf_cap=1, start_iter=1, grad=True, wnnc=True,
-           do_rescale=True, callback=None, schedule="linear", areas=None):
+           do_rescale=True, callback=None, schedule="linear", areas=None, order=0,
+           wsafe=False):
     """Alg. 3 on normalized points x (n,3).  Returns mu (n,3) in FP64.
 
     grad / wnnc / do_rescale switch the three steps off for the ablations of
     Sec. 5.5 (defaults: the full method).  schedule and areas select the
-    variants of the module docstring.  callback(i, mu, info) is called after
+    variants of the module docstring; order and wsafe the treecode's
+    far-field extension (Tree.apply).  callback(i, mu, info) is called after
     every iteration.
     """
     x = np.asarray(x, dtype=np.float64)
-    ops = _Ops(x, backend, c, max_depth, leaf_cap)
+    ops = _Ops(x, backend, c, max_depth, leaf_cap, order, wsafe)
     mu = np.zeros_like(x) if mu0 is None else np.array(mu0, dtype=np.float64)
     for i in range(start_iter, iters + 1):
         w = width_schedule(i, iters, w1, w2, schedule)

@@ -136,6 +136,10 @@ typedef struct {
     int max_depth, leaf_cap;
     /* per-call representatives */
     double *rep_x, *rep_nu, *rep_w;
+    /* per-call far-field moments about x_B (orders 1 and 2):
+     * rep_d[k][l] = sum_j d_jk nu_jl, rep_q[k][n][l] = sum_j d_jk d_jn nu_jl,
+     * d_j = x_j - x_B (l runs over 1 or 3 attribute components) */
+    double *rep_d, *rep_q;
 } or_tree;
 
 static int64_t push_node(or_tree *T)
@@ -236,6 +240,8 @@ void or_tree_free(or_tree *T)
     free(T->rep_x);
     free(T->rep_nu);
     free(T->rep_w);
+    free(T->rep_d);
+    free(T->rep_q);
     free(T);
 }
 
@@ -281,6 +287,35 @@ static void compute_reps(or_tree *T, const double *nu, int dim)
     }
 }
 
+/* Far-field moments of every node about its x_B (after compute_reps). */
+static void compute_moments(or_tree *T, const double *nu, int dim)
+{
+    if (!T->rep_d) {
+        T->rep_d = (double *)malloc((size_t)T->nnodes * 9 * sizeof(double));
+        T->rep_q = (double *)malloc((size_t)T->nnodes * 27 * sizeof(double));
+    }
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t k = 0; k < T->nnodes; ++k) {
+        const or_node *B = &T->nodes[k];
+        const double *xB = T->rep_x + 3 * k;
+        double *D = T->rep_d + 9 * k, *Q = T->rep_q + 27 * k;
+        memset(D, 0, 9 * sizeof(double));
+        memset(Q, 0, 27 * sizeof(double));
+        for (int64_t m = B->begin; m < B->end; ++m) {
+            int64_t i = T->order[m];
+            const double *v = nu + dim * i;
+            double d[3] = {T->x[3 * i] - xB[0], T->x[3 * i + 1] - xB[1], T->x[3 * i + 2] - xB[2]};
+            for (int a = 0; a < 3; ++a)
+                for (int l = 0; l < dim; ++l)
+                    D[3 * a + l] += d[a] * v[l];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    for (int l = 0; l < dim; ++l)
+                        Q[9 * a + 3 * b + l] += d[a] * d[b] * v[l];
+        }
+    }
+}
+
 /* Export the representatives of the last call (or compute them for nu). */
 void or_tree_reps(or_tree *T, const double *nu, int dim, double *xB, double *nuB, double *W)
 {
@@ -295,7 +330,111 @@ typedef struct {
     double w, c;
     const double *nu;
     int din;
+    int order;
+    int wsafe; /* also require dist > w + sqrt(3) width (see or_tree_apply_order) */
 } apply_args;
+
+/* Derivative tensors of Phi(y) = 1/(4 pi |y|) (the kernel of Thm. 1):
+ *   T1_i     = -y_i / (4 pi r^3)
+ *   T2_ij    = (3 y_i y_j - r^2 d_ij) / (4 pi r^5)                 (= H Phi)
+ *   T3_ijk   = (3 r^2 (d_ij y_k + d_ik y_j + d_jk y_i) - 15 y_i y_j y_k)
+ *              / (4 pi r^7)
+ *   T4_ijkl  = (105 y_i y_j y_k y_l
+ *               - 15 r^2 (d_ij y_k y_l + d_ik y_j y_l + d_il y_j y_k
+ *                         + d_jk y_i y_l + d_jl y_i y_k + d_kl y_i y_j)
+ *               + 3 r^4 (d_ij d_kl + d_ik d_jl + d_il d_jk)) / (4 pi r^9)
+ * each the gradient of the one before. */
+static double kd(int i, int j) { return i == j ? 1.0 : 0.0; }
+
+static void phi_derivs(const double *y, double T1[3], double T2[3][3], double T3[3][3][3],
+                       double T4[3][3][3][3])
+{
+    double r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2], r = sqrt(r2);
+    double f = 1.0 / (4.0 * OR_PI);
+    for (int i = 0; i < 3; ++i) {
+        T1[i] = -f * y[i] / (r2 * r);
+        for (int j = 0; j < 3; ++j) {
+            T2[i][j] = f * (3.0 * y[i] * y[j] - r2 * kd(i, j)) / (r2 * r2 * r);
+            for (int k = 0; k < 3; ++k) {
+                T3[i][j][k] = f * (3.0 * r2 * (kd(i, j) * y[k] + kd(i, k) * y[j] + kd(j, k) * y[i])
+                                   - 15.0 * y[i] * y[j] * y[k]) / (r2 * r2 * r2 * r);
+                for (int l = 0; l < 3; ++l)
+                    T4[i][j][k][l] =
+                        f * (105.0 * y[i] * y[j] * y[k] * y[l]
+                             - 15.0 * r2 * (kd(i, j) * y[k] * y[l] + kd(i, k) * y[j] * y[l]
+                                            + kd(i, l) * y[j] * y[k] + kd(j, k) * y[i] * y[l]
+                                            + kd(j, l) * y[i] * y[k] + kd(k, l) * y[i] * y[j])
+                             + 3.0 * r2 * r2 * (kd(i, j) * kd(k, l) + kd(i, k) * kd(j, l)
+                                                + kd(i, l) * kd(j, k)))
+                        / (r2 * r2 * r2 * r2 * r);
+            }
+        }
+    }
+}
+
+/* Far term of node id for target xt, with the Taylor expansion of the pair
+ * term about x_B to `order` (0: the representative term of Alg. 4).  With
+ * y = xt - x_B and a source at x_B + d, each term f(y - d) is expanded as
+ * f(y) - d_k df/dy_k + (1/2) d_k d_n d2f/dy_k dy_n, summed over the node's
+ * sources through the moments nu_B, D, Q:
+ *   A  : f = T1 . nu         -> T1_l nu_l - T2_lk D_kl + 1/2 T3_lkn Q_knl
+ *   A^T: f_m = -rho T1_m     -> -T1_m rho + T2_mk D_k - 1/2 T3_mkn Q_kn
+ *   G  : f_m = -T2_ml nu_l   -> -T2_ml nu_l + T3_mlk D_kl - 1/2 T4_mlkn Q_knl
+ * (the order-0 parts are the pair terms of pair_term).  Zero, like the
+ * order-0 term, when |y| < w or y = 0. */
+static void far_term(const or_tree *T, const apply_args *a, int64_t id, const double *xt,
+                     double *acc, double *mag)
+{
+    const double *xB = T->rep_x + 3 * id, *nuB = T->rep_nu + 3 * id;
+    if (a->order == 0) {
+        pair_term(a->op, xt, xB, nuB, a->w, acc, mag);
+        return;
+    }
+    double y[3] = {xt[0] - xB[0], xt[1] - xB[1], xt[2] - xB[2]};
+    double r = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+    if (r == 0.0 || r < a->w)
+        return;
+    double T1[3], T2[3][3], T3[3][3][3], T4[3][3][3][3];
+    phi_derivs(y, T1, T2, T3, T4);
+    const double *D = T->rep_d + 9 * id, *Q = T->rep_q + 27 * id;
+    const double o2 = a->order >= 2 ? 1.0 : 0.0;
+    double t[3] = {0, 0, 0};
+    if (a->op == OR_OP_A) {
+        for (int l = 0; l < 3; ++l) {
+            t[0] += T1[l] * nuB[l];
+            for (int k = 0; k < 3; ++k) {
+                t[0] -= T2[l][k] * D[3 * k + l];
+                for (int n = 0; n < 3; ++n)
+                    t[0] += o2 * 0.5 * T3[l][k][n] * Q[9 * k + 3 * n + l];
+            }
+        }
+        acc[0] += t[0];
+        *mag += fabs(t[0]);
+        return;
+    }
+    for (int m = 0; m < 3; ++m) {
+        if (a->op == OR_OP_AT) {
+            t[m] -= T1[m] * nuB[0];
+            for (int k = 0; k < 3; ++k) {
+                t[m] += T2[m][k] * D[3 * k];
+                for (int n = 0; n < 3; ++n)
+                    t[m] -= o2 * 0.5 * T3[m][k][n] * Q[9 * k + 3 * n];
+            }
+        } else {
+            for (int l = 0; l < 3; ++l) {
+                t[m] -= T2[m][l] * nuB[l];
+                for (int k = 0; k < 3; ++k) {
+                    t[m] += T3[m][l][k] * D[3 * k + l];
+                    for (int n = 0; n < 3; ++n)
+                        t[m] -= o2 * 0.5 * T4[m][l][k][n] * Q[9 * k + 3 * n + l];
+                }
+            }
+        }
+    }
+    for (int m = 0; m < 3; ++m)
+        acc[m] += t[m];
+    *mag += sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+}
 
 /* Alg. 4 for one target xt starting at node id. */
 static void apply_node(const or_tree *T, const apply_args *a, int64_t id, const double *xt,
@@ -308,8 +447,8 @@ static void apply_node(const or_tree *T, const apply_args *a, int64_t id, const 
     double dx = xt[0] - xB[0], dy = xt[1] - xB[1], dz = xt[2] - xB[2];
     double dist = sqrt(dx * dx + dy * dy + dz * dz);
     double width = ldexp(2.0, -B->depth);
-    if (dist > a->c * width) {
-        pair_term(a->op, xt, xB, T->rep_nu + 3 * id, a->w, acc, mag);
+    if (dist > a->c * width && (!a->wsafe || dist > a->w + sqrt(3.0) * width)) {
+        far_term(T, a, id, xt, acc, mag);
         (*pairs)++;
     } else if (!B->leaf) {
         for (int k = 0; k < B->nchild; ++k)
@@ -325,13 +464,23 @@ static void apply_node(const or_tree *T, const apply_args *a, int64_t id, const 
 
 /* Treecode operator over targets tgt (n_tgt x 3).  Computes the
  * representatives for nu first (every call, as they move with nu).
- * out: (n_tgt, out_dim); mag, pairs optional per-target outputs. */
-void or_tree_apply(or_tree *T, int op, const double *nu, double w, double c,
-                   const double *tgt, int64_t n_tgt, double *out, double *mag, int64_t *pairs)
+ * out: (n_tgt, out_dim); mag, pairs optional per-target outputs.
+ *
+ * Extensions (not in the paper; precision control): `order` 1 or 2 uses
+ * the Taylor expansion of the pair term about x_B for accepted nodes
+ * (far_term); `wsafe` accepts a node only if, besides Alg. 4's test, the
+ * target is farther than w + sqrt(3) width from x_B: x_B lies in the
+ * node's cell, whose points are all within sqrt(3) width of it, so no
+ * accepted node holds a point the cutoff w would drop. */
+void or_tree_apply_order(or_tree *T, int op, const double *nu, double w, double c, int order,
+                         int wsafe, const double *tgt, int64_t n_tgt, double *out, double *mag,
+                         int64_t *pairs)
 {
     int din = op_in_dim(op), dout = op_out_dim(op);
     compute_reps(T, nu, din);
-    apply_args a = {op, w, c, nu, din};
+    if (order > 0)
+        compute_moments(T, nu, din);
+    apply_args a = {op, w, c, nu, din, order, wsafe};
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t i = 0; i < n_tgt; ++i) {
         double acc[3] = {0, 0, 0}, m = 0.0;
@@ -344,6 +493,12 @@ void or_tree_apply(or_tree *T, int op, const double *nu, double w, double c,
         if (pairs)
             pairs[i] = np;
     }
+}
+
+void or_tree_apply(or_tree *T, int op, const double *nu, double w, double c,
+                   const double *tgt, int64_t n_tgt, double *out, double *mag, int64_t *pairs)
+{
+    or_tree_apply_order(T, op, nu, w, c, 0, 0, tgt, n_tgt, out, mag, pairs);
 }
 
 int or_num_threads(void)

@@ -462,3 +462,76 @@ def test_knn_areas_tiny_clouds():
     x = synth.fibonacci_sphere(400, 2).points.astype(np.float64)
     assert np.allclose(knn_areas(3.0 * x), 9.0 * knn_areas(x), rtol=1e-9)
     assert np.all(knn_areas(x) > 0)
+
+
+# ------------------------- far-field extension: Taylor orders, cutoff-safe test
+
+def test_far_field_taylor_orders_converge_at_their_rate(oracle_mod):
+    """A cluster accepted as one node by far targets: the error of the order-p
+    far field against the exact sum falls by 2^(p+1) when the cluster shrinks
+    by 2 (p = 0: the representative term, whose x_B cancels no first moment
+    of random vectors; p = 1, 2: the Taylor terms).  A wrong sign, index or
+    factor in a term of order p leaves an error of that order and breaks the
+    rate."""
+    rng = np.random.default_rng(1)
+    base = rng.standard_normal((12, 3)) * 0.05
+    mu = synth.random_unit(rng, 12) * 0.01
+    rho = rng.uniform(-1, 1, 12)
+    tg = np.array([[0.9, 0.7, -0.6], [-0.8, 0.9, 0.85]])
+    want = {0: (1.7, 2.4), 1: (3.3, 4.7), 2: (6.5, 9.5)}
+    for op, nu in (("A", mu), ("AT", rho), ("G", mu)):
+        prev = None
+        for order in (0, 1, 2):
+            errs = []
+            for s_ in (0.5, 0.25):
+                x = base * s_ + np.array([0.1, -0.05, 0.02])
+                t = oracle_mod.Tree(x).apply(op, nu, 0.0, 0.3, targets=tg, order=order)
+                ex = oracle_mod.direct(op, x, nu, 0.0, targets=tg)
+                errs.append(np.linalg.norm(t - ex) / np.linalg.norm(ex))
+            lo, hi = want[order]
+            assert lo < errs[0] / errs[1] < hi, (op, order, errs)
+            if prev is not None:
+                assert errs[1] < prev
+            prev = errs[1]
+
+
+def test_far_field_of_coincident_sources_is_the_representative(oracle_mod):
+    """Sources at one location: every moment about x_B is 0, so orders 1 and 2
+    equal order 0 (and the exact sum)."""
+    rng = np.random.default_rng(2)
+    x = np.repeat(np.array([[0.2, -0.1, 0.3]]), 5, axis=0)
+    mu = synth.random_unit(rng, 5)
+    tg = np.array([[-0.7, 0.8, -0.9]])
+    for op, nu in (("A", mu), ("AT", rng.uniform(-1, 1, 5)), ("G", mu)):
+        T = oracle_mod.Tree(x, max_depth=3)
+        r0 = T.apply(op, nu, 0.0, 0.3, targets=tg)
+        for order in (1, 2):
+            assert np.allclose(T.apply(op, nu, 0.0, 0.3, targets=tg, order=order), r0,
+                               rtol=1e-14, atol=0)
+        assert np.allclose(r0, oracle_mod.direct(op, x, nu, 0.0, targets=tg), rtol=1e-12)
+
+
+def test_cutoff_safe_acceptance_restores_the_cutoff(oracle_mod):
+    """On a dense 20k cloud most targets have points within w = 0.002, which
+    Alg. 4's representatives carry although the exact sum drops them: the
+    gradient error stays at a few 1e-2 whatever the order.  Accepting only
+    nodes whose cell is beyond w removes that error; with order 2 the
+    remaining Taylor error is below 1e-3."""
+    rng = np.random.default_rng(3)
+    c = synth.torus_knot(20000, 5, with_init=False)
+    x, _, sc = oracle_mod.normalize(c.points)
+    nrm = np.nan_to_num(c.normals)
+    bad = ~np.isfinite(c.normals).all(1)
+    nrm[bad] = synth.random_unit(rng, int(bad.sum()))
+    mu = nrm * c.area * sc * sc / c.n
+    T = oracle_mod.Tree(x)
+    ex = oracle_mod.direct("G", x, mu, 0.002)
+
+    def err(order, ws):
+        g = T.apply("G", mu, 0.002, 2.0, order=order, wsafe=ws)
+        return np.linalg.norm(g - ex) / np.linalg.norm(ex)
+
+    plain, safe2 = err(0, False), err(2, True)
+    assert plain > 1e-2 and err(2, False) > 1e-2
+    assert err(0, True) < 0.2 * plain
+    assert safe2 < 1e-3
