@@ -140,6 +140,37 @@ def warm_start_section(ctx, w, mu_plain, stream, iters, w1, w2, gt):
             "equal_accuracy": bool(flip_s <= 1e-3 and pco_warm >= pco_plain - 1e-3)}
 
 
+def far_field_section(ctx, w, step, mu, stream, steps, normals):
+    """The same step with the order-2 far field and the cutoff-safe
+    acceptance (the precision-control extension): time per step, per-kind
+    traversal launch times, and agreement with the generator's normals."""
+    import torch
+    ctx.set_far_field(2, True)
+    step()
+    ctx.set_flags(w.FLAG_TIME_KERNELS)
+    ctx.reset_stats()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    st = ctx.stats()
+    ctx.set_flags(0)
+    ctx.set_far_field(0, False)
+    ms = e0.elapsed_time(e1) / steps
+    m = mu.cpu().numpy()
+    ok = np.isfinite(normals).all(axis=1)
+    pco = float(((m[ok] * normals[ok]).sum(1) > 0).mean())
+    return {"order": 2, "wsafe": True, "ms_per_step": round(ms, 3),
+            "traverse_avg_ms": {KIND[k]: round(st["traverse_ms"][k] / max(st["calls"][k], 1), 4)
+                                for k in range(3)},
+            "moments_ms_per_step": round(st["moments_ms"] / steps, 3),
+            "P_co": round(pco, 5)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -274,6 +305,7 @@ def main():
     ok = np.isfinite(cloud.normals).all(axis=1)
     pco = float(((nrm_h[ok] * cloud.normals[ok]).sum(1) > 0).mean())
     ae = float(((1.0 - (nrm_h[ok] * cloud.normals[ok]).sum(1)) / 2.0).mean())
+    far = far_field_section(ctx, w, step, mu, stream, max(1, min(args.steps, 3)), cloud.normals)
 
     out = {
         "metric": METRIC,
@@ -310,6 +342,7 @@ def main():
         "context_paper_rtx3090_s": {"N=50k": 1.25, "N=500k": 31.63},
         "roofline": roofline,
         "warm_start": warm,
+        "far_field_order2_wsafe": far,
     }
     if rank == 0 and not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cloud, w1, c)

@@ -235,6 +235,21 @@ wnnc_status wnnc_gradient(wnnc_ctx ctx, const float *n, const float *sigma, floa
  * |s|-weighted representatives). */
 wnnc_status wnnc_adjoint(wnnc_ctx ctx, const float *s, float w, float *out);
 
+/* Far field of the treecode (an extension for precision control; the
+ * paper's Alg. 4 is order 0 without wsafe, the default).
+ *   order 0: an accepted node contributes its representative term;
+ *   order 1, 2: plus the terms of that order of the Taylor expansion of the
+ *     pair term about x_B (from the node's moments sum d nu and
+ *     sum d d^T nu, d = x - x_B), for nodes of more than one point;
+ *   wsafe 1: a node is accepted only if also |x - x_B| > w + sqrt(3) width,
+ *     i.e. no point of its cell is within the cutoff w of the target, so
+ *     the representative does not carry pairs the cutoff would drop.
+ * Applies to every later operator call (winding, gradient, adjoint,
+ * queries, orientation).  The moments take 40 floats per node more of
+ * device memory while order > 0.  Walk plans and tasks are unchanged. */
+wnnc_status wnnc_set_far_field(wnnc_ctx ctx, int order, int wsafe);
+wnnc_status wnnc_get_far_field(wnnc_ctx ctx, int *order, int *wsafe);
+
 /* Parameter sets of the paper's experiments, for wnnc_orient_preset.  All
  * keep the linear schedule and c = 2, D = 15; widths in the normalized
  * frame. */

@@ -34,7 +34,7 @@ EXPORTED = [
     "wnnc_autotune", "wnnc_orient_preset", "wnnc_knn_features", "wnnc_knn_areas",
     "wnnc_mlp_forward", "wnnc_mlp_grad", "wnnc_mlp_adam",
     "wnnc_warm_orient", "wnnc_set_prefetch", "wnnc_set_split", "wnnc_get_split",
-    "wnnc_winding_at",
+    "wnnc_winding_at", "wnnc_set_far_field", "wnnc_get_far_field",
 ]
 MLP_PARAMS = 7491
 AUTOTUNE_CONFIGS = 12
@@ -136,6 +136,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "wnnc_knn_features": [vp, vp, vp],
         "wnnc_knn_areas": [vp, ctypes.c_int, vp],
         "wnnc_orient_preset": [ctypes.c_int, P(OrientOpts)],
+        "wnnc_set_far_field": [vp, ctypes.c_int, ctypes.c_int],
+        "wnnc_get_far_field": [vp, P(ctypes.c_int), P(ctypes.c_int)],
         "wnnc_mlp_forward": [vp, vp, vp, i64, vp],
         "wnnc_mlp_grad": [vp, vp, vp, vp, i64, vp, P(dbl)],
         "wnnc_mlp_adam": [vp, vp, vp, vp, vp, ctypes.c_int, f32, f32, f32, f32],
@@ -329,6 +331,16 @@ def wnnc_knn_features(ctx, feat_out, nbr_out=None) -> None:
     _check(load_library().wnnc_knn_features(ctx, _dev(feat_out, "feat_out", shape=(N, 48)),
                                             _dev(nbr_out, "nbr_out", dtype=torch.int32,
                                                  shape=(N, 16))))
+
+
+def wnnc_set_far_field(ctx, order: int = 0, wsafe: bool = False) -> None:
+    _check(load_library().wnnc_set_far_field(ctx, int(order), int(bool(wsafe))))
+
+
+def wnnc_get_far_field(ctx) -> tuple:
+    o, ws = ctypes.c_int(), ctypes.c_int()
+    _check(load_library().wnnc_get_far_field(ctx, ctypes.byref(o), ctypes.byref(ws)))
+    return o.value, bool(ws.value)
 
 
 def wnnc_orient_preset(preset: str) -> dict:
@@ -564,6 +576,13 @@ class Context:
                if with_neighbours else None)
         wnnc_knn_features(self._h, feat, nbr)
         return (feat, nbr) if with_neighbours else feat
+
+    def set_far_field(self, order: int = 0, wsafe: bool = False) -> None:
+        """Far-field order (0 = Alg. 4, 1, 2) and the cutoff-safe acceptance."""
+        wnnc_set_far_field(self._h, order, wsafe)
+
+    def far_field(self) -> tuple:
+        return wnnc_get_far_field(self._h)
 
     def knn_areas(self, k: int = 16, out=None):
         """kNN local areas of every point (normalized frame, caller order)."""

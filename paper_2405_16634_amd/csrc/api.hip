@@ -65,7 +65,20 @@ struct Timed {
     }
 };
 
-MomArgs mom_args(wnnc_ctx_s *c) {
+// Squared acceptance distance per depth: (c 2^(1-d))^2 (Alg. 4), or with
+// the cutoff-safe test also at least (w + sqrt(3) 2^(1-d))^2, so that an
+// accepted node's cell holds no point closer to the target than w.
+static void fill_thresholds(const wnnc_ctx_s *c, float w, float *thr2) {
+    for (int d = 0; d < 16; ++d) {
+        const double width = ldexp(2.0, -d);
+        double t = (double)c->c * width;
+        if (c->far_wsafe) t = fmax(t, (double)w + sqrt(3.0) * width);
+        thr2[d] = (float)(t * t);
+    }
+}
+
+// Moment-pass arguments for an operator call at width w.
+MomArgs mom_args(wnnc_ctx_s *c, float w) {
     // (fields not set here are per-call inputs and outputs)
     MomArgs a;
     memset(&a, 0, sizeof(a));
@@ -85,10 +98,9 @@ MomArgs mom_args(wnnc_ctx_s *c) {
     a.alpha = c->scalars.p;
     a.n = (int)c->n;
     a.n_strad = c->n_strad;
-    for (int d = 0; d < 16; ++d) {
-        const double t = (double)c->c * ldexp(2.0, -d);
-        a.thr2[d] = (float)(t * t);
-    }
+    fill_thresholds(c, w, a.thr2);
+    a.order = c->far_order;
+    a.momhi = c->far_order > 0 ? c->momhi.p : nullptr;
     return a;
 }
 
@@ -116,10 +128,8 @@ TravArgs trav_args(wnnc_ctx_s *c, float w) {
     a.m = (int)c->m;
     // pairs closer than w, and coincident pairs, contribute nothing
     a.w2 = fmaxf((float)((double)w * (double)w), FLT_MIN);
-    for (int d = 0; d < 16; ++d) {
-        const double t = (double)c->c * ldexp(2.0, -d);
-        a.thr2[d] = (float)(t * t);
-    }
+    a.order = c->far_order;
+    a.momhi = c->far_order > 0 ? c->momhi.p : nullptr;
     return a;
 }
 
@@ -226,6 +236,7 @@ wnnc_status wnnc_destroy(wnnc_ctx ctx) {
     ctx->task_lo.release();
     ctx->knn_groups.release();
     ctx->areas.release();
+    ctx->momhi.release();
     ctx->qkeys_a.release();
     ctx->qkeys_b.release();
     ctx->qperm.release();
@@ -329,10 +340,12 @@ static hipError_t plan_walks(wnnc_ctx_s *ctx) {
     const int64_t len = (int64_t)ctx->ngroups * kPlanStride;
     TRY(ctx->d_plan.ensure(len));
     TRY(hipMemsetAsync(ctx->d_plan.p, 0, (size_t)len * sizeof(int32_t), ctx->stream));
-    MomArgs ma = mom_args(ctx);
+    MomArgs ma = mom_args(ctx, 0.0f);
+    ma.order = 0;  // the walk plan follows Alg. 4's acceptance only
     ma.outs = ctx->rho.p;
     TRY(launch_moments(ctx, MOM_CONST_HALF, ma));
     TravArgs ta = trav_args(ctx, 0.0f);
+    ta.order = 0;
     ta.srcs = ctx->rho.p;
     ta.plan = ctx->d_plan.p;
     TRY(record_plan(ctx, ta));
@@ -371,6 +384,7 @@ static wnnc_status build_impl(wnnc_ctx ctx, const float *P, const int64_t *offse
     hipError_t e = build_tree(ctx, P);
     if (e == hipSuccess) e = plan_walks(ctx);
     if (e == hipSuccess) e = make_tasks(ctx, tpl, split);
+    if (e == hipSuccess && ctx->far_order > 0) e = ctx->momhi.ensure(ctx->m * kHiStride);
     if (e != hipSuccess) {
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -428,6 +442,24 @@ wnnc_status wnnc_set_split(wnnc_ctx ctx, int visits) {
     return WNNC_OK;
 }
 
+wnnc_status wnnc_set_far_field(wnnc_ctx ctx, int order, int wsafe) {
+    CHECK_CTX(ctx);
+    if (order < 0 || order > 2) return fail(WNNC_EINVAL, "far-field order must be 0, 1 or 2");
+    if (wsafe != 0 && wsafe != 1) return fail(WNNC_EINVAL, "wsafe must be 0 or 1");
+    if (order > 0 && ctx->built) HIPCHK(ctx->momhi.ensure(ctx->m * kHiStride));
+    ctx->far_order = order;
+    ctx->far_wsafe = wsafe;
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_get_far_field(wnnc_ctx ctx, int *order, int *wsafe) {
+    CHECK_CTX(ctx);
+    if (!order || !wsafe) return fail(WNNC_EINVAL, "null output");
+    *order = ctx->far_order;
+    *wsafe = ctx->far_wsafe;
+    return WNNC_OK;
+}
+
 wnnc_status wnnc_get_split(wnnc_ctx ctx, int *visits) {
     CHECK_CTX(ctx);
     if (!visits) return fail(WNNC_EINVAL, "null output");
@@ -454,7 +486,7 @@ wnnc_status wnnc_autotune(wnnc_ctx ctx, float w, wnnc_tile_time *times_out) {
     if (!finite_nonneg(w)) return fail(WNNC_EINVAL, "w must be finite and >= 0");
     // the adjoint traversal with the constant scalar 1/2: every weight is
     // positive, so it visits the nodes a smooth attribute would
-    MomArgs ma = mom_args(ctx);
+    MomArgs ma = mom_args(ctx, 0.0f);
     ma.outs = ctx->rho.p;
     RETURN_IF(run_moments(ctx, MOM_CONST_HALF, ma));
     // (tpl, split) pairs, each with and without prefetch
@@ -512,7 +544,7 @@ wnnc_status wnnc_winding(wnnc_ctx ctx, const float *n, const float *sigma, float
     CHECK_BUILT(ctx);
     if (!n || !s_out) return fail(WNNC_EINVAL, "null pointer");
     if (!finite_nonneg(w)) return fail(WNNC_EINVAL, "w must be finite and >= 0");
-    MomArgs ma = mom_args(ctx);
+    MomArgs ma = mom_args(ctx, w);
     ma.cn = n;
     ma.csig = sigma;
     ma.out4 = ctx->va.p;
@@ -532,7 +564,7 @@ wnnc_status wnnc_winding_at(wnnc_ctx ctx, const float *n, const float *sigma, fl
     if (!finite_nonneg(w)) return fail(WNNC_EINVAL, "w must be finite and >= 0");
     if (ctx->nclouds != 1) return fail(WNNC_EINVAL, "queries need a tree of one cloud");
     hipStream_t st = ctx->stream;
-    MomArgs ma = mom_args(ctx);
+    MomArgs ma = mom_args(ctx, w);
     ma.cn = n;
     ma.csig = sigma;
     ma.out4 = ctx->va.p;
@@ -582,7 +614,7 @@ wnnc_status wnnc_gradient(wnnc_ctx ctx, const float *n, const float *sigma, floa
     CHECK_BUILT(ctx);
     if (!n || !grad_out) return fail(WNNC_EINVAL, "null pointer");
     if (!finite_nonneg(w)) return fail(WNNC_EINVAL, "w must be finite and >= 0");
-    MomArgs ma = mom_args(ctx);
+    MomArgs ma = mom_args(ctx, w);
     ma.cn = n;
     ma.csig = sigma;
     ma.out4 = ctx->va.p;
@@ -598,7 +630,7 @@ wnnc_status wnnc_adjoint(wnnc_ctx ctx, const float *s, float w, float *out) {
     CHECK_BUILT(ctx);
     if (!s || !out) return fail(WNNC_EINVAL, "null pointer");
     if (!finite_nonneg(w)) return fail(WNNC_EINVAL, "w must be finite and >= 0");
-    MomArgs ma = mom_args(ctx);
+    MomArgs ma = mom_args(ctx, w);
     ma.cs = s;
     ma.outs = ctx->rho.p;
     RETURN_IF(run_moments(ctx, MOM_SCALAR_CALLER, ma));
@@ -638,11 +670,11 @@ static wnnc_status run_iterations(wnnc_ctx ctx, int iters, float w1, float w2, i
         const bool first = zero && i == start;
         if (first) {
             // mu = 0: A mu = 0 exactly, so rho = 1/2 everywhere
-            MomArgs ma = mom_args(ctx);
+            MomArgs ma = mom_args(ctx, wf);
             ma.outs = rho;
             RETURN_IF(run_moments(ctx, MOM_CONST_HALF, ma));
         } else {
-            MomArgs ma = mom_args(ctx);
+            MomArgs ma = mom_args(ctx, wf);
             ma.src4 = mu;
             RETURN_IF(run_moments(ctx, MOM_VEC_SORTED, ma));
             TravArgs ta = trav_args(ctx, wf);
@@ -650,7 +682,7 @@ static wnnc_status run_iterations(wnnc_ctx ctx, int iters, float w1, float w2, i
             ta.rho = rho;
             ta.partial = ctx->partial.p;
             RETURN_IF(run_traverse(ctx, OP_A, TR_RHO, ta));
-            MomArgs mb = mom_args(ctx);
+            MomArgs mb = mom_args(ctx, wf);
             mb.srcs = rho;
             RETURN_IF(run_moments(ctx, MOM_SCALAR_SORTED, mb));
         }
@@ -662,7 +694,7 @@ static wnnc_status run_iterations(wnnc_ctx ctx, int iters, float w1, float w2, i
             RETURN_IF(run_traverse(ctx, OP_AT, TR_R, ta));
         }
         {
-            MomArgs ma = mom_args(ctx);
+            MomArgs ma = mom_args(ctx, wf);
             ma.src4 = r;
             RETURN_IF(run_moments(ctx, MOM_VEC_SORTED, ma));
             TravArgs ta = trav_args(ctx, wf);
@@ -673,7 +705,7 @@ static wnnc_status run_iterations(wnnc_ctx ctx, int iters, float w1, float w2, i
         HIPCHK(launch_alpha(ctx, first, erow));
         // mu <- mu + alpha r, then the WNNC update and rescale
         {
-            MomArgs ma = mom_args(ctx);
+            MomArgs ma = mom_args(ctx, wf);
             ma.src4 = mu;
             ma.r4 = r;
             ma.out4 = tmp;
@@ -771,7 +803,7 @@ wnnc_status wnnc_warm_orient(wnnc_ctx ctx, const float *params, const wnnc_warm_
     // 2. per-cloud least-squares scale beta = <A n, 1/2> / |A n|^2 at the
     //    first width of the warm schedule; mu0 = beta n
     {
-        MomArgs ma = mom_args(ctx);
+        MomArgs ma = mom_args(ctx, o.iters > 1 ? o.w2 : o.w1);
         ma.cn = ctx->nhat.p;
         ma.out4 = ctx->vb.p;
         RETURN_IF(run_moments(ctx, MOM_VEC_CALLER, ma));
@@ -975,7 +1007,7 @@ wnnc_status wnnc_moments_export(wnnc_ctx ctx, const float *nu, int dim, float *x
     if (!nu) return fail(WNNC_EINVAL, "null nu");
     if (dim != 1 && dim != 3) return fail(WNNC_EINVAL, "dim must be 1 or 3");
     HIPCHK(ctx->wbuf.ensure(ctx->m));
-    MomArgs ma = mom_args(ctx);
+    MomArgs ma = mom_args(ctx, 0.0f);
     ma.wout = ctx->wbuf.p;
     if (dim == 3) {
         ma.cn = nu;

@@ -60,8 +60,8 @@ struct wnnc_ctx_s {
     int32_t n_strad = 0;
     DevBuf<uint32_t> tail_off;     // chunks+1
     DevBuf<int32_t> tail_list;     // n_strad
-    DevBuf<double> chunk_tot;      // 8 per chunk
-    DevBuf<double> head, tail;     // 8 per straddler
+    DevBuf<double> chunk_tot;      // kMomSlots per chunk
+    DevBuf<double> head, tail;     // kMomSlots per straddler
     DevBuf<float4> mom;            // kRecStride per node
     DevBuf<float> wbuf;            // per-node W, filled on request
 
@@ -112,7 +112,10 @@ struct wnnc_ctx_s {
     // iteration buffers (sorted order)
     DevBuf<float4> va, vb, vr;
     DevBuf<float> rho;
-    DevBuf<float> areas;           // fixed areas (sorted), when an orientation uses them
+    DevBuf<float> areas;
+    DevBuf<float> momhi;           // far-field moments (far_order >= 1)
+    int far_order = 0;             // 0: Alg. 4's representative term; 1, 2: Taylor orders
+    int far_wsafe = 0;             // accept a node only when its cell is beyond w           // fixed areas (sorted), when an orientation uses them
     DevBuf<double> partial;        // 3 rows of ngroups per-group sums
     DevBuf<double> scalars;        // alpha per cloud
     DevBuf<double> energy;

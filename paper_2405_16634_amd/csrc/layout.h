@@ -36,6 +36,26 @@ __host__ __device__ inline int topo_leaf(int meta) { return (meta >> 4) & 1; }
 // The traversal addresses records with 32-bit byte offsets: at most
 // kMaxNodes nodes.
 constexpr int kRecStride = 4;
+// Far-field moments about x_B of every node (orders 1 and 2 of the far
+// field), kHiStride floats per node.  The Taylor terms contract them with
+// derivatives of 1/r, which are symmetric in all their indices, so only the
+// symmetric parts are kept (d_j = x_j - x_B):
+//   vector nu: [0..5]   D_(k,n)   = sym of sum_j d_jk nu_jn, pairs
+//                                   (0,0) (0,1) (0,2) (1,1) (1,2) (2,2)
+//              [6]      tr D      = sum_j d_j . nu_j
+//              [7..16]  Q_(k,n,l) = sym of sum_j d_jk d_jn nu_jl, triples
+//                                   000 001 002 011 012 022 111 112 122 222
+//              [17..19] e_m       = sum_k Q_(k,k,m)
+//   scalar rho: [0..2]  p_k       = sum_j rho_j d_jk
+//              [3..8]   q_(k,n)   = sum_j rho_j d_jk d_jn, pairs as above
+//              [9]      tr q
+constexpr int kHiStride = 24;
+// FP64 partial sums per chunk and per straddler in the moment pass: 7 for
+// the representatives, 16 more with the raw (about the origin) symmetric
+// far-field moments.
+constexpr int kMomSlots = 24;
+constexpr int kMomBase = 7;
+constexpr int kMomHi = kMomBase + 16;
 constexpr int64_t kMaxNodes = int64_t(1) << 26;
 constexpr int kRecLeaf = 16;
 constexpr int kRecSingle = 32;
@@ -106,14 +126,17 @@ struct MomArgs {
     const float *cs;         // caller-order scalar input
     float4 *out4;
     float *outs;
-    double *chunk_tot;       // 8 doubles per chunk
-    double *head;            // 8 doubles per straddler
-    double *tail;            // 8 doubles per straddler
+    double *chunk_tot;       // kMomSlots doubles per chunk
+    double *head;            // kMomSlots doubles per straddler
+    double *tail;            // kMomSlots doubles per straddler
     float4 *mom;             // node records, kRecStride float4 per node
+    float *momhi;            // far-field moments, kHiStride floats per node (order >= 1)
     float *wout;             // optional: W = sum |nu| per node (inspection)
-    float thr2[16];          // (c * 2^(1-d))^2 per depth d, copied into records
+    float thr2[16];          // squared acceptance distance per depth d, into records
     int n;
     int n_strad;
+    int order;               // far-field order: 0 (Alg. 4), 1 or 2 (also writes momhi)
+    int scalar;              // the attribute is scalar (set by launch_moments)
 };
 
 struct TravArgs {
@@ -144,8 +167,9 @@ struct TravArgs {
     int tpl;                 // target groups of 64 per wavefront (1, 2, 4)
     int prefetch;            // software-pipelined node walk
     int n, m;
+    const float *momhi;      // far-field moments (order >= 1)
     float w2;
-    float thr2[16];          // (c * 2^(1-d))^2 per depth d
+    int order;               // far-field order 0, 1, 2
 };
 
 }  // namespace wnnc

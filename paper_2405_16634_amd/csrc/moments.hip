@@ -10,6 +10,23 @@
 // tail partial from their last, and the totals of the chunks in between in a
 // second launch (one wavefront per straddler).  All sums run in a fixed
 // order, so the moments are bitwise reproducible from run to run.
+//
+// With a far field of order 1 or 2 (an extension: the Taylor expansion of
+// the pair term about x_B) the same pass also sums raw moments about the
+// origin in FP64 and writes the central ones about x_B (d = x - x_B) by the
+// parallel-axis shift.  For a vector attribute only the parts symmetric in
+// all indices are needed (the Taylor terms contract them with derivatives
+// of 1/r), and those shift among themselves:
+//   M1_kn = sym sum x_k nu_n,  M2_knl = sym sum x_k x_n nu_l,
+//   D_kn  = M1_kn - sym(x_Bk nu_Bn),
+//   Q_knl = M2_knl - (2/3)(x_Bk M1_nl + x_Bn M1_kl + x_Bl M1_kn)
+//           + sym(x_Bk x_Bn nu_Bl),
+// with sym(a_k b_n) = (a_k b_n + a_n b_k)/2 and sym(a_k a_n b_l) =
+// (a_k a_n b_l + a_k a_l b_n + a_n a_l b_k)/3.  For a scalar rho:
+//   p_k = sum rho x_k - x_Bk rho_B,
+//   q_kn = sum rho x_k x_n - x_Bk P_n - x_Bn P_k + x_Bk x_Bn rho_B (P = sum rho x).
+// (In FP64 the shift loses about (1/width)^2 of relative precision: 1e-8 at
+// the deepest level, far below the FP32 the moments are stored in.)
 #include <float.h>
 
 #include "common.h"
@@ -17,10 +34,52 @@
 
 namespace wnnc {
 
-constexpr int kMomVals = 7;  // |nu|, |nu| x (3), nu (3)
+// values per point: |nu|, |nu| x (3), nu (3); with HI also, for a vector
+// attribute, M1 (6 pairs) and M2 (10 triples), for a scalar one rho x_k (3)
+// and rho x_k x_n (6 pairs)
+template <bool HI>
+constexpr int mom_vals() { return HI ? kMomHi : kMomBase; }
+constexpr int kPairK[6] = {0, 0, 0, 1, 1, 2};
+constexpr int kPairN[6] = {0, 1, 2, 1, 2, 2};
+constexpr int kTriK[10] = {0, 0, 0, 0, 0, 0, 1, 1, 1, 2};
+constexpr int kTriN[10] = {0, 0, 0, 1, 1, 2, 1, 1, 2, 2};
+constexpr int kTriL[10] = {0, 1, 2, 1, 2, 2, 1, 2, 2, 2};
+
+// The pair index of (k, n) in either order.
+__device__ constexpr int pair_of(int k, int n) {
+    return k > n ? pair_of(n, k) : (k == 0 ? n : (k == 1 ? 2 + n : 5));
+}
+
+// The raw far-field values of one point (slots kMomBase..kMomHi-1).
+__device__ inline void raw_hi(const float4 x, double n0, double n1, double n2, bool scalar,
+                              double *v) {
+    const double xs[3] = {(double)x.x, (double)x.y, (double)x.z};
+    const double ns[3] = {n0, n1, n2};
+    if (scalar) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) v[kMomBase + k] = xs[k] * n0;
+#pragma unroll
+        for (int p = 0; p < 6; ++p) v[kMomBase + 3 + p] = xs[kPairK[p]] * xs[kPairN[p]] * n0;
+#pragma unroll
+        for (int i = kMomBase + 9; i < kMomHi; ++i) v[i] = 0.0;
+        return;
+    }
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+        const int k = kPairK[p], n = kPairN[p];
+        v[kMomBase + p] = 0.5 * (xs[k] * ns[n] + xs[n] * ns[k]);
+    }
+#pragma unroll
+    for (int t = 0; t < 10; ++t) {
+        const int k = kTriK[t], n = kTriN[t], l = kTriL[t];
+        v[kMomBase + 6 + t] = (xs[k] * xs[n] * ns[l] + xs[k] * xs[l] * ns[n] +
+                               xs[n] * xs[l] * ns[k]) * (1.0 / 3.0);
+    }
+}
 
 // Node record: x_B = X / W and nu_B in FP32 with the node's topology (skip
 // pointer and flags) so that the traversal needs one 32-byte load per node.
+template <bool HI>
 __device__ inline void write_moment(const MomArgs &a, int node, const int4 t, const double *s) {
     const double W = s[0];
     int flags = t.w & 31;  // depth | leaf << 4
@@ -42,6 +101,53 @@ __device__ inline void write_moment(const MomArgs &a, int node, const int4 t, co
     rec[1] = make_float4((float)s[4], (float)s[5], (float)s[6], __int_as_float(t.x));
     rec[2] = lo;  // rec[3] (the point range) is written once, with the tree
     if (a.wout) a.wout[node] = W > 0.0 ? fmaxf((float)W, FLT_MIN) : 0.f;
+    if (HI) {
+        // central moments about x_B (0 for a node that carries nothing)
+        const bool live = W > 0.0;
+        const double xb[3] = {live ? s[1] / W : 0.0, live ? s[2] / W : 0.0,
+                              live ? s[3] / W : 0.0};
+        const double nb[3] = {s[4], s[5], s[6]};
+        const double *m = s + kMomBase;
+        float *h = a.momhi + (int64_t)kHiStride * node;
+        if (a.scalar) {
+            double q[6], tr = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) h[k] = live ? (float)(m[k] - xb[k] * nb[0]) : 0.f;
+#pragma unroll
+            for (int p = 0; p < 6; ++p) {
+                const int k = kPairK[p], n = kPairN[p];
+                q[p] = m[3 + p] - xb[k] * m[n] - xb[n] * m[k] + xb[k] * xb[n] * nb[0];
+                if (k == n) tr += q[p];
+                h[3 + p] = live ? (float)q[p] : 0.f;
+            }
+            h[9] = live ? (float)tr : 0.f;
+        } else {
+            double D[6], Q[10];
+#pragma unroll
+            for (int p = 0; p < 6; ++p) {
+                const int k = kPairK[p], n = kPairN[p];
+                D[p] = m[p] - 0.5 * (xb[k] * nb[n] + xb[n] * nb[k]);
+            }
+#pragma unroll
+            for (int t = 0; t < 10; ++t) {
+                const int k = kTriK[t], n = kTriN[t], l = kTriL[t];
+                Q[t] = m[6 + t] -
+                       (2.0 / 3.0) * (xb[k] * m[pair_of(n, l)] + xb[n] * m[pair_of(k, l)] +
+                                      xb[l] * m[pair_of(k, n)]) +
+                       (xb[k] * xb[n] * nb[l] + xb[k] * xb[l] * nb[n] + xb[n] * xb[l] * nb[k]) *
+                           (1.0 / 3.0);
+            }
+#pragma unroll
+            for (int p = 0; p < 6; ++p) h[p] = live ? (float)D[p] : 0.f;
+            h[6] = live ? (float)(D[0] + D[3] + D[5]) : 0.f;
+#pragma unroll
+            for (int t = 0; t < 10; ++t) h[7 + t] = live ? (float)Q[t] : 0.f;
+            // e_m = sum_k Q_(k,k,m): triples (0,0,m) (1,1,m) (2,2,m) sorted
+            h[17] = live ? (float)(Q[0] + Q[3] + Q[5]) : 0.f;  // 000 011 022
+            h[18] = live ? (float)(Q[1] + Q[6] + Q[8]) : 0.f;  // 001 111 122
+            h[19] = live ? (float)(Q[2] + Q[7] + Q[9]) : 0.f;  // 002 112 222
+        }
+    }
 }
 
 // One DPP step on an FP64 value: each lane receives the value of the lane
@@ -68,8 +174,9 @@ __device__ inline double wave_scan(double x) {
     return x;
 }
 
-template <int MODE>
+template <int MODE, bool HI>
 __global__ __launch_bounds__(kChunk) void k_moments_chunk(MomArgs a) {
+    constexpr int kMomVals = mom_vals<HI>();
     __shared__ double P[kMomVals][kChunk];
     __shared__ double wtot[kMomVals][kChunk / kWave];
     const int tid = threadIdx.x;
@@ -122,6 +229,7 @@ __global__ __launch_bounds__(kChunk) void k_moments_chunk(MomArgs a) {
         v[4] = d0;
         v[5] = d1;
         v[6] = d2;
+        if (HI) raw_hi(x, d0, d1, d2, scalar, v);
     }
     // inclusive scan over the chunk: within each wavefront, then wave totals
 #pragma unroll
@@ -139,7 +247,7 @@ __global__ __launch_bounds__(kChunk) void k_moments_chunk(MomArgs a) {
     }
     __syncthreads();
 
-    if (tid < kMomVals) a.chunk_tot[8 * c + tid] = P[tid][cnt - 1];
+    if (tid < kMomVals) a.chunk_tot[kMomSlots * c + tid] = P[tid][cnt - 1];
 
     // nodes started inside this chunk
     const int nlo = (int)a.node_off[c0];
@@ -152,12 +260,12 @@ __global__ __launch_bounds__(kChunk) void k_moments_chunk(MomArgs a) {
             const int e = t.z - c0 - 1;
 #pragma unroll
             for (int k = 0; k < kMomVals; ++k) s[k] = P[k][e] - (b > 0 ? P[k][b - 1] : 0.0);
-            write_moment(a, nd, t, s);
+            write_moment<HI>(a, nd, t, s);
         } else {
             const int sl = a.node_strad[nd];
 #pragma unroll
             for (int k = 0; k < kMomVals; ++k)
-                a.head[8 * sl + k] = P[k][cnt - 1] - (b > 0 ? P[k][b - 1] : 0.0);
+                a.head[kMomSlots * sl + k] = P[k][cnt - 1] - (b > 0 ? P[k][b - 1] : 0.0);
         }
     }
     // straddlers whose range ends inside this chunk
@@ -166,12 +274,14 @@ __global__ __launch_bounds__(kChunk) void k_moments_chunk(MomArgs a) {
         const int sl = a.tail_list[q];
         const int e = a.topo[a.strad_node[sl]].z - c0 - 1;
 #pragma unroll
-        for (int k = 0; k < kMomVals; ++k) a.tail[8 * sl + k] = P[k][e];
+        for (int k = 0; k < kMomVals; ++k) a.tail[kMomSlots * sl + k] = P[k][e];
     }
 }
 
 // One wavefront per straddler: head + totals of the chunks in between + tail.
+template <bool HI>
 __global__ __launch_bounds__(256) void k_moments_strad(MomArgs a) {
+    constexpr int kMomVals = mom_vals<HI>();
     const int lane = threadIdx.x & (kWave - 1);
     const int sl = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
     if (sl >= a.n_strad) return;
@@ -186,7 +296,7 @@ __global__ __launch_bounds__(256) void k_moments_strad(MomArgs a) {
 #pragma unroll 4
     for (int c = cb + 1 + lane; c < ce; c += kWave) {
 #pragma unroll
-        for (int k = 0; k < kMomVals; ++k) s[k] += a.chunk_tot[8 * c + k];
+        for (int k = 0; k < kMomVals; ++k) s[k] += a.chunk_tot[kMomSlots * c + k];
     }
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) {
@@ -196,38 +306,53 @@ __global__ __launch_bounds__(256) void k_moments_strad(MomArgs a) {
     if (lane == 0) {
         double tot[kMomVals];
 #pragma unroll
-        for (int k = 0; k < kMomVals; ++k) tot[k] = (a.head[8 * sl + k] + s[k]) + a.tail[8 * sl + k];
-        write_moment(a, nd, t, tot);
+        for (int k = 0; k < kMomVals; ++k) tot[k] = (a.head[kMomSlots * sl + k] + s[k]) + a.tail[kMomSlots * sl + k];
+        write_moment<HI>(a, nd, t, tot);
     }
 }
 
-hipError_t launch_moments(wnnc_ctx_s *ctx, MomMode mode, const MomArgs &a) {
+template <bool HI>
+void launch_moments_t(MomMode mode, const MomArgs &a, hipStream_t st) {
     const unsigned nchunks = (unsigned)((a.n + kChunk - 1) / kChunk);
-    hipStream_t st = ctx->stream;
     switch (mode) {
         case MOM_VEC_SORTED:
-            hipLaunchKernelGGL(k_moments_chunk<MOM_VEC_SORTED>, dim3(nchunks), dim3(kChunk), 0, st, a);
+            hipLaunchKernelGGL((k_moments_chunk<MOM_VEC_SORTED, HI>), dim3(nchunks), dim3(kChunk), 0,
+                               st, a);
             break;
         case MOM_SCALAR_SORTED:
-            hipLaunchKernelGGL(k_moments_chunk<MOM_SCALAR_SORTED>, dim3(nchunks), dim3(kChunk), 0, st, a);
+            hipLaunchKernelGGL((k_moments_chunk<MOM_SCALAR_SORTED, HI>), dim3(nchunks),
+                               dim3(kChunk), 0, st, a);
             break;
         case MOM_VEC_CALLER:
-            hipLaunchKernelGGL(k_moments_chunk<MOM_VEC_CALLER>, dim3(nchunks), dim3(kChunk), 0, st, a);
+            hipLaunchKernelGGL((k_moments_chunk<MOM_VEC_CALLER, HI>), dim3(nchunks), dim3(kChunk), 0,
+                               st, a);
             break;
         case MOM_SCALAR_CALLER:
-            hipLaunchKernelGGL(k_moments_chunk<MOM_SCALAR_CALLER>, dim3(nchunks), dim3(kChunk), 0, st, a);
+            hipLaunchKernelGGL((k_moments_chunk<MOM_SCALAR_CALLER, HI>), dim3(nchunks),
+                               dim3(kChunk), 0, st, a);
             break;
         case MOM_AXPY:
-            hipLaunchKernelGGL(k_moments_chunk<MOM_AXPY>, dim3(nchunks), dim3(kChunk), 0, st, a);
+            hipLaunchKernelGGL((k_moments_chunk<MOM_AXPY, HI>), dim3(nchunks), dim3(kChunk), 0, st,
+                               a);
             break;
         case MOM_CONST_HALF:
-            hipLaunchKernelGGL(k_moments_chunk<MOM_CONST_HALF>, dim3(nchunks), dim3(kChunk), 0, st, a);
+            hipLaunchKernelGGL((k_moments_chunk<MOM_CONST_HALF, HI>), dim3(nchunks), dim3(kChunk),
+                               0, st, a);
             break;
     }
     if (a.n_strad > 0) {
         const unsigned nb = (unsigned)((a.n_strad + 3) / 4);
-        hipLaunchKernelGGL(k_moments_strad, dim3(nb), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_moments_strad<HI>), dim3(nb), dim3(256), 0, st, a);
     }
+}
+
+hipError_t launch_moments(wnnc_ctx_s *ctx, MomMode mode, const MomArgs &args) {
+    MomArgs a = args;
+    a.scalar = mode == MOM_SCALAR_SORTED || mode == MOM_SCALAR_CALLER || mode == MOM_CONST_HALF;
+    if (a.order > 0 && a.momhi)
+        launch_moments_t<true>(mode, a, ctx->stream);
+    else
+        launch_moments_t<false>(mode, a, ctx->stream);
     return hipGetLastError();
 }
 

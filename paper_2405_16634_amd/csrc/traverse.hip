@@ -14,6 +14,11 @@
 //
 // Node records are read with scalar loads: the node index is uniform across
 // the wavefront.  The 1/(4 pi) factor is applied in the epilogue.
+//
+// HI (an extension of Alg. 4, for precision control): the representative
+// term of an accepted node holding more than one point is followed by the
+// order-1 (and, at order 2, order-2) terms of the Taylor expansion of the
+// pair term about x_B, from the node's far-field moments.
 #include <float.h>
 
 #include "common.h"
@@ -83,6 +88,100 @@ __device__ inline void pair_term(float dx, float dy, float dz, float r2, float4 
         gy += (double)fmaf(v.y, a3, -c5 * dy);
         gz += (double)fmaf(v.z, a3, -c5 * dz);
     }
+}
+
+typedef float v8f __attribute__((ext_vector_type(8)));
+
+// Higher-order far-field terms (without the 1/(4 pi) factor) for target
+// offset y = x - x_B = r u (|u| = 1), from the node's symmetric moments H
+// (layout kHiStride; uniform across the wavefront).  With the derivatives
+// of 1/r, each symmetric in all its indices,
+//   T2_ij  = (3 y_i y_j - r^2 d_ij) / r^5
+//   T3_ijk = (3 r^2 (d_ij y_k + d_ik y_j + d_jk y_i) - 15 y_i y_j y_k) / r^7
+//   T4     = (105 yyyy - 15 r^2 (six d yy terms) + 3 r^4 (three d d terms)) / r^9
+// the terms added to the representative term are, written in u so that no
+// power of 1/r beyond the fifth is formed,
+//   A  : - T2 : D + 1/2 T3 : Q   = (tr D - 3 u.D.u) / r^3 + (9 u.e - 15 q3) / (2 r^4)
+//   A^T: T2 p - 1/2 T3 : q       = (3 u (u.p) - p) / r^3
+//                                  - (3 (2 q u + u tr q) - 15 u (u.q.u)) / (2 r^4)
+//   G  : T3 : D - 1/2 T4 : Q     = (3 (2 D u + u tr D) - 15 u (u.D.u)) / r^4
+//                                  - (105 u q3 - 45 (a + u (u.e)) + 9 e) / (2 r^5)
+// with a_m = sum_(k,n) u_k u_n Q_(m,k,n) and q3 = u.a.  The order-2 part is
+// skipped at order 1.  `take` as in pair_term (a lane that does not take
+// gets u = 0 and 1/r = 0: an exact 0).
+template <int OP>
+__device__ inline void far_terms(float dx, float dy, float dz, float r2, const v16f &H0,
+                                 const v8f &H1, bool order2, bool take, double &s, double &gx,
+                                 double &gy, double &gz) {
+    const float ri = take ? __builtin_amdgcn_rsqf(r2) : 0.0f;
+    const float u0 = dx * ri, u1 = dy * ri, u2 = dz * ri;
+    const float ri2 = ri * ri;
+    const float ri3 = ri2 * ri;
+    const float ri4 = ri2 * ri2;
+    auto h = [&](int i) -> float { return i < 16 ? H0[i] : H1[i - 16]; };
+    if (OP == OP_AT) {
+        // p_k = h(k); q pairs (00 01 02 11 12 22) = h(3..8); tr q = h(9)
+        const float up = fmaf(u0, h(0), fmaf(u1, h(1), u2 * h(2)));
+        float t0 = fmaf(3.0f * up, u0, -h(0)) * ri3;
+        float t1 = fmaf(3.0f * up, u1, -h(1)) * ri3;
+        float t2 = fmaf(3.0f * up, u2, -h(2)) * ri3;
+        if (order2) {
+            const float qu0 = fmaf(h(3), u0, fmaf(h(4), u1, h(5) * u2));
+            const float qu1 = fmaf(h(4), u0, fmaf(h(6), u1, h(7) * u2));
+            const float qu2 = fmaf(h(5), u0, fmaf(h(7), u1, h(8) * u2));
+            const float uqu = fmaf(u0, qu0, fmaf(u1, qu1, u2 * qu2));
+            const float trq = h(9), c = -7.5f * uqu;
+            t0 -= fmaf(1.5f, fmaf(2.0f, qu0, u0 * trq), c * u0) * ri4;
+            t1 -= fmaf(1.5f, fmaf(2.0f, qu1, u1 * trq), c * u1) * ri4;
+            t2 -= fmaf(1.5f, fmaf(2.0f, qu2, u2 * trq), c * u2) * ri4;
+        }
+        gx += (double)t0;
+        gy += (double)t1;
+        gz += (double)t2;
+        return;
+    }
+    // D pairs (00 01 02 11 12 22) = h(0..5), tr D = h(6)
+    const float Du0 = fmaf(h(0), u0, fmaf(h(1), u1, h(2) * u2));
+    const float Du1 = fmaf(h(1), u0, fmaf(h(3), u1, h(4) * u2));
+    const float Du2 = fmaf(h(2), u0, fmaf(h(4), u1, h(5) * u2));
+    const float uDu = fmaf(u0, Du0, fmaf(u1, Du1, u2 * Du2));
+    const float trD = h(6);
+    // Q triples (000 001 002 011 012 022 111 112 122 222) = h(7..16),
+    // e = h(17..19)
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, q3 = 0.f, ue = 0.f;
+    if (order2) {
+        const float s00 = u0 * u0, s01 = 2.0f * u0 * u1, s02 = 2.0f * u0 * u2, s11 = u1 * u1,
+                    s12 = 2.0f * u1 * u2, s22 = u2 * u2;
+        a0 = fmaf(s00, h(7), fmaf(s01, h(8), fmaf(s02, h(9), fmaf(s11, h(10),
+             fmaf(s12, h(11), s22 * h(12))))));
+        a1 = fmaf(s00, h(8), fmaf(s01, h(10), fmaf(s02, h(11), fmaf(s11, h(13),
+             fmaf(s12, h(14), s22 * h(15))))));
+        a2 = fmaf(s00, h(9), fmaf(s01, h(11), fmaf(s02, h(12), fmaf(s11, h(14),
+             fmaf(s12, h(15), s22 * h(16))))));
+        q3 = fmaf(u0, a0, fmaf(u1, a1, u2 * a2));
+        ue = fmaf(u0, h(17), fmaf(u1, h(18), u2 * h(19)));
+    }
+    if (OP == OP_A) {
+        float t = fmaf(-3.0f, uDu, trD) * ri3;
+        if (order2) t += fmaf(4.5f, ue, -7.5f * q3) * ri4;
+        s += (double)t;
+        return;
+    }
+    // G
+    const float ri5 = ri4 * ri;
+    const float c15 = -15.0f * uDu;
+    float t0 = fmaf(3.0f, fmaf(2.0f, Du0, u0 * trD), c15 * u0) * ri4;
+    float t1 = fmaf(3.0f, fmaf(2.0f, Du1, u1 * trD), c15 * u1) * ri4;
+    float t2 = fmaf(3.0f, fmaf(2.0f, Du2, u2 * trD), c15 * u2) * ri4;
+    if (order2) {
+        const float c105 = 105.0f * q3;
+        t0 -= 0.5f * fmaf(c105, u0, fmaf(-45.0f, fmaf(u0, ue, a0), 9.0f * h(17))) * ri5;
+        t1 -= 0.5f * fmaf(c105, u1, fmaf(-45.0f, fmaf(u1, ue, a1), 9.0f * h(18))) * ri5;
+        t2 -= 0.5f * fmaf(c105, u2, fmaf(-45.0f, fmaf(u2, ue, a2), 9.0f * h(19))) * ri5;
+    }
+    gx += (double)t0;
+    gy += (double)t1;
+    gz += (double)t2;
 }
 
 // The calling lane's bit of a wave-uniform lane mask (the mask is used as a
@@ -191,7 +290,7 @@ __device__ inline void finish_group(const TravArgs &a, int sl, int first, int la
 // pointer (subtree done) or the next node (descend); the skip successor's
 // record is loaded while the node is visited, so that load overlaps the
 // work on the node.
-template <int OP, int MODE, bool COUNT, int TPL, bool PF>
+template <int OP, int MODE, bool COUNT, int TPL, bool PF, bool HI>
 __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
     // the wavefront index is uniform; say so, so that the node walk below is
@@ -292,6 +391,20 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
         }
         unsigned long long open[TPL];
         unsigned long long any = 0ull;
+        // HI: the accepted lanes and their offsets, for the far-field terms;
+        // the node's moments are loaded first, so that their latency
+        // overlaps the representative terms
+        unsigned long long htake[TPL];
+        float hdx[TPL], hdy[TPL], hdz[TPL], hr2[TPL];
+        v16f H0;
+        v8f H1;
+        const bool hi_node = HI && !(flags & kRecSingle);
+        if (hi_node) {
+            const WNNC_AS4 char *hb =
+                (const WNNC_AS4 char *)a.momhi + (unsigned)node * (unsigned)(kHiStride * 4);
+            H0 = *(const WNNC_AS4 v16f *)hb;
+            H1 = *(const WNNC_AS4 v8f *)(hb + 64);
+        }
 #pragma unroll
         for (int k = 0; k < TPL; ++k) {
             // lanes of group k inside at this depth; of those, the ones that
@@ -310,6 +423,18 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
             if (COUNT) cnt += (uint32_t)__popcll(far);
             open[k] = act & ~far;
             any |= open[k];
+            if (HI) htake[k] = take, hdx[k] = dx, hdy[k] = dy, hdz[k] = dz, hr2[k] = r2;
+        }
+        if (hi_node) {
+            unsigned long long anyt = 0ull;
+#pragma unroll
+            for (int k = 0; k < TPL; ++k) anyt |= htake[k];
+            if (anyt != 0ull) {
+#pragma unroll
+                for (int k = 0; k < TPL; ++k)
+                    far_terms<OP>(hdx[k], hdy[k], hdz[k], hr2[k], H0, H1, a.order >= 2,
+                                  lane_in(htake[k]), s[k], gx[k], gy[k], gz[k]);
+            }
         }
         if (any == 0ull) return skip;
         if (flags & kRecLeaf) {
@@ -428,20 +553,29 @@ int trav_blocks(int64_t ntasks) {
     return (int)((ntasks + kTravBlock / kWave - 1) / (kTravBlock / kWave));
 }
 
-template <int OP, int MODE, int TPL>
-static void launch_tpl(bool count, const TravArgs &a, hipStream_t st) {
+template <int OP, int MODE, int TPL, bool HI>
+static void launch_tpl_hi(bool count, const TravArgs &a, hipStream_t st) {
     const dim3 grid((unsigned)trav_blocks(a.ntasks)), block(kTravBlock);
     if (a.prefetch) {
         if (count)
-            hipLaunchKernelGGL((k_traverse<OP, MODE, true, TPL, true>), grid, block, 0, st, a);
+            hipLaunchKernelGGL((k_traverse<OP, MODE, true, TPL, true, HI>), grid, block, 0, st, a);
         else
-            hipLaunchKernelGGL((k_traverse<OP, MODE, false, TPL, true>), grid, block, 0, st, a);
+            hipLaunchKernelGGL((k_traverse<OP, MODE, false, TPL, true, HI>), grid, block, 0, st, a);
     } else {
         if (count)
-            hipLaunchKernelGGL((k_traverse<OP, MODE, true, TPL, false>), grid, block, 0, st, a);
+            hipLaunchKernelGGL((k_traverse<OP, MODE, true, TPL, false, HI>), grid, block, 0, st, a);
         else
-            hipLaunchKernelGGL((k_traverse<OP, MODE, false, TPL, false>), grid, block, 0, st, a);
+            hipLaunchKernelGGL((k_traverse<OP, MODE, false, TPL, false, HI>), grid, block, 0, st,
+                               a);
     }
+}
+
+template <int OP, int MODE, int TPL>
+static void launch_tpl(bool count, const TravArgs &a, hipStream_t st) {
+    if (a.order > 0 && a.momhi)
+        launch_tpl_hi<OP, MODE, TPL, true>(count, a, st);
+    else
+        launch_tpl_hi<OP, MODE, TPL, false>(count, a, st);
 }
 
 template <int OP, int MODE>
@@ -501,8 +635,8 @@ hipError_t record_plan(wnnc_ctx_s *ctx, const TravArgs &a) {
     if (a.ntasks <= 0) return hipSuccess;
     if (a.tpl != 1 || ctx->nsplit != 0) return hipErrorInvalidValue;
     const dim3 grid((unsigned)trav_blocks(a.ntasks)), block(kTravBlock);
-    hipLaunchKernelGGL((k_traverse<OP_AT, TR_PLAN, false, 1, false>), grid, block, 0, ctx->stream,
-                       a);
+    hipLaunchKernelGGL((k_traverse<OP_AT, TR_PLAN, false, 1, false, false>), grid, block, 0,
+                       ctx->stream, a);
     return hipGetLastError();
 }
 

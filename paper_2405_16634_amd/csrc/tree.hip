@@ -480,7 +480,7 @@ hipError_t build_tree(wnnc_ctx_s *ctx, const float *P) {
     TRY(ctx->u32_tmp.ensure(n + 1));
     TRY(ctx->hist.ensure(hsize));
     TRY(ctx->tail_off.ensure(nchunks + 1));
-    TRY(ctx->chunk_tot.ensure(8 * nchunks));
+    TRY(ctx->chunk_tot.ensure((int64_t)kMomSlots * nchunks));
     TRY(ctx->cloud_of.ensure(n));
     TRY(ctx->va.ensure(n));
     TRY(ctx->vb.ensure(n));
@@ -537,8 +537,8 @@ hipError_t build_tree(wnnc_ctx_s *ctx, const float *P) {
     ctx->n_strad = (int32_t)ns;
     TRY(ctx->strad_node.ensure(ns + 1));
     TRY(ctx->tail_list.ensure(ns + 1));
-    TRY(ctx->head.ensure(8 * (ns + 1)));
-    TRY(ctx->tail.ensure(8 * (ns + 1)));
+    TRY(ctx->head.ensure((int64_t)kMomSlots * (ns + 1)));
+    TRY(ctx->tail.ensure((int64_t)kMomSlots * (ns + 1)));
     hipLaunchKernelGGL(k_strad_compact, dim3(blocks_for(m, 256)), dim3(256), 0, st, ctx->mflag.p,
                        ctx->mslot.p, m, ctx->node_strad.p, ctx->strad_node.p);
     // chunk -> straddlers whose range ends inside it (CSR); counts reuse mflag

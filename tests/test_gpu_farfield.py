@@ -1,0 +1,167 @@
+"""The higher-order far field and the cutoff-safe acceptance (an extension of
+the treecode of Sec. 4.5 for precision control) on the HIP path.
+
+* parity: A, A^T and G at far-field orders 1 and 2, with and without the
+  cutoff-safe test, against the oracle's treecode with the same settings,
+  per target at the bar of the plain operators (|error| <= 1e-5 of the sum
+  of term magnitudes, all but 0.2 % of targets: acceptance decisions that
+  flip between FP32 and FP64 x_B); queries too;
+* the stated bound: order 2 with the cutoff-safe test at the paper's c = 2
+  keeps the gradient of the winding number within 1e-3 (relative L2) of the
+  exact sums, on a smooth ellipsoid union and on the 500k benchmark cloud;
+* Alg. 3 with that far field against the oracle's run (flip rate);
+* order 0 without the test is the paper's path, bit for bit.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+MAX_FLIP_FRAC = 2e-3
+BOUND = 1e-3
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2405_16634_amd as w
+    w.load_library()
+    return torch.device("cuda:0")
+
+
+def _t(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+
+
+def _setup(dev, cloud, c=2.0):
+    import paper_2405_16634_amd as w
+    import oracle
+    ctx = w.Context(0)
+    x_dev, _ = ctx.normalize(_t(cloud.points, dev))
+    x_or, _, sc = oracle.normalize(cloud.points)
+    ctx.build(x_dev, c, 15)
+    return ctx, x_or, sc
+
+
+def _cloud(name):
+    if name == "sphere2k":
+        return synth.fibonacci_sphere(2000, 0)
+    if name == "ragged3077":
+        return synth.ellipsoid_union(3077, 9, noise=0.001, with_init=False)
+    return synth.torus_knot(20000, 5, with_init=False)
+
+
+@pytest.mark.parametrize("name", ["sphere2k", "ragged3077", "knot20k"])
+@pytest.mark.parametrize("order,wsafe", [(1, False), (2, False), (2, True)])
+def test_operators_match_oracle(dev, name, order, wsafe, oracle_mod):
+    cloud = _cloud(name)
+    print(f"[case] far field order={order} wsafe={wsafe} {name}", flush=True)
+    ctx, x_or, sc = _setup(dev, cloud)
+    ctx.set_far_field(order, wsafe)
+    assert ctx.far_field() == (order, wsafe)
+    T = oracle_mod.Tree(x_or)
+    rng = np.random.default_rng(7)
+    sig = cloud.area * sc * sc / cloud.n
+    mu = (synth.random_unit(rng, cloud.n) * sig).astype(np.float32)
+    rho = (0.5 - rng.uniform(0, 1, cloud.n)).astype(np.float32)
+    for w_ in (0.002, 0.016):
+        got = {"A": ctx.winding(_t(mu, dev), w_).cpu().numpy(),
+               "G": -ctx.gradient(_t(mu, dev), w_).cpu().numpy(),
+               "AT": ctx.adjoint(_t(rho, dev), w_).cpu().numpy()}
+        for op, nu in (("A", mu), ("G", mu), ("AT", rho)):
+            ref, mag, _ = T.apply(op, nu.astype(np.float64), w_, 2.0, with_stats=True,
+                                  order=order, wsafe=wsafe)
+            err = np.abs(got[op].astype(np.float64) - ref)
+            if err.ndim == 2:
+                err = np.linalg.norm(err, axis=1)
+            rel = err / np.maximum(mag, 1e-300)
+            frac = (rel > TOL).mean()
+            print(f"  {op} w={w_}: frac>tol={frac:.2e} max_rel={rel.max():.2e}", flush=True)
+            assert frac <= MAX_FLIP_FRAC, (op, w_, frac)
+    ctx.close()
+
+
+def test_queries_match_oracle(dev, oracle_mod):
+    cloud = _cloud("knot20k")
+    print("[case] far field queries knot20k", flush=True)
+    ctx, x_or, sc = _setup(dev, cloud)
+    ctx.set_far_field(2, True)
+    rng = np.random.default_rng(8)
+    mu = (synth.random_unit(rng, cloud.n) * (cloud.area * sc * sc / cloud.n)).astype(np.float32)
+    Q = rng.uniform(-1, 1, (3001, 3))
+    Q[:500] = x_or[:500] + 1e-3 * rng.standard_normal((500, 3))
+    got = ctx.winding_at(_t(mu, dev), 0.002, _t(Q, dev)).cpu().numpy().astype(np.float64)
+    ref, mag, _ = oracle_mod.Tree(x_or).apply("A", mu.astype(np.float64), 0.002, 2.0,
+                                               targets=Q.astype(np.float32).astype(np.float64),
+                                               with_stats=True, order=2, wsafe=True)
+    rel = np.abs(got - ref) / np.maximum(mag, 1e-300)
+    print(f"  frac>tol={(rel > TOL).mean():.2e} max_rel={rel.max():.2e}", flush=True)
+    assert (rel > TOL).mean() <= MAX_FLIP_FRAC
+    ctx.close()
+
+
+def _smooth_mu(cloud, sc):
+    nrm = np.nan_to_num(cloud.normals)
+    bad = ~np.isfinite(cloud.normals).all(1)
+    nrm[bad] = synth.random_unit(np.random.default_rng(9), int(bad.sum()))
+    return (nrm * (cloud.area * sc * sc / cloud.n)).astype(np.float32)
+
+
+@pytest.mark.parametrize("name", ["ellipsoids20k", "torusknot500k"])
+def test_stated_bound_at_c2(dev, name, oracle_mod):
+    """Relative L2 error of grad F against the exact sums: the paper's far
+    field (printed) and order 2 with the cutoff-safe test (<= 1e-3)."""
+    cloud = (synth.ellipsoid_union(20000, 2, noise=0.0, with_init=False) if name == "ellipsoids20k"
+             else synth.torus_knot(500000, 3, with_init=False))
+    print(f"[case] far-field bound {name}", flush=True)
+    ctx, x_or, sc = _setup(dev, cloud)
+    mu = _smooth_mu(cloud, sc)
+    tg = (np.arange(cloud.n) if cloud.n <= 20000
+          else np.sort(np.random.default_rng(12).choice(cloud.n, 2000, replace=False)))
+    exact = -oracle_mod.direct("G", x_or, mu.astype(np.float64), 0.002, targets=x_or[tg])
+    errs = {}
+    for order, ws in ((0, False), (2, True)):
+        ctx.set_far_field(order, ws)
+        g = ctx.gradient(_t(mu, dev), 0.002).cpu().numpy().astype(np.float64)[tg]
+        errs[(order, ws)] = np.linalg.norm(g - exact) / np.linalg.norm(exact)
+        print(f"  order={order} wsafe={ws}: grad rel-L2 {errs[(order, ws)]:.2e}", flush=True)
+    assert errs[(2, True)] <= BOUND
+    assert errs[(2, True)] < errs[(0, False)]
+    ctx.close()
+
+
+def test_orient_matches_oracle(dev, oracle_mod):
+    cloud = _cloud("ragged3077")
+    print("[case] far field orient ragged3077", flush=True)
+    ctx, x_or, _ = _setup(dev, cloud)
+    ctx.set_far_field(2, True)
+    mu_g = ctx.orient(40, 0.01, 0.08).cpu().numpy().astype(np.float64)
+    mu_o = oracle_mod.orient(x_or, iters=40, w1=0.01, w2=0.08, order=2, wsafe=True)
+    flip = float(((mu_g * mu_o).sum(1) <= 0).mean())
+    print(f"  flip={flip:.2e}", flush=True)
+    assert flip <= 1e-3
+    ctx.close()
+
+
+def test_order0_is_the_default_path_bit_for_bit(dev):
+    import paper_2405_16634_amd as w
+    cloud = _cloud("knot20k")
+    print("[case] far field default path", flush=True)
+    ctx, x_or, sc = _setup(dev, cloud)
+    rng = np.random.default_rng(10)
+    mu = _t(synth.random_unit(rng, cloud.n) * (cloud.area * sc * sc / cloud.n), dev)
+    g0 = ctx.gradient(mu, 0.002).clone()
+    ctx.set_far_field(2, True)
+    g2 = ctx.gradient(mu, 0.002).clone()
+    ctx.set_far_field(0, False)
+    assert bool((ctx.gradient(mu, 0.002) == g0).all())
+    assert not bool((g2 == g0).all())
+    with pytest.raises(w.WnncError):
+        ctx.set_far_field(3, False)
+    ctx.close()
