@@ -30,8 +30,8 @@ import numpy as np
 
 from . import build as _build
 
-OP_A, OP_AT, OP_G = 0, 1, 2
-_OPS = {"A": OP_A, "AT": OP_AT, "G": OP_G}
+OP_A, OP_AT, OP_G, OP_P = 0, 1, 2, 3
+_OPS = {"A": OP_A, "AT": OP_AT, "G": OP_G, "P": OP_P}
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _lib = None
 
@@ -46,6 +46,8 @@ def _load():
     i64 = ctypes.c_int64
     lib.or_direct.argtypes = [ctypes.c_int, d, i64, d, d, i64, ctypes.c_double, d, d]
     lib.or_direct.restype = None
+    lib.or_direct_tv.argtypes = [ctypes.c_int, d, i64, d, d, i64, d, ctypes.c_double, d, d]
+    lib.or_direct_tv.restype = None
     lib.or_tree_new.argtypes = [d, i64, ctypes.c_int, ctypes.c_int]
     lib.or_tree_new.restype = ctypes.c_void_p
     lib.or_tree_free.argtypes = [ctypes.c_void_p]
@@ -57,6 +59,9 @@ def _load():
     lib.or_tree_reps.argtypes = [ctypes.c_void_p, d, ctypes.c_int, d, d, d]
     lib.or_tree_apply.argtypes = [ctypes.c_void_p, ctypes.c_int, d, ctypes.c_double,
                                   ctypes.c_double, d, i64, d, d, p64]
+    lib.or_tree_apply_tv.argtypes = [ctypes.c_void_p, ctypes.c_int, d, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_int, ctypes.c_int, d, i64, d, d,
+                                     d, p64]
     lib.or_tree_apply_order.argtypes = [ctypes.c_void_p, ctypes.c_int, d, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_int, ctypes.c_int, d, i64, d,
                                         d, p64]
@@ -103,21 +108,32 @@ def normalize(points):
     return x, center, scale
 
 
-def direct(op: str, x, nu, w: float, targets=None, with_mag: bool = False):
-    """Exact FP64 sum of operator op in {"A","AT","G"} over all source points x
-    (n,3) with attributes nu ((n,3) for A and G, (n,) for AT), evaluated at
-    targets (default: the points themselves)."""
+def direct(op: str, x, nu, w: float, targets=None, with_mag: bool = False, tvec=None):
+    """Exact FP64 sum of operator op in {"A","AT","G","P"} over all source
+    points x (n,3) with attributes nu ((n,3) for A and G, (n,) for AT and P),
+    evaluated at targets (default: the points themselves); P also takes the
+    targets' vectors tvec (n_targets,3)."""
     lib = _load()
     o = _OPS[op]
     x = _f64(x, (-1, 3))
-    nu = _f64(nu, (x.shape[0], -1) if o != OP_AT else (x.shape[0],))
+    nu = _f64(nu, (x.shape[0], -1) if o not in (OP_AT, OP_P) else (x.shape[0],))
     t = x if targets is None else _f64(targets, (-1, 3))
     dout = 1 if o == OP_A else 3
     out = np.zeros((t.shape[0], dout))
     mag = np.zeros(t.shape[0])
-    lib.or_direct(o, _dp(x), x.shape[0], _dp(nu), _dp(t), t.shape[0], float(w), _dp(out), _dp(mag))
+    tv = _tvec(o, tvec, t.shape[0])
+    lib.or_direct_tv(o, _dp(x), x.shape[0], _dp(nu), _dp(t), t.shape[0],
+                     _dp(tv) if tv is not None else None, float(w), _dp(out), _dp(mag))
     out = out[:, 0] if dout == 1 else out
     return (out, mag) if with_mag else out
+
+
+def _tvec(o, tvec, n):
+    if o != OP_P:
+        return None
+    if tvec is None:
+        raise ValueError("P needs the targets' vectors")
+    return _f64(tvec, (n, 3))
 
 
 class Tree:
@@ -172,27 +188,53 @@ class Tree:
         return xB, (nuB[:, 0] if dim == 1 else nuB), W
 
     def apply(self, op: str, nu, w: float, c: float = 2.0, targets=None, with_stats: bool = False,
-              order: int = 0, wsafe: bool = False):
+              order: int = 0, wsafe: bool = False, tvec=None):
         """Treecode operator; returns out (and per-target magnitude sums and
         pair counts with with_stats).  order 1 or 2 replaces each accepted
         node's representative term by the Taylor expansion of the pair term
         about x_B to that order (the higher-order far field; 0 is Alg. 4)."""
         lib = _load()
         o = _OPS[op]
-        nu = _f64(nu, (self.n, 3) if o != OP_AT else (self.n,))
+        nu = _f64(nu, (self.n, 3) if o not in (OP_AT, OP_P) else (self.n,))
         t = self.x if targets is None else _f64(targets, (-1, 3))
+        if o == OP_P and order != 0:
+            raise ValueError("P has the representative far field only")
+        tv = _tvec(o, tvec, t.shape[0])
         dout = 1 if o == OP_A else 3
         out = np.zeros((t.shape[0], dout))
         mag = np.zeros(t.shape[0])
         pairs = np.zeros(t.shape[0], np.int64)
         if order not in (0, 1, 2):
             raise ValueError("order must be 0, 1 or 2")
-        lib.or_tree_apply_order(self._h, o, _dp(nu), float(w), float(c), int(order),
-                                int(bool(wsafe)), _dp(t),
-                                t.shape[0], _dp(out), _dp(mag),
-                                pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+        lib.or_tree_apply_tv(self._h, o, _dp(nu), float(w), float(c), int(order),
+                             int(bool(wsafe)), _dp(t), t.shape[0],
+                             _dp(tv) if tv is not None else None, _dp(out), _dp(mag),
+                             pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
         out = out[:, 0] if dout == 1 else out
         return (out, mag, pairs) if with_stats else out
+
+
+def winding_grad_x(x, mu, g, w: float, backend: str = "direct", c: float = 2.0, tree=None):
+    """Gradient with respect to the points x of L = sum_i g_i s_i, s = A_w(mu)
+    (an extension: differentiable winding numbers in the positions).  With
+    s_i = sum_j gradPhi(x_i - x_j) . mu_j, differentiating each pair term in
+    both of its end points gives
+      dL/dx_k = g_k sum_j HPhi(x_k - x_j) mu_j - sum_i g_i HPhi(x_i - x_k) mu_k
+              = -g_k G(mu)_k + P(g; mu)_k
+    (HPhi is even).  Pairs cut off at w contribute nothing (the cutoff is
+    held fixed).  backend "direct" (exact sums) or "tree" (the treecode, both
+    terms with Alg. 4's far field)."""
+    x = np.asarray(x, dtype=np.float64)
+    mu = np.asarray(mu, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    if backend == "direct":
+        G = direct("G", x, mu, w)
+        P = direct("P", x, g, w, tvec=mu)
+    else:
+        T = tree if tree is not None else Tree(x)
+        G = T.apply("G", mu, w, c)
+        P = T.apply("P", g, w, c, tvec=mu)
+    return -g[:, None] * G + P
 
 
 from .iterate import grad_step, orient, width_schedule, rescale  # noqa: E402

@@ -19,6 +19,10 @@
  *   A^T: rho -> v,    v_j   = sum_i rho_i gradPhi(x_i - x_j)      (Alg. 2)
  *   G  : mu -> mu^,   mu^_i = -grad F(x_i; mu)
  *                            = -sum_j HPhi(x_i - x_j) mu_j        (Sec. 4.2)
+ *   P  : g -> p,      p_k   = -sum_i g_i HPhi(x_k - x_i) mu_k     (position
+ *        gradient of the winding number, an extension: with L = sum_i g_i s_i,
+ *        dL/dx_k = -g_k G(mu)_k + p_k; the source attribute is the scalar g,
+ *        the target carries its own vector mu_k)
  *
  * Smoothing (Sec. 4.4): a pair term is set to 0 when |x_i - x_j| < w.  The
  * coincident pair |y| = 0 is also 0 (it is excluded for every w > 0 anyway).
@@ -47,6 +51,7 @@
 #define OR_OP_A 0
 #define OR_OP_AT 1
 #define OR_OP_G 2
+#define OR_OP_P 3
 
 /* ---------------------------------------------------------------- pairs -- */
 
@@ -56,7 +61,7 @@
  * Adds the term to out (1 value for A, 3 for A^T and G) and its magnitude to
  * *mag.  A pair closer than w (or coincident) adds nothing. */
 static void pair_term(int op, const double *xt, const double *xs, const double *nu,
-                      double w, double *out, double *mag)
+                      const double *tv, double w, double *out, double *mag)
 {
     double y[3] = {xt[0] - xs[0], xt[1] - xs[1], xt[2] - xs[2]};
     double r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
@@ -78,6 +83,17 @@ static void pair_term(int op, const double *xt, const double *xs, const double *
         out[1] += t1;
         out[2] += t2;
         *mag += sqrt(t0 * t0 + t1 * t1 + t2 * t2);
+    } else if (op == OR_OP_P) {
+        /* g (-HPhi(y) v) with the target's vector v */
+        double r5 = r3 * r2;
+        double yv = y[0] * tv[0] + y[1] * tv[1] + y[2] * tv[2];
+        double t[3];
+        for (int k = 0; k < 3; ++k)
+            t[k] = nu[0] * (tv[k] / (4.0 * OR_PI * r3) - 3.0 * yv * y[k] / (4.0 * OR_PI * r5));
+        out[0] += t[0];
+        out[1] += t[1];
+        out[2] += t[2];
+        *mag += sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
     } else {
         /* -HPhi(y) mu = mu/(4 pi r^3) - 3 (y . mu) y /(4 pi r^5) */
         double r5 = r3 * r2;
@@ -92,27 +108,35 @@ static void pair_term(int op, const double *xt, const double *xs, const double *
     }
 }
 
-static int op_in_dim(int op) { return op == OR_OP_AT ? 1 : 3; }
+static int op_in_dim(int op) { return (op == OR_OP_AT || op == OR_OP_P) ? 1 : 3; }
 static int op_out_dim(int op) { return op == OR_OP_A ? 1 : 3; }
 
 /* ---------------------------------------------------------- direct sums -- */
 
 /* Exact O(n_src * n_tgt) sums.  tgt may equal src.  out: (n_tgt, out_dim).
  * mag (optional): per target sum of term magnitudes. */
-void or_direct(int op, const double *src, int64_t n_src, const double *nu,
-               const double *tgt, int64_t n_tgt, double w, double *out, double *mag)
+void or_direct_tv(int op, const double *src, int64_t n_src, const double *nu,
+                  const double *tgt, int64_t n_tgt, const double *tv, double w, double *out,
+                  double *mag)
 {
     int din = op_in_dim(op), dout = op_out_dim(op);
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t i = 0; i < n_tgt; ++i) {
         double acc[3] = {0, 0, 0}, m = 0.0;
         for (int64_t j = 0; j < n_src; ++j)
-            pair_term(op, tgt + 3 * i, src + 3 * j, nu + din * j, w, acc, &m);
+            pair_term(op, tgt + 3 * i, src + 3 * j, nu + din * j, tv ? tv + 3 * i : NULL, w,
+                      acc, &m);
         for (int k = 0; k < dout; ++k)
             out[dout * i + k] = acc[k];
         if (mag)
             mag[i] = m;
     }
+}
+
+void or_direct(int op, const double *src, int64_t n_src, const double *nu,
+               const double *tgt, int64_t n_tgt, double w, double *out, double *mag)
+{
+    or_direct_tv(op, src, n_src, nu, tgt, n_tgt, NULL, w, out, mag);
 }
 
 /* ------------------------------------------------------------- octree -- */
@@ -383,11 +407,11 @@ static void phi_derivs(const double *y, double T1[3], double T2[3][3], double T3
  * (the order-0 parts are the pair terms of pair_term).  Zero, like the
  * order-0 term, when |y| < w or y = 0. */
 static void far_term(const or_tree *T, const apply_args *a, int64_t id, const double *xt,
-                     double *acc, double *mag)
+                     const double *tv, double *acc, double *mag)
 {
     const double *xB = T->rep_x + 3 * id, *nuB = T->rep_nu + 3 * id;
     if (a->order == 0) {
-        pair_term(a->op, xt, xB, nuB, a->w, acc, mag);
+        pair_term(a->op, xt, xB, nuB, tv, a->w, acc, mag);
         return;
     }
     double y[3] = {xt[0] - xB[0], xt[1] - xB[1], xt[2] - xB[2]};
@@ -436,9 +460,9 @@ static void far_term(const or_tree *T, const apply_args *a, int64_t id, const do
     *mag += sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
 }
 
-/* Alg. 4 for one target xt starting at node id. */
+/* Alg. 4 for one target xt (with its vector tv for P) starting at node id. */
 static void apply_node(const or_tree *T, const apply_args *a, int64_t id, const double *xt,
-                       double *acc, double *mag, int64_t *pairs)
+                       const double *tv, double *acc, double *mag, int64_t *pairs)
 {
     const or_node *B = &T->nodes[id];
     if (T->rep_w[id] == 0.0)
@@ -448,15 +472,15 @@ static void apply_node(const or_tree *T, const apply_args *a, int64_t id, const 
     double dist = sqrt(dx * dx + dy * dy + dz * dz);
     double width = ldexp(2.0, -B->depth);
     if (dist > a->c * width && (!a->wsafe || dist > a->w + sqrt(3.0) * width)) {
-        far_term(T, a, id, xt, acc, mag);
+        far_term(T, a, id, xt, tv, acc, mag);
         (*pairs)++;
     } else if (!B->leaf) {
         for (int k = 0; k < B->nchild; ++k)
-            apply_node(T, a, B->child[k], xt, acc, mag, pairs);
+            apply_node(T, a, B->child[k], xt, tv, acc, mag, pairs);
     } else {
         for (int64_t m = B->begin; m < B->end; ++m) {
             int64_t j = T->order[m];
-            pair_term(a->op, xt, T->x + 3 * j, a->nu + a->din * j, a->w, acc, mag);
+            pair_term(a->op, xt, T->x + 3 * j, a->nu + a->din * j, tv, a->w, acc, mag);
             (*pairs)++;
         }
     }
@@ -472,11 +496,13 @@ static void apply_node(const or_tree *T, const apply_args *a, int64_t id, const 
  * target is farther than w + sqrt(3) width from x_B: x_B lies in the
  * node's cell, whose points are all within sqrt(3) width of it, so no
  * accepted node holds a point the cutoff w would drop. */
-void or_tree_apply_order(or_tree *T, int op, const double *nu, double w, double c, int order,
-                         int wsafe, const double *tgt, int64_t n_tgt, double *out, double *mag,
-                         int64_t *pairs)
+void or_tree_apply_tv(or_tree *T, int op, const double *nu, double w, double c, int order,
+                      int wsafe, const double *tgt, int64_t n_tgt, const double *tv,
+                      double *out, double *mag, int64_t *pairs)
 {
     int din = op_in_dim(op), dout = op_out_dim(op);
+    if (op == OR_OP_P)
+        order = 0; /* P: the representative term only */
     compute_reps(T, nu, din);
     if (order > 0)
         compute_moments(T, nu, din);
@@ -485,7 +511,7 @@ void or_tree_apply_order(or_tree *T, int op, const double *nu, double w, double 
     for (int64_t i = 0; i < n_tgt; ++i) {
         double acc[3] = {0, 0, 0}, m = 0.0;
         int64_t np = 0;
-        apply_node(T, &a, 0, tgt + 3 * i, acc, &m, &np);
+        apply_node(T, &a, 0, tgt + 3 * i, tv ? tv + 3 * i : NULL, acc, &m, &np);
         for (int k = 0; k < dout; ++k)
             out[dout * i + k] = acc[k];
         if (mag)
@@ -493,6 +519,13 @@ void or_tree_apply_order(or_tree *T, int op, const double *nu, double w, double 
         if (pairs)
             pairs[i] = np;
     }
+}
+
+void or_tree_apply_order(or_tree *T, int op, const double *nu, double w, double c, int order,
+                         int wsafe, const double *tgt, int64_t n_tgt, double *out, double *mag,
+                         int64_t *pairs)
+{
+    or_tree_apply_tv(T, op, nu, w, c, order, wsafe, tgt, n_tgt, NULL, out, mag, pairs);
 }
 
 void or_tree_apply(or_tree *T, int op, const double *nu, double w, double c,

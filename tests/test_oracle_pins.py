@@ -535,3 +535,58 @@ def test_cutoff_safe_acceptance_restores_the_cutoff(oracle_mod):
     assert plain > 1e-2 and err(2, False) > 1e-2
     assert err(0, True) < 0.2 * plain
     assert safe2 < 1e-3
+
+
+# -------------------- position gradients of the winding number (extension)
+
+def test_winding_grad_x_matches_finite_differences(oracle_mod):
+    """dL/dx of L = g . A(mu) from the closed form (-g G + P) against central
+    differences of the exact sums, on a random cloud with no pair near the
+    cutoff; the gradient sums to 0 (L is translation invariant)."""
+    rng = np.random.default_rng(0)
+    x = rng.uniform(-1, 1, (60, 3))
+    mu = rng.standard_normal((60, 3))
+    g = rng.standard_normal(60)
+    for w in (0.0, 0.05):
+        d = np.linalg.norm(x[:, None] - x[None], axis=2) + 10.0 * np.eye(len(x))
+        assert np.all(np.abs(d - w) > 1e-3)  # no pair within the FD step of w
+        gx = oracle_mod.winding_grad_x(x, mu, g, w)
+        h = 1e-6
+        fd = np.zeros_like(x)
+        for k in range(len(x)):
+            for a in range(3):
+                xp, xm = x.copy(), x.copy()
+                xp[k, a] += h
+                xm[k, a] -= h
+                fd[k, a] = (g @ oracle_mod.direct("A", xp, mu, w)
+                            - g @ oracle_mod.direct("A", xm, mu, w)) / (2 * h)
+        assert np.abs(gx - fd).max() <= 1e-7 * np.abs(fd).max()
+        assert np.abs(gx.sum(axis=0)).max() <= 1e-12 * np.abs(gx).max()
+
+
+def test_winding_grad_x_two_points_by_hand(oracle_mod):
+    """x1 = 0, x2 = (1,0,0), mu1 = (1,0,0), mu2 = 0, g = (0,1): L = s_2 =
+    -(x2 - x1).mu1 / (4 pi |x2 - x1|^3), so dL/dx2 = (1/(2 pi), 0, 0) and
+    dL/dx1 = -dL/dx2."""
+    x = np.array([[0.0, 0, 0], [1.0, 0, 0]])
+    mu = np.array([[1.0, 0, 0], [0.0, 0, 0]])
+    g = np.array([0.0, 1.0])
+    gx = oracle_mod.winding_grad_x(x, mu, g, 0.0)
+    assert np.allclose(gx[1], [1 / (2 * np.pi), 0, 0], rtol=1e-14, atol=1e-16)
+    assert np.allclose(gx[0], -gx[1], rtol=1e-14, atol=1e-16)
+
+
+def test_winding_grad_x_treecode_limits(oracle_mod):
+    """The treecode's position gradient equals the exact one when no node is
+    accepted (c -> infinity) and approaches it at c = 2."""
+    rng = np.random.default_rng(4)
+    c = synth.fibonacci_sphere(1500, 1)
+    x, _, sc = oracle_mod.normalize(c.points)
+    mu = c.normals * (4 * np.pi * sc * sc / c.n)
+    g = rng.standard_normal(c.n)
+    ex = oracle_mod.winding_grad_x(x, mu, g, 0.002)
+    T = oracle_mod.Tree(x)
+    big = oracle_mod.winding_grad_x(x, mu, g, 0.002, backend="tree", c=1e6, tree=T)
+    assert np.abs(big - ex).max() <= 1e-12 * np.abs(ex).max()
+    tc = oracle_mod.winding_grad_x(x, mu, g, 0.002, backend="tree", c=2.0, tree=T)
+    assert np.linalg.norm(tc - ex) / np.linalg.norm(ex) < 0.05
