@@ -103,15 +103,16 @@ typedef struct {
 #define WNNC_OP_A 0
 #define WNNC_OP_AT 1
 #define WNNC_OP_G 2
+#define WNNC_OP_P 3 /* the position-gradient walk of wnnc_winding_grad_x */
 
 typedef struct {
     int64_t n_points;       /* N of the current tree */
     int64_t n_nodes;        /* octree nodes */
-    int64_t calls[3];       /* operator applications per kind since reset */
-    int64_t pairs[3];       /* pair evaluations per kind (WNNC_FLAG_COUNT_PAIRS):
+    int64_t calls[4];       /* operator applications per kind since reset */
+    int64_t pairs[4];       /* pair evaluations per kind (WNNC_FLAG_COUNT_PAIRS):
                                accepted representatives plus points summed
                                directly, cut-off pairs included */
-    double traverse_ms[3];  /* summed traversal-kernel time per kind
+    double traverse_ms[4];  /* summed traversal-kernel time per kind
                                (WNNC_FLAG_TIME_KERNELS) */
     double moments_ms;      /* summed moment-pass time (WNNC_FLAG_TIME_KERNELS) */
     double build_ms;        /* last wnnc_build, device time (always timed) */
@@ -234,6 +235,23 @@ wnnc_status wnnc_gradient(wnnc_ctx ctx, const float *n, const float *sigma, floa
  * out_j = sum_i s_i gradPhi(x_i - x_j) (with the treecode, using the
  * |s|-weighted representatives). */
 wnnc_status wnnc_adjoint(wnnc_ctx ctx, const float *s, float w, float *out);
+
+/* Gradient of L = sum_i g_i s_i, s = A_w(mu) (wnnc_winding), with respect to
+ * the point positions (an extension: differentiable winding numbers in the
+ * points).  Differentiating each pair term of A in both of its end points
+ * (the cutoff held fixed) gives
+ *   dL/dx_k = g_k grad F(x_k; mu) + p_k,
+ *   p_k = -sum_i g_i HPhi(x_k - x_i) mu_k,
+ * where p is one more treecode walk: scalar sources g (|g|-weighted
+ * representatives, Alg. 4's acceptance) and, at each target, the target's
+ * own mu_k.  mu (N,3) or n (N,3) with sigma (N) as in wnnc_winding, g (N),
+ * dx_out (N,3): device, caller order, with respect to the normalized
+ * points (multiply by the normalization scale s for the input points, since
+ * x_norm = (x - centre) s).  Both walks
+ * use Alg. 4's far field (order 0, without the cutoff-safe test) whatever
+ * wnnc_set_far_field says. */
+wnnc_status wnnc_winding_grad_x(wnnc_ctx ctx, const float *n, const float *sigma, float w,
+                                const float *g, float *dx_out);
 
 /* Far field of the treecode (an extension for precision control; the
  * paper's Alg. 4 is order 0 without wsafe, the default).

@@ -34,7 +34,7 @@ EXPORTED = [
     "wnnc_autotune", "wnnc_orient_preset", "wnnc_knn_features", "wnnc_knn_areas",
     "wnnc_mlp_forward", "wnnc_mlp_grad", "wnnc_mlp_adam",
     "wnnc_warm_orient", "wnnc_set_prefetch", "wnnc_set_split", "wnnc_get_split",
-    "wnnc_winding_at", "wnnc_set_far_field", "wnnc_get_far_field",
+    "wnnc_winding_at", "wnnc_set_far_field", "wnnc_get_far_field", "wnnc_winding_grad_x",
 ]
 MLP_PARAMS = 7491
 AUTOTUNE_CONFIGS = 12
@@ -80,8 +80,8 @@ class TileTime(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("n_points", ctypes.c_int64), ("n_nodes", ctypes.c_int64),
-                ("calls", ctypes.c_int64 * 3), ("pairs", ctypes.c_int64 * 3),
-                ("traverse_ms", ctypes.c_double * 3), ("moments_ms", ctypes.c_double),
+                ("calls", ctypes.c_int64 * 4), ("pairs", ctypes.c_int64 * 4),
+                ("traverse_ms", ctypes.c_double * 4), ("moments_ms", ctypes.c_double),
                 ("build_ms", ctypes.c_double), ("n_clouds", ctypes.c_int64),
                 ("tile", ctypes.c_int64), ("n_groups", ctypes.c_int64),
                 ("n_tasks", ctypes.c_int64), ("combine_ms", ctypes.c_double)]
@@ -137,6 +137,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "wnnc_knn_areas": [vp, ctypes.c_int, vp],
         "wnnc_orient_preset": [ctypes.c_int, P(OrientOpts)],
         "wnnc_set_far_field": [vp, ctypes.c_int, ctypes.c_int],
+        "wnnc_winding_grad_x": [vp, vp, vp, f32, vp, vp],
         "wnnc_get_far_field": [vp, P(ctypes.c_int), P(ctypes.c_int)],
         "wnnc_mlp_forward": [vp, vp, vp, i64, vp],
         "wnnc_mlp_grad": [vp, vp, vp, vp, i64, vp, P(dbl)],
@@ -331,6 +332,14 @@ def wnnc_knn_features(ctx, feat_out, nbr_out=None) -> None:
     _check(load_library().wnnc_knn_features(ctx, _dev(feat_out, "feat_out", shape=(N, 48)),
                                             _dev(nbr_out, "nbr_out", dtype=torch.int32,
                                                  shape=(N, 16))))
+
+
+def wnnc_winding_grad_x(ctx, mu, sigma, w: float, g, dx_out) -> None:
+    """dL/dx of L = g . A_w(mu) with respect to the (normalized) points."""
+    N = mu.shape[0]
+    _check(load_library().wnnc_winding_grad_x(
+        ctx, _dev(mu, "mu", shape=(N, 3)), _dev(sigma, "sigma", shape=(N,)), float(w),
+        _dev(g, "g", shape=(N,)), _dev(dx_out, "dx_out", shape=(N, 3))))
 
 
 def wnnc_set_far_field(ctx, order: int = 0, wsafe: bool = False) -> None:
@@ -576,6 +585,12 @@ class Context:
                if with_neighbours else None)
         wnnc_knn_features(self._h, feat, nbr)
         return (feat, nbr) if with_neighbours else feat
+
+    def winding_grad_x(self, mu, w: float, g, sigma=None):
+        """Gradient of g . A_w(mu) with respect to the normalized points."""
+        out = torch.empty(mu.shape[0], 3, device=mu.device, dtype=torch.float32)
+        wnnc_winding_grad_x(self._h, mu, sigma, w, g, out)
+        return out
 
     def set_far_field(self, order: int = 0, wsafe: bool = False) -> None:
         """Far-field order (0 = Alg. 4, 1, 2) and the cutoff-safe acceptance."""

@@ -7,6 +7,9 @@ The adjoint operator is the backward of the winding-number operator
 * ``adjoint(ctx, s, w)``    v = A_w^T s          backward: g -> A_w g
 * ``gradient(ctx, mu, w)``  grad F = -G_w(mu)    backward: g -> -G_w g
   (G is symmetric: HPhi is an even, symmetric matrix field)
+* ``winding_at_points(ctx, x, mu, w)``  s = A_w(mu) on the tree built from
+  the normalized points x; differentiable in x and mu (an extension:
+  backward in x is wnnc_winding_grad_x, g -> g grad F + p)
 
 All three evaluate with the context's treecode; every forward and backward
 runs in the library's kernels (argument marshalling only here).  With the
@@ -18,7 +21,7 @@ from __future__ import annotations
 
 import torch
 
-from . import wnnc_adjoint, wnnc_gradient, wnnc_winding
+from . import wnnc_adjoint, wnnc_build, wnnc_gradient, wnnc_winding, wnnc_winding_grad_x
 
 
 def _prep(t):
@@ -94,3 +97,33 @@ def pgr_energy(ctx, mu, w: float, b: float = 0.5):
     2 A_w^T (A_w mu - b) = -2 r of Alg. 2."""
     s = winding(ctx, mu, w)
     return ((s - b) ** 2).sum()
+
+
+class WindingPositions(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, handle, x, mu, w, c, max_depth):
+        fctx.handle, fctx.w = handle, float(w)
+        wnnc_build(handle, _prep(x), float(c), int(max_depth))
+        m = _prep(mu)
+        out = torch.empty(m.shape[0], device=m.device, dtype=torch.float32)
+        wnnc_winding(handle, m, None, fctx.w, out)
+        fctx.save_for_backward(m)
+        return out
+
+    @staticmethod
+    def backward(fctx, g):
+        (m,) = fctx.saved_tensors
+        gg = _prep(g)
+        gx = torch.empty(m.shape[0], 3, device=g.device, dtype=torch.float32)
+        wnnc_winding_grad_x(fctx.handle, m, None, fctx.w, gg, gx)
+        gm = torch.empty(m.shape[0], 3, device=g.device, dtype=torch.float32)
+        wnnc_adjoint(fctx.handle, gg, fctx.w, gm)
+        return None, gx, gm, None, None, None
+
+
+def winding_at_points(ctx, x, mu, w: float, c: float = 2.0, max_depth: int = 15):
+    """s = A_w(mu) at the normalized points x, building ctx's tree on x;
+    differentiable in x and in mu.  The backward reuses the tree of the
+    forward, so call backward before the next build on ctx."""
+    return WindingPositions.apply(_handle(ctx), x, mu, w, c, max_depth)
+

@@ -68,17 +68,18 @@ struct Timed {
 // Squared acceptance distance per depth: (c 2^(1-d))^2 (Alg. 4), or with
 // the cutoff-safe test also at least (w + sqrt(3) 2^(1-d))^2, so that an
 // accepted node's cell holds no point closer to the target than w.
-static void fill_thresholds(const wnnc_ctx_s *c, float w, float *thr2) {
+static void fill_thresholds(const wnnc_ctx_s *c, float w, bool wsafe, float *thr2) {
     for (int d = 0; d < 16; ++d) {
         const double width = ldexp(2.0, -d);
         double t = (double)c->c * width;
-        if (c->far_wsafe) t = fmax(t, (double)w + sqrt(3.0) * width);
+        if (wsafe) t = fmax(t, (double)w + sqrt(3.0) * width);
         thr2[d] = (float)(t * t);
     }
 }
 
-// Moment-pass arguments for an operator call at width w.
-MomArgs mom_args(wnnc_ctx_s *c, float w) {
+// Moment-pass arguments for an operator call at width w (paper = true:
+// Alg. 4's far field whatever the context's far-field setting).
+MomArgs mom_args(wnnc_ctx_s *c, float w, bool paper = false) {
     // (fields not set here are per-call inputs and outputs)
     MomArgs a;
     memset(&a, 0, sizeof(a));
@@ -98,9 +99,9 @@ MomArgs mom_args(wnnc_ctx_s *c, float w) {
     a.alpha = c->scalars.p;
     a.n = (int)c->n;
     a.n_strad = c->n_strad;
-    fill_thresholds(c, w, a.thr2);
-    a.order = c->far_order;
-    a.momhi = c->far_order > 0 ? c->momhi.p : nullptr;
+    fill_thresholds(c, w, c->far_wsafe && !paper, a.thr2);
+    a.order = paper ? 0 : c->far_order;
+    a.momhi = a.order > 0 ? c->momhi.p : nullptr;
     return a;
 }
 
@@ -133,8 +134,11 @@ TravArgs trav_args(wnnc_ctx_s *c, float w) {
     return a;
 }
 
+// Timed kinds: 0..3 the traversal of each operator, then these two.
+constexpr int kKindMoments = 4, kKindCombine = 5;
+
 wnnc_status run_moments(wnnc_ctx_s *c, MomMode mode, const MomArgs &a) {
-    Timed tm(c, 3);
+    Timed tm(c, kKindMoments);
     HIPCHK(launch_moments(c, mode, a));
     tm.done();
     return WNNC_OK;
@@ -144,7 +148,7 @@ wnnc_status run_traverse(wnnc_ctx_s *c, Op op, TravMode mode, const TravArgs &a)
     Timed tm(c, (int)op);
     HIPCHK(launch_traverse(c, op, mode, (c->flags & WNNC_FLAG_COUNT_PAIRS) != 0, a));
     tm.done();
-    Timed tc(c, 4);
+    Timed tc(c, kKindCombine);
     HIPCHK(launch_combine(c, op, mode, a));
     tc.done();
     c->calls[op] += 1;
@@ -237,6 +241,7 @@ wnnc_status wnnc_destroy(wnnc_ctx ctx) {
     ctx->knn_groups.release();
     ctx->areas.release();
     ctx->momhi.release();
+    ctx->gradf.release();
     ctx->qkeys_a.release();
     ctx->qkeys_b.release();
     ctx->qperm.release();
@@ -625,6 +630,42 @@ wnnc_status wnnc_gradient(wnnc_ctx ctx, const float *n, const float *sigma, floa
     return run_traverse(ctx, OP_G, TR_OUT_CALLER, ta);
 }
 
+wnnc_status wnnc_winding_grad_x(wnnc_ctx ctx, const float *n, const float *sigma, float w,
+                                const float *g, float *dx_out) {
+    CHECK_CTX(ctx);
+    CHECK_BUILT(ctx);
+    if (!n || !g || !dx_out) return fail(WNNC_EINVAL, "null pointer");
+    if (!finite_nonneg(w)) return fail(WNNC_EINVAL, "w must be finite and >= 0");
+    const int64_t N = ctx->n;
+    HIPCHK(ctx->gradf.ensure(3 * N));
+    // grad F(x_k; mu), caller order
+    MomArgs ma = mom_args(ctx, w, true);
+    ma.cn = n;
+    ma.csig = sigma;
+    ma.out4 = ctx->va.p;
+    RETURN_IF(run_moments(ctx, MOM_VEC_CALLER, ma));
+    TravArgs ta = trav_args(ctx, w);
+    ta.order = 0;
+    ta.momhi = nullptr;
+    ta.src4 = ctx->va.p;
+    ta.out = ctx->gradf.p;
+    RETURN_IF(run_traverse(ctx, OP_G, TR_OUT_CALLER, ta));
+    // p: sources g, each target with its own mu (sorted, kept in va)
+    MomArgs mb = mom_args(ctx, w, true);
+    mb.cs = g;
+    mb.outs = ctx->rho.p;
+    RETURN_IF(run_moments(ctx, MOM_SCALAR_CALLER, mb));
+    TravArgs tb = trav_args(ctx, w);
+    tb.order = 0;
+    tb.momhi = nullptr;
+    tb.srcs = ctx->rho.p;
+    tb.tvec = ctx->va.p;
+    tb.gc = g;
+    tb.gradf = ctx->gradf.p;
+    tb.out = dx_out;
+    return run_traverse(ctx, OP_P, TR_POSGRAD, tb);
+}
+
 wnnc_status wnnc_adjoint(wnnc_ctx ctx, const float *s, float w, float *out) {
     CHECK_CTX(ctx);
     CHECK_BUILT(ctx);
@@ -926,9 +967,9 @@ wnnc_status wnnc_stats(wnnc_ctx ctx, wnnc_stats_t *out) {
     for (auto &t : ctx->pending) {
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, t.a, t.b));
-        if (t.kind < 3)
+        if (t.kind < kKindMoments)
             ctx->trav_ms[t.kind] += ms;
-        else if (t.kind == 3)
+        else if (t.kind == kKindMoments)
             ctx->mom_ms += ms;
         else
             ctx->comb_ms += ms;
@@ -939,11 +980,11 @@ wnnc_status wnnc_stats(wnnc_ctx ctx, wnnc_stats_t *out) {
     memset(out, 0, sizeof(*out));
     out->n_points = ctx->built ? ctx->n : 0;
     out->n_nodes = ctx->built ? ctx->m : 0;
-    unsigned long long pc[3] = {0, 0, 0};
+    unsigned long long pc[4] = {0, 0, 0, 0};
     if (ctx->pair_ctr.p) {
         HIPCHK(hipMemcpy(pc, ctx->pair_ctr.p, sizeof(pc), hipMemcpyDeviceToHost));
     }
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
         out->calls[k] = ctx->calls[k];
         out->pairs[k] = (int64_t)pc[k];
         out->traverse_ms[k] = ctx->trav_ms[k];
@@ -966,7 +1007,7 @@ wnnc_status wnnc_reset_stats(wnnc_ctx ctx) {
         ctx->event_pool.push_back(t.b);
     }
     ctx->pending.clear();
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
         ctx->calls[k] = 0;
         ctx->trav_ms[k] = 0;
     }

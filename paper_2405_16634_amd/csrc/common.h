@@ -114,13 +114,14 @@ struct wnnc_ctx_s {
     DevBuf<float> rho;
     DevBuf<float> areas;
     DevBuf<float> momhi;           // far-field moments (far_order >= 1)
+    DevBuf<float> gradf;           // caller-order grad F for the position gradient
     int far_order = 0;             // 0: Alg. 4's representative term; 1, 2: Taylor orders
     int far_wsafe = 0;             // accept a node only when its cell is beyond w           // fixed areas (sorted), when an orientation uses them
     DevBuf<double> partial;        // 3 rows of ngroups per-group sums
     DevBuf<double> scalars;        // alpha per cloud
     DevBuf<double> energy;
     int last_energy_count = 0;
-    DevBuf<unsigned long long> pair_ctr;  // 3 counters
+    DevBuf<unsigned long long> pair_ctr;  // one counter per operator kind
 
     // warm start: neighbours, features, MLP activations and scratch
     DevBuf<int4> knn_groups;       // 64-point groups of every cloud (first, last; root, end)
@@ -134,8 +135,8 @@ struct wnnc_ctx_s {
     DevBuf<float> nhat;            // n * 3 predicted unit normals (caller order)
 
     // statistics
-    int64_t calls[3] = {0, 0, 0};
-    double trav_ms[3] = {0, 0, 0};
+    int64_t calls[4] = {0, 0, 0, 0};
+    double trav_ms[4] = {0, 0, 0, 0};
     double mom_ms = 0;
     double comb_ms = 0;
     double build_ms = 0;

@@ -57,6 +57,8 @@ constexpr double kInv4Pi = 0.0795774715459476678844;  // 1 / (4 pi)
 //   A  : -(d . nu) / r^3
 //   A^T: nu d / r^3                      (nu scalar, in v.x)
 //   G  : nu / r^3 - 3 (d . nu) d / r^5
+//   P  : g (m / r^3 - 3 (d . m) d / r^5) (g scalar in v.x; m = tv, the
+//        target's own vector: the position-gradient walk)
 // `take` is false for lanes whose pair does not count: not selected by the
 // traversal, or cut off (r < w, Sec. 4.4).  Their term is an exact zero, so
 // that the unconditional add below leaves the sum unchanged.  The term is
@@ -64,8 +66,9 @@ constexpr double kInv4Pi = 0.0795774715459476678844;  // 1 / (4 pi)
 // FP32 rate on this chip), so the sum's rounding does not grow with the
 // number of terms.
 template <int OP>
-__device__ inline void pair_term(float dx, float dy, float dz, float r2, float4 v, bool take,
-                                 double &s, double &gx, double &gy, double &gz) {
+__device__ inline void pair_term(float dx, float dy, float dz, float r2, float4 v,
+                                 const float4 &tv, bool take, double &s, double &gx, double &gy,
+                                 double &gz) {
     const float ri = __builtin_amdgcn_rsqf(r2);  // about 1 ulp
     const float ri2 = ri * ri;
     const float ri3 = ri2 * ri;
@@ -73,6 +76,15 @@ __device__ inline void pair_term(float dx, float dy, float dz, float r2, float4 
         const float dm = fmaf(dx, v.x, fmaf(dy, v.y, dz * v.z));
         const float m3 = take ? -ri3 : 0.0f;
         s += (double)(dm * m3);
+    } else if (OP == OP_P) {
+        const float dm = fmaf(dx, tv.x, fmaf(dy, tv.y, dz * tv.z));
+        // both factors masked: at r = 0 (the target's own point), ri is infinite
+        const float a3 = take ? v.x * ri3 : 0.0f;
+        const float b5 = take ? v.x * (ri3 * ri2) : 0.0f;
+        const float c5 = 3.0f * dm * b5;
+        gx += (double)fmaf(tv.x, a3, -c5 * dx);
+        gy += (double)fmaf(tv.y, a3, -c5 * dy);
+        gz += (double)fmaf(tv.z, a3, -c5 * dz);
     } else if (OP == OP_AT) {
         const float f = take ? v.x * ri3 : 0.0f;
         gx += (double)(f * dx);
@@ -206,7 +218,14 @@ __device__ inline unsigned long long read_mask(uint32_t lo, uint32_t hi, int dep
 template <int OP, int MODE>
 __device__ inline void finish_target(const TravArgs &a, int t, double s, double gx, double gy,
                                      double gz, double &e, double &e2, unsigned &nflip) {
-    if (MODE == TR_OUT_CALLER) {
+    if (MODE == TR_POSGRAD) {
+        // dL/dx = p + g grad F at the target's caller row
+        const int64_t j = a.tperm[t];
+        const double gj = (double)a.gc[j];
+        a.out[3 * j] = (float)(gx * kInv4Pi + gj * (double)a.gradf[3 * j]);
+        a.out[3 * j + 1] = (float)(gy * kInv4Pi + gj * (double)a.gradf[3 * j + 1]);
+        a.out[3 * j + 2] = (float)(gz * kInv4Pi + gj * (double)a.gradf[3 * j + 2]);
+    } else if (MODE == TR_OUT_CALLER) {
         const int64_t j = a.tperm[t];
         if (OP == OP_A) {
             a.out[j] = (float)(s * kInv4Pi);
@@ -309,6 +328,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
     const int tslot = ldc_i(a.task_slot + wave);
 
     float tx[TPL], ty[TPL], tz[TPL];
+    float4 tv[TPL];  // P: the target's own vector (unused by the other operators)
     double s[TPL], gx[TPL], gy[TPL], gz[TPL];
     bool valid[TPL];
     uint32_t mlo[TPL], mhi[TPL];
@@ -324,6 +344,8 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
         const int t = first + k * kWave + lane;
         valid[k] = t < last;
         tx[k] = ty[k] = tz[k] = 0.f;
+        tv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (OP == OP_P && valid[k]) tv[k] = a.tvec[t];
         if (valid[k]) {
             const float4 p = a.tpts[t];
             tx[k] = p.x, ty[k] = p.y, tz[k] = p.z;
@@ -419,7 +441,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
             // w2 >= the smallest normal float, so the cutoff also drops r = 0
             // (and keeps denormal arguments away from the hardware rsq).
             const unsigned long long take = far & __ballot(r2 >= a.w2);
-            pair_term<OP>(dx, dy, dz, r2, V, lane_in(take), s[k], gx[k], gy[k], gz[k]);
+            pair_term<OP>(dx, dy, dz, r2, V, tv[k], lane_in(take), s[k], gx[k], gy[k], gz[k]);
             if (COUNT) cnt += (uint32_t)__popcll(far);
             open[k] = act & ~far;
             any |= open[k];
@@ -444,7 +466,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
             for (int j = jb; j < je; ++j) {
                 const float4 Q = ldc_f4(a.pts + j);
                 float4 S;
-                if (OP == OP_AT)
+                if (OP == OP_AT || OP == OP_P)
                     S = make_float4(ldc_f(a.srcs + j), 0.f, 0.f, 0.f);
                 else
                     S = ldc_f4(a.src4 + j);
@@ -453,7 +475,8 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
                     const float ex = tx[k] - Q.x, ey = ty[k] - Q.y, ez = tz[k] - Q.z;
                     const float e2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
                     const unsigned long long take = open[k] & __ballot(e2 >= a.w2);
-                    pair_term<OP>(ex, ey, ez, e2, S, lane_in(take), s[k], gx[k], gy[k], gz[k]);
+                    pair_term<OP>(ex, ey, ez, e2, S, tv[k], lane_in(take), s[k], gx[k], gy[k],
+                                  gz[k]);
                     if (COUNT) cnt += (uint32_t)__popcll(open[k]);
                 }
             }
@@ -572,10 +595,15 @@ static void launch_tpl_hi(bool count, const TravArgs &a, hipStream_t st) {
 
 template <int OP, int MODE, int TPL>
 static void launch_tpl(bool count, const TravArgs &a, hipStream_t st) {
-    if (a.order > 0 && a.momhi)
-        launch_tpl_hi<OP, MODE, TPL, true>(count, a, st);
-    else
+    if constexpr (OP == OP_P) {
+        // the position-gradient walk has the representative far field only
         launch_tpl_hi<OP, MODE, TPL, false>(count, a, st);
+    } else {
+        if (a.order > 0 && a.momhi)
+            launch_tpl_hi<OP, MODE, TPL, true>(count, a, st);
+        else
+            launch_tpl_hi<OP, MODE, TPL, false>(count, a, st);
+    }
 }
 
 template <int OP, int MODE>
@@ -608,9 +636,11 @@ hipError_t launch_traverse(wnnc_ctx_s *ctx, Op op, TravMode mode, bool count, co
     } else if (op == OP_AT) {
         if (mode == TR_OUT_CALLER) return launch_one<OP_AT, TR_OUT_CALLER>(ctx, count, a);
         if (mode == TR_R) return launch_one<OP_AT, TR_R>(ctx, count, a);
-    } else {
+    } else if (op == OP_G) {
         if (mode == TR_OUT_CALLER) return launch_one<OP_G, TR_OUT_CALLER>(ctx, count, a);
         if (mode == TR_RESCALE) return launch_one<OP_G, TR_RESCALE>(ctx, count, a);
+    } else {
+        if (mode == TR_POSGRAD) return launch_one<OP_P, TR_POSGRAD>(ctx, count, a);
     }
     return hipErrorInvalidValue;
 }
@@ -624,9 +654,11 @@ hipError_t launch_combine(wnnc_ctx_s *ctx, Op op, TravMode mode, const TravArgs 
     } else if (op == OP_AT) {
         if (mode == TR_OUT_CALLER) return launch_comb<OP_AT, TR_OUT_CALLER>(ctx, a);
         if (mode == TR_R) return launch_comb<OP_AT, TR_R>(ctx, a);
-    } else {
+    } else if (op == OP_G) {
         if (mode == TR_OUT_CALLER) return launch_comb<OP_G, TR_OUT_CALLER>(ctx, a);
         if (mode == TR_RESCALE) return launch_comb<OP_G, TR_RESCALE>(ctx, a);
+    } else {
+        if (mode == TR_POSGRAD) return launch_comb<OP_P, TR_POSGRAD>(ctx, a);
     }
     return hipErrorInvalidValue;
 }

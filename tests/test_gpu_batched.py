@@ -104,6 +104,7 @@ def test_batched_operators(dev, oracle_mod, split):
             T = oracle_mod.Tree(xh[a:b_])
             for op, got, nu, sign in (("A", s, mu, 1.0), ("G", g, mu, -1.0), ("AT", at, rho, 1.0)):
                 ref, mag, _ = T.apply(op, nu[a:b_].astype(np.float64), w_, 2.0, with_stats=True)
+                assert np.all(np.isfinite(got[a:b_]))
                 err = np.abs(got[a:b_] - sign * ref)
                 if err.ndim == 2:
                     err = np.linalg.norm(err, axis=1)
@@ -292,6 +293,7 @@ def test_split_walks_with_zero_weight_regions(dev, oracle_mod):
         for op, got, nu, sign in (("A", outs[split][0], mu, 1.0), ("G", outs[split][1], mu, -1.0),
                                   ("AT", outs[split][2], rho, 1.0)):
             ref, mag, _ = T.apply(op, nu.astype(np.float64), 0.002, 2.0, with_stats=True)
+            assert np.all(np.isfinite(got))
             err = np.abs(got - sign * ref)
             if err.ndim == 2:
                 err = np.linalg.norm(err, axis=1)

@@ -77,6 +77,7 @@ def test_operators_match_oracle(dev, name, order, wsafe, oracle_mod):
         for op, nu in (("A", mu), ("G", mu), ("AT", rho)):
             ref, mag, _ = T.apply(op, nu.astype(np.float64), w_, 2.0, with_stats=True,
                                   order=order, wsafe=wsafe)
+            assert np.all(np.isfinite(got[op]))
             err = np.abs(got[op].astype(np.float64) - ref)
             if err.ndim == 2:
                 err = np.linalg.norm(err, axis=1)
@@ -97,6 +98,7 @@ def test_queries_match_oracle(dev, oracle_mod):
     Q = rng.uniform(-1, 1, (3001, 3))
     Q[:500] = x_or[:500] + 1e-3 * rng.standard_normal((500, 3))
     got = ctx.winding_at(_t(mu, dev), 0.002, _t(Q, dev)).cpu().numpy().astype(np.float64)
+    assert np.all(np.isfinite(got))
     ref, mag, _ = oracle_mod.Tree(x_or).apply("A", mu.astype(np.float64), 0.002, 2.0,
                                                targets=Q.astype(np.float32).astype(np.float64),
                                                with_stats=True, order=2, wsafe=True)

@@ -56,6 +56,7 @@ def test_fullsize_operators_on_sampled_targets(knot, oracle_mod):
         at = ctx.adjoint(torch.from_numpy(rho).to(dev), w_).cpu().numpy()
         for op, got, nu, sign in (("A", s, mu, 1.0), ("G", g, mu, -1.0), ("AT", at, rho, 1.0)):
             ref, mag, _ = T.apply(op, nu.astype(np.float64), w_, 2.0, targets=x[sample], with_stats=True)
+            assert np.all(np.isfinite(got[sample]))
             err = np.abs(got[sample] - sign * ref)
             if err.ndim == 2:
                 err = np.linalg.norm(err, axis=1)

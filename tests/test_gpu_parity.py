@@ -150,7 +150,9 @@ def test_moments_match(dev, name, oracle_mod):
 
 
 def _op_compare(gpu, ref, mag):
-    """Per-target error relative to the sum of term magnitudes."""
+    """Per-target error relative to the sum of term magnitudes (a NaN or an
+    infinity on either side fails: it would compare false against TOL)."""
+    assert np.all(np.isfinite(gpu)) and np.all(np.isfinite(ref))
     err = np.abs(gpu - ref)
     if err.ndim == 2:
         err = np.linalg.norm(err, axis=1)

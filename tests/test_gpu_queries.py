@@ -33,6 +33,7 @@ def _check(oracle_mod, xh, mu, Q, got, w_):
     ref, mag, _ = T.apply("A", mu.astype(np.float64), w_, 2.0, targets=Q.astype(np.float64),
                           with_stats=True)
     ref = ref.reshape(-1)
+    assert np.all(np.isfinite(got))
     err = np.abs(got - ref)
     ok = mag > 0
     bad = (err[ok] / mag[ok] > TOL).mean() if ok.any() else 0.0
