@@ -91,8 +91,11 @@ __device__ inline void write_moment(const MomArgs &a, int node, const int4 t, co
         const double x = s[1] / W, y = s[2] / W, z = s[3] / W;
         const float hx = (float)x, hy = (float)y, hz = (float)z;
         p = make_float4(hx, hy, hz, __int_as_float(flags));
-        lo = make_float4((float)(x - (double)hx), (float)(y - (double)hy), (float)(z - (double)hz),
-                         lo.w);
+        // a single point's representative is the point itself: hi is the
+        // point exactly (the FP64 quotient is within an FP64 ulp of it), lo 0
+        if (!(flags & kRecSingle))
+            lo = make_float4((float)(x - (double)hx), (float)(y - (double)hy),
+                             (float)(z - (double)hz), lo.w);
     } else {
         p = make_float4(0.f, 0.f, 0.f, __int_as_float(flags | kRecZero));
     }

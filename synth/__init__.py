@@ -20,6 +20,8 @@ Sec. 5):
 * ``torus_knot``        -- a (2,3) torus-knot tube with a 10:1 sampling
   density variation along the curve plus uniform outliers (non-uniform raw
   scans with outliers, Sec. 5.2.6).
+* ``torus_chain``       -- fused tori in a row, a closed surface of genus
+  ``count`` (the high-genus case of Sec. 5.2.3).
 * ``batched_sizes``     -- the log-uniform cloud sizes of the batched case.
 * ``icosphere``         -- vertices of a subdivided icosahedron projected on
   the unit sphere (163,842 vertices at level 7: the sphere of Table 5).
@@ -36,6 +38,7 @@ __all__ = [
     "fibonacci_sphere",
     "ellipsoid_union",
     "torus_knot",
+    "torus_chain",
     "batched_sizes",
     "batched_clouds",
     "icosphere",
@@ -199,6 +202,56 @@ def ellipsoid_union(n: int = 50000, seed: int = 2, members: int = 6,
                  area=float(areas.sum()), mu0=mu0,
                  meta=dict(kind="ellipsoid_union", n=n, seed=seed, members=members,
                            noise=noise, diag=diag))
+
+
+def torus_chain(n: int = 8000, seed: int = 6, count: int = 6, R: float = 0.1,
+                r: float = 0.025, spacing: float = 1.8, with_init: bool = True) -> Cloud:
+    """A closed surface of genus ``count``: ``count`` equal tori (major radius
+    R, tube radius r, axis z) with centres on a line ``spacing * R`` apart,
+    so that neighbouring tubes fuse while every hole stays open (the
+    high-genus case of Sec. 5.2.3).  Each torus is sampled uniformly by
+    area (u, v uniform, v accepted with probability (R + r cos v)/(R + r));
+    points inside another torus are discarded and a seeded subset of exactly
+    ``n`` is kept.  Ground truth is the owning torus's outward normal.  The
+    chain is centred in [0,1]^3.
+    """
+    rng = np.random.default_rng(seed)
+    cx = (np.arange(count) - (count - 1) / 2.0) * spacing * R + 0.5
+
+    def inside(p, k):
+        mask = np.zeros(len(p), dtype=bool)
+        for j in range(count):
+            if j == k:
+                continue
+            rho = np.hypot(p[:, 0] - cx[j], p[:, 1] - 0.5)
+            mask |= (rho - R) ** 2 + (p[:, 2] - 0.5) ** 2 < r * r
+        return mask
+
+    pts, nrms = [], []
+    total = 0
+    per = int(1.5 * n / count) + 64
+    while total < n:
+        for k in range(count):
+            u = rng.uniform(0.0, 2.0 * np.pi, per)
+            v = rng.uniform(0.0, 2.0 * np.pi, per)
+            keep = rng.random(per) * (R + r) < R + r * np.cos(v)
+            u, v = u[keep], v[keep]
+            rho = R + r * np.cos(v)
+            p = np.stack([cx[k] + rho * np.cos(u), 0.5 + rho * np.sin(u), 0.5 + r * np.sin(v)], 1)
+            nn = np.stack([np.cos(v) * np.cos(u), np.cos(v) * np.sin(u), np.sin(v)], 1)
+            ok = ~inside(p, k)
+            pts.append(p[ok])
+            nrms.append(nn[ok])
+            total += int(ok.sum())
+    P = np.concatenate(pts)
+    Nn = np.concatenate(nrms)
+    sel = rng.choice(len(P), size=n, replace=False)
+    P, Nn = P[sel], Nn[sel]
+    mu0 = random_unit(rng, n).astype(np.float32) if with_init else None
+    return Cloud(points=P.astype(np.float32), normals=Nn.astype(np.float32),
+                 area=float(count * 4 * np.pi ** 2 * R * r), mu0=mu0,
+                 meta=dict(kind="torus_chain", n=n, seed=seed, count=count, R=R, r=r,
+                           spacing=spacing))
 
 
 def _rmf(curve_pts, tangents):
