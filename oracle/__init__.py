@@ -30,8 +30,8 @@ import numpy as np
 
 from . import build as _build
 
-OP_A, OP_AT, OP_G, OP_P = 0, 1, 2, 3
-_OPS = {"A": OP_A, "AT": OP_AT, "G": OP_G, "P": OP_P}
+OP_A, OP_AT, OP_G, OP_P, OP_T = 0, 1, 2, 3, 4
+_OPS = {"A": OP_A, "AT": OP_AT, "G": OP_G, "P": OP_P, "T": OP_T}
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _lib = None
 
@@ -109,10 +109,10 @@ def normalize(points):
 
 
 def direct(op: str, x, nu, w: float, targets=None, with_mag: bool = False, tvec=None):
-    """Exact FP64 sum of operator op in {"A","AT","G","P"} over all source
-    points x (n,3) with attributes nu ((n,3) for A and G, (n,) for AT and P),
-    evaluated at targets (default: the points themselves); P also takes the
-    targets' vectors tvec (n_targets,3)."""
+    """Exact FP64 sum of operator op in {"A","AT","G","P","T"} over all source
+    points x (n,3) with attributes nu ((n,3) for A, G and T, (n,) for AT and
+    P), evaluated at targets (default: the points themselves); P and T also
+    take the targets' vectors tvec (n_targets,3)."""
     lib = _load()
     o = _OPS[op]
     x = _f64(x, (-1, 3))
@@ -129,7 +129,7 @@ def direct(op: str, x, nu, w: float, targets=None, with_mag: bool = False, tvec=
 
 
 def _tvec(o, tvec, n):
-    if o != OP_P:
+    if o not in (OP_P, OP_T):
         return None
     if tvec is None:
         raise ValueError("P needs the targets' vectors")
@@ -197,8 +197,8 @@ class Tree:
         o = _OPS[op]
         nu = _f64(nu, (self.n, 3) if o not in (OP_AT, OP_P) else (self.n,))
         t = self.x if targets is None else _f64(targets, (-1, 3))
-        if o == OP_P and order != 0:
-            raise ValueError("P has the representative far field only")
+        if o in (OP_P, OP_T) and order != 0:
+            raise ValueError("P and T have the representative far field only")
         tv = _tvec(o, tvec, t.shape[0])
         dout = 1 if o == OP_A else 3
         out = np.zeros((t.shape[0], dout))
@@ -235,6 +235,22 @@ def winding_grad_x(x, mu, g, w: float, backend: str = "direct", c: float = 2.0, 
         G = T.apply("G", mu, w, c)
         P = T.apply("P", g, w, c, tvec=mu)
     return -g[:, None] * G + P
+
+
+def gradient_grad_x(x, mu, v, w: float, backend: str = "direct", c: float = 2.0, tree=None):
+    """Gradient with respect to the points x of L = sum_i v_i . grad F(x_i; mu)
+    (grad F = -G(mu); an extension).  With grad F_i = sum_j HPhi(x_i - x_j) mu_j,
+    differentiating each pair term in both end points (T3Phi odd) gives
+      dL/dx_k = sum_j T3Phi(x_k - x_j)[v_k, mu_j] + sum_i T3Phi(x_k - x_i)[mu_k, v_i]
+              = T(mu; v)_k + T(v; mu)_k
+    (T(a; b): sources a, target vectors b).  The cutoff is held fixed."""
+    x = np.asarray(x, dtype=np.float64)
+    mu = np.asarray(mu, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    if backend == "direct":
+        return direct("T", x, mu, w, tvec=v) + direct("T", x, v, w, tvec=mu)
+    T = tree if tree is not None else Tree(x)
+    return T.apply("T", mu, w, c, tvec=v) + T.apply("T", v, w, c, tvec=mu)
 
 
 from .iterate import grad_step, orient, width_schedule, rescale  # noqa: E402

@@ -23,6 +23,11 @@
  *        gradient of the winding number, an extension: with L = sum_i g_i s_i,
  *        dL/dx_k = -g_k G(mu)_k + p_k; the source attribute is the scalar g,
  *        the target carries its own vector mu_k)
+ *   T  : a -> t,      t_k   = sum_j T3Phi(x_k - x_j)[b_k, a_j]       (position
+ *        gradient of grad F, an extension: with L = sum_i v_i . grad F(x_i; mu),
+ *        dL/dx_k = T(mu; v)_k + T(v; mu)_k; T3Phi is the third derivative
+ *        tensor of Phi, the source attribute is the vector a, the target
+ *        carries its own vector b)
  *
  * Smoothing (Sec. 4.4): a pair term is set to 0 when |x_i - x_j| < w.  The
  * coincident pair |y| = 0 is also 0 (it is excluded for every w > 0 anyway).
@@ -52,6 +57,7 @@
 #define OR_OP_AT 1
 #define OR_OP_G 2
 #define OR_OP_P 3
+#define OR_OP_T 4
 
 /* ---------------------------------------------------------------- pairs -- */
 
@@ -83,6 +89,21 @@ static void pair_term(int op, const double *xt, const double *xs, const double *
         out[1] += t1;
         out[2] += t2;
         *mag += sqrt(t0 * t0 + t1 * t1 + t2 * t2);
+    } else if (op == OR_OP_T) {
+        /* T3Phi(y)[b, a]_m = (3 r^2 (b_m (y.a) + a_m (y.b) + y_m (a.b))
+         *                     - 15 y_m (y.a)(y.b)) / (4 pi r^7) */
+        double r7 = r3 * r2 * r2;
+        double ya = y[0] * nu[0] + y[1] * nu[1] + y[2] * nu[2];
+        double yb = y[0] * tv[0] + y[1] * tv[1] + y[2] * tv[2];
+        double ab = nu[0] * tv[0] + nu[1] * tv[1] + nu[2] * tv[2];
+        double t[3];
+        for (int k = 0; k < 3; ++k)
+            t[k] = (3.0 * r2 * (tv[k] * ya + nu[k] * yb + y[k] * ab) - 15.0 * y[k] * ya * yb) /
+                   (4.0 * OR_PI * r7);
+        out[0] += t[0];
+        out[1] += t[1];
+        out[2] += t[2];
+        *mag += sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
     } else if (op == OR_OP_P) {
         /* g (-HPhi(y) v) with the target's vector v */
         double r5 = r3 * r2;
@@ -501,8 +522,8 @@ void or_tree_apply_tv(or_tree *T, int op, const double *nu, double w, double c, 
                       double *out, double *mag, int64_t *pairs)
 {
     int din = op_in_dim(op), dout = op_out_dim(op);
-    if (op == OR_OP_P)
-        order = 0; /* P: the representative term only */
+    if (op == OR_OP_P || op == OR_OP_T)
+        order = 0; /* P, T: the representative term only */
     compute_reps(T, nu, din);
     if (order > 0)
         compute_moments(T, nu, din);

@@ -590,3 +590,31 @@ def test_winding_grad_x_treecode_limits(oracle_mod):
     assert np.abs(big - ex).max() <= 1e-12 * np.abs(ex).max()
     tc = oracle_mod.winding_grad_x(x, mu, g, 0.002, backend="tree", c=2.0, tree=T)
     assert np.linalg.norm(tc - ex) / np.linalg.norm(ex) < 0.05
+
+
+def test_gradient_grad_x_matches_finite_differences(oracle_mod):
+    """dL/dx of L = v . grad F(mu) = -v . G(mu) from the closed form
+    T(mu; v) + T(v; mu) against central differences of the exact sums; it
+    sums to 0 (translation invariance); the treecode version equals it when
+    no node is accepted."""
+    rng = np.random.default_rng(5)
+    x = rng.uniform(-1, 1, (50, 3))
+    mu = rng.standard_normal((50, 3))
+    v = rng.standard_normal((50, 3))
+    for w in (0.0, 0.05):
+        d = np.linalg.norm(x[:, None] - x[None], axis=2) + 10.0 * np.eye(len(x))
+        assert np.all(np.abs(d - w) > 1e-3)
+        gx = oracle_mod.gradient_grad_x(x, mu, v, w)
+        h = 1e-6
+        fd = np.zeros_like(x)
+        for k in range(len(x)):
+            for a in range(3):
+                xp, xm = x.copy(), x.copy()
+                xp[k, a] += h
+                xm[k, a] -= h
+                fd[k, a] = ((v * -oracle_mod.direct("G", xp, mu, w)).sum()
+                            - (v * -oracle_mod.direct("G", xm, mu, w)).sum()) / (2 * h)
+        assert np.abs(gx - fd).max() <= 1e-7 * np.abs(fd).max()
+        assert np.abs(gx.sum(axis=0)).max() <= 1e-12 * np.abs(gx).max()
+        big = oracle_mod.gradient_grad_x(x, mu, v, w, backend="tree", c=1e6)
+        assert np.abs(big - gx).max() <= 1e-12 * np.abs(gx).max()
