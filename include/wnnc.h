@@ -104,15 +104,16 @@ typedef struct {
 #define WNNC_OP_AT 1
 #define WNNC_OP_G 2
 #define WNNC_OP_P 3 /* the position-gradient walk of wnnc_winding_grad_x */
+#define WNNC_OP_T 4 /* the position-gradient walks of wnnc_gradient_grad_x */
 
 typedef struct {
     int64_t n_points;       /* N of the current tree */
     int64_t n_nodes;        /* octree nodes */
-    int64_t calls[4];       /* operator applications per kind since reset */
-    int64_t pairs[4];       /* pair evaluations per kind (WNNC_FLAG_COUNT_PAIRS):
+    int64_t calls[5];       /* operator applications per kind since reset */
+    int64_t pairs[5];       /* pair evaluations per kind (WNNC_FLAG_COUNT_PAIRS):
                                accepted representatives plus points summed
                                directly, cut-off pairs included */
-    double traverse_ms[4];  /* summed traversal-kernel time per kind
+    double traverse_ms[5];  /* summed traversal-kernel time per kind
                                (WNNC_FLAG_TIME_KERNELS) */
     double moments_ms;      /* summed moment-pass time (WNNC_FLAG_TIME_KERNELS) */
     double build_ms;        /* last wnnc_build, device time (always timed) */
@@ -252,6 +253,19 @@ wnnc_status wnnc_adjoint(wnnc_ctx ctx, const float *s, float w, float *out);
  * wnnc_set_far_field says. */
 wnnc_status wnnc_winding_grad_x(wnnc_ctx ctx, const float *n, const float *sigma, float w,
                                 const float *g, float *dx_out);
+
+/* Gradient of L = sum_i v_i . grad F(x_i; mu) (wnnc_gradient) with respect to
+ * the point positions (an extension).  With the third-derivative tensor
+ * T3Phi of Phi, differentiating each pair term of grad F in both end points
+ * (the cutoff held fixed) gives
+ *   dL/dx_k = sum_j T3Phi(x_k - x_j)[v_k, mu_j] + sum_i T3Phi(x_k - x_i)[mu_k, v_i],
+ * two treecode walks of one kernel (vector sources, each target with its own
+ * vector): sources mu with targets' v, then sources v with targets' mu.
+ * n (N,3) with sigma (N) or NULL as in wnnc_gradient, v (N,3), dx_out (N,3):
+ * device, caller order, with respect to the normalized points.  Both walks
+ * use Alg. 4's far field whatever wnnc_set_far_field says. */
+wnnc_status wnnc_gradient_grad_x(wnnc_ctx ctx, const float *n, const float *sigma, float w,
+                                 const float *v, float *dx_out);
 
 /* Far field of the treecode (an extension for precision control; the
  * paper's Alg. 4 is order 0 without wsafe, the default).

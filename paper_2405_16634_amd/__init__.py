@@ -35,6 +35,7 @@ EXPORTED = [
     "wnnc_mlp_forward", "wnnc_mlp_grad", "wnnc_mlp_adam",
     "wnnc_warm_orient", "wnnc_set_prefetch", "wnnc_set_split", "wnnc_get_split",
     "wnnc_winding_at", "wnnc_set_far_field", "wnnc_get_far_field", "wnnc_winding_grad_x",
+    "wnnc_gradient_grad_x",
 ]
 MLP_PARAMS = 7491
 AUTOTUNE_CONFIGS = 12
@@ -80,8 +81,8 @@ class TileTime(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("n_points", ctypes.c_int64), ("n_nodes", ctypes.c_int64),
-                ("calls", ctypes.c_int64 * 4), ("pairs", ctypes.c_int64 * 4),
-                ("traverse_ms", ctypes.c_double * 4), ("moments_ms", ctypes.c_double),
+                ("calls", ctypes.c_int64 * 5), ("pairs", ctypes.c_int64 * 5),
+                ("traverse_ms", ctypes.c_double * 5), ("moments_ms", ctypes.c_double),
                 ("build_ms", ctypes.c_double), ("n_clouds", ctypes.c_int64),
                 ("tile", ctypes.c_int64), ("n_groups", ctypes.c_int64),
                 ("n_tasks", ctypes.c_int64), ("combine_ms", ctypes.c_double)]
@@ -138,6 +139,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "wnnc_orient_preset": [ctypes.c_int, P(OrientOpts)],
         "wnnc_set_far_field": [vp, ctypes.c_int, ctypes.c_int],
         "wnnc_winding_grad_x": [vp, vp, vp, f32, vp, vp],
+        "wnnc_gradient_grad_x": [vp, vp, vp, f32, vp, vp],
         "wnnc_get_far_field": [vp, P(ctypes.c_int), P(ctypes.c_int)],
         "wnnc_mlp_forward": [vp, vp, vp, i64, vp],
         "wnnc_mlp_grad": [vp, vp, vp, vp, i64, vp, P(dbl)],
@@ -340,6 +342,14 @@ def wnnc_winding_grad_x(ctx, mu, sigma, w: float, g, dx_out) -> None:
     _check(load_library().wnnc_winding_grad_x(
         ctx, _dev(mu, "mu", shape=(N, 3)), _dev(sigma, "sigma", shape=(N,)), float(w),
         _dev(g, "g", shape=(N,)), _dev(dx_out, "dx_out", shape=(N, 3))))
+
+
+def wnnc_gradient_grad_x(ctx, mu, sigma, w: float, v, dx_out) -> None:
+    """dL/dx of L = v . grad F(mu) with respect to the (normalized) points."""
+    N = mu.shape[0]
+    _check(load_library().wnnc_gradient_grad_x(
+        ctx, _dev(mu, "mu", shape=(N, 3)), _dev(sigma, "sigma", shape=(N,)), float(w),
+        _dev(v, "v", shape=(N, 3)), _dev(dx_out, "dx_out", shape=(N, 3))))
 
 
 def wnnc_set_far_field(ctx, order: int = 0, wsafe: bool = False) -> None:
@@ -590,6 +600,12 @@ class Context:
         """Gradient of g . A_w(mu) with respect to the normalized points."""
         out = torch.empty(mu.shape[0], 3, device=mu.device, dtype=torch.float32)
         wnnc_winding_grad_x(self._h, mu, sigma, w, g, out)
+        return out
+
+    def gradient_grad_x(self, mu, w: float, v, sigma=None):
+        """Gradient of v . grad F(mu) with respect to the normalized points."""
+        out = torch.empty(mu.shape[0], 3, device=mu.device, dtype=torch.float32)
+        wnnc_gradient_grad_x(self._h, mu, sigma, w, v, out)
         return out
 
     def set_far_field(self, order: int = 0, wsafe: bool = False) -> None:

@@ -10,6 +10,8 @@ The adjoint operator is the backward of the winding-number operator
 * ``winding_at_points(ctx, x, mu, w)``  s = A_w(mu) on the tree built from
   the normalized points x; differentiable in x and mu (an extension:
   backward in x is wnnc_winding_grad_x, g -> g grad F + p)
+* ``gradient_at_points(ctx, x, mu, w)``  grad F = -G_w(mu) likewise (backward
+  in x is wnnc_gradient_grad_x)
 
 All three evaluate with the context's treecode; every forward and backward
 runs in the library's kernels (argument marshalling only here).  With the
@@ -21,7 +23,8 @@ from __future__ import annotations
 
 import torch
 
-from . import wnnc_adjoint, wnnc_build, wnnc_gradient, wnnc_winding, wnnc_winding_grad_x
+from . import (wnnc_adjoint, wnnc_build, wnnc_gradient, wnnc_gradient_grad_x, wnnc_winding,
+               wnnc_winding_grad_x)
 
 
 def _prep(t):
@@ -126,4 +129,32 @@ def winding_at_points(ctx, x, mu, w: float, c: float = 2.0, max_depth: int = 15)
     differentiable in x and in mu.  The backward reuses the tree of the
     forward, so call backward before the next build on ctx."""
     return WindingPositions.apply(_handle(ctx), x, mu, w, c, max_depth)
+
+
+class GradientPositions(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, handle, x, mu, w, c, max_depth):
+        fctx.handle, fctx.w = handle, float(w)
+        wnnc_build(handle, _prep(x), float(c), int(max_depth))
+        m = _prep(mu)
+        out = torch.empty_like(m)
+        wnnc_gradient(handle, m, None, fctx.w, out)
+        fctx.save_for_backward(m)
+        return out
+
+    @staticmethod
+    def backward(fctx, g):
+        (m,) = fctx.saved_tensors
+        gg = _prep(g)
+        gx = torch.empty_like(m)
+        wnnc_gradient_grad_x(fctx.handle, m, None, fctx.w, gg, gx)
+        gm = torch.empty_like(m)
+        wnnc_gradient(fctx.handle, gg, None, fctx.w, gm)
+        return None, gx, gm, None, None, None
+
+
+def gradient_at_points(ctx, x, mu, w: float, c: float = 2.0, max_depth: int = 15):
+    """grad F = -G_w(mu) at the normalized points x, building ctx's tree on
+    x; differentiable in x and in mu (as winding_at_points)."""
+    return GradientPositions.apply(_handle(ctx), x, mu, w, c, max_depth)
 

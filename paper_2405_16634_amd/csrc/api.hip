@@ -134,8 +134,8 @@ TravArgs trav_args(wnnc_ctx_s *c, float w) {
     return a;
 }
 
-// Timed kinds: 0..3 the traversal of each operator, then these two.
-constexpr int kKindMoments = 4, kKindCombine = 5;
+// Timed kinds: 0..kOpKinds-1 the traversal of each operator, then these two.
+constexpr int kKindMoments = kOpKinds, kKindCombine = kOpKinds + 1;
 
 wnnc_status run_moments(wnnc_ctx_s *c, MomMode mode, const MomArgs &a) {
     Timed tm(c, kKindMoments);
@@ -666,6 +666,44 @@ wnnc_status wnnc_winding_grad_x(wnnc_ctx ctx, const float *n, const float *sigma
     return run_traverse(ctx, OP_P, TR_POSGRAD, tb);
 }
 
+wnnc_status wnnc_gradient_grad_x(wnnc_ctx ctx, const float *n, const float *sigma, float w,
+                                 const float *v, float *dx_out) {
+    CHECK_CTX(ctx);
+    CHECK_BUILT(ctx);
+    if (!n || !v || !dx_out) return fail(WNNC_EINVAL, "null pointer");
+    if (!finite_nonneg(w)) return fail(WNNC_EINVAL, "w must be finite and >= 0");
+    const int64_t N = ctx->n;
+    hipStream_t st = ctx->stream;
+    HIPCHK(ctx->gradf.ensure(3 * N));
+    // v in sorted order (vb); mu in sorted order with its representatives (va)
+    HIPCHK(launch_gather_vec(v, ctx->perm.p, ctx->vb.p, N, st));
+    MomArgs ma = mom_args(ctx, w, true);
+    ma.cn = n;
+    ma.csig = sigma;
+    ma.out4 = ctx->va.p;
+    RETURN_IF(run_moments(ctx, MOM_VEC_CALLER, ma));
+    // T(mu; v): sources mu, each target with its v -> gradf (caller order)
+    TravArgs ta = trav_args(ctx, w);
+    ta.order = 0;
+    ta.momhi = nullptr;
+    ta.src4 = ctx->va.p;
+    ta.tvec = ctx->vb.p;
+    ta.out = ctx->gradf.p;
+    RETURN_IF(run_traverse(ctx, OP_T, TR_OUT_CALLER, ta));
+    // T(v; mu): sources v, each target with its mu, added to the first
+    MomArgs mb = mom_args(ctx, w, true);
+    mb.src4 = ctx->vb.p;
+    RETURN_IF(run_moments(ctx, MOM_VEC_SORTED, mb));
+    TravArgs tb = trav_args(ctx, w);
+    tb.order = 0;
+    tb.momhi = nullptr;
+    tb.src4 = ctx->vb.p;
+    tb.tvec = ctx->va.p;
+    tb.gradf = ctx->gradf.p;
+    tb.out = dx_out;
+    return run_traverse(ctx, OP_T, TR_ACCUM, tb);
+}
+
 wnnc_status wnnc_adjoint(wnnc_ctx ctx, const float *s, float w, float *out) {
     CHECK_CTX(ctx);
     CHECK_BUILT(ctx);
@@ -980,11 +1018,11 @@ wnnc_status wnnc_stats(wnnc_ctx ctx, wnnc_stats_t *out) {
     memset(out, 0, sizeof(*out));
     out->n_points = ctx->built ? ctx->n : 0;
     out->n_nodes = ctx->built ? ctx->m : 0;
-    unsigned long long pc[4] = {0, 0, 0, 0};
+    unsigned long long pc[kOpKinds] = {};
     if (ctx->pair_ctr.p) {
         HIPCHK(hipMemcpy(pc, ctx->pair_ctr.p, sizeof(pc), hipMemcpyDeviceToHost));
     }
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < kOpKinds; ++k) {
         out->calls[k] = ctx->calls[k];
         out->pairs[k] = (int64_t)pc[k];
         out->traverse_ms[k] = ctx->trav_ms[k];
@@ -1007,14 +1045,14 @@ wnnc_status wnnc_reset_stats(wnnc_ctx ctx) {
         ctx->event_pool.push_back(t.b);
     }
     ctx->pending.clear();
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < kOpKinds; ++k) {
         ctx->calls[k] = 0;
         ctx->trav_ms[k] = 0;
     }
     ctx->mom_ms = 0;
     ctx->comb_ms = 0;
-    HIPCHK(ctx->pair_ctr.ensure(4));
-    HIPCHK(hipMemsetAsync(ctx->pair_ctr.p, 0, 4 * sizeof(unsigned long long), ctx->stream));
+    HIPCHK(ctx->pair_ctr.ensure(kOpKinds));
+    HIPCHK(hipMemsetAsync(ctx->pair_ctr.p, 0, kOpKinds * sizeof(unsigned long long), ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return WNNC_OK;
 }

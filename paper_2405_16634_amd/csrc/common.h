@@ -135,8 +135,8 @@ struct wnnc_ctx_s {
     DevBuf<float> nhat;            // n * 3 predicted unit normals (caller order)
 
     // statistics
-    int64_t calls[4] = {0, 0, 0, 0};
-    double trav_ms[4] = {0, 0, 0, 0};
+    int64_t calls[wnnc::kOpKinds] = {};
+    double trav_ms[wnnc::kOpKinds] = {};
     double mom_ms = 0;
     double comb_ms = 0;
     double build_ms = 0;

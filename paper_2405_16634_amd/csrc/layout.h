@@ -61,7 +61,8 @@ constexpr int kRecLeaf = 16;
 constexpr int kRecSingle = 32;
 constexpr int kRecZero = 64;
 
-enum Op { OP_A = WNNC_OP_A, OP_AT = WNNC_OP_AT, OP_G = WNNC_OP_G, OP_P = WNNC_OP_P };
+enum Op { OP_A = WNNC_OP_A, OP_AT = WNNC_OP_AT, OP_G = WNNC_OP_G, OP_P = WNNC_OP_P, OP_T = WNNC_OP_T };
+constexpr int kOpKinds = 5;
 
 // Warm-start MLP: 48 -> 64 -> 64 -> 3; flat FP32 parameter vector, row-major
 // [in][out] weights each followed by its bias.
@@ -99,6 +100,7 @@ enum TravMode {
     TR_SCALE = 5,       // A: block partials of s and s^2 (warm-start scale)
     TR_PLAN = 6,        // no output: record the walk of each group (split planning)
     TR_POSGRAD = 7,     // P: out = p / (4 pi) + g grad F, caller order (position gradient)
+    TR_ACCUM = 8,       // out = sum / (4 pi) + base, caller order (base in gradf)
 };
 
 // Split planning: the walk of every 64-target group is recorded as its node
@@ -171,7 +173,7 @@ struct TravArgs {
     const float *momhi;      // far-field moments (order >= 1)
     const float4 *tvec;      // P: each target's own vector (sorted)
     const float *gc;         // TR_POSGRAD: caller-order g
-    const float *gradf;      // TR_POSGRAD: caller-order grad F (N,3)
+    const float *gradf;      // TR_POSGRAD: caller-order grad F; TR_ACCUM: the base (N,3)
     float w2;
     int order;               // far-field order 0, 1, 2
 };

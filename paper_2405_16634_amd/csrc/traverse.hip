@@ -59,6 +59,9 @@ constexpr double kInv4Pi = 0.0795774715459476678844;  // 1 / (4 pi)
 //   G  : nu / r^3 - 3 (d . nu) d / r^5
 //   P  : g (m / r^3 - 3 (d . m) d / r^5) (g scalar in v.x; m = tv, the
 //        target's own vector: the position-gradient walk)
+//   T  : (3 r^2 (b (d . a) + a (d . b) + d (a . b)) - 15 d (d . a)(d . b)) / r^7
+//        (a = v, b = tv: the third derivative of Phi contracted with the
+//        source's and the target's vectors)
 // `take` is false for lanes whose pair does not count: not selected by the
 // traversal, or cut off (r < w, Sec. 4.4).  Their term is an exact zero, so
 // that the unconditional add below leaves the sum unchanged.  The term is
@@ -76,6 +79,17 @@ __device__ inline void pair_term(float dx, float dy, float dz, float r2, float4 
         const float dm = fmaf(dx, v.x, fmaf(dy, v.y, dz * v.z));
         const float m3 = take ? -ri3 : 0.0f;
         s += (double)(dm * m3);
+    } else if (OP == OP_T) {
+        const float da = fmaf(dx, v.x, fmaf(dy, v.y, dz * v.z));
+        const float db = fmaf(dx, tv.x, fmaf(dy, tv.y, dz * tv.z));
+        const float ab = fmaf(v.x, tv.x, fmaf(v.y, tv.y, v.z * tv.z));
+        // both factors masked: at r = 0, ri is infinite
+        const float r5 = take ? 3.0f * (ri3 * ri2) : 0.0f;  // 3 / r^5
+        const float r7 = take ? 15.0f * (ri3 * ri2) * ri2 : 0.0f;  // 15 / r^7
+        const float q = r7 * da * db;
+        gx += (double)fmaf(r5, fmaf(tv.x, da, fmaf(v.x, db, dx * ab)), -q * dx);
+        gy += (double)fmaf(r5, fmaf(tv.y, da, fmaf(v.y, db, dy * ab)), -q * dy);
+        gz += (double)fmaf(r5, fmaf(tv.z, da, fmaf(v.z, db, dz * ab)), -q * dz);
     } else if (OP == OP_P) {
         const float dm = fmaf(dx, tv.x, fmaf(dy, tv.y, dz * tv.z));
         // both factors masked: at r = 0 (the target's own point), ri is infinite
@@ -218,7 +232,12 @@ __device__ inline unsigned long long read_mask(uint32_t lo, uint32_t hi, int dep
 template <int OP, int MODE>
 __device__ inline void finish_target(const TravArgs &a, int t, double s, double gx, double gy,
                                      double gz, double &e, double &e2, unsigned &nflip) {
-    if (MODE == TR_POSGRAD) {
+    if (MODE == TR_ACCUM) {
+        const int64_t j = a.tperm[t];
+        a.out[3 * j] = (float)(gx * kInv4Pi + (double)a.gradf[3 * j]);
+        a.out[3 * j + 1] = (float)(gy * kInv4Pi + (double)a.gradf[3 * j + 1]);
+        a.out[3 * j + 2] = (float)(gz * kInv4Pi + (double)a.gradf[3 * j + 2]);
+    } else if (MODE == TR_POSGRAD) {
         // dL/dx = p + g grad F at the target's caller row
         const int64_t j = a.tperm[t];
         const double gj = (double)a.gc[j];
@@ -345,7 +364,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
         valid[k] = t < last;
         tx[k] = ty[k] = tz[k] = 0.f;
         tv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (OP == OP_P && valid[k]) tv[k] = a.tvec[t];
+        if ((OP == OP_P || OP == OP_T) && valid[k]) tv[k] = a.tvec[t];
         if (valid[k]) {
             const float4 p = a.tpts[t];
             tx[k] = p.x, ty[k] = p.y, tz[k] = p.z;
@@ -595,7 +614,7 @@ static void launch_tpl_hi(bool count, const TravArgs &a, hipStream_t st) {
 
 template <int OP, int MODE, int TPL>
 static void launch_tpl(bool count, const TravArgs &a, hipStream_t st) {
-    if constexpr (OP == OP_P) {
+    if constexpr (OP == OP_P || OP == OP_T) {
         // the position-gradient walk has the representative far field only
         launch_tpl_hi<OP, MODE, TPL, false>(count, a, st);
     } else {
@@ -639,8 +658,11 @@ hipError_t launch_traverse(wnnc_ctx_s *ctx, Op op, TravMode mode, bool count, co
     } else if (op == OP_G) {
         if (mode == TR_OUT_CALLER) return launch_one<OP_G, TR_OUT_CALLER>(ctx, count, a);
         if (mode == TR_RESCALE) return launch_one<OP_G, TR_RESCALE>(ctx, count, a);
-    } else {
+    } else if (op == OP_P) {
         if (mode == TR_POSGRAD) return launch_one<OP_P, TR_POSGRAD>(ctx, count, a);
+    } else {
+        if (mode == TR_OUT_CALLER) return launch_one<OP_T, TR_OUT_CALLER>(ctx, count, a);
+        if (mode == TR_ACCUM) return launch_one<OP_T, TR_ACCUM>(ctx, count, a);
     }
     return hipErrorInvalidValue;
 }
@@ -657,8 +679,11 @@ hipError_t launch_combine(wnnc_ctx_s *ctx, Op op, TravMode mode, const TravArgs 
     } else if (op == OP_G) {
         if (mode == TR_OUT_CALLER) return launch_comb<OP_G, TR_OUT_CALLER>(ctx, a);
         if (mode == TR_RESCALE) return launch_comb<OP_G, TR_RESCALE>(ctx, a);
-    } else {
+    } else if (op == OP_P) {
         if (mode == TR_POSGRAD) return launch_comb<OP_P, TR_POSGRAD>(ctx, a);
+    } else {
+        if (mode == TR_OUT_CALLER) return launch_comb<OP_T, TR_OUT_CALLER>(ctx, a);
+        if (mode == TR_ACCUM) return launch_comb<OP_T, TR_ACCUM>(ctx, a);
     }
     return hipErrorInvalidValue;
 }

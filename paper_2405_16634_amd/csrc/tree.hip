@@ -487,7 +487,7 @@ hipError_t build_tree(wnnc_ctx_s *ctx, const float *P) {
     TRY(ctx->vr.ensure(n));
     TRY(ctx->rho.ensure(n));
     TRY(ctx->scalars.ensure(nclouds));
-    TRY(ctx->pair_ctr.ensure(4));
+    TRY(ctx->pair_ctr.ensure(kOpKinds));
     {
         int64_t big = hsize > n + 1 ? hsize : n + 1;
         TRY(ctx->scan_tmp.ensure(scan_tmp_size(16 * big + 16)));
@@ -554,7 +554,7 @@ hipError_t build_tree(wnnc_ctx_s *ctx, const float *P) {
     if (ns > 0)
         hipLaunchKernelGGL(k_tail_fill, dim3(blocks_for(ns, 256)), dim3(256), 0, st,
                            ctx->strad_node.p, ctx->topo.p, (int)ns, cursor, ctx->tail_list.p);
-    TRY(hipMemsetAsync(ctx->pair_ctr.p, 0, 4 * sizeof(unsigned long long), st));
+    TRY(hipMemsetAsync(ctx->pair_ctr.p, 0, kOpKinds * sizeof(unsigned long long), st));
     return hipGetLastError();
 }
 

@@ -153,3 +153,57 @@ def test_batched_matches_standalone(dev):
         assert err < 1e-5
         one.close()
     ctx.close()
+
+
+# ---------------------- position gradient of grad F (third derivatives of Phi)
+
+def _check_t(got, x_or, mu, v, w, c, oracle_mod):
+    T = oracle_mod.Tree(x_or)
+    m64, v64 = mu.astype(np.float64), v.astype(np.float64)
+    t1, mag1, _ = T.apply("T", m64, w, c, with_stats=True, tvec=v64)
+    t2, mag2, _ = T.apply("T", v64, w, c, with_stats=True, tvec=m64)
+    assert np.all(np.isfinite(got))
+    ref = t1 + t2
+    rel = np.linalg.norm(got.astype(np.float64) - ref, axis=1) / np.maximum(mag1 + mag2, 1e-300)
+    frac = (rel > TOL).mean()
+    print(f"  frac>tol={frac:.2e} max_rel={rel.max():.2e}", flush=True)
+    assert frac <= MAX_FLIP_FRAC
+    return ref
+
+
+@pytest.mark.parametrize("name", ["sphere2k", "ragged3077", "knot20k"])
+def test_gradient_grad_x_matches_oracle_treecode(dev, name, oracle_mod):
+    cloud = {"sphere2k": lambda: synth.fibonacci_sphere(2000, 0),
+             "ragged3077": lambda: synth.ellipsoid_union(3077, 9, noise=0.001, with_init=False),
+             "knot20k": lambda: synth.torus_knot(20000, 5, with_init=False)}[name]()
+    print(f"[case] grad F position gradient {name}", flush=True)
+    ctx, _, x_or, sc = _setup(dev, cloud)
+    mu, _ = _inputs(cloud, sc, 31)
+    v = np.random.default_rng(32).standard_normal((cloud.n, 3)).astype(np.float32)
+    for w_ in (0.002, 0.016):
+        got = ctx.gradient_grad_x(_t(mu, dev), w_, _t(v, dev)).cpu().numpy()
+        _check_t(got, x_or, mu, v, w_, 2.0, oracle_mod)
+    ctx.close()
+
+
+def test_gradient_grad_x_exact_limit_and_autograd(dev, oracle_mod):
+    import torch
+    from paper_2405_16634_amd.autograd import gradient_at_points
+    cloud = synth.fibonacci_sphere(2000, 0)
+    print("[case] grad F position gradient exact limit + autograd", flush=True)
+    ctx, x_dev, x_or, sc = _setup(dev, cloud, c=1e6)
+    mu, _ = _inputs(cloud, sc, 33)
+    v = np.random.default_rng(34).standard_normal((cloud.n, 3)).astype(np.float32)
+    got = ctx.gradient_grad_x(_t(mu, dev), 0.002, _t(v, dev)).cpu().numpy().astype(np.float64)
+    ref = oracle_mod.gradient_grad_x(x_or, mu.astype(np.float64), v.astype(np.float64), 0.002)
+    _check_t(got, x_or, mu, v, 0.002, 1e6, oracle_mod)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-5
+    # autograd at c = 2
+    x = x_dev.clone().requires_grad_(True)
+    m = _t(mu, dev).requires_grad_(True)
+    gF = gradient_at_points(ctx, x, m, 0.002)
+    (gF * _t(v, dev)).sum().backward()
+    assert torch.equal(x.grad, ctx.gradient_grad_x(_t(mu, dev), 0.002, _t(v, dev)))
+    assert torch.equal(m.grad, ctx.gradient(_t(v, dev), 0.002))
+    _check_t(x.grad.cpu().numpy(), x_or, mu, v, 0.002, 2.0, oracle_mod)
+    ctx.close()
