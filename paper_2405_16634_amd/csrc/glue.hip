@@ -14,26 +14,32 @@ __global__ __launch_bounds__(256) void k_alpha(const double *__restrict__ partia
                                                const int64_t *__restrict__ off, int first,
                                                double *__restrict__ alpha,
                                                double *__restrict__ energy_row) {
-    __shared__ double sh[3][256];
+    // per thread a strided sum, per wavefront a butterfly, then the four
+    // wavefront sums in order: a fixed order, so the result is reproducible
+    __shared__ double sh[3][256 / kWave];
     const int c = blockIdx.x;
     const int lo = task_lo[c], hi = task_lo[c + 1];
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     double acc[3] = {0.0, 0.0, 0.0};
     for (int i = lo + threadIdx.x; i < hi; i += 256) {
         if (!first) acc[0] += partial[i];
         acc[1] += partial[nslots + i];
         acc[2] += partial[2 * nslots + i];
     }
-    for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] = acc[k];
-    __syncthreads();
-    for (int d = 128; d > 0; d >>= 1) {
-        if (threadIdx.x < d)
-            for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + d];
-        __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+#pragma unroll
+        for (int d = kWave / 2; d > 0; d >>= 1) acc[k] += __shfl_xor(acc[k], d, kWave);
+        if (lane == 0) sh[k][wv] = acc[k];
     }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        const double r2 = sh[1][0], t2 = sh[2][0];
+        double tot[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) tot[k] = (sh[k][0] + sh[k][1]) + (sh[k][2] + sh[k][3]);
+        const double r2 = tot[1], t2 = tot[2];
         alpha[c] = t2 > 0.0 ? r2 / t2 : 0.0;
-        if (energy_row) energy_row[c] = first ? 0.25 * (double)(off[c + 1] - off[c]) : sh[0][0];
+        if (energy_row) energy_row[c] = first ? 0.25 * (double)(off[c + 1] - off[c]) : tot[0];
     }
 }
 
