@@ -239,6 +239,7 @@ wnnc_status wnnc_destroy(wnnc_ctx ctx) {
     ctx->task_slot.release();
     ctx->task_lo.release();
     ctx->knn_groups.release();
+    ctx->knn_tmp.release();
     ctx->areas.release();
     ctx->momhi.release();
     ctx->gradf.release();
@@ -337,11 +338,7 @@ wnnc_status wnnc_normalize_batched(wnnc_ctx ctx, const float *P, const int64_t *
 static hipError_t plan_walks(wnnc_ctx_s *ctx) {
     ctx->plan.clear();
     TRY(make_tasks(ctx, 1, 0));
-    // the same 64-point groups (whole walks) serve the neighbour search
-    TRY(ctx->knn_groups.ensure(ctx->ntasks));
-    TRY(hipMemcpyAsync(ctx->knn_groups.p, ctx->tasks.p, (size_t)ctx->ntasks * sizeof(int4),
-                       hipMemcpyDeviceToDevice, ctx->stream));
-    ctx->knn_ngroups = ctx->ntasks;
+    ctx->knn_ngroups = 0;  // the neighbour search builds its groups on first use
     const int64_t len = (int64_t)ctx->ngroups * kPlanStride;
     TRY(ctx->d_plan.ensure(len));
     TRY(hipMemsetAsync(ctx->d_plan.p, 0, (size_t)len * sizeof(int32_t), ctx->stream));

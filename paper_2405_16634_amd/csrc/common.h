@@ -124,8 +124,9 @@ struct wnnc_ctx_s {
     DevBuf<unsigned long long> pair_ctr;  // one counter per operator kind
 
     // warm start: neighbours, features, MLP activations and scratch
-    DevBuf<int4> knn_groups;       // 64-point groups of every cloud (first, last; root, end)
-    int knn_ngroups = 0;
+    DevBuf<int4> knn_groups;       // neighbour-search groups (first, last; root, end)
+    int knn_ngroups = 0;           // 0: not built for the current tree
+    DevBuf<uint32_t> knn_tmp;      // 4 n: group construction
     DevBuf<int32_t> knn_idx;       // n * 16 sorted neighbour positions
     DevBuf<float> knn_d2;          // n * 16 squared distances
     DevBuf<float> feat;            // n * 48 features (caller order)

@@ -219,12 +219,96 @@ __global__ __launch_bounds__(256) void k_features(const float4 *__restrict__ pts
     }
 }
 
+// Neighbour-search groups: runs of sorted points inside one octree cell of
+// depth kKnnGroupDepth (so of one cloud), cut every 64 points.  A wavefront
+// walks the union of its lanes' search balls; capping the cell keeps that
+// union small where points are sparse (64 Morton-consecutive isolated
+// points can span much of the cloud's box), at the price of partly filled
+// wavefronts there.
+constexpr int kKnnGroupDepth = 6;
+
+__global__ __launch_bounds__(256) void k_knn_brk(const unsigned long long *__restrict__ keys,
+                                                 int n, uint32_t *__restrict__ brk) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int sh = 3 * (kMaxDepth - kKnnGroupDepth);  // the cloud index sits above the key
+    brk[i] = (i == 0 || (keys[i] >> sh) != (keys[i - 1] >> sh)) ? 1u : 0u;
+}
+
+// run starts: runs[r] = first point of run r (rx = exclusive scan of brk)
+__global__ __launch_bounds__(256) void k_knn_runs(const uint32_t *__restrict__ brk,
+                                                  const uint32_t *__restrict__ rx, int n,
+                                                  uint32_t *__restrict__ runs) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n && brk[i]) runs[rx[i]] = (uint32_t)i;
+}
+
+// group starts: every 64th point of its run
+__global__ __launch_bounds__(256) void k_knn_gflag(const uint32_t *__restrict__ brk,
+                                                   const uint32_t *__restrict__ rx,
+                                                   const uint32_t *__restrict__ runs, int n,
+                                                   uint32_t *__restrict__ gs) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t r = rx[i] + brk[i] - 1u;
+    gs[i] = ((i - (int)runs[r]) & (kWave - 1)) == 0 ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(256) void k_knn_groups(const uint32_t *__restrict__ brk,
+                                                    const uint32_t *__restrict__ rx,
+                                                    const uint32_t *__restrict__ runs,
+                                                    const uint32_t *__restrict__ gs,
+                                                    const uint32_t *__restrict__ gx, int n,
+                                                    const int32_t *__restrict__ cloud,
+                                                    const int32_t *__restrict__ roots,
+                                                    int4 *__restrict__ groups,
+                                                    uint32_t *__restrict__ count) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    if (i == n - 1) {
+        count[0] = gx[i] + gs[i];
+    }
+    if (!gs[i]) return;
+    const uint32_t r = rx[i] + brk[i] - 1u;
+    const uint32_t nruns = rx[n - 1] + brk[n - 1];
+    const int run_end = r + 1u < nruns ? (int)runs[r + 1] : n;
+    const int c = cloud[i];
+    groups[gx[i]] = make_int4(i, min(i + kWave, run_end), roots[c], roots[c + 1]);
+}
+
+static hipError_t knn_groups(wnnc_ctx_s *ctx) {
+    const int n = (int)ctx->n;
+    hipStream_t st = ctx->stream;
+    hipError_t e = ctx->knn_tmp.ensure(5 * (int64_t)n + 1);
+    if (e != hipSuccess) return e;
+    uint32_t *brk = ctx->knn_tmp.p, *rx = brk + n, *runs = rx + n, *gs = runs + n, *gx = gs + n;
+    uint32_t *cnt = gx + n;
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_knn_brk, dim3(nb), dim3(256), 0, st, ctx->keys_a.p, n, brk);
+    if ((e = exclusive_scan_u32(brk, rx, n, ctx->scan_tmp.p, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_knn_runs, dim3(nb), dim3(256), 0, st, brk, rx, n, runs);
+    hipLaunchKernelGGL(k_knn_gflag, dim3(nb), dim3(256), 0, st, brk, rx, runs, n, gs);
+    if ((e = exclusive_scan_u32(gs, gx, n, ctx->scan_tmp.p, st)) != hipSuccess) return e;
+    // at most one group per point
+    if ((e = ctx->knn_groups.ensure(n)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_knn_groups, dim3(nb), dim3(256), 0, st, brk, rx, runs, gs, gx, n,
+                       ctx->cloud_of.p, ctx->d_roots.p, ctx->knn_groups.p, cnt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    uint32_t ng = 0;
+    if ((e = hipMemcpyAsync(&ng, cnt, sizeof(ng), hipMemcpyDeviceToHost, st)) != hipSuccess)
+        return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    ctx->knn_ngroups = (int)ng;
+    return hipSuccess;
+}
+
 hipError_t launch_knn(wnnc_ctx_s *ctx) {
     const int n = (int)ctx->n;
     hipError_t e = ctx->knn_idx.ensure((int64_t)n * kK);
     if (e != hipSuccess) return e;
     e = ctx->knn_d2.ensure((int64_t)n * kK);
     if (e != hipSuccess) return e;
+    if (ctx->knn_ngroups == 0 && (e = knn_groups(ctx)) != hipSuccess) return e;
     if (ctx->knn_ngroups > 0)
         hipLaunchKernelGGL(k_knn, dim3((unsigned)ctx->knn_ngroups), dim3(kWave), 0, ctx->stream,
                            ctx->pts.p, ctx->cells.p, ctx->topo.p, ctx->knn_groups.p,
