@@ -389,7 +389,7 @@ wnnc_status wnnc_mlp_adam(wnnc_ctx ctx, float *params, float *m, float *v, const
 
 /* Warm-started orientation options (defaults in brackets). */
 typedef struct {
-    int iters;            /* iterations of the warm schedule [8] */
+    int iters;            /* iterations of the warm schedule [6] */
     float w1, w2;         /* warm schedule widths, w2 first [0.002, 0.016]:
                              the plain schedule compressed into `iters` */
     float max_disagree;   /* self-check: largest tolerated fraction of points

@@ -401,7 +401,7 @@ def wnnc_mlp_adam(ctx, params, m, v, grad, step: int, lr: float = 1e-3, beta1: f
                                         float(lr), float(beta1), float(beta2), float(eps)))
 
 
-def wnnc_warm_orient(ctx, params, mu_out, iters: int = 8, w1: float = 0.002, w2: float = 0.016,
+def wnnc_warm_orient(ctx, params, mu_out, iters: int = 6, w1: float = 0.002, w2: float = 0.016,
                      max_disagree: float = 0.005, fallback_iters: int = 40,
                      fallback_w2: float = 0.016, max_pred_disagree: float = 0.4) -> dict:
     N = mu_out.shape[0]

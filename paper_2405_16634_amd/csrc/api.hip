@@ -857,7 +857,7 @@ wnnc_status wnnc_warm_orient(wnnc_ctx ctx, const float *params, const wnnc_warm_
     CHECK_CTX(ctx);
     CHECK_BUILT(ctx);
     if (!params || !mu_out) return fail(WNNC_EINVAL, "null pointer");
-    wnnc_warm_opts o = {8, 0.002f, 0.016f, 0.005f, 40, 0.016f, 0.4f};
+    wnnc_warm_opts o = {6, 0.002f, 0.016f, 0.005f, 40, 0.016f, 0.4f};
     if (opts) o = *opts;
     if (o.iters < 1 || o.fallback_iters < 1) return fail(WNNC_EINVAL, "iteration counts must be >= 1");
     if (!finite_nonneg(o.w1) || !finite_nonneg(o.w2) || !finite_nonneg(o.fallback_w2))
