@@ -26,6 +26,14 @@
  * are visited (a leaf sums its points directly).  Nodes whose attributes are
  * all zero are skipped.
  *
+ * Beyond the paper (each call documents its own definition): many clouds in
+ * one forest (wnnc_build_batched), the winding number at query points
+ * (wnnc_winding_at), a far field of higher order and a cutoff-safe
+ * acceptance (wnnc_set_far_field), other width schedules and fixed areas
+ * (wnnc_orient_opts), kNN local areas (wnnc_knn_areas), position gradients
+ * (wnnc_winding_grad_x, wnnc_gradient_grad_x) and a learned warm start
+ * (wnnc_warm_orient).
+ *
  * Conventions
  * -----------
  * * Every float pointer is a DEVICE pointer to contiguous FP32 data owned by
