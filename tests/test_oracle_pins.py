@@ -618,3 +618,32 @@ def test_gradient_grad_x_matches_finite_differences(oracle_mod):
         assert np.abs(gx.sum(axis=0)).max() <= 1e-12 * np.abs(gx).max()
         big = oracle_mod.gradient_grad_x(x, mu, v, w, backend="tree", c=1e6)
         assert np.abs(big - gx).max() <= 1e-12 * np.abs(gx).max()
+
+
+# ------------------------------------- leaves of more than one point (extension)
+
+def test_leaf_capacity_tree_invariants(oracle_mod):
+    """With leaf capacity K every leaf holds at most K points (or sits at the
+    depth limit), every internal node more than K, children partition their
+    parent; K >= N leaves the root alone, and then the treecode is the exact
+    sum (no target in [-1,1]^3 is farther than c * 2 = 4 from x_B)."""
+    rng = np.random.default_rng(8)
+    x = rng.uniform(-0.9, 0.9, (700, 3))
+    x[:40] = x[0]  # coincident points beyond every K below
+    for K in (2, 8, 33):
+        T = oracle_mod.Tree(x, leaf_cap=K)
+        d, leaf, b, e, order = T.export()
+        cnt = e - b
+        assert np.all((cnt[leaf == 1] <= K) | (d[leaf == 1] == 15))
+        assert np.all(cnt[leaf == 0] > K)
+        assert np.all(cnt[leaf == 1] >= 1)
+        # the leaves partition the points
+        assert np.array_equal(np.sort(np.concatenate([order[bb:ee] for bb, ee, l in
+                                                     zip(b, e, leaf) if l])), np.arange(len(x)))
+    T = oracle_mod.Tree(x, leaf_cap=len(x))
+    assert T.nnodes == 1
+    mu = rng.standard_normal((len(x), 3))
+    for op, nu in (("A", mu), ("G", mu), ("AT", rng.standard_normal(len(x)))):
+        tc = T.apply(op, nu, 0.01, 2.0)
+        ex = oracle_mod.direct(op, x, nu, 0.01)
+        assert np.allclose(tc, ex, rtol=1e-12, atol=1e-12 * np.abs(ex).max())
