@@ -171,6 +171,49 @@ def far_field_section(ctx, w, step, mu, stream, steps, normals):
             "P_co": round(pco, 5)}
 
 
+def leaf_cap_section(w, P, stream, iters, w1, w2, c, depth, steps, normals, K=8):
+    """The same step on a tree whose leaves hold up to K points (an
+    extension: the paper splits down to single points); the targets that do
+    not accept such a leaf sum its points directly."""
+    import torch
+    ctx = w.Context(0, stream)
+    Pn = torch.empty_like(P)
+    mu = torch.empty_like(P)
+    nrm = torch.empty_like(P)
+
+    def step():
+        cs = w.wnnc_normalize(ctx.handle, P, Pn)
+        w.wnnc_build(ctx.handle, Pn, c, depth, K)
+        w.wnnc_orient(ctx.handle, mu, None, iters, w1, w2)
+        w.wnnc_normals(ctx.handle, mu, cs[1], nrm)
+
+    w.wnnc_normalize(ctx.handle, P, Pn)
+    w.wnnc_build(ctx.handle, Pn, c, depth, K)
+    ctx.autotune(w1)
+    ctx.set_flags(w.FLAG_COUNT_PAIRS)
+    ctx.reset_stats()
+    step()
+    torch.cuda.synchronize()
+    pairs = int(sum(ctx.stats()["pairs"][:3]))
+    ctx.set_flags(0)
+    step()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    m = nrm.cpu().numpy()
+    ok = np.isfinite(normals).all(axis=1)
+    pco = float(((m[ok] * normals[ok]).sum(1) > 0).mean())
+    ctx.close()
+    return {"leaf_cap": K, "ms_per_step": round(ms, 3), "pairs_per_step": pairs,
+            "gpairs_per_s": round(pairs / (ms * 1e-3) / 1e9, 3), "P_co": round(pco, 5)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -306,6 +349,8 @@ def main():
     pco = float(((nrm_h[ok] * cloud.normals[ok]).sum(1) > 0).mean())
     ae = float(((1.0 - (nrm_h[ok] * cloud.normals[ok]).sum(1)) / 2.0).mean())
     far = far_field_section(ctx, w, step, mu, stream, max(1, min(args.steps, 3)), cloud.normals)
+    leaf = leaf_cap_section(w, P, stream, args.iters, w1, w2, c, depth, max(1, min(args.steps, 3)),
+                            cloud.normals)
 
     out = {
         "metric": METRIC,
@@ -343,6 +388,7 @@ def main():
         "roofline": roofline,
         "warm_start": warm,
         "far_field_order2_wsafe": far,
+        "tree_leaf_cap_8": leaf,
     }
     if rank == 0 and not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cloud, w1, c)

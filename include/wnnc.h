@@ -74,6 +74,10 @@ typedef enum {
 typedef struct {
     float c;        /* acceptance threshold c > 0 [2] */
     int max_depth;  /* maximum octree depth D, 1..15 [15] */
+    int leaf_cap;   /* a node is split while it holds more than leaf_cap
+                       points (and is shallower than D), 1..256 [1: the
+                       paper's tree]; larger leaves are summed directly by
+                       the targets that do not accept them (an extension) */
 } wnnc_tree_opts;
 
 /* Alg. 3 options (Sec. 5.1.1 defaults in brackets). */

@@ -49,7 +49,7 @@ class WnncError(RuntimeError):
 
 
 class TreeOpts(ctypes.Structure):
-    _fields_ = [("c", ctypes.c_float), ("max_depth", ctypes.c_int)]
+    _fields_ = [("c", ctypes.c_float), ("max_depth", ctypes.c_int), ("leaf_cap", ctypes.c_int)]
 
 
 class OrientOpts(ctypes.Structure):
@@ -236,10 +236,11 @@ def wnnc_normalize_batched(ctx, P, P_norm, offsets):
     return [((cs[4 * k], cs[4 * k + 1], cs[4 * k + 2]), cs[4 * k + 3]) for k in range(B)]
 
 
-def wnnc_build_batched(ctx, P, offsets, c: float = 2.0, max_depth: int = 15) -> None:
+def wnnc_build_batched(ctx, P, offsets, c: float = 2.0, max_depth: int = 15,
+                       leaf_cap: int = 1) -> None:
     n = P.shape[0]
     off, B = _offsets(offsets)
-    opts = TreeOpts(float(c), int(max_depth))
+    opts = TreeOpts(float(c), int(max_depth), int(leaf_cap))
     _check(load_library().wnnc_build_batched(ctx, _dev(P, "P", shape=(n, 3)), off, B,
                                              ctypes.byref(opts)))
 
@@ -276,9 +277,9 @@ def wnnc_autotune(ctx, w: float = 0.002):
     return {(r.tpl, r.prefetch, r.split): r.ms for r in out}
 
 
-def wnnc_build(ctx, P, c: float = 2.0, max_depth: int = 15) -> None:
+def wnnc_build(ctx, P, c: float = 2.0, max_depth: int = 15, leaf_cap: int = 1) -> None:
     n = P.shape[0]
-    opts = TreeOpts(float(c), int(max_depth))
+    opts = TreeOpts(float(c), int(max_depth), int(leaf_cap))
     _check(load_library().wnnc_build(ctx, _dev(P, "P", shape=(n, 3)), n, ctypes.byref(opts)))
 
 
@@ -508,8 +509,8 @@ class Context:
         c, s = wnnc_normalize(self._h, P, out)
         return out, Normalization(c, s)
 
-    def build(self, P_norm, c: float = 2.0, max_depth: int = 15) -> None:
-        wnnc_build(self._h, P_norm, c, max_depth)
+    def build(self, P_norm, c: float = 2.0, max_depth: int = 15, leaf_cap: int = 1) -> None:
+        wnnc_build(self._h, P_norm, c, max_depth, leaf_cap)
         self.n = int(P_norm.shape[0])
         self.nclouds = 1
 
@@ -518,8 +519,9 @@ class Context:
         cs = wnnc_normalize_batched(self._h, P, out, offsets)
         return out, [Normalization(c, s) for c, s in cs]
 
-    def build_batched(self, P_norm, offsets, c: float = 2.0, max_depth: int = 15) -> None:
-        wnnc_build_batched(self._h, P_norm, offsets, c, max_depth)
+    def build_batched(self, P_norm, offsets, c: float = 2.0, max_depth: int = 15,
+                      leaf_cap: int = 1) -> None:
+        wnnc_build_batched(self._h, P_norm, offsets, c, max_depth, leaf_cap)
         self.n = int(P_norm.shape[0])
         self.nclouds = len(offsets) - 1
 

@@ -364,15 +364,17 @@ static wnnc_status build_impl(wnnc_ctx ctx, const float *P, const int64_t *offse
     int64_t N = 0;
     RETURN_IF(check_offsets(offsets, B, &N));
     if (!P) return fail(WNNC_EINVAL, "null point pointer");
-    wnnc_tree_opts o = {2.0f, 15};
+    wnnc_tree_opts o = {2.0f, 15, 1};
     if (opts) o = *opts;
     if (!(isfinite(o.c) && o.c > 0.0f)) return fail(WNNC_EINVAL, "c must be finite and > 0");
     if (o.max_depth < 1 || o.max_depth > kMaxDepth)
         return fail(WNNC_EINVAL, "max_depth must be in 1..15");
+    if (o.leaf_cap < 1 || o.leaf_cap > 256) return fail(WNNC_EINVAL, "leaf_cap must be in 1..256");
     ctx->built = false;
     ctx->n = N;
     ctx->c = o.c;
     ctx->depth = o.max_depth;
+    ctx->leaf_cap = o.leaf_cap;
     ctx->nclouds = B;
     ctx->offsets.assign(offsets, offsets + B + 1);
     HIPCHK(ctx->d_offsets.ensure(B + 1));

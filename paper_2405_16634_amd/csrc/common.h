@@ -47,6 +47,7 @@ struct wnnc_ctx_s {
     int64_t n = 0, m = 0;
     float c = 2.0f;
     int depth = 15;
+    int leaf_cap = 1;
     bool built = false;
 
     // tree (sorted order; nodes in depth-first pre-order)

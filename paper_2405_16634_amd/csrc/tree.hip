@@ -262,22 +262,6 @@ __device__ inline void neighbour_lcp(const unsigned long long *keys, int64_t n, 
     *R = r > D ? D : r;
 }
 
-__global__ __launch_bounds__(256) void k_count_nodes(const unsigned long long *__restrict__ keys,
-                                                     int64_t n, int D,
-                                                     uint32_t *__restrict__ counts) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > n) return;
-    if (i == n) {
-        counts[n] = 0;
-        return;
-    }
-    int L, R;
-    neighbour_lcp(keys, n, i, D, &L, &R);
-    int hi = (L > R ? L : R) + 1;
-    if (hi > D) hi = D;
-    counts[i] = L >= D ? 0u : (uint32_t)(hi - L);
-}
-
 // First sorted position after i whose key leaves the depth-d cell of key i
 // (at depth 0 the cell is the cloud: the shift keeps only the cloud bits).
 __device__ inline int64_t run_end(const unsigned long long *keys, int64_t n, int64_t i, int d) {
@@ -299,26 +283,96 @@ __device__ inline int64_t run_end(const unsigned long long *keys, int64_t n, int
     return hi;
 }
 
+// First sorted position of the run of depth-d cells that holds i (the
+// mirror of run_end).
+__device__ inline int64_t run_start(const unsigned long long *keys, int64_t i, int d) {
+    const int shift = 3 * (15 - d);
+    const unsigned long long pre = keys[i] >> shift;
+    int64_t hi = i, step = 1;
+    while (hi - step >= 0 && (keys[hi - step] >> shift) == pre) {
+        hi -= step;
+        step <<= 1;
+    }
+    int64_t lo = hi - step >= 0 ? hi - step : -1;  // keys[lo] differs, or lo == -1
+    while (hi - lo > 1) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if ((keys[mid] >> shift) == pre)
+            hi = mid;
+        else
+            lo = mid;
+    }
+    return hi;
+}
+
+// The nodes whose first point is i, outermost first (pre-order), as
+// emit(depth, end, leaf).  A node at depth d >= 1 is there when its parent
+// (the depth d-1 run holding i) holds more than K points; it is a leaf when
+// it holds at most K points or d == D.  With K = 1 (Alg. 4's tree) these
+// are the depths from one below the common prefix with the left neighbour
+// down to where i is alone, with no search.  Returns the node count.
+template <class Emit>
+__device__ inline int node_chain(const unsigned long long *keys, int64_t n, int64_t i, int D,
+                                 int K, Emit &&emit) {
+    int L, R;
+    neighbour_lcp(keys, n, i, D, &L, &R);
+    if (L >= D) return 0;
+    if (K <= 1) {
+        int hi = (L > R ? L : R) + 1;
+        if (hi > D) hi = D;
+        for (int d = L + 1; d <= hi; ++d) {
+            const int64_t end = run_end(keys, n, i, d);
+            emit(d, end, (end - i == 1) || (d == D));
+        }
+        return hi - L;
+    }
+    int cnt = 0;
+    for (int d = L + 1; d <= D; ++d) {
+        if (d >= 1) {
+            const int64_t pb = d - 1 == L ? run_start(keys, i, L) : i;
+            if (run_end(keys, n, i, d - 1) - pb <= K) break;
+        }
+        const int64_t end = run_end(keys, n, i, d);
+        const bool leaf = end - i <= K || d == D;
+        emit(d, end, leaf);
+        ++cnt;
+        if (leaf) break;
+    }
+    return cnt;
+}
+
+__global__ __launch_bounds__(256) void k_count_nodes(const unsigned long long *__restrict__ keys,
+                                                     int64_t n, int D, int K,
+                                                     uint32_t *__restrict__ counts) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    if (i == n) {
+        counts[n] = 0;
+        return;
+    }
+    if (K <= 1) {  // no run boundaries needed for the count
+        int L, R;
+        neighbour_lcp(keys, n, i, D, &L, &R);
+        int hi = (L > R ? L : R) + 1;
+        if (hi > D) hi = D;
+        counts[i] = L >= D ? 0u : (uint32_t)(hi - L);
+        return;
+    }
+    counts[i] = (uint32_t)node_chain(keys, n, i, D, K, [](int, int64_t, bool) {});
+}
+
 __global__ __launch_bounds__(256) void k_emit_nodes(const unsigned long long *__restrict__ keys,
-                                                    int64_t n, int D,
+                                                    int64_t n, int D, int K,
                                                     const uint32_t *__restrict__ node_off,
                                                     int4 *__restrict__ topo,
                                                     uint32_t *__restrict__ strad_flag) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    int L, R;
-    neighbour_lcp(keys, n, i, D, &L, &R);
-    if (L >= D) return;
-    int hi = (L > R ? L : R) + 1;
-    if (hi > D) hi = D;
-    const uint32_t base = node_off[i];
-    for (int d = L + 1; d <= hi; ++d) {
-        const uint32_t idx = base + (uint32_t)(d - (L + 1));
-        const int64_t end = run_end(keys, n, i, d);
-        const int leaf = (end - i == 1) || (d == D);
-        topo[idx] = make_int4((int)node_off[end], (int)i, (int)end, d | (leaf << 4));
+    uint32_t idx = node_off[i];
+    node_chain(keys, n, i, D, K, [&](int d, int64_t end, bool leaf) {
+        topo[idx] = make_int4((int)node_off[end], (int)i, (int)end, d | ((leaf ? 1 : 0) << 4));
         strad_flag[idx] = ((i / kChunk) != ((end - 1) / kChunk)) ? 1u : 0u;
-    }
+        ++idx;
+    });
 }
 
 __global__ __launch_bounds__(256) void k_gather_roots(const uint32_t *__restrict__ node_off,
@@ -500,7 +554,7 @@ hipError_t build_tree(wnnc_ctx_s *ctx, const float *P) {
 
     // nodes started per point -> pre-order offsets; M is read back once
     hipLaunchKernelGGL(k_count_nodes, dim3(blocks_for(n + 1, 256)), dim3(256), 0, st,
-                       ctx->keys_a.p, n, D, ctx->u32_tmp.p);
+                       ctx->keys_a.p, n, D, ctx->leaf_cap, ctx->u32_tmp.p);
     TRY(exclusive_scan_u32(ctx->u32_tmp.p, ctx->node_off.p, n + 1, ctx->scan_tmp.p, st));
     // first node of every cloud (node_off at the cloud starts); the last
     // entry is M
@@ -523,7 +577,7 @@ hipError_t build_tree(wnnc_ctx_s *ctx, const float *P) {
 
     TRY(hipMemsetAsync(ctx->mflag.p, 0, (size_t)(m + 1) * sizeof(uint32_t), st));
     hipLaunchKernelGGL(k_emit_nodes, dim3(blocks_for(n, 256)), dim3(256), 0, st, ctx->keys_a.p,
-                       n, D, ctx->node_off.p, ctx->topo.p, ctx->mflag.p);
+                       n, D, ctx->leaf_cap, ctx->node_off.p, ctx->topo.p, ctx->mflag.p);
     hipLaunchKernelGGL(k_gather_points, dim3(blocks_for(n, 256)), dim3(256), 0, st, P,
                        ctx->perm.p, n, ctx->pts.p);
     TRY(ctx->cells.ensure(m));
