@@ -214,6 +214,66 @@ def leaf_cap_section(w, P, stream, iters, w1, w2, c, depth, steps, normals, K=8)
             "gpairs_per_s": round(pairs / (ms * 1e-3) / 1e9, 3), "P_co": round(pco, 5)}
 
 
+def batched_section(w, stream, iters, w1, w2, c, depth):
+    """The 64-cloud workload (sizes log-uniform in [5k, 200k], seed 1): one
+    forest with one launch per operator and per-cloud step lengths, against
+    the same clouds run one by one (normalize, build, 40 iterations each),
+    wall time on the same GPU; equal accuracy as the flip rate between the
+    two results."""
+    import torch
+    import synth
+    sizes = synth.batched_sizes(64, 1)
+    clouds = synth.batched_clouds(64, 1, sizes)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    P = torch.from_numpy(np.concatenate([cl.points for cl in clouds])).to("cuda:0")
+    ctx = w.Context(0, stream)
+    Pn = torch.empty_like(P)
+    mu_b = torch.empty_like(P)
+
+    def batched():
+        w.wnnc_normalize_batched(ctx.handle, P, Pn, off)
+        w.wnnc_build_batched(ctx.handle, Pn, off, c, depth)
+        w.wnnc_orient(ctx.handle, mu_b, None, iters, w1, w2)
+
+    batched()
+    ctx.autotune(w1)
+    batched()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    batched()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_batched = e0.elapsed_time(e1)
+    one = w.Context(0, stream)
+    parts = [P[off[k]:off[k + 1]] for k in range(64)]
+    outs = [torch.empty_like(p_) for p_ in parts]
+    norms = [torch.empty_like(p_) for p_ in parts]
+
+    def one_by_one():
+        for p_, q_, o_ in zip(parts, norms, outs):
+            w.wnnc_normalize(one.handle, p_, q_)
+            w.wnnc_build(one.handle, q_, c, depth)
+            w.wnnc_orient(one.handle, o_, None, iters, w1, w2)
+
+    one_by_one()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    one_by_one()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_single = e0.elapsed_time(e1)
+    a = mu_b.cpu().numpy()
+    b = torch.cat(outs).cpu().numpy()
+    flip = float(((a * b).sum(1) <= 0).mean())
+    ctx.close()
+    one.close()
+    return {"clouds": 64, "points": int(off[-1]), "batched_ms": round(t_batched, 2),
+            "one_by_one_ms": round(t_single, 2), "speedup": round(t_single / t_batched, 3),
+            "flip_batched_vs_one_by_one": flip, "equal_accuracy": bool(flip <= 1e-3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -351,6 +411,7 @@ def main():
     far = far_field_section(ctx, w, step, mu, stream, max(1, min(args.steps, 3)), cloud.normals)
     leaf = leaf_cap_section(w, P, stream, args.iters, w1, w2, c, depth, max(1, min(args.steps, 3)),
                             cloud.normals)
+    batched = batched_section(w, stream, args.iters, w1, w2, c, depth)
 
     out = {
         "metric": METRIC,
@@ -389,6 +450,7 @@ def main():
         "warm_start": warm,
         "far_field_order2_wsafe": far,
         "tree_leaf_cap_8": leaf,
+        "batched64": batched,
     }
     if rank == 0 and not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cloud, w1, c)
