@@ -1,0 +1,112 @@
+"""Extensions in combination, against the oracle or against each other:
+the far field of order 2 and leaves of several points on a batched forest,
+queries and the neighbour search on a tree with leaves of several points.
+The per-target bar is the operator bar (|error| <= 1e-5 of the summed term
+magnitudes, all but 0.2 % of targets).
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+MAX_FLIP_FRAC = 2e-3
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2405_16634_amd as w
+    w.load_library()
+    return torch.device("cuda:0")
+
+
+def _t(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+
+
+def _frac(got, ref, mag):
+    assert np.all(np.isfinite(got))
+    err = np.abs(got.astype(np.float64) - ref)
+    if err.ndim == 2:
+        err = np.linalg.norm(err, axis=1)
+    ok = mag > 0
+    assert np.all(err[~ok] == 0.0)
+    return float((err[ok] / mag[ok] > TOL).mean()) if ok.any() else 0.0
+
+
+@pytest.mark.parametrize("order,wsafe,K", [(2, True, 1), (0, False, 8), (2, True, 8)])
+def test_batched_forest_matches_oracle_per_cloud(dev, order, wsafe, K, oracle_mod):
+    import torch
+    import paper_2405_16634_amd as w
+    import oracle
+    clouds = [synth.fibonacci_sphere(2000, 0).points,
+              synth.ellipsoid_union(3077, 9, noise=0.001, with_init=False).points,
+              np.repeat(np.random.default_rng(3).uniform(-1, 1, (4, 3)).astype(np.float32), 3, 0)]
+    off = np.concatenate([[0], np.cumsum([len(c) for c in clouds])]).astype(np.int64)
+    print(f"[case] batched order={order} wsafe={wsafe} K={K}", flush=True)
+    ctx = w.Context(0)
+    x, _ = ctx.normalize_batched(torch.from_numpy(np.concatenate(clouds)).to(dev), off)
+    ctx.build_batched(x, off, 2.0, 15, K)
+    ctx.set_far_field(order, wsafe)
+    rng = np.random.default_rng(11)
+    mu = (synth.random_unit(rng, int(off[-1])) * 1e-3).astype(np.float32)
+    rho = (0.5 - rng.uniform(0, 1, int(off[-1]))).astype(np.float32)
+    got = {"A": ctx.winding(_t(mu, dev), 0.002).cpu().numpy(),
+           "G": -ctx.gradient(_t(mu, dev), 0.002).cpu().numpy(),
+           "AT": ctx.adjoint(_t(rho, dev), 0.002).cpu().numpy()}
+    for c, pts in enumerate(clouds):
+        a, b = off[c], off[c + 1]
+        x_or, _, _ = oracle.normalize(pts)
+        T = oracle_mod.Tree(x_or, leaf_cap=K)
+        for op, nu in (("A", mu), ("G", mu), ("AT", rho)):
+            ref, mag, _ = T.apply(op, nu[a:b].astype(np.float64), 0.002, 2.0, with_stats=True,
+                                  order=order, wsafe=wsafe)
+            frac = _frac(got[op][a:b], ref, mag)
+            print(f"  cloud {c} {op}: frac>tol={frac:.2e}", flush=True)
+            assert frac <= MAX_FLIP_FRAC
+    ctx.close()
+
+
+def test_queries_on_leaves_of_several_points(dev, oracle_mod):
+    import paper_2405_16634_amd as w
+    import oracle
+    cloud = synth.torus_knot(20000, 5, with_init=False)
+    print("[case] queries K=8 knot20k", flush=True)
+    ctx = w.Context(0)
+    x, _ = ctx.normalize(_t(cloud.points, dev))
+    x_or, _, sc = oracle.normalize(cloud.points)
+    ctx.build(x, 2.0, 15, 8)
+    rng = np.random.default_rng(12)
+    mu = (synth.random_unit(rng, cloud.n) * (cloud.area * sc * sc / cloud.n)).astype(np.float32)
+    Q = rng.uniform(-1, 1, (2001, 3)).astype(np.float32)
+    Q[:400] = x_or[:400] + 1e-3 * rng.standard_normal((400, 3))
+    got = ctx.winding_at(_t(mu, dev), 0.002, _t(Q, dev)).cpu().numpy()
+    ref, mag, _ = oracle_mod.Tree(x_or, leaf_cap=8).apply(
+        "A", mu.astype(np.float64), 0.002, 2.0, targets=Q.astype(np.float64), with_stats=True)
+    frac = _frac(got, ref, mag)
+    print(f"  frac>tol={frac:.2e}", flush=True)
+    assert frac <= MAX_FLIP_FRAC
+    ctx.close()
+
+
+def test_neighbour_search_does_not_depend_on_the_leaves(dev):
+    """The 16 nearest neighbours are a property of the points: the same on
+    trees with single-point leaves and with leaves of up to 8 or 64 points."""
+    import paper_2405_16634_amd as w
+    cloud = synth.torus_knot(50000, 5, with_init=False)
+    print("[case] kNN vs leaf capacity knot50k", flush=True)
+    res = []
+    for K in (1, 8, 64):
+        ctx = w.Context(0)
+        x, _ = ctx.normalize(_t(cloud.points, dev))
+        ctx.build(x, 2.0, 15, K)
+        _, nbr = ctx.features(with_neighbours=True)
+        res.append(nbr.cpu().numpy())
+        ctx.close()
+    assert np.array_equal(res[0], res[1]) and np.array_equal(res[0], res[2])
