@@ -48,8 +48,9 @@
  * * Errors: every call returns a wnnc_status; on failure wnnc_last_error()
  *   gives a message (thread-local, valid until the next failing call on the
  *   thread).  Invalid arguments return WNNC_EINVAL before any work is
- *   enqueued.  Non-finite inputs are not detected and give unspecified
- *   (finite or not) results.
+ *   enqueued.  Non-finite inputs give unspecified (finite or not) results,
+ *   unless WNNC_FLAG_CHECK_FINITE is set: then they return WNNC_ENUMERIC
+ *   before any work is enqueued.
  */
 #ifndef WNNC_H
 #define WNNC_H
@@ -68,6 +69,7 @@ typedef enum {
     WNNC_ENOMEM = -2,   /* device allocation failed */
     WNNC_EDEVICE = -3,  /* a HIP runtime call or kernel launch failed */
     WNNC_ESTATE = -4,   /* no tree built yet (call wnnc_build first) */
+    WNNC_ENUMERIC = -5, /* an input holds NaN or infinity (WNNC_FLAG_CHECK_FINITE) */
 } wnnc_status;
 
 /* Treecode options (Sec. 5.1.1 defaults in brackets). */
@@ -110,6 +112,9 @@ typedef struct {
 /* Instrumentation flags (wnnc_set_flags). */
 #define WNNC_FLAG_COUNT_PAIRS 1u  /* count pair evaluations (slower kernels) */
 #define WNNC_FLAG_TIME_KERNELS 2u /* time every launch with HIP events */
+#define WNNC_FLAG_CHECK_FINITE 4u /* check every float input array for NaN and
+                                     infinity first (WNNC_ENUMERIC; each such
+                                     call then synchronizes) */
 
 /* Operator kinds, indices of the per-kind statistics. */
 #define WNNC_OP_A 0

@@ -20,9 +20,10 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libwnnc.so")
 
-WNNC_OK, WNNC_EINVAL, WNNC_ENOMEM, WNNC_EDEVICE, WNNC_ESTATE = 0, -1, -2, -3, -4
+WNNC_OK, WNNC_EINVAL, WNNC_ENOMEM, WNNC_EDEVICE, WNNC_ESTATE, WNNC_ENUMERIC = 0, -1, -2, -3, -4, -5
 FLAG_COUNT_PAIRS = 1
 FLAG_TIME_KERNELS = 2
+FLAG_CHECK_FINITE = 4
 OP_A, OP_AT, OP_G = 0, 1, 2
 
 EXPORTED = [

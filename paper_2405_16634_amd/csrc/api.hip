@@ -282,9 +282,24 @@ wnnc_status wnnc_set_stream(wnnc_ctx ctx, void *stream) {
 
 wnnc_status wnnc_set_flags(wnnc_ctx ctx, unsigned flags) {
     CHECK_CTX(ctx);
-    if (flags & ~(WNNC_FLAG_COUNT_PAIRS | WNNC_FLAG_TIME_KERNELS))
+    if (flags & ~(WNNC_FLAG_COUNT_PAIRS | WNNC_FLAG_TIME_KERNELS | WNNC_FLAG_CHECK_FINITE))
         return fail(WNNC_EINVAL, "unknown flags 0x%x", flags);
     ctx->flags = flags;
+    return WNNC_OK;
+}
+
+// With WNNC_FLAG_CHECK_FINITE: WNNC_ENUMERIC if any of the n floats at p
+// (device) is NaN or infinite (synchronizes); WNNC_OK otherwise, and always
+// without the flag or for a null p.
+static wnnc_status check_finite(wnnc_ctx_s *ctx, const float *p, int64_t n, const char *name) {
+    if (!(ctx->flags & WNNC_FLAG_CHECK_FINITE) || !p || n <= 0) return WNNC_OK;
+    HIPCHK(ctx->finite_flag.ensure(1));
+    HIPCHK(hipMemsetAsync(ctx->finite_flag.p, 0, sizeof(uint32_t), ctx->stream));
+    HIPCHK(launch_check_finite(p, n, ctx->finite_flag.p, ctx->stream));
+    uint32_t bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, ctx->finite_flag.p, sizeof(bad), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (bad) return fail(WNNC_ENUMERIC, "%s holds a NaN or an infinity", name);
     return WNNC_OK;
 }
 
@@ -304,6 +319,7 @@ static wnnc_status normalize_impl(wnnc_ctx ctx, const float *P, const int64_t *o
     int64_t N = 0;
     RETURN_IF(check_offsets(offsets, B, &N));
     if (!P || !P_norm) return fail(WNNC_EINVAL, "null point pointer");
+    RETURN_IF(check_finite(ctx, P, 3 * N, "P"));
     HIPCHK(ctx->norm_tmp.ensure(normalize_tmp_doubles(B)));
     HIPCHK(ctx->norm_off.ensure(B + 1));
     HIPCHK(hipMemcpyAsync(ctx->norm_off.p, offsets, (size_t)(B + 1) * sizeof(int64_t),
@@ -370,6 +386,7 @@ static wnnc_status build_impl(wnnc_ctx ctx, const float *P, const int64_t *offse
     if (o.max_depth < 1 || o.max_depth > kMaxDepth)
         return fail(WNNC_EINVAL, "max_depth must be in 1..15");
     if (o.leaf_cap < 1 || o.leaf_cap > 256) return fail(WNNC_EINVAL, "leaf_cap must be in 1..256");
+    RETURN_IF(check_finite(ctx, P, 3 * N, "P"));
     ctx->built = false;
     ctx->n = N;
     ctx->c = o.c;
@@ -548,6 +565,8 @@ wnnc_status wnnc_winding(wnnc_ctx ctx, const float *n, const float *sigma, float
     CHECK_BUILT(ctx);
     if (!n || !s_out) return fail(WNNC_EINVAL, "null pointer");
     if (!finite_nonneg(w)) return fail(WNNC_EINVAL, "w must be finite and >= 0");
+    RETURN_IF(check_finite(ctx, n, 3 * ctx->n, "n"));
+    RETURN_IF(check_finite(ctx, sigma, ctx->n, "sigma"));
     MomArgs ma = mom_args(ctx, w);
     ma.cn = n;
     ma.csig = sigma;
@@ -567,6 +586,9 @@ wnnc_status wnnc_winding_at(wnnc_ctx ctx, const float *n, const float *sigma, fl
     if (M < 1 || M > INT32_MAX - 1) return fail(WNNC_EINVAL, "M = %lld out of range", (long long)M);
     if (!finite_nonneg(w)) return fail(WNNC_EINVAL, "w must be finite and >= 0");
     if (ctx->nclouds != 1) return fail(WNNC_EINVAL, "queries need a tree of one cloud");
+    RETURN_IF(check_finite(ctx, n, 3 * ctx->n, "n"));
+    RETURN_IF(check_finite(ctx, sigma, ctx->n, "sigma"));
+    RETURN_IF(check_finite(ctx, Q, 3 * M, "Q"));
     hipStream_t st = ctx->stream;
     MomArgs ma = mom_args(ctx, w);
     ma.cn = n;
@@ -618,6 +640,8 @@ wnnc_status wnnc_gradient(wnnc_ctx ctx, const float *n, const float *sigma, floa
     CHECK_BUILT(ctx);
     if (!n || !grad_out) return fail(WNNC_EINVAL, "null pointer");
     if (!finite_nonneg(w)) return fail(WNNC_EINVAL, "w must be finite and >= 0");
+    RETURN_IF(check_finite(ctx, n, 3 * ctx->n, "n"));
+    RETURN_IF(check_finite(ctx, sigma, ctx->n, "sigma"));
     MomArgs ma = mom_args(ctx, w);
     ma.cn = n;
     ma.csig = sigma;
@@ -635,6 +659,9 @@ wnnc_status wnnc_winding_grad_x(wnnc_ctx ctx, const float *n, const float *sigma
     CHECK_BUILT(ctx);
     if (!n || !g || !dx_out) return fail(WNNC_EINVAL, "null pointer");
     if (!finite_nonneg(w)) return fail(WNNC_EINVAL, "w must be finite and >= 0");
+    RETURN_IF(check_finite(ctx, n, 3 * ctx->n, "n"));
+    RETURN_IF(check_finite(ctx, sigma, ctx->n, "sigma"));
+    RETURN_IF(check_finite(ctx, g, ctx->n, "g"));
     const int64_t N = ctx->n;
     HIPCHK(ctx->gradf.ensure(3 * N));
     // grad F(x_k; mu), caller order
@@ -671,6 +698,9 @@ wnnc_status wnnc_gradient_grad_x(wnnc_ctx ctx, const float *n, const float *sigm
     CHECK_BUILT(ctx);
     if (!n || !v || !dx_out) return fail(WNNC_EINVAL, "null pointer");
     if (!finite_nonneg(w)) return fail(WNNC_EINVAL, "w must be finite and >= 0");
+    RETURN_IF(check_finite(ctx, n, 3 * ctx->n, "n"));
+    RETURN_IF(check_finite(ctx, sigma, ctx->n, "sigma"));
+    RETURN_IF(check_finite(ctx, v, 3 * ctx->n, "v"));
     const int64_t N = ctx->n;
     hipStream_t st = ctx->stream;
     HIPCHK(ctx->gradf.ensure(3 * N));
@@ -708,6 +738,7 @@ wnnc_status wnnc_adjoint(wnnc_ctx ctx, const float *s, float w, float *out) {
     CHECK_BUILT(ctx);
     if (!s || !out) return fail(WNNC_EINVAL, "null pointer");
     if (!finite_nonneg(w)) return fail(WNNC_EINVAL, "w must be finite and >= 0");
+    RETURN_IF(check_finite(ctx, s, ctx->n, "s"));
     MomArgs ma = mom_args(ctx, w);
     ma.cs = s;
     ma.outs = ctx->rho.p;
@@ -835,6 +866,8 @@ wnnc_status wnnc_orient(wnnc_ctx ctx, const wnnc_orient_opts *opts, const float 
         return fail(WNNC_EINVAL, "stop_iter must be 0 or in start_iter..iters");
     if (!finite_nonneg(o.w1) || !finite_nonneg(o.w2))
         return fail(WNNC_EINVAL, "widths must be finite and >= 0");
+    RETURN_IF(check_finite(ctx, mu0, 3 * ctx->n, "mu0"));
+    RETURN_IF(check_finite(ctx, o.areas, ctx->n, "areas"));
     const int64_t N = ctx->n;
     hipStream_t st = ctx->stream;
     const bool zero = mu0 == nullptr;
@@ -859,6 +892,7 @@ wnnc_status wnnc_warm_orient(wnnc_ctx ctx, const float *params, const wnnc_warm_
     CHECK_CTX(ctx);
     CHECK_BUILT(ctx);
     if (!params || !mu_out) return fail(WNNC_EINVAL, "null pointer");
+    RETURN_IF(check_finite(ctx, params, kMlpParams, "params"));
     wnnc_warm_opts o = {6, 0.002f, 0.016f, 0.005f, 40, 0.016f, 0.4f};
     if (opts) o = *opts;
     if (o.iters < 1 || o.fallback_iters < 1) return fail(WNNC_EINVAL, "iteration counts must be >= 1");

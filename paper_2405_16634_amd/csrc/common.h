@@ -115,6 +115,7 @@ struct wnnc_ctx_s {
     DevBuf<float> rho;
     DevBuf<float> areas;
     DevBuf<float> momhi;           // far-field moments (far_order >= 1)
+    DevBuf<uint32_t> finite_flag;  // WNNC_FLAG_CHECK_FINITE result
     DevBuf<float> gradf;           // caller-order grad F for the position gradient
     int far_order = 0;             // 0: Alg. 4's representative term; 1, 2: Taylor orders
     int far_wsafe = 0;             // accept a node only when its cell is beyond w           // fixed areas (sorted), when an orientation uses them

@@ -43,6 +43,24 @@ __global__ __launch_bounds__(256) void k_alpha(const double *__restrict__ partia
     }
 }
 
+// flag <- 1 if any of the n floats is NaN or infinite (every writer
+// stores the same value, so the race is benign)
+__global__ __launch_bounds__(256) void k_check_finite(const float *__restrict__ a, int64_t n,
+                                                      uint32_t *__restrict__ flag) {
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        bad |= !isfinite(a[i]);
+    if (__ballot(bad) != 0ull && (threadIdx.x & (kWave - 1)) == 0) *flag = 1u;
+}
+
+hipError_t launch_check_finite(const float *a, int64_t n, uint32_t *flag, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_check_finite, dim3((unsigned)(blocks < 1024 ? blocks : 1024)), dim3(256),
+                       0, st, a, n, flag);
+    return hipGetLastError();
+}
+
 hipError_t launch_alpha(wnnc_ctx_s *ctx, bool first, double *energy_row) {
     hipLaunchKernelGGL(k_alpha, dim3(ctx->nclouds), dim3(256), 0, ctx->stream, ctx->partial.p,
                        ctx->ngroups, ctx->task_lo.p, ctx->d_offsets.p, first ? 1 : 0,

@@ -58,6 +58,7 @@ hipError_t launch_zero_f4(float4 *p, int64_t n, hipStream_t st);
 hipError_t launch_gather_vec(const float *src, const uint32_t *perm, float4 *dst, int64_t n,
                              hipStream_t st);
 // dst[i] = src[perm[i]] (caller order to sorted order)
+hipError_t launch_check_finite(const float *a, int64_t n, uint32_t *flag, hipStream_t st);
 hipError_t launch_gather_scalar(const float *src, const uint32_t *perm, float *dst, int64_t n,
                                 hipStream_t st);
 hipError_t launch_scatter_vec(const float4 *src, const uint32_t *perm, float *dst, int64_t n,
