@@ -82,12 +82,10 @@ def cpu_baseline(cloud, w: float, c: float):
 
 
 def _dirs(a, b, mask):
-    """Flip rate and mean (1 - cos)/2 of directions a against b over mask
-    (rows where both are nonzero)."""
-    na, nb = np.linalg.norm(a, axis=1), np.linalg.norm(b, axis=1)
-    ok = mask & (na > 0) & (nb > 0)
-    cos = (a[ok] * b[ok]).sum(1) / (na[ok] * nb[ok])
-    return float((cos <= 0).mean()), float(((1.0 - cos) / 2.0).mean())
+    """Flip rate and AE_pcd (Sec. 5.1.4) of directions a against b over mask
+    (rows where both are nonzero and finite)."""
+    from paper_2405_16634_amd.metrics import ae_pcd, flip_rate
+    return flip_rate(a, b, mask), ae_pcd(a, b, mask)
 
 
 def warm_start_section(ctx, w, mu_plain, stream, iters, w1, w2, gt):
@@ -404,10 +402,10 @@ def main():
 
     warm = warm_start_section(ctx, w, mu, stream, args.iters, w1, w2, cloud.normals)
 
+    from paper_2405_16634_amd.metrics import ae_pcd, p_co
     nrm_h = nrm.cpu().numpy()
-    ok = np.isfinite(cloud.normals).all(axis=1)
-    pco = float(((nrm_h[ok] * cloud.normals[ok]).sum(1) > 0).mean())
-    ae = float(((1.0 - (nrm_h[ok] * cloud.normals[ok]).sum(1)) / 2.0).mean())
+    pco = p_co(nrm_h, cloud.normals)
+    ae = ae_pcd(nrm_h, cloud.normals)
     far = far_field_section(ctx, w, step, mu, stream, max(1, min(args.steps, 3)), cloud.normals)
     leaf = leaf_cap_section(w, P, stream, args.iters, w1, w2, c, depth, max(1, min(args.steps, 3)),
                             cloud.normals)

@@ -647,3 +647,4 @@ def test_leaf_capacity_tree_invariants(oracle_mod):
         tc = T.apply(op, nu, 0.01, 2.0)
         ex = oracle_mod.direct(op, x, nu, 0.01)
         assert np.allclose(tc, ex, rtol=1e-12, atol=1e-12 * np.abs(ex).max())
+
