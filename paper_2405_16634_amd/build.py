@@ -15,6 +15,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwnnc.so")
+# the hardware-rate probes: a library of their own, not part of libwnnc.so
+RATES_SRC = os.path.join(HERE, "hwrates", "rates.hip")
+RATES_LIB = os.path.join(HERE, "libwnnc_rates.so")
 OBJ = os.path.join(HERE, "_build")
 ARCH = os.environ.get("WNNC_OFFLOAD_ARCH", "gfx950")
 
@@ -46,21 +49,26 @@ def _compile(src):
     return obj, errs
 
 
+def _link(objs, lib):
+    tmp = lib + ".tmp"
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    if p.returncode != 0:
+        raise RuntimeError(f"link failed:\n{p.stderr}")
+    os.replace(tmp, lib)
+
+
 def build(verbose: bool = False) -> str:
     srcs = sources()
-    with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        results = list(ex.map(_compile, srcs))
+    with ThreadPoolExecutor(max_workers=min(8, len(srcs) + 1)) as ex:
+        results = list(ex.map(_compile, srcs + [RATES_SRC]))
     objs = [o for o, _ in results]
     if verbose:
         for o, e in results:
             if e.strip():
                 print(e)
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
-    p = subprocess.run(cmd, capture_output=True, text=True)
-    if p.returncode != 0:
-        raise RuntimeError(f"link failed:\n{p.stderr}")
-    os.replace(tmp, LIB)
+    _link(objs[:-1], LIB)
+    _link(objs[-1:], RATES_LIB)
     return LIB
 
 

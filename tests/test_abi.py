@@ -67,3 +67,16 @@ def test_orient_presets_are_the_papers_parameter_sets():
     o = w.OrientOpts()
     assert w.load_library().wnnc_orient_preset(6, ctypes.byref(o)) == w.WNNC_EINVAL
     assert "preset" in w.wnnc_last_error()
+
+
+def test_rate_probe_library_is_separate_and_loads():
+    """The hardware-rate probes live in a library of their own (not part of
+    the boundary): it loads without a device and exports its three calls."""
+    from paper_2405_16634_amd import hwrates
+    import paper_2405_16634_amd as w
+    lib = hwrates.load()
+    assert lib.wnnc_rates_block() == 256 and lib.wnnc_rates_chains() == 8
+    data = open(hwrates.LIB, "rb").read()
+    assert set(re.findall(rb"amdgcn-amd-amdhsa--(gfx[0-9a-f]+)", data)) == {b"gfx950"}
+    main = w.load_library()
+    assert not hasattr(main, "wnnc_rates_run")
