@@ -32,9 +32,10 @@ KIND = {0: "A", 1: "AT", 2: "G"}
 PEAK_FP32_TFLOPS = 157.3
 
 
-def load_profile(name: str):
+def load_profile(name: str, grid=None):
     """A committed rocprofv3 summary (profiles/NAME.json), if it was taken on
-    the current traversal sources."""
+    the current traversal sources (and, given `grid`, on dispatches of that
+    many threads: the same workload)."""
     path = os.path.join(ROOT, "profiles", name + ".json")
     if not os.path.exists(path):
         return None
@@ -44,6 +45,8 @@ def load_profile(name: str):
         return None
     from paper_2405_16634_amd.profiling import traversal_digest
     if d.get("source_sha") != traversal_digest():
+        return None
+    if grid is not None and d.get("grid_threads") != grid:
         return None
     return d
 
@@ -330,8 +333,9 @@ def main():
         step()
     torch.cuda.synchronize()
 
-    # timed steps, with per-launch HIP events on the library's stream
-    ctx.set_flags(w.FLAG_TIME_KERNELS)
+    # timed steps; each traversal launch carries HIP events (on the library's
+    # stream), the other launches none
+    ctx.set_flags(w.FLAG_TIME_TRAVERSAL)
     ctx.reset_stats()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -346,6 +350,13 @@ def main():
     ms_total = ev0.elapsed_time(ev1)
     ms_step = ms_total / args.steps
     st = ctx.stats()
+    ctx.set_flags(0)
+    # the moment and combining passes: one more step with every launch timed
+    ctx.set_flags(w.FLAG_TIME_KERNELS)
+    ctx.reset_stats()
+    step()
+    torch.cuda.synchronize()
+    st_all = ctx.stats()
     ctx.set_flags(0)
 
     # build time and the main loop, separately (one more untimed-kernel step)
@@ -379,16 +390,19 @@ def main():
                                  gpairs_per_s=pairs_per_launch / (avg_ms * 1e-3) / 1e9)
     dom = max(per_kind, key=lambda k: per_kind[k]["total_ms"])
     d = per_kind[dom]
-    tr = load_profile(f"traffic_traverse_{dom}_torusknot500k")
+    # one wavefront (64 threads, one workgroup) per task
+    grid = int(st["n_tasks"]) * 64
+    tr = load_profile(f"traffic_traverse_{dom}_torusknot500k", grid)
     roofline = {"bound": "alu", "achieved": round(d["tflops"], 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(d["tflops"] / PEAK_FP32_TFLOPS, 4),
                 # without packed FP32 (disabled in this build) the ceiling is half
                 "frac_nonpacked": round(d["tflops"] / (PEAK_FP32_TFLOPS / 2), 4),
                 "traffic": tr["bytes_per_launch"] if tr else None,
                 "kernel": f"k_traverse<{dom}>",
+                "grid_threads": grid,
                 "avg_launch_ms": round(d["avg_ms"], 4),
                 "flop_per_launch": round(d["pairs_per_launch"] * FLOPS_PER_PAIR[{"A": 0, "AT": 1, "G": 2}[dom]])}
-    sq = load_profile(f"sq_traverse_{dom}_torusknot500k")
+    sq = load_profile(f"sq_traverse_{dom}_torusknot500k", grid)
     if sq and "SQ_INSTS_VALU" in sq["per_dispatch"]:
         # the instruction-issue view: wave64 vector instructions per launch
         # (committed counters) over this run's launch time
@@ -439,8 +453,8 @@ def main():
                  "tasks_per_launch": int(st["n_tasks"])},
         "tile_autotune_ms": {f"tpl{k[0]}_pf{k[1]}_split{k[2]}": round(v, 4)
                              for k, v in tile_ms.items()},
-        "moments_ms_per_step": round(st["moments_ms"] / args.steps, 3),
-        "combine_ms_per_step": round(st["combine_ms"] / args.steps, 3),
+        "moments_ms_per_step": round(st_all["moments_ms"], 3),
+        "combine_ms_per_step": round(st_all["combine_ms"], 3),
         "host_wall_s_per_step": round((t_host1 - t_host0) / args.steps, 4),
         "accuracy_vs_generator": {"P_co": round(pco, 5), "AE_pcd": round(ae, 6)},
         "context_paper_rtx3090_s": {"N=50k": 1.25, "N=500k": 31.63},

@@ -111,10 +111,15 @@ typedef struct {
 
 /* Instrumentation flags (wnnc_set_flags). */
 #define WNNC_FLAG_COUNT_PAIRS 1u  /* count pair evaluations (slower kernels) */
-#define WNNC_FLAG_TIME_KERNELS 2u /* time every launch with HIP events */
+#define WNNC_FLAG_TIME_KERNELS 2u /* time every traversal, moment and
+                                     combining launch with HIP events carried
+                                     by the launches themselves */
 #define WNNC_FLAG_CHECK_FINITE 4u /* check every float input array for NaN and
                                      infinity first (WNNC_ENUMERIC; each such
                                      call then synchronizes) */
+#define WNNC_FLAG_TIME_TRAVERSAL 8u /* time the traversal launches only (fills
+                                       traverse_ms; about a third of the
+                                       timing overhead of WNNC_FLAG_TIME_KERNELS) */
 
 /* Operator kinds, indices of the per-kind statistics. */
 #define WNNC_OP_A 0
@@ -131,7 +136,8 @@ typedef struct {
                                accepted representatives plus points summed
                                directly, cut-off pairs included */
     double traverse_ms[5];  /* summed traversal-kernel time per kind
-                               (WNNC_FLAG_TIME_KERNELS) */
+                               (WNNC_FLAG_TIME_KERNELS or
+                               WNNC_FLAG_TIME_TRAVERSAL) */
     double moments_ms;      /* summed moment-pass time (WNNC_FLAG_TIME_KERNELS) */
     double build_ms;        /* last wnnc_build, device time (always timed) */
     int64_t n_clouds;       /* clouds in the current tree (1 for wnnc_build) */
@@ -214,7 +220,8 @@ wnnc_status wnnc_get_split(wnnc_ctx ctx, int *visits);
  * Default off. */
 wnnc_status wnnc_set_prefetch(wnnc_ctx ctx, int on);
 
-/* Autotuner: times one adjoint-operator traversal at width w for each of
+/* Autotuner: times the adjoint-operator traversal at width w (the fastest
+ * of five launches after a warm-up launch) for each of
  * WNNC_AUTOTUNE_CONFIGS settings on the current tree and keeps the fastest:
  * (tpl, split) = (1, 0), (2, 0), (4, 0), (1, 1024), (1, 512), (1, 256),
  * each with prefetch off and on (in that order).  times_out (host,

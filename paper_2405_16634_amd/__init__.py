@@ -24,6 +24,7 @@ WNNC_OK, WNNC_EINVAL, WNNC_ENOMEM, WNNC_EDEVICE, WNNC_ESTATE, WNNC_ENUMERIC = 0,
 FLAG_COUNT_PAIRS = 1
 FLAG_TIME_KERNELS = 2
 FLAG_CHECK_FINITE = 4
+FLAG_TIME_TRAVERSAL = 8
 OP_A, OP_AT, OP_G = 0, 1, 2
 
 EXPORTED = [

@@ -36,16 +36,24 @@ wnnc_status fail(wnnc_status s, const char *fmt, ...) {
                         #x, hipGetErrorString(_e));                                       \
     } while (0)
 
-// Events around one launch when WNNC_FLAG_TIME_KERNELS is set.
+// The events of one timed call when WNNC_FLAG_TIME_KERNELS is set: the
+// call's launches carry them (launch_k), its first launch the start, its
+// last the stop.  A call that launched nothing records no time.
 struct Timed {
     wnnc_ctx_s *ctx;
     int kind;
     hipEvent_t a = nullptr, b = nullptr;
     Timed(wnnc_ctx_s *c, int k) : ctx(c), kind(k) {
-        if (!(ctx->flags & WNNC_FLAG_TIME_KERNELS)) return;
+        const bool on = (ctx->flags & WNNC_FLAG_TIME_KERNELS) ||
+                        ((ctx->flags & WNNC_FLAG_TIME_TRAVERSAL) && kind < kOpKinds);
+        if (!on) return;
         a = get();
         b = get();
-        if (a && b) (void)hipEventRecord(a, ctx->stream);
+        if (a && b) {
+            ctx->lev = wnnc_ctx_s::LaunchEvents();
+            ctx->lev.start = a;
+            ctx->lev.stop = b;
+        }
     }
     hipEvent_t get() {
         if (!ctx->event_pool.empty()) {
@@ -58,10 +66,19 @@ struct Timed {
         return e;
     }
     void done() {
-        if (!a || !b) return;
-        (void)hipEventRecord(b, ctx->stream);
-        ctx->pending.push_back({a, b, kind});
+        const bool recorded = ctx->lev.started && ctx->lev.stopped;
+        ctx->lev = wnnc_ctx_s::LaunchEvents();
+        if (recorded) {
+            ctx->pending.push_back({a, b, kind});
+        } else {
+            if (a) ctx->event_pool.push_back(a);
+            if (b) ctx->event_pool.push_back(b);
+        }
         a = b = nullptr;
+    }
+    // an early return (a failed launch) still closes the call
+    ~Timed() {
+        if (a || b) done();
     }
 };
 
@@ -282,7 +299,8 @@ wnnc_status wnnc_set_stream(wnnc_ctx ctx, void *stream) {
 
 wnnc_status wnnc_set_flags(wnnc_ctx ctx, unsigned flags) {
     CHECK_CTX(ctx);
-    if (flags & ~(WNNC_FLAG_COUNT_PAIRS | WNNC_FLAG_TIME_KERNELS | WNNC_FLAG_CHECK_FINITE))
+    if (flags & ~(WNNC_FLAG_COUNT_PAIRS | WNNC_FLAG_TIME_KERNELS | WNNC_FLAG_CHECK_FINITE |
+                  WNNC_FLAG_TIME_TRAVERSAL))
         return fail(WNNC_EINVAL, "unknown flags 0x%x", flags);
     ctx->flags = flags;
     return WNNC_OK;
@@ -527,15 +545,19 @@ wnnc_status wnnc_autotune(wnnc_ctx ctx, float w, wnnc_tile_time *times_out) {
             ta.srcs = ctx->rho.p;
             ta.out4 = ctx->vr.p;
             ta.partial = ctx->partial.p + ctx->ngroups;
-            double t = 0.0;
-            for (int rep = 0; rep < 2; ++rep) {  // first launch warms the caches
+            // the first launch warms the caches; then the fastest of
+            // kAutotuneReps, so that run-to-run noise does not flip a choice
+            // between candidates a few per cent apart
+            constexpr int kAutotuneReps = 5;
+            double t = 1e300;
+            for (int rep = 0; rep <= kAutotuneReps; ++rep) {
                 HIPCHK(hipEventRecord(e0, ctx->stream));
                 HIPCHK(launch_traverse_all(ctx, OP_AT, TR_R, false, ta));
                 HIPCHK(hipEventRecord(e1, ctx->stream));
                 HIPCHK(hipEventSynchronize(e1));
                 float ms = 0.f;
                 HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                t = ms;
+                if (rep > 0) t = std::min(t, (double)ms);
             }
             if (times_out) {
                 wnnc_tile_time &o = times_out[2 * k + pf];

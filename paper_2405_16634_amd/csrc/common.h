@@ -147,8 +147,16 @@ struct wnnc_ctx_s {
     // event pairs of timed launches, resolved by wnnc_stats
     struct Timed {
         hipEvent_t a, b;
-        int kind;  // 0..2 traversal of an operator kind, 3 moment pass, 4 combining pass
+        // 0..kOpKinds-1 the traversal of an operator kind, then the moment
+        // pass and the combining pass
+        int kind;
     };
     std::vector<Timed> pending;
     std::vector<hipEvent_t> event_pool;
+    // the events of the timed call in progress (null when none is): its
+    // first launch carries the start event, its last the stop event
+    struct LaunchEvents {
+        hipEvent_t start = nullptr, stop = nullptr;
+        bool started = false, stopped = false;
+    } lev;
 };

@@ -1,9 +1,42 @@
 // Host-side entry points shared between the library's translation units.
 #pragma once
 
+#include <hip/hip_ext.h>
+
+#include <tuple>
+#include <utility>
+
 #include "common.h"
 
 namespace wnnc {
+
+template <typename Tup, size_t... I>
+inline hipError_t launch_packed(wnnc_ctx_s::LaunchEvents &ev, bool last, const void *k, dim3 grid,
+                                dim3 block, hipStream_t st, Tup &vals, std::index_sequence<I...>) {
+    void *argv[] = {(void *)&std::get<I>(vals)...};
+    if (!ev.start) return hipLaunchKernel(k, grid, block, argv, 0, st);
+    // a timed call: the kernel's own dispatch records the events, so that
+    // timing adds no marker commands (and no idle gaps) to the stream
+    hipEvent_t a = ev.started ? nullptr : ev.start, b = last ? ev.stop : nullptr;
+    const hipError_t e = hipExtLaunchKernel(k, grid, block, argv, 0, st, a, b, 0);
+    if (e == hipSuccess) {
+        ev.started = true;
+        ev.stopped = ev.stopped || last;
+    }
+    return e;
+}
+
+// Launches `kernel` (no dynamic LDS) on st, carrying the events of the timed
+// call in progress: the start event on the call's first launch, the stop
+// event on the launch marked `last`.
+template <typename... KArgs, typename... Args>
+inline hipError_t launch_k(wnnc_ctx_s::LaunchEvents &ev, bool last, void (*kernel)(KArgs...),
+                           dim3 grid, dim3 block, hipStream_t st, Args... args) {
+    static_assert(sizeof...(KArgs) == sizeof...(Args), "kernel argument count");
+    std::tuple<KArgs...> vals{args...};
+    return launch_packed(ev, last, (const void *)kernel, grid, block, st, vals,
+                         std::index_sequence_for<KArgs...>{});
+}
 
 // Returns a HIP error from the enclosing function (host code).
 #define TRY(x)                           \

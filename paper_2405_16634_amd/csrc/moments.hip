@@ -315,48 +315,44 @@ __global__ __launch_bounds__(256) void k_moments_strad(MomArgs a) {
 }
 
 template <bool HI>
-void launch_moments_t(MomMode mode, const MomArgs &a, hipStream_t st) {
+hipError_t launch_moments_t(wnnc_ctx_s *ctx, MomMode mode, const MomArgs &a) {
     const unsigned nchunks = (unsigned)((a.n + kChunk - 1) / kChunk);
+    const dim3 grid(nchunks), block(kChunk);
+    auto &ev = ctx->lev;
+    hipStream_t st = ctx->stream;
+    // the straddler pass, when there is one, is the call's last launch
+    const bool last = a.n_strad <= 0;
+    hipError_t e = hipErrorInvalidValue;
     switch (mode) {
         case MOM_VEC_SORTED:
-            hipLaunchKernelGGL((k_moments_chunk<MOM_VEC_SORTED, HI>), dim3(nchunks), dim3(kChunk), 0,
-                               st, a);
+            e = launch_k(ev, last, k_moments_chunk<MOM_VEC_SORTED, HI>, grid, block, st, a);
             break;
         case MOM_SCALAR_SORTED:
-            hipLaunchKernelGGL((k_moments_chunk<MOM_SCALAR_SORTED, HI>), dim3(nchunks),
-                               dim3(kChunk), 0, st, a);
+            e = launch_k(ev, last, k_moments_chunk<MOM_SCALAR_SORTED, HI>, grid, block, st, a);
             break;
         case MOM_VEC_CALLER:
-            hipLaunchKernelGGL((k_moments_chunk<MOM_VEC_CALLER, HI>), dim3(nchunks), dim3(kChunk), 0,
-                               st, a);
+            e = launch_k(ev, last, k_moments_chunk<MOM_VEC_CALLER, HI>, grid, block, st, a);
             break;
         case MOM_SCALAR_CALLER:
-            hipLaunchKernelGGL((k_moments_chunk<MOM_SCALAR_CALLER, HI>), dim3(nchunks),
-                               dim3(kChunk), 0, st, a);
+            e = launch_k(ev, last, k_moments_chunk<MOM_SCALAR_CALLER, HI>, grid, block, st, a);
             break;
         case MOM_AXPY:
-            hipLaunchKernelGGL((k_moments_chunk<MOM_AXPY, HI>), dim3(nchunks), dim3(kChunk), 0, st,
-                               a);
+            e = launch_k(ev, last, k_moments_chunk<MOM_AXPY, HI>, grid, block, st, a);
             break;
         case MOM_CONST_HALF:
-            hipLaunchKernelGGL((k_moments_chunk<MOM_CONST_HALF, HI>), dim3(nchunks), dim3(kChunk),
-                               0, st, a);
+            e = launch_k(ev, last, k_moments_chunk<MOM_CONST_HALF, HI>, grid, block, st, a);
             break;
     }
-    if (a.n_strad > 0) {
-        const unsigned nb = (unsigned)((a.n_strad + 3) / 4);
-        hipLaunchKernelGGL((k_moments_strad<HI>), dim3(nb), dim3(256), 0, st, a);
-    }
+    if (e != hipSuccess || last) return e;
+    const unsigned nb = (unsigned)((a.n_strad + 3) / 4);
+    return launch_k(ev, true, k_moments_strad<HI>, dim3(nb), dim3(256), st, a);
 }
 
 hipError_t launch_moments(wnnc_ctx_s *ctx, MomMode mode, const MomArgs &args) {
     MomArgs a = args;
     a.scalar = mode == MOM_SCALAR_SORTED || mode == MOM_SCALAR_CALLER || mode == MOM_CONST_HALF;
-    if (a.order > 0 && a.momhi)
-        launch_moments_t<true>(mode, a, ctx->stream);
-    else
-        launch_moments_t<false>(mode, a, ctx->stream);
-    return hipGetLastError();
+    if (a.order > 0 && a.momhi) return launch_moments_t<true>(ctx, mode, a);
+    return launch_moments_t<false>(ctx, mode, a);
 }
 
 }  // namespace wnnc

@@ -596,54 +596,44 @@ int trav_blocks(int64_t ntasks) {
 }
 
 template <int OP, int MODE, int TPL, bool HI>
-static void launch_tpl_hi(bool count, const TravArgs &a, hipStream_t st) {
+static hipError_t launch_tpl_hi(wnnc_ctx_s *ctx, bool count, const TravArgs &a) {
     const dim3 grid((unsigned)trav_blocks(a.ntasks)), block(kTravBlock);
-    if (a.prefetch) {
-        if (count)
-            hipLaunchKernelGGL((k_traverse<OP, MODE, true, TPL, true, HI>), grid, block, 0, st, a);
-        else
-            hipLaunchKernelGGL((k_traverse<OP, MODE, false, TPL, true, HI>), grid, block, 0, st, a);
-    } else {
-        if (count)
-            hipLaunchKernelGGL((k_traverse<OP, MODE, true, TPL, false, HI>), grid, block, 0, st, a);
-        else
-            hipLaunchKernelGGL((k_traverse<OP, MODE, false, TPL, false, HI>), grid, block, 0, st,
-                               a);
-    }
+    auto &ev = ctx->lev;
+    hipStream_t st = ctx->stream;
+    if (a.prefetch)
+        return count ? launch_k(ev, true, k_traverse<OP, MODE, true, TPL, true, HI>, grid, block, st, a)
+                     : launch_k(ev, true, k_traverse<OP, MODE, false, TPL, true, HI>, grid, block, st, a);
+    return count ? launch_k(ev, true, k_traverse<OP, MODE, true, TPL, false, HI>, grid, block, st, a)
+                 : launch_k(ev, true, k_traverse<OP, MODE, false, TPL, false, HI>, grid, block, st, a);
 }
 
 template <int OP, int MODE, int TPL>
-static void launch_tpl(bool count, const TravArgs &a, hipStream_t st) {
+static hipError_t launch_tpl(wnnc_ctx_s *ctx, bool count, const TravArgs &a) {
     if constexpr (OP == OP_P || OP == OP_T) {
         // the position-gradient walk has the representative far field only
-        launch_tpl_hi<OP, MODE, TPL, false>(count, a, st);
+        return launch_tpl_hi<OP, MODE, TPL, false>(ctx, count, a);
     } else {
-        if (a.order > 0 && a.momhi)
-            launch_tpl_hi<OP, MODE, TPL, true>(count, a, st);
-        else
-            launch_tpl_hi<OP, MODE, TPL, false>(count, a, st);
+        if (a.order > 0 && a.momhi) return launch_tpl_hi<OP, MODE, TPL, true>(ctx, count, a);
+        return launch_tpl_hi<OP, MODE, TPL, false>(ctx, count, a);
     }
 }
 
 template <int OP, int MODE>
 static hipError_t launch_one(wnnc_ctx_s *ctx, bool count, const TravArgs &a) {
-    hipStream_t st = ctx->stream;
     if (a.ntasks <= 0) return hipSuccess;
     switch (a.tpl) {
-        case 1: launch_tpl<OP, MODE, 1>(count, a, st); break;
-        case 2: launch_tpl<OP, MODE, 2>(count, a, st); break;
-        case 4: launch_tpl<OP, MODE, 4>(count, a, st); break;
+        case 1: return launch_tpl<OP, MODE, 1>(ctx, count, a);
+        case 2: return launch_tpl<OP, MODE, 2>(ctx, count, a);
+        case 4: return launch_tpl<OP, MODE, 4>(ctx, count, a);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 template <int OP, int MODE>
 static hipError_t launch_comb(wnnc_ctx_s *ctx, const TravArgs &a) {
     if (a.ntasks <= 0 || ctx->nsplit <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_combine<OP, MODE>), dim3((unsigned)ctx->nsplit), dim3(kWave), 0,
-                       ctx->stream, a, ctx->split_groups.p, ctx->split_slot.p);
-    return hipGetLastError();
+    return launch_k(ctx->lev, true, k_combine<OP, MODE>, dim3((unsigned)ctx->nsplit), dim3(kWave),
+                    ctx->stream, a, ctx->split_groups.p, ctx->split_slot.p);
 }
 
 hipError_t launch_traverse(wnnc_ctx_s *ctx, Op op, TravMode mode, bool count, const TravArgs &a) {

@@ -57,18 +57,30 @@ def _rows(path):
         return list(csv.DictReader(f))
 
 
-def counter_per_dispatch(path: str, counter: str, kernel: str) -> tuple[float, int]:
+def _grid(r) -> int:
+    """Threads in the dispatch (PMC CSV: Grid_Size; kernel trace: Grid_Size_X)."""
+    return int(float(r.get("Grid_Size") or r.get("Grid_Size_X") or 0))
+
+
+def _match(r, rx, grid) -> bool:
+    """The row is a dispatch of a kernel matching rx (and of `grid` threads,
+    when given: one workload among several that the command ran)."""
+    return bool(rx.search(r["Kernel_Name"])) and (grid is None or _grid(r) == grid)
+
+
+def counter_per_dispatch(path: str, counter: str, kernel: str, grid=None) -> tuple[float, int]:
     """Mean value of `counter` over the dispatches of kernels matching the
-    regex `kernel` (one row per dispatch and counter), and the count."""
+    regex `kernel` (one row per dispatch and counter; only dispatches of
+    `grid` threads when given), and the count."""
     rx = re.compile(kernel)
     vals = [float(r["Counter_Value"]) for r in _rows(path)
-            if r["Counter_Name"] == counter and rx.search(r["Kernel_Name"])]
+            if r["Counter_Name"] == counter and _match(r, rx, grid)]
     if not vals:
         raise ValueError(f"{path}: no {counter} rows for kernels matching {kernel!r}")
     return sum(vals) / len(vals), len(vals)
 
 
-def traffic(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, mb, kernel, cmd):
+def traffic(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, mb, kernel, cmd, grid=None):
     copy_kib = mb * 1024.0  # each copy dispatch reads and writes this much
     cal = "copyBuffer|elementwise_kernel|copy"
     cf, ncf = counter_per_dispatch(cal_fetch_csv, "FETCH_SIZE", cal)
@@ -88,12 +100,13 @@ def traffic(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, mb, kernel, cmd)
         cw, ncw = sum(big_w) / len(big_w), len(big_w)
     f_fetch = copy_kib / cf
     f_write = copy_kib / cw
-    kf, nf = counter_per_dispatch(fetch_csv, "FETCH_SIZE", kernel)
-    kw, nw = counter_per_dispatch(write_csv, "WRITE_SIZE", kernel)
+    kf, nf = counter_per_dispatch(fetch_csv, "FETCH_SIZE", kernel, grid)
+    kw, nw = counter_per_dispatch(write_csv, "WRITE_SIZE", kernel, grid)
     read_b = kf * 1024.0 * f_fetch
     write_b = kw * 1024.0 * f_write
     return {
         "kernel": kernel,
+        "grid_threads": grid,
         "source_sha": traversal_digest(),
         "bytes_per_launch": round(read_b + write_b),
         "read_bytes_per_launch": round(read_b),
@@ -113,22 +126,23 @@ def traffic(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, mb, kernel, cmd)
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
-def sq(csv_paths, kernel: str, trace_csv: str, cmd: str) -> dict:
+def sq(csv_paths, kernel: str, trace_csv: str, cmd: str, grid=None) -> dict:
     """Instruction counters (and derived metrics such as VALUBusy) per
-    dispatch of the kernels matching `kernel`, from one or more --pmc runs,
-    with the kernels' average duration from a kernel trace of the same
-    command (kernel_trace CSV)."""
+    dispatch of the kernels matching `kernel` (of `grid` threads when
+    given), from one or more --pmc runs, with the kernels' average duration
+    from a kernel trace of the same command (kernel_trace CSV)."""
     rx = re.compile(kernel)
     per = {}
     for path in ([csv_paths] if isinstance(csv_paths, str) else csv_paths):
         for r in _rows(path):
-            if rx.search(r["Kernel_Name"]):
+            if _match(r, rx, grid):
                 per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
     out = {k: round(sum(v) / len(v), 3) for k, v in per.items()}
     durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
-            for r in _rows(trace_csv) if rx.search(r["Kernel_Name"])]
+            for r in _rows(trace_csv) if _match(r, rx, grid)]
     avg = sum(durs) / len(durs)
-    d = {"kernel": kernel, "source_sha": traversal_digest(), "per_dispatch": out,
+    d = {"kernel": kernel, "grid_threads": grid, "source_sha": traversal_digest(),
+         "per_dispatch": out,
          "dispatches": len(next(iter(per.values()))), "trace_avg_s": avg,
          "valu_issue_peak_per_s": VALU_ISSUE_PEAK, "command": cmd}
     if "SQ_INSTS_VALU" in out:
@@ -136,9 +150,13 @@ def sq(csv_paths, kernel: str, trace_csv: str, cmd: str) -> dict:
     return d
 
 
-def trace_markdown(stats_csv: str, title: str, cmd: str, groups=(), top: int = 25) -> str:
+def trace_markdown(stats_csv: str, title: str, cmd: str, groups=(), top: int = 25,
+                   trace_csv=None, dispatch_groups=()) -> str:
     """groups: (label, regex) pairs; each gets the call-weighted average
-    duration of the kernels whose names match."""
+    duration of the kernels whose names match.  dispatch_groups: (label,
+    regex, grid) triples, averaged over the dispatches of `grid` threads in
+    the per-dispatch trace (trace_csv): one workload among several that the
+    command ran."""
     rows = _rows(stats_csv)
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     out = [f"# {title}", "", "Command (run from the repository root on one MI355X):", "",
@@ -157,6 +175,16 @@ def trace_markdown(stats_csv: str, title: str, cmd: str, groups=(), top: int = 2
             tot = sum(float(r["TotalDurationNs"]) for r in m)
             avg = tot / calls / 1e3 if calls else float("nan")
             out.append(f"| {label} | `{rx}` | {calls} | {avg:.2f} |")
+    if dispatch_groups:
+        trows = _rows(trace_csv)
+        out += ["", "Dispatches of one workload (kernel trace rows of the given grid size):", "",
+                "| group | regex | grid threads | calls | average us |", "|---|---|---|---|---|"]
+        for label, rx, grid in dispatch_groups:
+            r_ = re.compile(rx)
+            d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+                 for r in trows if _match(r, r_, grid)]
+            avg = sum(d) / len(d) if d else float("nan")
+            out.append(f"| {label} | `{rx}` | {grid} | {len(d)} | {avg:.2f} |")
     return "\n".join(out) + "\n"
 
 
@@ -169,32 +197,42 @@ def main():
     t.add_argument("--cmd", required=True)
     t.add_argument("--out", required=True)
     t.add_argument("--group", action="append", default=[], metavar="LABEL=REGEX")
+    t.add_argument("--trace", help="kernel_trace CSV (per dispatch), for --dispatch-group")
+    t.add_argument("--dispatch-group", action="append", default=[], metavar="LABEL=REGEX@GRID")
     q = sub.add_parser("traffic")
     for k in ("fetch", "write", "cal_fetch", "cal_write"):
         q.add_argument("--" + k.replace("_", "-"), required=True)
     q.add_argument("--mb", type=int, default=512)
     q.add_argument("--kernel", required=True)
+    q.add_argument("--grid", type=int, default=None, help="only dispatches of this many threads")
     q.add_argument("--cmd", required=True)
     q.add_argument("--out", required=True)
     c = sub.add_parser("sq")
     c.add_argument("--csv", required=True, action="append")
     c.add_argument("--trace", required=True, help="kernel_trace CSV of the same workload")
     c.add_argument("--kernel", required=True)
+    c.add_argument("--grid", type=int, default=None, help="only dispatches of this many threads")
     c.add_argument("--cmd", required=True)
     c.add_argument("--out", required=True)
     a = ap.parse_args()
     if a.what == "trace":
+        dg = []
+        for g in a.dispatch_group:
+            label, rest = g.split("=", 1)
+            rx, grid = rest.rsplit("@", 1)
+            dg.append((label, rx, int(grid)))
         text = trace_markdown(a.csv, a.title, a.cmd,
-                              [tuple(g.split("=", 1)) for g in a.group])
+                              [tuple(g.split("=", 1)) for g in a.group],
+                              trace_csv=a.trace, dispatch_groups=dg)
         with open(a.out, "w") as f:
             f.write(text)
     elif a.what == "sq":
-        d = sq(a.csv, a.kernel, a.trace, a.cmd)
+        d = sq(a.csv, a.kernel, a.trace, a.cmd, a.grid)
         with open(a.out, "w") as f:
             json.dump(d, f, indent=1)
             f.write("\n")
     else:
-        d = traffic(a.fetch, a.write, a.cal_fetch, a.cal_write, a.mb, a.kernel, a.cmd)
+        d = traffic(a.fetch, a.write, a.cal_fetch, a.cal_write, a.mb, a.kernel, a.cmd, a.grid)
         with open(a.out, "w") as f:
             json.dump(d, f, indent=1)
             f.write("\n")
