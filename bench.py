@@ -268,9 +268,11 @@ def batched_section(w, stream, iters, w1, w2, c, depth):
     a = mu_b.cpu().numpy()
     b = torch.cat(outs).cpu().numpy()
     flip = float(((a * b).sum(1) <= 0).mean())
+    tile = {"targets_per_lane": ctx.tile(), "prefetch": bool(ctx.prefetch()),
+            "split_visits": ctx.split()}
     ctx.close()
     one.close()
-    return {"clouds": 64, "points": int(off[-1]), "batched_ms": round(t_batched, 2),
+    return {"clouds": 64, "points": int(off[-1]), "tile": tile, "batched_ms": round(t_batched, 2),
             "one_by_one_ms": round(t_single, 2), "speedup": round(t_single / t_batched, 3),
             "flip_batched_vs_one_by_one": flip, "equal_accuracy": bool(flip <= 1e-3)}
 

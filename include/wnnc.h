@@ -220,13 +220,15 @@ wnnc_status wnnc_get_split(wnnc_ctx ctx, int *visits);
  * Default off. */
 wnnc_status wnnc_set_prefetch(wnnc_ctx ctx, int on);
 
-/* Autotuner: times the adjoint-operator traversal at width w (the fastest
- * of five launches after a warm-up launch) for each of
- * WNNC_AUTOTUNE_CONFIGS settings on the current tree and keeps the fastest:
+/* Autotuner: times three iterations of Alg. 3 at width w from mu = 0 (the
+ * fastest of two runs after a warm-up run) for each of
+ * WNNC_AUTOTUNE_CONFIGS settings on the current tree and keeps the fastest
+ * (a setting later in the list must be faster by more than 1 %):
  * (tpl, split) = (1, 0), (2, 0), (4, 0), (1, 1024), (1, 512), (1, 256),
  * each with prefetch off and on (in that order).  times_out (host,
  * WNNC_AUTOTUNE_CONFIGS entries, may be NULL) receives the settings and
- * their times.  Overwrites the context's iteration buffers.  Synchronizes. */
+ * their times per iteration.  Overwrites the context's iteration buffers.
+ * Synchronizes. */
 #define WNNC_AUTOTUNE_CONFIGS 12
 typedef struct {
     int tpl;

@@ -519,15 +519,14 @@ wnnc_status wnnc_set_prefetch(wnnc_ctx ctx, int on) {
     return WNNC_OK;
 }
 
+static wnnc_status run_iterations(wnnc_ctx ctx, int iters, float w1, float w2, int start, int stop,
+                                  bool zero, unsigned long long *flips, int sched,
+                                  const float *areas);
+
 wnnc_status wnnc_autotune(wnnc_ctx ctx, float w, wnnc_tile_time *times_out) {
     CHECK_CTX(ctx);
     CHECK_BUILT(ctx);
     if (!finite_nonneg(w)) return fail(WNNC_EINVAL, "w must be finite and >= 0");
-    // the adjoint traversal with the constant scalar 1/2: every weight is
-    // positive, so it visits the nodes a smooth attribute would
-    MomArgs ma = mom_args(ctx, 0.0f);
-    ma.outs = ctx->rho.p;
-    RETURN_IF(run_moments(ctx, MOM_CONST_HALF, ma));
     // (tpl, split) pairs, each with and without prefetch
     static const int cand[WNNC_AUTOTUNE_CONFIGS / 2][2] = {
         {1, 0}, {2, 0}, {4, 0}, {1, 1024}, {1, 512}, {1, 256}};
@@ -536,28 +535,27 @@ wnnc_status wnnc_autotune(wnnc_ctx ctx, float w, wnnc_tile_time *times_out) {
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
+    // Each setting times what it is for: kTuneIters iterations of Alg. 3 at
+    // width w from mu = 0 (moment passes, A, A^T, A and G in their real mix
+    // and on the records the iteration makes).  The first run warms the
+    // caches; then the fastest of kTuneReps.
+    constexpr int kTuneIters = 3, kTuneReps = 2;
     for (int k = 0; k < WNNC_AUTOTUNE_CONFIGS / 2; ++k) {
         hipError_t e = make_tasks(ctx, cand[k][0], cand[k][1]);
         if (e != hipSuccess) return fail(WNNC_EDEVICE, "tasks: %s", hipGetErrorString(e));
         for (int pf = 0; pf < 2; ++pf) {
             ctx->prefetch = pf;
-            TravArgs ta = trav_args(ctx, w);
-            ta.srcs = ctx->rho.p;
-            ta.out4 = ctx->vr.p;
-            ta.partial = ctx->partial.p + ctx->ngroups;
-            // the first launch warms the caches; then the fastest of
-            // kAutotuneReps, so that run-to-run noise does not flip a choice
-            // between candidates a few per cent apart
-            constexpr int kAutotuneReps = 5;
             double t = 1e300;
-            for (int rep = 0; rep <= kAutotuneReps; ++rep) {
+            for (int rep = 0; rep <= kTuneReps; ++rep) {
+                HIPCHK(launch_zero_f4(ctx->va.p, ctx->n, ctx->stream));
                 HIPCHK(hipEventRecord(e0, ctx->stream));
-                HIPCHK(launch_traverse_all(ctx, OP_AT, TR_R, false, ta));
+                RETURN_IF(run_iterations(ctx, kTuneIters, w, w, 1, kTuneIters, true, nullptr,
+                                         WNNC_SCHEDULE_LINEAR, nullptr));
                 HIPCHK(hipEventRecord(e1, ctx->stream));
                 HIPCHK(hipEventSynchronize(e1));
                 float ms = 0.f;
                 HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                if (rep > 0) t = std::min(t, (double)ms);
+                if (rep > 0) t = std::min(t, (double)ms / kTuneIters);
             }
             if (times_out) {
                 wnnc_tile_time &o = times_out[2 * k + pf];
@@ -566,7 +564,9 @@ wnnc_status wnnc_autotune(wnnc_ctx ctx, float w, wnnc_tile_time *times_out) {
                 o.split = cand[k][1];
                 o.ms = t;
             }
-            if (t < best_ms) {
+            // a later setting must be faster by more than 1 %: the choice
+            // stays put between settings within run-to-run noise
+            if (t < best_ms * 0.99) {
                 best_ms = t;
                 best = cand[k][0];
                 best_pf = pf;
@@ -787,8 +787,8 @@ static double schedule_width(int sched, int i, int n, float w1, float w2) {
 }
 
 static wnnc_status run_iterations(wnnc_ctx ctx, int iters, float w1, float w2, int start, int stop,
-                                  bool zero, unsigned long long *flips,
-                                  int sched = WNNC_SCHEDULE_LINEAR, const float *areas = nullptr) {
+                                  bool zero, unsigned long long *flips, int sched,
+                                  const float *areas) {
     const int nt = ctx->ngroups;  // row stride of the per-group sums
     const int count = stop - start + 1;
     HIPCHK(ctx->energy.ensure((int64_t)count * ctx->nclouds));
@@ -952,7 +952,8 @@ wnnc_status wnnc_warm_orient(wnnc_ctx ctx, const float *params, const wnnc_warm_
     //    (flip_ctr[B..2B))
     HIPCHK(ctx->flip_ctr.ensure(2 * B));
     HIPCHK(hipMemsetAsync(ctx->flip_ctr.p, 0, (size_t)(2 * B) * sizeof(unsigned long long), st));
-    RETURN_IF(run_iterations(ctx, o.iters, o.w1, o.w2, 1, o.iters, false, ctx->flip_ctr.p));
+    RETURN_IF(run_iterations(ctx, o.iters, o.w1, o.w2, 1, o.iters, false, ctx->flip_ctr.p,
+                             WNNC_SCHEDULE_LINEAR, nullptr));
     HIPCHK(launch_pred_disagree(ctx, ctx->va.p, ctx->nhat.p, ctx->flip_ctr.p + B));
     std::vector<unsigned long long> fl((size_t)(2 * B));
     HIPCHK(hipMemcpyAsync(fl.data(), ctx->flip_ctr.p, (size_t)(2 * B) * sizeof(unsigned long long),
@@ -970,7 +971,7 @@ wnnc_status wnnc_warm_orient(wnnc_ctx ctx, const float *params, const wnnc_warm_
     if (fallback) {
         HIPCHK(launch_zero_f4(ctx->va.p, N, st));
         RETURN_IF(run_iterations(ctx, o.fallback_iters, o.w1, o.fallback_w2, 1, o.fallback_iters,
-                                 true, nullptr));
+                                 true, nullptr, WNNC_SCHEDULE_LINEAR, nullptr));
     }
     HIPCHK(launch_scatter_vec(ctx->va.p, ctx->perm.p, mu_out, N, st));
     if (report) {

@@ -51,6 +51,19 @@ __device__ inline v16f ld_rec(const float4 *base, int node) {
     return *(const WNNC_AS4 v16f *)(b + ((unsigned)node << 6));
 }
 
+// The same load, issued without waiting for it: the compiler neither sinks
+// it to its first use nor waits for it there.  rec_wait must come before
+// any read of the result.
+__device__ inline v16f rec_issue(const float4 *base, int node) {
+    v16f r;
+    const unsigned off = (unsigned)node << 6;
+    asm volatile("s_load_dwordx16 %0, %1, %2" : "=s"(r) : "s"(base), "s"(off));
+    return r;
+}
+// Waits for every scalar load in flight (they may complete out of order).
+// The record is an operand, so that no read of it moves above the wait.
+__device__ inline void rec_wait(v16f &r) { asm volatile("s_waitcnt lgkmcnt(0)" : "+s"(r)); }
+
 constexpr double kInv4Pi = 0.0795774715459476678844;  // 1 / (4 pi)
 
 // Pair term without the 1/(4 pi) factor.  d = target - source, r2 = |d|^2.
@@ -513,27 +526,45 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
         return node + 1;
     };
 
-    if (!PF) {
+    // (with the far-field moments the walk keeps plain loads: their extra
+    // scalar registers would crowd the record in flight)
+    if (!PF || HI) {
         for (int node = nbeg; node < nend;) node = visit(ld_rec(a.mom, node), node);
     } else if (nbeg < nend) {
-        // Two record buffers used in turn.  While a node is visited, the
-        // record of its skip successor is loaded into the other buffer; when
-        // the walk descends instead, that buffer is reloaded with the first
-        // child.  (Loads past the range's last node are clamped to it.)
+        // Software-pipelined walk.  A wait for a scalar load covers every
+        // scalar load in flight, so the skip successor's record is issued
+        // right after the wait for the current one and arrives while the
+        // current node is visited; when the walk descends instead, the first
+        // child is loaded then.  Loaded indices are clamped to the range,
+        // and the walk advances by at least one node per visit.
         int node = nbeg;
-        v16f RA = ld_rec(a.mom, node), RB;
+        // the cutoff is read in every visit: have the compiler wait for its
+        // load here, so that it places no wait (which would also wait for
+        // the record in flight) inside the loop
+        asm volatile("" ::"s"(a.w2));
+        // two record buffers in turn, so that no record is copied
+        v16f RA = rec_issue(a.mom, node), RB;
+        rec_wait(RA);
         for (;;) {
-            int sk = __float_as_int(RA[7]);
-            RB = ld_rec(a.mom, min(sk, nend - 1));
-            int nx = visit(RA, node);
+            int sk = min(max(__float_as_int(RA[7]), node + 1), nend - 1);
+            RB = rec_issue(a.mom, sk);
+            int nx = max(visit(RA, node), node + 1);
+            rec_wait(RB);
             if (nx >= nend) break;
-            if (nx != sk) RB = ld_rec(a.mom, nx);
+            if (nx != sk) {
+                RB = rec_issue(a.mom, nx);
+                rec_wait(RB);
+            }
             node = nx;
-            sk = __float_as_int(RB[7]);
-            RA = ld_rec(a.mom, min(sk, nend - 1));
-            nx = visit(RB, node);
+            sk = min(max(__float_as_int(RB[7]), node + 1), nend - 1);
+            RA = rec_issue(a.mom, sk);
+            nx = max(visit(RB, node), node + 1);
+            rec_wait(RA);
             if (nx >= nend) break;
-            if (nx != sk) RA = ld_rec(a.mom, nx);
+            if (nx != sk) {
+                RA = rec_issue(a.mom, nx);
+                rec_wait(RA);
+            }
             node = nx;
         }
     }

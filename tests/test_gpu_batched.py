@@ -234,7 +234,14 @@ def test_autotune_keeps_the_fastest(dev):
     ms = ctx.autotune(0.002)
     assert len(ms) == w.AUTOTUNE_CONFIGS and all(v > 0 for v in ms.values())
     assert {k[:2] for k in ms} == {(t, p) for t in (1, 2, 4) for p in (0, 1)}
-    assert (ctx.tile(), int(ctx.prefetch()), ctx.split()) == min(ms, key=ms.get)
+    # the fastest, except that a setting later in the list must beat the
+    # best so far by more than 1 %
+    best = None
+    for key, t in ms.items():
+        if best is None or t < ms[best] * 0.99:
+            best = key
+    assert (ctx.tile(), int(ctx.prefetch()), ctx.split()) == best
+    assert 0.99 * ms[best] <= min(ms.values())
     ctx.close()
 
 
