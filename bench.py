@@ -397,7 +397,7 @@ def main():
     tr = load_profile(f"traffic_traverse_{dom}_torusknot500k", grid)
     roofline = {"bound": "alu", "achieved": round(d["tflops"], 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(d["tflops"] / PEAK_FP32_TFLOPS, 4),
-                # without packed FP32 (disabled in this build) the ceiling is half
+                # without packed FP32 (the library is compiled without it) the ceiling is half
                 "frac_nonpacked": round(d["tflops"] / (PEAK_FP32_TFLOPS / 2), 4),
                 "traffic": tr["bytes_per_launch"] if tr else None,
                 "kernel": f"k_traverse<{dom}>",

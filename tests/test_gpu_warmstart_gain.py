@@ -2,7 +2,7 @@
 
 Held-out clouds (seeds not used in training): a torus knot with 2 %
 outliers and a noise-free ellipsoid union.  The plain method (40 iterations
-from mu = 0) is the judge.  Equal accuracy, on the surface points (outliers
+from mu = 0) is the reference.  Equal accuracy, on the surface points (outliers
 have no normal): the warm-started result disagrees with the plain one on at
 most 0.1 % of them, and orients at least as many correctly against the
 generator's normals (P_co within 0.1 %), while running fewer iterations and
