@@ -303,8 +303,11 @@ wnnc_status wnnc_gradient_grad_x(wnnc_ctx ctx, const float *n, const float *sigm
  *     i.e. no point of its cell is within the cutoff w of the target, so
  *     the representative does not carry pairs the cutoff would drop.
  * Applies to every later operator call (winding, gradient, adjoint,
- * queries, orientation).  The moments take 40 floats per node more of
- * device memory while order > 0.  Walk plans and tasks are unchanged. */
+ * queries, orientation).  The moments take 24 floats per node more of
+ * device memory while order > 0, and order > 0 takes trees of at most
+ * 44,739,242 nodes (2^32 bytes of those moments): WNNC_EINVAL from this
+ * call, or from a later build of a larger tree.  Walk plans and tasks are
+ * unchanged. */
 wnnc_status wnnc_set_far_field(wnnc_ctx ctx, int order, int wsafe);
 wnnc_status wnnc_get_far_field(wnnc_ctx ctx, int *order, int *wsafe);
 

@@ -151,6 +151,10 @@ TravArgs trav_args(wnnc_ctx_s *c, float w) {
     return a;
 }
 
+// The traversal addresses a node's far-field moments (kHiStride floats) with
+// a 32-bit byte offset.
+constexpr int64_t kMaxHiNodes = (int64_t(1) << 32) / (kHiStride * 4);
+
 // Timed kinds: 0..kOpKinds-1 the traversal of each operator, then these two.
 constexpr int kKindMoments = kOpKinds, kKindCombine = kOpKinds + 1;
 
@@ -423,7 +427,16 @@ static wnnc_status build_impl(wnnc_ctx ctx, const float *P, const int64_t *offse
     hipError_t e = build_tree(ctx, P);
     if (e == hipSuccess) e = plan_walks(ctx);
     if (e == hipSuccess) e = make_tasks(ctx, tpl, split);
-    if (e == hipSuccess && ctx->far_order > 0) e = ctx->momhi.ensure(ctx->m * kHiStride);
+    const bool hi_too_big = e == hipSuccess && ctx->far_order > 0 && ctx->m > kMaxHiNodes;
+    if (e == hipSuccess && ctx->far_order > 0 && !hi_too_big)
+        e = ctx->momhi.ensure(ctx->m * kHiStride);
+    if (hi_too_big) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        ctx->built = false;
+        return fail(WNNC_EINVAL, "tree build: %lld nodes; the far field of order > 0 takes at most %lld",
+                    (long long)ctx->m, (long long)kMaxHiNodes);
+    }
     if (e != hipSuccess) {
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -485,6 +498,9 @@ wnnc_status wnnc_set_far_field(wnnc_ctx ctx, int order, int wsafe) {
     CHECK_CTX(ctx);
     if (order < 0 || order > 2) return fail(WNNC_EINVAL, "far-field order must be 0, 1 or 2");
     if (wsafe != 0 && wsafe != 1) return fail(WNNC_EINVAL, "wsafe must be 0 or 1");
+    if (order > 0 && ctx->built && ctx->m > kMaxHiNodes)
+        return fail(WNNC_EINVAL, "the far field of order > 0 takes at most %lld nodes (tree: %lld)",
+                    (long long)kMaxHiNodes, (long long)ctx->m);
     if (order > 0 && ctx->built) HIPCHK(ctx->momhi.ensure(ctx->m * kHiStride));
     ctx->far_order = order;
     ctx->far_wsafe = wsafe;
