@@ -110,3 +110,28 @@ def test_neighbour_search_does_not_depend_on_the_leaves(dev):
         res.append(nbr.cpu().numpy())
         ctx.close()
     assert np.array_equal(res[0], res[1]) and np.array_equal(res[0], res[2])
+
+
+def test_prefetch_is_bit_identical_with_far_field_and_leaf_capacity(dev):
+    """The prefetch setting changes no bit, also with the far field of order
+    2 (which keeps the plain record loads) and with leaves of several points
+    (direct sums inside the prefetching walk)."""
+    import paper_2405_16634_amd as w
+    cloud = synth.torus_knot(20000, 5, with_init=False)
+    print("[case] prefetch x far field x leaf capacity knot20k", flush=True)
+    rng = np.random.default_rng(13)
+    mu = _t(synth.random_unit(rng, cloud.n) * 1e-4, dev)
+    rho = _t(0.5 - rng.uniform(0, 1, cloud.n), dev)
+    for K, order in ((1, 2), (8, 0), (8, 2)):
+        ctx = w.Context(0)
+        x, _ = ctx.normalize(_t(cloud.points, dev))
+        ctx.build(x, 2.0, 15, K)
+        ctx.set_far_field(order, order > 0)
+        res = []
+        for pf in (False, True):
+            ctx.set_prefetch(pf)
+            res.append((ctx.winding(mu, 0.002).clone(), ctx.gradient(mu, 0.002).clone(),
+                        ctx.adjoint(rho, 0.002).clone(), ctx.orient(5, 0.002, 0.016).clone()))
+        for a, b in zip(*res):
+            assert bool((a == b).all()), (K, order)
+        ctx.close()
