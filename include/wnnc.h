@@ -215,9 +215,10 @@ wnnc_status wnnc_get_tile(wnnc_ctx ctx, int *tpl);
 wnnc_status wnnc_set_split(wnnc_ctx ctx, int visits);
 wnnc_status wnnc_get_split(wnnc_ctx ctx, int *visits);
 
-/* Software-pipelined node walk in the traversal (the skip successor's
- * record is loaded during the visit); results do not depend on it.
- * Default off. */
+/* Software-pipelined node walk in the traversal: the skip successor's
+ * record is loaded while the current node is visited (with the far field of
+ * order > 0 the walk keeps plain loads).  Results do not depend on it, bit
+ * for bit.  Default off; wnnc_autotune may switch it on. */
 wnnc_status wnnc_set_prefetch(wnnc_ctx ctx, int on);
 
 /* Autotuner: times three iterations of Alg. 3 at width w from mu = 0 (the
