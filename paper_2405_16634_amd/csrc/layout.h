@@ -11,7 +11,7 @@
 namespace wnnc {
 
 constexpr int kWave = 64;
-constexpr int kChunk = 256;      // points per moment-pass chunk (one workgroup)
+constexpr int kChunk = 512;      // points per moment-pass chunk (one workgroup)
 constexpr int kTravBlock = 64;  // traversal workgroup: one wave (finest dispatch)
 constexpr int kMaxDepth = 15;    // 15 levels below the root: 45-bit Morton keys
 
