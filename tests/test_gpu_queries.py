@@ -117,3 +117,31 @@ def test_batched_tree_is_refused(dev):
     with pytest.raises(w.WnncError):
         ctx.winding_at(mu, 0.002, torch.zeros(5, 3, device=dev))
     ctx.close()
+
+
+def test_accept_test_is_strict_at_a_tie(dev, oracle_mod):
+    """A query at exactly c 2^(1-d) from a node's x_B opens the node, on the
+    device as in the oracle (dyadic coordinates: every distance is exact in
+    FP32 too); one ulp farther, the representative is taken."""
+    import torch
+    import paper_2405_16634_amd as w
+    print("[case] accept tie, two points, two queries", flush=True)
+    x = np.array([[0.0625, 0.0625, 0.0625], [0.1875, 0.0625, 0.0625]], np.float32)
+    mu = np.array([[0.01, 0.0, 0.0], [0.01, 0.0, 0.0]], np.float32)
+    tie = np.array([0.625, 0.0625, 0.0625], np.float32)
+    far = tie.copy()
+    far[0] = np.nextafter(far[0], np.float32(1.0))
+    Q = np.stack([tie, far])
+    ctx = w.Context(0)
+    ctx.build(torch.from_numpy(x).to(dev), 2.0, 15)
+    ctx.set_flags(w.FLAG_COUNT_PAIRS)
+    ctx.reset_stats()
+    got = ctx.winding_at(torch.from_numpy(mu).to(dev), 1e-3, torch.from_numpy(Q).to(dev))
+    torch.cuda.synchronize()
+    pairs = ctx.stats()["pairs"][0]
+    ctx.set_flags(0)
+    ref, _, opairs = oracle_mod.Tree(x.astype(np.float64)).apply(
+        "A", mu.astype(np.float64), 1e-3, 2.0, targets=Q.astype(np.float64), with_stats=True)
+    assert list(opairs) == [2, 1] and pairs == 3
+    assert np.allclose(got.cpu().numpy(), ref, rtol=1e-5, atol=0)
+    ctx.close()

@@ -244,6 +244,31 @@ def test_treecode_special_cases(oracle_mod):
     assert np.allclose(tr, mono, rtol=1e-12, atol=0)
 
 
+def test_accept_test_is_strict_at_a_tie(oracle_mod):
+    """Alg. 4 accepts a node only if the target is farther than c 2^(1-d)
+    from x_B: at exactly that distance the node is opened.  Two equal-weight
+    points share one depth-3 cell (width 1/4) and split at depth 4; x_B is
+    their midpoint; a query on the x axis at distance exactly 2 * 1/4 from it
+    (every coordinate dyadic, so every distance is exact) opens the node and
+    sums both points; a query one ulp farther takes the representative."""
+    x = np.array([[0.0625, 0.0625, 0.0625], [0.1875, 0.0625, 0.0625]])
+    mu = np.array([[0.01, 0.0, 0.0], [0.01, 0.0, 0.0]])
+    T = oracle_mod.Tree(x)
+    xb = np.array([0.125, 0.0625, 0.0625])
+    tie = xb + np.array([0.5, 0.0, 0.0])
+    far = tie.copy()
+    far[0] = np.nextafter(far[0], 1.0)
+    Q = np.stack([tie, far])
+    out, _, pairs = T.apply("A", mu, 1e-3, c=2.0, targets=Q, with_stats=True)
+    assert list(pairs) == [2, 1]
+    exact = oracle_mod.direct("A", x, mu, 1e-3, targets=Q)
+    assert out[0] == pytest.approx(exact[0], rel=1e-14)
+    d = far - xb
+    mono = -(d @ mu.sum(0)) / (FOUR_PI * np.linalg.norm(d) ** 3)
+    assert out[1] == pytest.approx(mono, rel=1e-14)
+    assert out[0] != pytest.approx(out[1], rel=1e-6)
+
+
 def test_treecode_zero_weight_nodes_are_skipped(oracle_mod):
     """A node whose attributes are all zero carries no representative; a
     zero input gives exactly zero with no pair evaluated."""
