@@ -119,9 +119,14 @@ __device__ inline void pair_term(float dx, float dy, float dz, float r2, float4 
         gz += (double)(f * dz);
     } else {
         const float dm = fmaf(dx, v.x, fmaf(dy, v.y, dz * v.z));
-        // both factors masked: at r = 0, ri is infinite
-        const float a3 = take ? ri3 : 0.0f;
-        const float b5 = take ? ri3 * ri2 : 0.0f;
+        // the mask goes on r^2 (one select instead of one per factor): a
+        // lane that does not take the pair gets rsq(inf) = 0, so both
+        // factors are exact zeros (also at r = 0); taken lanes compute
+        // exactly what they would from r^2 itself
+        const float gi = __builtin_amdgcn_rsqf(take ? r2 : __builtin_huge_valf());
+        const float gi2 = gi * gi;
+        const float a3 = gi2 * gi;
+        const float b5 = a3 * gi2;
         const float c5 = 3.0f * dm * b5;
         gx += (double)fmaf(v.x, a3, -c5 * dx);
         gy += (double)fmaf(v.y, a3, -c5 * dy);
