@@ -96,18 +96,23 @@ __device__ inline void pair_term(float dx, float dy, float dz, float r2, float4 
         const float da = fmaf(dx, v.x, fmaf(dy, v.y, dz * v.z));
         const float db = fmaf(dx, tv.x, fmaf(dy, tv.y, dz * tv.z));
         const float ab = fmaf(v.x, tv.x, fmaf(v.y, tv.y, v.z * tv.z));
-        // both factors masked: at r = 0, ri is infinite
-        const float r5 = take ? 3.0f * (ri3 * ri2) : 0.0f;  // 3 / r^5
-        const float r7 = take ? 15.0f * (ri3 * ri2) * ri2 : 0.0f;  // 15 / r^7
+        // masked on r^2 as in G: rsq(inf) = 0 zeroes both factors
+        const float ti = __builtin_amdgcn_rsqf(take ? r2 : __builtin_huge_valf());
+        const float ti2 = ti * ti, ti5 = (ti2 * ti) * ti2;
+        const float r5 = 3.0f * ti5;         // 3 / r^5
+        const float r7 = 15.0f * ti5 * ti2;  // 15 / r^7
         const float q = r7 * da * db;
         gx += (double)fmaf(r5, fmaf(tv.x, da, fmaf(v.x, db, dx * ab)), -q * dx);
         gy += (double)fmaf(r5, fmaf(tv.y, da, fmaf(v.y, db, dy * ab)), -q * dy);
         gz += (double)fmaf(r5, fmaf(tv.z, da, fmaf(v.z, db, dz * ab)), -q * dz);
     } else if (OP == OP_P) {
         const float dm = fmaf(dx, tv.x, fmaf(dy, tv.y, dz * tv.z));
-        // both factors masked: at r = 0 (the target's own point), ri is infinite
-        const float a3 = take ? v.x * ri3 : 0.0f;
-        const float b5 = take ? v.x * (ri3 * ri2) : 0.0f;
+        // masked on r^2 as in G: rsq(inf) = 0 zeroes both factors (also at
+        // r = 0, the target's own point)
+        const float qi = __builtin_amdgcn_rsqf(take ? r2 : __builtin_huge_valf());
+        const float qi2 = qi * qi, qi3 = qi2 * qi;
+        const float a3 = v.x * qi3;
+        const float b5 = v.x * (qi3 * qi2);
         const float c5 = 3.0f * dm * b5;
         gx += (double)fmaf(tv.x, a3, -c5 * dx);
         gy += (double)fmaf(tv.y, a3, -c5 * dy);
