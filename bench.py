@@ -268,8 +268,10 @@ def batched_section(w, stream, iters, w1, w2, c, depth):
     a = mu_b.cpu().numpy()
     b = torch.cat(outs).cpu().numpy()
     flip = float(((a * b).sum(1) <= 0).mean())
+    po = ctx.stats()["prefetch_ops"]
     tile = {"targets_per_lane": ctx.tile(), "prefetch": bool(ctx.prefetch()),
-            "split_visits": ctx.split()}
+            "split_visits": ctx.split(),
+            "prefetch_by_op": {KIND[k]: bool((po >> k) & 1) for k in range(3)}}
     ctx.close()
     one.close()
     return {"clouds": 64, "points": int(off[-1]), "tile": tile, "batched_ms": round(t_batched, 2),
@@ -452,7 +454,8 @@ def main():
         "traversal": per_kind,
         "tile": {"targets_per_lane": ctx.tile(), "prefetch": ctx.prefetch(),
                  "split_visits": ctx.split(), "groups": int(st["n_groups"]),
-                 "tasks_per_launch": int(st["n_tasks"])},
+                 "tasks_per_launch": int(st["n_tasks"]),
+                 "prefetch_by_op": {KIND[k]: bool((st["prefetch_ops"] >> k) & 1) for k in range(3)}},
         "tile_autotune_ms": {f"tpl{k[0]}_pf{k[1]}_split{k[2]}": round(v, 4)
                              for k, v in tile_ms.items()},
         "moments_ms_per_step": round(st_all["moments_ms"], 3),

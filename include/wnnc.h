@@ -149,6 +149,9 @@ typedef struct {
     double combine_ms;      /* summed time of the passes that add the parts of
                                split walks (WNNC_FLAG_TIME_KERNELS); not in
                                traverse_ms */
+    int64_t prefetch_ops;   /* bit k set: operator kind k walks with prefetch
+                               (wnnc_set_prefetch, or per kind by
+                               wnnc_autotune) */
 } wnnc_stats_t;
 
 /* Create a context on HIP device `device`, enqueuing on `stream`
@@ -218,7 +221,8 @@ wnnc_status wnnc_get_split(wnnc_ctx ctx, int *visits);
 /* Software-pipelined node walk in the traversal: the skip successor's
  * record is loaded while the current node is visited (with the far field of
  * order > 0 the walk keeps plain loads).  Results do not depend on it, bit
- * for bit.  Default off; wnnc_autotune may switch it on. */
+ * for bit.  Default off; sets every operator kind (wnnc_autotune may then
+ * choose per kind). */
 wnnc_status wnnc_set_prefetch(wnnc_ctx ctx, int on);
 
 /* Autotuner: times three iterations of Alg. 3 at width w from mu = 0 (the
@@ -228,8 +232,11 @@ wnnc_status wnnc_set_prefetch(wnnc_ctx ctx, int on);
  * (tpl, split) = (1, 0), (2, 0), (4, 0), (1, 1024), (1, 512), (1, 256),
  * each with prefetch off and on (in that order).  times_out (host,
  * WNNC_AUTOTUNE_CONFIGS entries, may be NULL) receives the settings and
- * their times per iteration.  Overwrites the context's iteration buffers.
- * Synchronizes. */
+ * their times per iteration.  Then, on the chosen tiles, each operator
+ * kind takes the other prefetch setting if its traversal launches are
+ * faster with it by more than 1 % (see wnnc_stats_t.prefetch_ops).
+ * Overwrites the context's iteration buffers; instrumentation statistics
+ * are kept.  Synchronizes. */
 #define WNNC_AUTOTUNE_CONFIGS 12
 typedef struct {
     int tpl;

@@ -87,14 +87,16 @@ class Stats(ctypes.Structure):
                 ("traverse_ms", ctypes.c_double * 5), ("moments_ms", ctypes.c_double),
                 ("build_ms", ctypes.c_double), ("n_clouds", ctypes.c_int64),
                 ("tile", ctypes.c_int64), ("n_groups", ctypes.c_int64),
-                ("n_tasks", ctypes.c_int64), ("combine_ms", ctypes.c_double)]
+                ("n_tasks", ctypes.c_int64), ("combine_ms", ctypes.c_double),
+                ("prefetch_ops", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return dict(n_points=self.n_points, n_nodes=self.n_nodes, calls=list(self.calls),
                     pairs=list(self.pairs), traverse_ms=list(self.traverse_ms),
                     moments_ms=self.moments_ms, build_ms=self.build_ms,
                     n_clouds=self.n_clouds, tile=self.tile, n_groups=self.n_groups,
-                    n_tasks=self.n_tasks, combine_ms=self.combine_ms)
+                    n_tasks=self.n_tasks, combine_ms=self.combine_ms,
+                    prefetch_ops=self.prefetch_ops)
 
 
 _lib = None

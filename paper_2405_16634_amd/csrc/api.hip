@@ -165,7 +165,12 @@ wnnc_status run_moments(wnnc_ctx_s *c, MomMode mode, const MomArgs &a) {
     return WNNC_OK;
 }
 
-wnnc_status run_traverse(wnnc_ctx_s *c, Op op, TravMode mode, const TravArgs &a) {
+// The walk an operator kind uses: the prefetching one or the plain one.
+int prefetch_of(const wnnc_ctx_s *c, Op op) { return c->pf_op[op] >= 0 ? c->pf_op[op] : c->prefetch; }
+
+wnnc_status run_traverse(wnnc_ctx_s *c, Op op, TravMode mode, const TravArgs &args) {
+    TravArgs a = args;
+    a.prefetch = prefetch_of(c, op);
     Timed tm(c, (int)op);
     HIPCHK(launch_traverse(c, op, mode, (c->flags & WNNC_FLAG_COUNT_PAIRS) != 0, a));
     tm.done();
@@ -532,6 +537,7 @@ wnnc_status wnnc_get_tile(wnnc_ctx ctx, int *tpl) {
 wnnc_status wnnc_set_prefetch(wnnc_ctx ctx, int on) {
     CHECK_CTX(ctx);
     ctx->prefetch = on ? 1 : 0;
+    for (int k = 0; k < kOpKinds; ++k) ctx->pf_op[k] = -1;
     return WNNC_OK;
 }
 
@@ -543,6 +549,7 @@ wnnc_status wnnc_autotune(wnnc_ctx ctx, float w, wnnc_tile_time *times_out) {
     CHECK_CTX(ctx);
     CHECK_BUILT(ctx);
     if (!finite_nonneg(w)) return fail(WNNC_EINVAL, "w must be finite and >= 0");
+    for (int k = 0; k < kOpKinds; ++k) ctx->pf_op[k] = -1;
     // (tpl, split) pairs, each with and without prefetch
     static const int cand[WNNC_AUTOTUNE_CONFIGS / 2][2] = {
         {1, 0}, {2, 0}, {4, 0}, {1, 1024}, {1, 512}, {1, 256}};
@@ -595,6 +602,57 @@ wnnc_status wnnc_autotune(wnnc_ctx ctx, float w, wnnc_tile_time *times_out) {
     ctx->prefetch = best_pf;
     hipError_t e = make_tasks(ctx, best, best_split);
     if (e != hipSuccess) return fail(WNNC_EDEVICE, "tasks: %s", hipGetErrorString(e));
+    // Then the walk per operator on the chosen tiles: the same iterations
+    // with each operator's traversal launches timed (the events ride on the
+    // launches), without and with prefetch; an operator takes the other
+    // walk than the chosen one only if that is faster by more than 1 %.  The
+    // caller's instrumentation is put back afterwards.
+    double t_op[2][kOpKinds] = {};
+    {
+        const unsigned saved_flags = ctx->flags;
+        std::vector<wnnc_ctx_s::Timed> saved_pending;
+        saved_pending.swap(ctx->pending);
+        double saved_ms[kOpKinds];
+        int64_t saved_calls[kOpKinds];
+        for (int k = 0; k < kOpKinds; ++k) saved_ms[k] = ctx->trav_ms[k], saved_calls[k] = ctx->calls[k];
+        wnnc_status st = WNNC_OK;
+        for (int pf = 0; pf < 2 && st == WNNC_OK; ++pf) {
+            ctx->prefetch = pf;
+            for (int k = 0; k < kOpKinds; ++k) t_op[pf][k] = 1e300;
+            for (int rep = 0; rep <= kTuneReps && st == WNNC_OK; ++rep) {
+                ctx->flags = rep > 0 ? WNNC_FLAG_TIME_TRAVERSAL : 0u;
+                hipError_t he = launch_zero_f4(ctx->va.p, ctx->n, ctx->stream);
+                if (he == hipSuccess) {
+                    st = run_iterations(ctx, kTuneIters, w, w, 1, kTuneIters, true, nullptr,
+                                        WNNC_SCHEDULE_LINEAR, nullptr);
+                    he = hipStreamSynchronize(ctx->stream);
+                }
+                if (he != hipSuccess && st == WNNC_OK)
+                    st = fail(WNNC_EDEVICE, "autotune: %s", hipGetErrorString(he));
+                double sum[kOpKinds] = {};
+                for (auto &t : ctx->pending) {
+                    float ms = 0.f;
+                    if (st == WNNC_OK && t.kind < kOpKinds &&
+                        hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess)
+                        sum[t.kind] += ms;
+                    ctx->event_pool.push_back(t.a);
+                    ctx->event_pool.push_back(t.b);
+                }
+                ctx->pending.clear();
+                if (rep > 0)
+                    for (int k = 0; k < kOpKinds; ++k) t_op[pf][k] = std::min(t_op[pf][k], sum[k]);
+            }
+        }
+        ctx->flags = saved_flags;
+        ctx->pending.swap(saved_pending);
+        for (int k = 0; k < kOpKinds; ++k) ctx->trav_ms[k] = saved_ms[k], ctx->calls[k] = saved_calls[k];
+        ctx->prefetch = best_pf;
+        if (st != WNNC_OK) return st;
+    }
+    for (int k = 0; k < kOpKinds; ++k) {
+        const int other = 1 - best_pf;
+        if (t_op[other][k] > 0.0 && t_op[other][k] < 0.99 * t_op[best_pf][k]) ctx->pf_op[k] = other;
+    }
     return WNNC_OK;
 }
 
@@ -662,6 +720,7 @@ wnnc_status wnnc_winding_at(wnnc_ctx ctx, const float *n, const float *sigma, fl
     ta.nslots = ng;
     ta.tpl = 1;
     {
+        ta.prefetch = prefetch_of(ctx, OP_A);
         Timed tm(ctx, (int)OP_A);
         HIPCHK(launch_traverse(ctx, OP_A, TR_OUT_CALLER, (ctx->flags & WNNC_FLAG_COUNT_PAIRS) != 0, ta));
         tm.done();
@@ -1106,6 +1165,8 @@ wnnc_status wnnc_stats(wnnc_ctx ctx, wnnc_stats_t *out) {
     out->tile = ctx->tpl | (ctx->prefetch << 8) | ((int64_t)ctx->split << 16);
     out->n_groups = ctx->built ? ctx->ngroups : 0;
     out->n_tasks = ctx->built ? ctx->ntasks : 0;
+    for (int k = 0; k < kOpKinds; ++k)
+        if (prefetch_of(ctx, (Op)k)) out->prefetch_ops |= int64_t(1) << k;
     return WNNC_OK;
 }
 

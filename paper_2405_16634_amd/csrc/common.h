@@ -89,6 +89,8 @@ struct wnnc_ctx_s {
     // combining pass (only for tpl = 1).
     int tpl = 1;
     int prefetch = 0;
+    // per operator kind: -1 follows `prefetch`, else the autotuner's choice
+    int pf_op[wnnc::kOpKinds] = {-1, -1, -1, -1, -1};
     int split = 256;               // node visits per part of a split walk (0: whole walks)
     int ntasks = 0;                // tasks launched per traversal
     int ngroups = 0;               // groups (per-group partial sums)

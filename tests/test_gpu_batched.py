@@ -242,6 +242,17 @@ def test_autotune_keeps_the_fastest(dev):
             best = key
     assert (ctx.tile(), int(ctx.prefetch()), ctx.split()) == best
     assert 0.99 * ms[best] <= min(ms.values())
+    # per operator kind the walk may differ from the chosen one; the
+    # position-gradient kinds, which the tuning iterations do not run,
+    # follow it
+    po = ctx.stats()["prefetch_ops"]
+    assert 0 <= po < 32
+    for k in (3, 4):
+        assert (po >> k) & 1 == int(ctx.prefetch())
+    ctx.set_prefetch(False)
+    assert ctx.stats()["prefetch_ops"] == 0
+    ctx.set_prefetch(True)
+    assert ctx.stats()["prefetch_ops"] == 31
     ctx.close()
 
 
