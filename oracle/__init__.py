@@ -63,6 +63,9 @@ def _load():
     lib.or_tree_apply_tv.argtypes = [ctypes.c_void_p, ctypes.c_int, d, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_int, ctypes.c_int, d, i64, d, d,
                                      d, p64]
+    lib.or_tree_apply_margins.argtypes = [ctypes.c_void_p, ctypes.c_int, d, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_int, ctypes.c_int, d, i64, d,
+                                          d, d, p64, d]
     lib.or_tree_apply_order.argtypes = [ctypes.c_void_p, ctypes.c_int, d, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_int, ctypes.c_int, d, i64, d,
                                         d, p64]
@@ -189,11 +192,17 @@ class Tree:
         return xB, (nuB[:, 0] if dim == 1 else nuB), W
 
     def apply(self, op: str, nu, w: float, c: float = 2.0, targets=None, with_stats: bool = False,
-              order: int = 0, wsafe: bool = False, tvec=None):
+              order: int = 0, wsafe: bool = False, tvec=None, with_margins: bool = False):
         """Treecode operator; returns out (and per-target magnitude sums and
         pair counts with with_stats).  order 1 or 2 replaces each accepted
         node's representative term by the Taylor expansion of the pair term
-        about x_B to that order (the higher-order far field; 0 is Alg. 4)."""
+        about x_B to that order (the higher-order far field; 0 is Alg. 4).
+
+        with_margins appends, per target, the decision margins (n_targets, 2):
+        column 0 the smallest |dist - thr| / thr over the acceptance tests of
+        Alg. 4 it evaluated, column 1 the smallest |r - w| / w over the pair
+        terms it formed (the cutoff of Sec. 4.4; inf for w = 0).  Diagnostics
+        only: the result does not depend on them."""
         lib = _load()
         o = _OPS[op]
         nu = _f64(nu, (self.n, 3) if o not in (OP_AT, OP_P) else (self.n,))
@@ -207,12 +216,17 @@ class Tree:
         pairs = np.zeros(t.shape[0], np.int64)
         if order not in (0, 1, 2):
             raise ValueError("order must be 0, 1 or 2")
-        lib.or_tree_apply_tv(self._h, o, _dp(nu), float(w), float(c), int(order),
-                             int(bool(wsafe)), _dp(t), t.shape[0],
-                             _dp(tv) if tv is not None else None, _dp(out), _dp(mag),
-                             pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+        margins = np.zeros((t.shape[0], 2)) if with_margins else None
+        lib.or_tree_apply_margins(self._h, o, _dp(nu), float(w), float(c), int(order),
+                                  int(bool(wsafe)), _dp(t), t.shape[0],
+                                  _dp(tv) if tv is not None else None, _dp(out), _dp(mag),
+                                  pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                  _dp(margins) if margins is not None else None)
         out = out[:, 0] if dout == 1 else out
-        return (out, mag, pairs) if with_stats else out
+        res = (out, mag, pairs) if with_stats else (out,)
+        if with_margins:
+            res = res + (margins,)
+        return res if len(res) > 1 else res[0]
 
 
 def winding_grad_x(x, mu, g, w: float, backend: str = "direct", c: float = 2.0, tree=None):

@@ -481,9 +481,26 @@ static void far_term(const or_tree *T, const apply_args *a, int64_t id, const do
     *mag += sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
 }
 
-/* Alg. 4 for one target xt (with its vector tv for P) starting at node id. */
+/* Decision margins of one target (diagnostics; they change no result):
+ * mg[0] = the smallest |dist - thr| / thr over the acceptance tests the
+ * target evaluated (thr the distance Alg. 4 compares with), mg[1] = the
+ * smallest |r - w| / w over the pair terms it formed, representatives and
+ * points alike (the cutoff of Sec. 4.4; only for w > 0).  A decision whose
+ * margin is far below one is one that a few roundings of the distance can
+ * turn. */
+static void note_margin(double *mg, int k, double r, double thr)
+{
+    if (mg && thr > 0.0) {
+        double m = fabs(r - thr) / thr;
+        if (m < mg[k])
+            mg[k] = m;
+    }
+}
+
+/* Alg. 4 for one target xt (with its vector tv for P) starting at node id;
+ * mg (NULL or 2 doubles) collects the decision margins. */
 static void apply_node(const or_tree *T, const apply_args *a, int64_t id, const double *xt,
-                       const double *tv, double *acc, double *mag, int64_t *pairs)
+                       const double *tv, double *acc, double *mag, int64_t *pairs, double *mg)
 {
     const or_node *B = &T->nodes[id];
     if (T->rep_w[id] == 0.0)
@@ -492,16 +509,26 @@ static void apply_node(const or_tree *T, const apply_args *a, int64_t id, const 
     double dx = xt[0] - xB[0], dy = xt[1] - xB[1], dz = xt[2] - xB[2];
     double dist = sqrt(dx * dx + dy * dy + dz * dz);
     double width = ldexp(2.0, -B->depth);
-    if (dist > a->c * width && (!a->wsafe || dist > a->w + sqrt(3.0) * width)) {
+    double thr = a->c * width;
+    if (a->wsafe && a->w + sqrt(3.0) * width > thr)
+        thr = a->w + sqrt(3.0) * width;
+    note_margin(mg, 0, dist, thr);
+    if (dist > thr) {
+        note_margin(mg, 1, dist, a->w);
         far_term(T, a, id, xt, tv, acc, mag);
         (*pairs)++;
     } else if (!B->leaf) {
         for (int k = 0; k < B->nchild; ++k)
-            apply_node(T, a, B->child[k], xt, tv, acc, mag, pairs);
+            apply_node(T, a, B->child[k], xt, tv, acc, mag, pairs, mg);
     } else {
         for (int64_t m = B->begin; m < B->end; ++m) {
             int64_t j = T->order[m];
-            pair_term(a->op, xt, T->x + 3 * j, a->nu + a->din * j, tv, a->w, acc, mag);
+            const double *xj = T->x + 3 * j;
+            if (mg) {
+                double ex = xt[0] - xj[0], ey = xt[1] - xj[1], ez = xt[2] - xj[2];
+                note_margin(mg, 1, sqrt(ex * ex + ey * ey + ez * ez), a->w);
+            }
+            pair_term(a->op, xt, xj, a->nu + a->din * j, tv, a->w, acc, mag);
             (*pairs)++;
         }
     }
@@ -516,10 +543,12 @@ static void apply_node(const or_tree *T, const apply_args *a, int64_t id, const 
  * (far_term); `wsafe` accepts a node only if, besides Alg. 4's test, the
  * target is farther than w + sqrt(3) width from x_B: x_B lies in the
  * node's cell, whose points are all within sqrt(3) width of it, so no
- * accepted node holds a point the cutoff w would drop. */
-void or_tree_apply_tv(or_tree *T, int op, const double *nu, double w, double c, int order,
-                      int wsafe, const double *tgt, int64_t n_tgt, const double *tv,
-                      double *out, double *mag, int64_t *pairs)
+ * accepted node holds a point the cutoff w would drop.
+ * margins (optional, (n_tgt, 2)): per target the decision margins of
+ * note_margin. */
+void or_tree_apply_margins(or_tree *T, int op, const double *nu, double w, double c, int order,
+                           int wsafe, const double *tgt, int64_t n_tgt, const double *tv,
+                           double *out, double *mag, int64_t *pairs, double *margins)
 {
     int din = op_in_dim(op), dout = op_out_dim(op);
     if (op == OR_OP_P || op == OR_OP_T)
@@ -532,7 +561,10 @@ void or_tree_apply_tv(or_tree *T, int op, const double *nu, double w, double c, 
     for (int64_t i = 0; i < n_tgt; ++i) {
         double acc[3] = {0, 0, 0}, m = 0.0;
         int64_t np = 0;
-        apply_node(T, &a, 0, tgt + 3 * i, tv ? tv + 3 * i : NULL, acc, &m, &np);
+        double *mg = margins ? margins + 2 * i : NULL;
+        if (mg)
+            mg[0] = mg[1] = HUGE_VAL;
+        apply_node(T, &a, 0, tgt + 3 * i, tv ? tv + 3 * i : NULL, acc, &m, &np, mg);
         for (int k = 0; k < dout; ++k)
             out[dout * i + k] = acc[k];
         if (mag)
@@ -540,6 +572,14 @@ void or_tree_apply_tv(or_tree *T, int op, const double *nu, double w, double c, 
         if (pairs)
             pairs[i] = np;
     }
+}
+
+/* Treecode operator without the decision margins. */
+void or_tree_apply_tv(or_tree *T, int op, const double *nu, double w, double c, int order,
+                      int wsafe, const double *tgt, int64_t n_tgt, const double *tv,
+                      double *out, double *mag, int64_t *pairs)
+{
+    or_tree_apply_margins(T, op, nu, w, c, order, wsafe, tgt, n_tgt, tv, out, mag, pairs, NULL);
 }
 
 void or_tree_apply_order(or_tree *T, int op, const double *nu, double w, double c, int order,

@@ -19,6 +19,55 @@ def exact_sphere(n):
     return x
 
 
+# ------------------------------------------------------- Sec. 5.1.1 input --
+
+def test_normalize_by_hand(oracle_mod):
+    """Sec. 5.1.1 reading: centre = midpoint of the bounding box, one uniform
+    scale so that the largest half-extent is 10/11.  Points (0,0,0) and
+    (2,4,6): centre (1,2,3), largest half-extent 3, scale (10/11)/3, and the
+    extreme z coordinates become -10/11 and +10/11."""
+    p = np.array([[0.0, 0.0, 0.0], [2.0, 4.0, 6.0]], np.float32)
+    x, centre, scale = oracle_mod.normalize(p)
+    assert np.array_equal(centre, [1.0, 2.0, 3.0])
+    assert scale == pytest.approx((10.0 / 11.0) / 3.0, rel=1e-15)
+    assert x.dtype == np.float32
+    assert x[0, 2] == np.float32(-10.0 / 11.0) and x[1, 2] == np.float32(10.0 / 11.0)
+    # uniform scale: the aspect ratio 1:2:3 is kept
+    assert np.array_equal(x[1], np.float32([10.0 / 33.0, 20.0 / 33.0, 10.0 / 11.0]))
+
+
+def test_normalize_centre_is_the_box_midpoint_not_the_mean(oracle_mod):
+    """An off-centre cloud (mean != midpoint): four points at x = 0 and one
+    at x = 10 (mean 2, midpoint 5); the extremes map to -10/11 and 10/11,
+    and y, z (extent 1) keep the scale of x (1/11 per unit)."""
+    p = np.array([[0, 0, 0], [0, 1, 0], [0, 0, 1], [0, 1, 1], [10, 0.5, 0.5]], np.float32)
+    x, centre, scale = oracle_mod.normalize(p)
+    assert centre[0] == 5.0 and centre[1] == 0.5 and centre[2] == 0.5
+    assert scale == pytest.approx(2.0 / 11.0, rel=1e-15)
+    assert x[0, 0] == np.float32(-10.0 / 11.0) and x[4, 0] == np.float32(10.0 / 11.0)
+    assert x[1, 1] == np.float32(1.0 / 11.0) and x[0, 1] == np.float32(-1.0 / 11.0)
+    assert np.abs(x).max() == np.float32(10.0 / 11.0)
+
+
+def test_normalize_is_invariant_to_exact_affine_changes(oracle_mod):
+    """Translating by a dyadic vector and scaling by a power of two change
+    neither the FP32 result (every step is exact), and the largest
+    half-extent always lands on 10/11."""
+    rng = np.random.default_rng(5)
+    # coordinates on a grid of 1/1024 with at most 14 significant bits, so
+    # the change below and the normalization's differences are exact
+    p = (rng.integers(-3000, 7000, size=(500, 3)) / 1024.0).astype(np.float32)
+    x0, c0, s0 = oracle_mod.normalize(p)
+    t = np.array([0.5, -2.25, 16.0])
+    q = (p.astype(np.float64) * 8.0 + t).astype(np.float32)
+    assert np.array_equal((q.astype(np.float64) - t) / 8.0, p)
+    x1, c1, s1 = oracle_mod.normalize(q)
+    assert np.array_equal(c1, 8.0 * c0 + t) and s1 == s0 / 8.0
+    assert np.array_equal(x1, x0)
+    half = (x0.max(0).astype(np.float64) - x0.min(0)) / 2
+    assert half.max() == pytest.approx(10.0 / 11.0, rel=1e-7)
+
+
 # ----------------------------------------------------------------- Thm. 1 --
 
 @pytest.mark.parametrize("n", [500, 2000])
@@ -267,6 +316,35 @@ def test_accept_test_is_strict_at_a_tie(oracle_mod):
     mono = -(d @ mu.sum(0)) / (FOUR_PI * np.linalg.norm(d) ** 3)
     assert out[1] == pytest.approx(mono, rel=1e-14)
     assert out[0] != pytest.approx(out[1], rel=1e-6)
+
+
+def test_decision_margins_by_hand(oracle_mod):
+    """The decision margins the oracle reports per target (diagnostics for
+    the parity bar): at the acceptance tie above the smallest relative
+    margin |dist - c width| / (c width) is exactly 0, one ulp farther it is
+    that ulp over c width = 1/2; two points exactly w apart (dyadic, so the
+    distance is exact) sit on the cutoff of Sec. 4.4: margin 0, and the pair
+    is kept (only |y| < w is dropped)."""
+    x = np.array([[0.0625, 0.0625, 0.0625], [0.1875, 0.0625, 0.0625]])
+    mu = np.array([[0.01, 0.0, 0.0], [0.01, 0.0, 0.0]])
+    T = oracle_mod.Tree(x)
+    tie = np.array([0.625, 0.0625, 0.0625])
+    far = tie.copy()
+    far[0] = np.nextafter(far[0], 1.0)
+    out, mg = T.apply("A", mu, 1e-3, c=2.0, targets=np.stack([tie, far]), with_margins=True)
+    assert mg[0, 0] == 0.0
+    assert mg[1, 0] == (far[0] - tie[0]) / 0.5
+    # the results do not depend on the diagnostics
+    assert np.array_equal(out, T.apply("A", mu, 1e-3, c=2.0, targets=np.stack([tie, far])))
+    y = np.array([[0.0, 0.0, 0.0], [0.125, 0.0, 0.0]])
+    m2 = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0]])
+    T2 = oracle_mod.Tree(y)
+    s, mg2 = T2.apply("A", m2, 0.125, c=2.0, with_margins=True)
+    assert mg2[0, 1] == 0.0
+    assert s[0] == pytest.approx(-(-0.125) / (FOUR_PI * 0.125 ** 3), rel=1e-15)
+    # w = 0: no cutoff, no cutoff margin
+    _, mg3 = T2.apply("A", m2, 0.0, c=2.0, with_margins=True)
+    assert np.all(np.isinf(mg3[:, 1]))
 
 
 def test_treecode_zero_weight_nodes_are_skipped(oracle_mod):
