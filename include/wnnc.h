@@ -271,6 +271,20 @@ wnnc_status wnnc_gradient(wnnc_ctx ctx, const float *n, const float *sigma, floa
  * |s|-weighted representatives). */
 wnnc_status wnnc_adjoint(wnnc_ctx ctx, const float *s, float w, float *out);
 
+/* The energy that the gradient step of Alg. 2 descends (Sec. 4.3),
+ * E(mu) = ||A_w mu - b||^2 with b_i = 1/2 (the winding number of the
+ * surface points), and, optionally, its gradient: with rho = b - A_w mu and
+ * r = A_w^T rho (the r of Alg. 2), dE/dmu = -2 r.
+ * mu (N,3) device, caller order.  E_out (host, may be NULL): E, the FP64 sum
+ * over every point of the tree (all clouds of a batched tree) of the FP32
+ * rho_i^2, as in the iteration.  grad_out ((N,3) device, caller order, may
+ * be NULL): gscale * dE/dmu = -2 gscale r (gscale the caller's chain-rule
+ * factor, 1 for dE/dmu itself).  The treecode A^T is used as the adjoint
+ * (with the treecode it is the gradient of E up to the treecode's
+ * approximation error).  Synchronizes when E_out is given. */
+wnnc_status wnnc_energy(wnnc_ctx ctx, const float *mu, float w, double gscale, double *E_out,
+                        float *grad_out);
+
 /* Gradient of L = sum_i g_i s_i, s = A_w(mu) (wnnc_winding), with respect to
  * the point positions (an extension: differentiable winding numbers in the
  * points).  Differentiating each pair term of A in both of its end points
@@ -440,10 +454,18 @@ typedef struct {
                              the prediction [0.4]; near 1/2 the prediction
                              carried no information and the result is
                              not trusted */
+    int max_iters;        /* "until convergence" [0: off]: when > iters, the
+                             warm schedule is followed by further iterations
+                             at width w1, one at a time, while some cloud's
+                             last WNNC update turned more than stop_frac of
+                             its points against mu (sign changes), up to
+                             max_iters iterations in all; the self-checks
+                             then use the last iteration */
+    float stop_frac;      /* sign-change fraction that counts as converged [0] */
 } wnnc_warm_opts;
 
 typedef struct {
-    int iterations;       /* iterations run (warm + fallback) */
+    int iterations;       /* iterations run (warm + until convergence + fallback) */
     int fallback;         /* 1 if the plain method was rerun */
     double max_disagree;  /* worst per-cloud update self-check fraction */
     double max_pred_disagree; /* worst per-cloud fraction of results against
@@ -453,10 +475,12 @@ typedef struct {
 /* Learned warm start on the built tree (every cloud): neighbourhood
  * features -> MLP unit normals n -> per cloud mu0 = beta n with the
  * least-squares scale beta = <A n, 1/2> / |A n|^2 -> `iters` iterations of
- * Alg. 3 with the warm schedule -> self-checks (the last update and the
- * agreement with the prediction, per cloud); when either fails, the plain
- * method from mu = 0.  mu_out (N,3) as wnnc_orient.  report (host) may be
- * NULL.  Synchronizes once (the self-check). */
+ * Alg. 3 with the warm schedule (then, with max_iters, iterations until the
+ * sign changes stop) -> self-checks (the last update and the agreement with
+ * the prediction, per cloud); when either fails, the plain method from
+ * mu = 0.  mu_out (N,3) as wnnc_orient.  report (host) may be NULL.
+ * Synchronizes once (the self-check), and once more per iteration run
+ * until convergence. */
 wnnc_status wnnc_warm_orient(wnnc_ctx ctx, const float *params, const wnnc_warm_opts *opts,
                              float *mu_out, wnnc_warm_report *report);
 

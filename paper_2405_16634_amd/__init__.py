@@ -37,7 +37,7 @@ EXPORTED = [
     "wnnc_mlp_forward", "wnnc_mlp_grad", "wnnc_mlp_adam",
     "wnnc_warm_orient", "wnnc_set_prefetch", "wnnc_set_split", "wnnc_get_split",
     "wnnc_winding_at", "wnnc_set_far_field", "wnnc_get_far_field", "wnnc_winding_grad_x",
-    "wnnc_gradient_grad_x",
+    "wnnc_gradient_grad_x", "wnnc_energy",
 ]
 MLP_PARAMS = 7491
 AUTOTUNE_CONFIGS = 12
@@ -68,7 +68,8 @@ PRESETS = {"default": 0, "noise_0.25": 1, "noise_0.5": 2, "noise_1": 3, "scan": 
 class WarmOpts(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("w1", ctypes.c_float), ("w2", ctypes.c_float),
                 ("max_disagree", ctypes.c_float), ("fallback_iters", ctypes.c_int),
-                ("fallback_w2", ctypes.c_float), ("max_pred_disagree", ctypes.c_float)]
+                ("fallback_w2", ctypes.c_float), ("max_pred_disagree", ctypes.c_float),
+                ("max_iters", ctypes.c_int), ("stop_frac", ctypes.c_float)]
 
 
 class WarmReport(ctypes.Structure):
@@ -123,6 +124,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "wnnc_winding_at": [vp, vp, vp, f32, vp, i64, vp],
         "wnnc_gradient": [vp, vp, vp, f32, vp],
         "wnnc_adjoint": [vp, vp, f32, vp],
+        "wnnc_energy": [vp, vp, f32, dbl, P(dbl), vp],
         "wnnc_orient": [vp, P(OrientOpts), vp, vp],
         "wnnc_orient_energy": [vp, P(dbl), ctypes.c_int],
         "wnnc_stats": [vp, P(Stats)],
@@ -316,6 +318,18 @@ def wnnc_adjoint(ctx, s, w: float, out) -> None:
                                        _dev(out, "out", shape=(N, 3))))
 
 
+def wnnc_energy(ctx, mu, w: float, gscale: float = 1.0, want_energy: bool = True,
+                grad_out=None):
+    """E = ||A_w mu - 1/2||^2 (returned when want_energy, else None) and, into
+    grad_out (N,3) if given, gscale * dE/dmu = -2 gscale A_w^T (1/2 - A_w mu)."""
+    N = mu.shape[0]
+    e = ctypes.c_double(0.0)
+    _check(load_library().wnnc_energy(ctx, _dev(mu, "mu", shape=(N, 3)), float(w), float(gscale),
+                                      ctypes.byref(e) if want_energy else None,
+                                      _dev(grad_out, "grad_out", shape=(N, 3))))
+    return e.value if want_energy else None
+
+
 def wnnc_orient(ctx, mu_out, mu0=None, iters: int = 40, w1: float = 0.002, w2: float = 0.016,
                 start_iter: int = 1, stop_iter: int = 0, schedule: str = "linear",
                 areas=None) -> None:
@@ -408,10 +422,11 @@ def wnnc_mlp_adam(ctx, params, m, v, grad, step: int, lr: float = 1e-3, beta1: f
 
 def wnnc_warm_orient(ctx, params, mu_out, iters: int = 6, w1: float = 0.002, w2: float = 0.016,
                      max_disagree: float = 0.005, fallback_iters: int = 40,
-                     fallback_w2: float = 0.016, max_pred_disagree: float = 0.4) -> dict:
+                     fallback_w2: float = 0.016, max_pred_disagree: float = 0.4,
+                     max_iters: int = 0, stop_frac: float = 0.0) -> dict:
     N = mu_out.shape[0]
     opts = WarmOpts(int(iters), float(w1), float(w2), float(max_disagree), int(fallback_iters),
-                    float(fallback_w2), float(max_pred_disagree))
+                    float(fallback_w2), float(max_pred_disagree), int(max_iters), float(stop_frac))
     rep = WarmReport()
     _check(load_library().wnnc_warm_orient(ctx, _dev(params, "params", shape=(MLP_PARAMS,)),
                                            ctypes.byref(opts), _dev(mu_out, "mu_out", shape=(N, 3)),

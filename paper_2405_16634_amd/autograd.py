@@ -7,6 +7,8 @@ The adjoint operator is the backward of the winding-number operator
 * ``adjoint(ctx, s, w)``    v = A_w^T s          backward: g -> A_w g
 * ``gradient(ctx, mu, w)``  grad F = -G_w(mu)    backward: g -> -G_w g
   (G is symmetric: HPhi is an even, symmetric matrix field)
+* ``pgr_energy(ctx, mu, w)``  E = ||A_w mu - 1/2||^2   backward: g -> -2 g r
+  (r of Alg. 2; both from wnnc_energy)
 * ``winding_at_points(ctx, x, mu, w)``  s = A_w(mu) on the tree built from
   the normalized points x; differentiable in x and mu (an extension:
   backward in x is wnnc_winding_grad_x, g -> g grad F + p)
@@ -23,8 +25,8 @@ from __future__ import annotations
 
 import torch
 
-from . import (wnnc_adjoint, wnnc_build, wnnc_gradient, wnnc_gradient_grad_x, wnnc_winding,
-               wnnc_winding_grad_x)
+from . import (wnnc_adjoint, wnnc_build, wnnc_energy, wnnc_gradient, wnnc_gradient_grad_x,
+               wnnc_winding, wnnc_winding_grad_x)
 
 
 def _prep(t):
@@ -95,11 +97,29 @@ def gradient(ctx, mu, w: float):
     return WindingGradient.apply(_handle(ctx), mu, w)
 
 
-def pgr_energy(ctx, mu, w: float, b: float = 0.5):
-    """E(mu) = ||A_w mu - b||^2 (eq. value-energy); its autograd gradient is
-    2 A_w^T (A_w mu - b) = -2 r of Alg. 2."""
-    s = winding(ctx, mu, w)
-    return ((s - b) ** 2).sum()
+class PgrEnergy(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, handle, mu, w):
+        fctx.handle, fctx.w = handle, float(w)
+        m = _prep(mu)
+        fctx.save_for_backward(m)
+        E = wnnc_energy(handle, m, fctx.w)
+        return torch.tensor(E, dtype=torch.float64, device=mu.device)
+
+    @staticmethod
+    def backward(fctx, g):
+        (m,) = fctx.saved_tensors
+        gm = torch.empty_like(m)
+        # the chain-rule factor goes to the library as a host scalar
+        wnnc_energy(fctx.handle, m, fctx.w, gscale=float(g), want_energy=False, grad_out=gm)
+        return None, gm, None
+
+
+def pgr_energy(ctx, mu, w: float):
+    """E(mu) = ||A_w mu - b||^2 with b = 1/2 (the energy of Alg. 2's gradient
+    step), evaluated by the library (wnnc_energy); its gradient is
+    2 A_w^T (A_w mu - b) = -2 r of Alg. 2, also from the library."""
+    return PgrEnergy.apply(_handle(ctx), mu, w)
 
 
 class WindingPositions(torch.autograd.Function):

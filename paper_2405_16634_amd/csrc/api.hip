@@ -148,6 +148,7 @@ TravArgs trav_args(wnnc_ctx_s *c, float w) {
     a.w2 = fmaxf((float)((double)w * (double)w), FLT_MIN);
     a.order = c->far_order;
     a.momhi = c->far_order > 0 ? c->momhi.p : nullptr;
+    a.oscale = 1.0;
     return a;
 }
 
@@ -750,17 +751,18 @@ wnnc_status wnnc_gradient(wnnc_ctx ctx, const float *n, const float *sigma, floa
     return run_traverse(ctx, OP_G, TR_OUT_CALLER, ta);
 }
 
-wnnc_status wnnc_winding_grad_x(wnnc_ctx ctx, const float *n, const float *sigma, float w,
-                                const float *g, float *dx_out) {
-    CHECK_CTX(ctx);
-    CHECK_BUILT(ctx);
+}  // extern "C"
+
+// The position gradient of sum_i g_i A(mu)_i (wnnc_winding_grad_x) with the
+// caller-order grad F kept in `gradf` (3 N floats of scratch); allocates
+// nothing after a build.
+static wnnc_status winding_grad_x_impl(wnnc_ctx ctx, const float *n, const float *sigma, float w,
+                                       const float *g, float *dx_out, float *gradf) {
     if (!n || !g || !dx_out) return fail(WNNC_EINVAL, "null pointer");
     if (!finite_nonneg(w)) return fail(WNNC_EINVAL, "w must be finite and >= 0");
     RETURN_IF(check_finite(ctx, n, 3 * ctx->n, "n"));
     RETURN_IF(check_finite(ctx, sigma, ctx->n, "sigma"));
     RETURN_IF(check_finite(ctx, g, ctx->n, "g"));
-    const int64_t N = ctx->n;
-    HIPCHK(ctx->gradf.ensure(3 * N));
     // grad F(x_k; mu), caller order
     MomArgs ma = mom_args(ctx, w, true);
     ma.cn = n;
@@ -771,7 +773,7 @@ wnnc_status wnnc_winding_grad_x(wnnc_ctx ctx, const float *n, const float *sigma
     ta.order = 0;
     ta.momhi = nullptr;
     ta.src4 = ctx->va.p;
-    ta.out = ctx->gradf.p;
+    ta.out = gradf;
     RETURN_IF(run_traverse(ctx, OP_G, TR_OUT_CALLER, ta));
     // p: sources g, each target with its own mu (sorted, kept in va)
     MomArgs mb = mom_args(ctx, w, true);
@@ -784,9 +786,19 @@ wnnc_status wnnc_winding_grad_x(wnnc_ctx ctx, const float *n, const float *sigma
     tb.srcs = ctx->rho.p;
     tb.tvec = ctx->va.p;
     tb.gc = g;
-    tb.gradf = ctx->gradf.p;
+    tb.gradf = gradf;
     tb.out = dx_out;
     return run_traverse(ctx, OP_P, TR_POSGRAD, tb);
+}
+
+extern "C" {
+
+wnnc_status wnnc_winding_grad_x(wnnc_ctx ctx, const float *n, const float *sigma, float w,
+                                const float *g, float *dx_out) {
+    CHECK_CTX(ctx);
+    CHECK_BUILT(ctx);
+    HIPCHK(ctx->gradf.ensure(3 * ctx->n));
+    return winding_grad_x_impl(ctx, n, sigma, w, g, dx_out, ctx->gradf.p);
 }
 
 wnnc_status wnnc_gradient_grad_x(wnnc_ctx ctx, const float *n, const float *sigma, float w,
@@ -844,6 +856,47 @@ wnnc_status wnnc_adjoint(wnnc_ctx ctx, const float *s, float w, float *out) {
     ta.srcs = ctx->rho.p;
     ta.out = out;
     return run_traverse(ctx, OP_AT, TR_OUT_CALLER, ta);
+}
+
+wnnc_status wnnc_energy(wnnc_ctx ctx, const float *mu, float w, double gscale, double *E_out,
+                        float *grad_out) {
+    CHECK_CTX(ctx);
+    CHECK_BUILT(ctx);
+    if (!mu) return fail(WNNC_EINVAL, "null mu");
+    if (!finite_nonneg(w)) return fail(WNNC_EINVAL, "w must be finite and >= 0");
+    if (!isfinite(gscale)) return fail(WNNC_EINVAL, "gscale must be finite");
+    RETURN_IF(check_finite(ctx, mu, 3 * ctx->n, "mu"));
+    if (!E_out && !grad_out) return WNNC_OK;
+    hipStream_t st = ctx->stream;
+    // rho = 1/2 - A mu (sorted), with per-group partial sums of rho^2
+    MomArgs ma = mom_args(ctx, w);
+    ma.cn = mu;
+    ma.out4 = ctx->va.p;
+    RETURN_IF(run_moments(ctx, MOM_VEC_CALLER, ma));
+    TravArgs ta = trav_args(ctx, w);
+    ta.src4 = ctx->va.p;
+    ta.rho = ctx->rho.p;
+    ta.partial = ctx->partial.p;
+    RETURN_IF(run_traverse(ctx, OP_A, TR_RHO, ta));
+    if (grad_out) {
+        // gscale dE/dmu = -2 gscale A^T rho, in caller order
+        MomArgs mb = mom_args(ctx, w);
+        mb.srcs = ctx->rho.p;
+        RETURN_IF(run_moments(ctx, MOM_SCALAR_SORTED, mb));
+        TravArgs tb = trav_args(ctx, w);
+        tb.srcs = ctx->rho.p;
+        tb.out = grad_out;
+        tb.oscale = -2.0 * gscale;
+        RETURN_IF(run_traverse(ctx, OP_AT, TR_OUT_CALLER, tb));
+    }
+    if (E_out) {
+        HIPCHK(ctx->scalars.ensure(ctx->nclouds + 1));
+        double *dE = ctx->scalars.p + ctx->nclouds;
+        HIPCHK(launch_sum_partials(ctx->partial.p, ctx->ngroups, dE, st));
+        HIPCHK(hipMemcpyAsync(E_out, dE, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    return WNNC_OK;
 }
 
 // Iterations start..stop of Alg. 3 (schedule over iters) on the sorted mu in
@@ -990,9 +1043,12 @@ wnnc_status wnnc_warm_orient(wnnc_ctx ctx, const float *params, const wnnc_warm_
     CHECK_BUILT(ctx);
     if (!params || !mu_out) return fail(WNNC_EINVAL, "null pointer");
     RETURN_IF(check_finite(ctx, params, kMlpParams, "params"));
-    wnnc_warm_opts o = {6, 0.002f, 0.016f, 0.005f, 40, 0.016f, 0.4f};
+    wnnc_warm_opts o = {6, 0.002f, 0.016f, 0.005f, 40, 0.016f, 0.4f, 0, 0.0f};
     if (opts) o = *opts;
     if (o.iters < 1 || o.fallback_iters < 1) return fail(WNNC_EINVAL, "iteration counts must be >= 1");
+    if (o.max_iters < 0 || o.max_iters > 100000) return fail(WNNC_EINVAL, "max_iters out of range");
+    if (!(o.stop_frac >= 0.0f && o.stop_frac <= 1.0f))
+        return fail(WNNC_EINVAL, "stop_frac must be in [0, 1]");
     if (!finite_nonneg(o.w1) || !finite_nonneg(o.w2) || !finite_nonneg(o.fallback_w2))
         return fail(WNNC_EINVAL, "widths must be finite and >= 0");
     if (!(o.max_disagree >= 0.0f && o.max_disagree <= 1.0f))
@@ -1029,17 +1085,32 @@ wnnc_status wnnc_warm_orient(wnnc_ctx ctx, const float *params, const wnnc_warm_
     HIPCHK(hipMemsetAsync(ctx->flip_ctr.p, 0, (size_t)(2 * B) * sizeof(unsigned long long), st));
     RETURN_IF(run_iterations(ctx, o.iters, o.w1, o.w2, 1, o.iters, false, ctx->flip_ctr.p,
                              WNNC_SCHEDULE_LINEAR, nullptr));
-    HIPCHK(launch_pred_disagree(ctx, ctx->va.p, ctx->nhat.p, ctx->flip_ctr.p + B));
     std::vector<unsigned long long> fl((size_t)(2 * B));
+    // the worst per-cloud fraction of the counters at `base`
+    auto worst_of = [&](int base) {
+        double wv = 0.0;
+        for (int c = 0; c < B; ++c)
+            wv = std::max(wv, (double)fl[base + c] / (double)(ctx->offsets[c + 1] - ctx->offsets[c]));
+        return wv;
+    };
+    int ran = o.iters;
+    // until convergence: one more iteration at w1 while an update still
+    // turns more than stop_frac of some cloud's points
+    while (o.max_iters > ran) {
+        HIPCHK(hipMemcpyAsync(fl.data(), ctx->flip_ctr.p, (size_t)B * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (worst_of(0) <= (double)o.stop_frac) break;
+        HIPCHK(hipMemsetAsync(ctx->flip_ctr.p, 0, (size_t)B * sizeof(unsigned long long), st));
+        RETURN_IF(run_iterations(ctx, 1, o.w1, o.w1, 1, 1, false, ctx->flip_ctr.p,
+                                 WNNC_SCHEDULE_LINEAR, nullptr));
+        ++ran;
+    }
+    HIPCHK(launch_pred_disagree(ctx, ctx->va.p, ctx->nhat.p, ctx->flip_ctr.p + B));
     HIPCHK(hipMemcpyAsync(fl.data(), ctx->flip_ctr.p, (size_t)(2 * B) * sizeof(unsigned long long),
                           hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    double worst = 0.0, worst_pred = 0.0;
-    for (int c = 0; c < B; ++c) {
-        const double nc = (double)(ctx->offsets[c + 1] - ctx->offsets[c]);
-        worst = std::max(worst, (double)fl[c] / nc);
-        worst_pred = std::max(worst_pred, (double)fl[B + c] / nc);
-    }
+    const double worst = worst_of(0), worst_pred = worst_of(B);
     const bool fallback =
         worst > (double)o.max_disagree || worst_pred > (double)o.max_pred_disagree;
     // 4. the plain method when the check fails
@@ -1050,7 +1121,7 @@ wnnc_status wnnc_warm_orient(wnnc_ctx ctx, const float *params, const wnnc_warm_
     }
     HIPCHK(launch_scatter_vec(ctx->va.p, ctx->perm.p, mu_out, N, st));
     if (report) {
-        report->iterations = o.iters + (fallback ? o.fallback_iters : 0);
+        report->iterations = ran + (fallback ? o.fallback_iters : 0);
         report->fallback = fallback ? 1 : 0;
         report->max_disagree = worst;
         report->max_pred_disagree = worst_pred;

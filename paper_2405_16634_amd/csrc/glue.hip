@@ -43,6 +43,27 @@ __global__ __launch_bounds__(256) void k_alpha(const double *__restrict__ partia
     }
 }
 
+// out = the sum of n per-group partial sums (one workgroup; per thread a
+// strided sum, then a tree over the workgroup: a fixed order)
+__global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__ partial, int n,
+                                                      double *__restrict__ out) {
+    __shared__ double sh[256];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) a += partial[i];
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int d = 128; d > 0; d >>= 1) {
+        if (threadIdx.x < d) sh[threadIdx.x] += sh[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+hipError_t launch_sum_partials(const double *partial, int n, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, n, out);
+    return hipGetLastError();
+}
+
 // flag <- 1 if any of the n floats is NaN or infinite (every writer
 // stores the same value, so the race is benign)
 __global__ __launch_bounds__(256) void k_check_finite(const float *__restrict__ a, int64_t n,

@@ -87,6 +87,7 @@ hipError_t record_plan(wnnc_ctx_s *ctx, const TravArgs &a);
 // iteration started from mu = 0 (its energy is N_c / 4).  energy_row holds
 // one entry per cloud.
 hipError_t launch_alpha(wnnc_ctx_s *ctx, bool first, double *energy_row);
+hipError_t launch_sum_partials(const double *partial, int n, double *out, hipStream_t st);
 hipError_t launch_zero_f4(float4 *p, int64_t n, hipStream_t st);
 hipError_t launch_gather_vec(const float *src, const uint32_t *perm, float4 *dst, int64_t n,
                              hipStream_t st);

@@ -176,6 +176,7 @@ struct TravArgs {
     const float *gradf;      // TR_POSGRAD: caller-order grad F; TR_ACCUM: the base (N,3)
     float w2;
     int order;               // far-field order 0, 1, 2
+    double oscale;           // TR_OUT_CALLER: factor on the output (1 unless a caller scales)
 };
 
 }  // namespace wnnc

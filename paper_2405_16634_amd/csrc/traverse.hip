@@ -270,9 +270,9 @@ __device__ inline void finish_target(const TravArgs &a, int t, double s, double 
     } else if (MODE == TR_OUT_CALLER) {
         const int64_t j = a.tperm[t];
         if (OP == OP_A) {
-            a.out[j] = (float)(s * kInv4Pi);
+            a.out[j] = (float)(s * (kInv4Pi * a.oscale));
         } else {
-            const double sg = OP == OP_G ? -kInv4Pi : kInv4Pi;  // grad F = -G
+            const double sg = (OP == OP_G ? -kInv4Pi : kInv4Pi) * a.oscale;  // grad F = -G
             a.out[3 * j] = (float)(gx * sg);
             a.out[3 * j + 1] = (float)(gy * sg);
             a.out[3 * j + 2] = (float)(gz * sg);

@@ -542,6 +542,7 @@ hipError_t build_tree(wnnc_ctx_s *ctx, const float *P) {
     TRY(ctx->rho.ensure(n));
     TRY(ctx->scalars.ensure(nclouds));
     TRY(ctx->pair_ctr.ensure(kOpKinds));
+    TRY(ctx->finite_flag.ensure(1));
     {
         int64_t big = hsize > n + 1 ? hsize : n + 1;
         TRY(ctx->scan_tmp.ensure(scan_tmp_size(16 * big + 16)));

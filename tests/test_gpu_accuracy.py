@@ -6,7 +6,9 @@ the gradient of the winding number (the G operator) with smooth oriented
 elements (mu = generator normal x mean area) on a smooth cloud is <= 1e-3 at
 c = 4 and about 1e-2 at the paper's c = 2 (printed); it must shrink as c
 grows, and A (the winding number itself) is reported beside it.  The bound
-at c = 2 holds for the far-field extension (test_gpu_farfield).
+at c = 2 holds for the far-field extension (test_gpu_farfield).  On the
+benchmark cloud the paper path's error equals the FP64 oracle treecode's
+own error (to 1e-3 of it) and stays in its measured band.
 
 The device treecode (FP32 terms, FP64 sums) is compared with the oracle's
 FP64 direct sums over all pairs.
@@ -35,7 +37,10 @@ def _rel(got, ref):
     return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
 
 
-def _errors(dev, cloud, mu_of, targets, oracle_mod, cs=(2.0, 3.0, 4.0), w=0.002):
+def _errors(dev, cloud, mu_of, targets, oracle_mod, cs=(2.0, 3.0, 4.0), w=0.002,
+            with_oracle_tree=False):
+    """Per c: (device grad rel-L2, device A rel-L2) against the exact sums,
+    and with_oracle_tree also the oracle treecode's own (grad, A) errors."""
     import torch
     import paper_2405_16634_amd as w_
     import oracle
@@ -43,6 +48,7 @@ def _errors(dev, cloud, mu_of, targets, oracle_mod, cs=(2.0, 3.0, 4.0), w=0.002)
     mu = mu_of(sc).astype(np.float32)
     exact_g = -oracle_mod.direct("G", x_or, mu.astype(np.float64), w, targets=x_or[targets])
     exact_a = oracle_mod.direct("A", x_or, mu.astype(np.float64), w, targets=x_or[targets])
+    T = oracle_mod.Tree(x_or.astype(np.float64)) if with_oracle_tree else None
     out = {}
     for c in cs:
         ctx = w_.Context(0)
@@ -52,7 +58,13 @@ def _errors(dev, cloud, mu_of, targets, oracle_mod, cs=(2.0, 3.0, 4.0), w=0.002)
         g = ctx.gradient(m, w).cpu().numpy().astype(np.float64)[targets]
         a = ctx.winding(m, w).cpu().numpy().astype(np.float64)[targets]
         out[c] = (_rel(g, exact_g), _rel(a, exact_a))
-        print(f"  c={c:g}: grad rel-L2 {out[c][0]:.2e}  A rel-L2 {out[c][1]:.2e}", flush=True)
+        if T is not None:
+            tg = -T.apply("G", mu.astype(np.float64), w, c, targets=x_or[targets])
+            ta = T.apply("A", mu.astype(np.float64), w, c, targets=x_or[targets])
+            out[c] = out[c] + (_rel(tg, exact_g), _rel(ta, exact_a))
+            print(f"  c={c:g}: oracle treecode grad rel-L2 {out[c][2]:.4e}  A rel-L2 "
+                  f"{out[c][3]:.4e}", flush=True)
+        print(f"  c={c:g}: grad rel-L2 {out[c][0]:.4e}  A rel-L2 {out[c][1]:.4e}", flush=True)
         ctx.close()
     return out
 
@@ -85,6 +97,16 @@ def test_error_on_the_benchmark_cloud_sampled(dev, oracle_mod):
     cloud = synth.torus_knot(500000, 3, with_init=False)
     print("[case] accuracy torusknot500k sampled", flush=True)
     targets = np.sort(np.random.default_rng(12).choice(cloud.n, 2000, replace=False))
-    e = _errors(dev, cloud, _smooth(cloud), targets, oracle_mod, cs=(2.0, 4.0))
+    e = _errors(dev, cloud, _smooth(cloud), targets, oracle_mod, cs=(2.0, 4.0),
+                with_oracle_tree=True)
     assert e[2.0][0] > e[4.0][0]
     assert e[2.0][1] > e[4.0][1]
+    # the paper path's error is the treecode's own, not the device's: it
+    # equals the FP64 oracle treecode's error against the same exact sums
+    for c in (2.0, 4.0):
+        assert abs(e[c][0] - e[c][2]) <= 1e-3 * e[c][2], c
+        assert abs(e[c][1] - e[c][3]) <= 1e-3 * e[c][3], c
+    # and it stays in the measured band (4.6e-2 at c = 2, 1.5e-2 at c = 4):
+    # a regression of the paper path's accuracy fails here
+    assert 3.5e-2 <= e[2.0][0] <= 6.0e-2
+    assert 1.1e-2 <= e[4.0][0] <= 2.0e-2

@@ -3,7 +3,8 @@ shapes.
 
 * every cloud of a batch has the octree its standalone build has (node sets
   against the oracle's recursive partition of that cloud alone);
-* operators on a batch equal the oracle treecode of each cloud alone;
+* operators on a batch equal the oracle treecode of each cloud alone (the
+  operator bar of `parity_bar.check`);
 * the 40-iteration orientation of a batch agrees with running each cloud
   alone (per-cloud step lengths and energies);
 * the tile shape (targets per lane) does not change any result bit;
@@ -14,11 +15,10 @@ shapes.
 import numpy as np
 import pytest
 
+import parity_bar
 import synth
 
 pytestmark = pytest.mark.gpu
-
-TOL = 1e-5
 
 
 @pytest.fixture(scope="module")
@@ -103,15 +103,10 @@ def test_batched_operators(dev, oracle_mod, split):
             a, b_ = off[k], off[k + 1]
             T = oracle_mod.Tree(xh[a:b_])
             for op, got, nu, sign in (("A", s, mu, 1.0), ("G", g, mu, -1.0), ("AT", at, rho, 1.0)):
-                ref, mag, _ = T.apply(op, nu[a:b_].astype(np.float64), w_, 2.0, with_stats=True)
-                assert np.all(np.isfinite(got[a:b_]))
-                err = np.abs(got[a:b_] - sign * ref)
-                if err.ndim == 2:
-                    err = np.linalg.norm(err, axis=1)
-                ok = mag > 0
-                bad = (err[ok] / mag[ok] > TOL).mean() if ok.any() else 0.0
-                assert bad <= 2e-3, (k, op, w_, bad)
-                assert np.all(err[~ok] == 0.0)
+                ref, mag, _, mg = T.apply(op, nu[a:b_].astype(np.float64), w_, 2.0,
+                                          with_stats=True, with_margins=True)
+                parity_bar.check(f"split={split} cloud {k} {op} w={w_}", got[a:b_], sign * ref,
+                                 mag, mg)
     ctx.close()
 
 
@@ -310,15 +305,10 @@ def test_split_walks_with_zero_weight_regions(dev, oracle_mod):
                        ctx.adjoint(torch.from_numpy(rho).to(dev), 0.002).cpu().numpy())
         for op, got, nu, sign in (("A", outs[split][0], mu, 1.0), ("G", outs[split][1], mu, -1.0),
                                   ("AT", outs[split][2], rho, 1.0)):
-            ref, mag, _ = T.apply(op, nu.astype(np.float64), 0.002, 2.0, with_stats=True)
-            assert np.all(np.isfinite(got))
-            err = np.abs(got - sign * ref)
-            if err.ndim == 2:
-                err = np.linalg.norm(err, axis=1)
-            ok = mag > 0
-            bad = (err[ok] / mag[ok] > TOL).mean()
-            assert bad <= 2e-3, (split, op, bad)
-            assert np.all(err[~ok] == 0.0), (split, op)
+            ref, mag, _, mg = T.apply(op, nu.astype(np.float64), 0.002, 2.0, with_stats=True,
+                                      with_margins=True)
+            r = parity_bar.check(f"split={split} {op}", got, sign * ref, mag, mg)
+            print(f"  split={split} {op}: {parity_bar.fmt(r)}", flush=True)
     for a, b in zip(outs[0], outs[64]):
         assert np.allclose(a, b, rtol=1e-6, atol=0.0), float(np.abs(a - b).max())
     ctx.close()
