@@ -112,7 +112,8 @@ def warm_start_section(ctx, w, mu_plain, stream, iters, w1, w2, gt, mu0_random):
     points and orients at least as many correctly (P_co against the
     generator's normals gt, within 0.1 %).  Beside it: the same short
     schedule from mu = 0 without the network (what the network adds), the
-    warm start run until the sign changes stop, and the plain method from
+    warm start continued until at most 0.1 % of the points change sign per
+    update (or the count stops falling), and the plain method from
     random initial vectors scaled by the mean area (mu0_random)."""
     import torch
     from paper_2405_16634_amd import warmstart as ws
@@ -128,7 +129,7 @@ def warm_start_section(ctx, w, mu_plain, stream, iters, w1, w2, gt, mu0_random):
     t_ctrl, _ = _timed(stream, lambda: w.wnnc_orient(ctx.handle, ctrl, None, warm_iters, w1, w2))
     conv = torch.empty_like(mu_plain)
     t_conv, rep_c = _timed(stream, lambda: w.wnnc_warm_orient(ctx.handle, params, conv,
-                                                              max_iters=iters, stop_frac=0.0))
+                                                              max_iters=iters, stop_frac=1e-3))
     rnd = torch.empty_like(mu_plain)
     m0 = torch.from_numpy(mu0_random).to(mu_plain.device)
     t_rnd, _ = _timed(stream, lambda: w.wnnc_orient(ctx.handle, rnd, m0, iters, w1, w2))

@@ -456,11 +456,12 @@ typedef struct {
                              not trusted */
     int max_iters;        /* "until convergence" [0: off]: when > iters, the
                              warm schedule is followed by further iterations
-                             at width w1, one at a time, while some cloud's
-                             last WNNC update turned more than stop_frac of
-                             its points against mu (sign changes), up to
-                             max_iters iterations in all; the self-checks
-                             then use the last iteration */
+                             at width w1, one at a time, while the largest
+                             per-cloud fraction of points that the last WNNC
+                             update turned against mu (sign changes) exceeds
+                             stop_frac and is smaller than after the update
+                             before, up to max_iters iterations in all; the
+                             self-checks then use the last iteration */
     float stop_frac;      /* sign-change fraction that counts as converged [0] */
 } wnnc_warm_opts;
 

@@ -1095,12 +1095,17 @@ wnnc_status wnnc_warm_orient(wnnc_ctx ctx, const float *params, const wnnc_warm_
     };
     int ran = o.iters;
     // until convergence: one more iteration at w1 while an update still
-    // turns more than stop_frac of some cloud's points
+    // turns more than stop_frac of some cloud's points and fewer than the
+    // update before (at a fixed width the sign changes need not vanish:
+    // points can keep turning back and forth)
+    double prev = HUGE_VAL;
     while (o.max_iters > ran) {
         HIPCHK(hipMemcpyAsync(fl.data(), ctx->flip_ctr.p, (size_t)B * sizeof(unsigned long long),
                               hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        if (worst_of(0) <= (double)o.stop_frac) break;
+        const double cur = worst_of(0);
+        if (cur <= (double)o.stop_frac || cur >= prev) break;
+        prev = cur;
         HIPCHK(hipMemsetAsync(ctx->flip_ctr.p, 0, (size_t)B * sizeof(unsigned long long), st));
         RETURN_IF(run_iterations(ctx, 1, o.w1, o.w1, 1, 1, false, ctx->flip_ctr.p,
                                  WNNC_SCHEDULE_LINEAR, nullptr));
