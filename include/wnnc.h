@@ -302,6 +302,22 @@ wnnc_status wnnc_energy(wnnc_ctx ctx, const float *mu, float w, double gscale, d
 wnnc_status wnnc_winding_grad_x(wnnc_ctx ctx, const float *n, const float *sigma, float w,
                                 const float *g, float *dx_out);
 
+/* wnnc_winding_grad_x for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same result, bit for bit, with the
+ * N x 3 grad F scratch in a static device array of the library instead of
+ * context memory.  The call allocates nothing (no hipMalloc, hipFree or
+ * event creation: timing flags are ignored for it); the tree and every
+ * other buffer come from the last wnnc_build.  N (the built tree's point
+ * count) <= WNNC_NOALLOC_MAX_POINTS, else WNNC_EINVAL before any work.  The
+ * array (12 MiB) is held on every GPU the library runs on until the
+ * process ends and is shared by all contexts on that GPU: calls that
+ * overlap on one GPU (other streams, other threads) race and must be
+ * serialized by the caller.  Arguments as wnnc_winding_grad_x. */
+#define WNNC_NOALLOC_MAX_POINTS (1 << 20)
+wnnc_status wnnc_winding_grad_x_noalloc(wnnc_ctx ctx, const float *n, const float *sigma,
+                                        float w, const float *g, float *dx_out);
+
 /* Gradient of L = sum_i v_i . grad F(x_i; mu) (wnnc_gradient) with respect to
  * the point positions (an extension).  With the third-derivative tensor
  * T3Phi of Phi, differentiating each pair term of grad F in both end points

@@ -37,8 +37,9 @@ EXPORTED = [
     "wnnc_mlp_forward", "wnnc_mlp_grad", "wnnc_mlp_adam",
     "wnnc_warm_orient", "wnnc_set_prefetch", "wnnc_set_split", "wnnc_get_split",
     "wnnc_winding_at", "wnnc_set_far_field", "wnnc_get_far_field", "wnnc_winding_grad_x",
-    "wnnc_gradient_grad_x", "wnnc_energy",
+    "wnnc_gradient_grad_x", "wnnc_energy", "wnnc_winding_grad_x_noalloc",
 ]
+NOALLOC_MAX_POINTS = 1 << 20
 MLP_PARAMS = 7491
 AUTOTUNE_CONFIGS = 12
 MAX_SPLIT = 1 << 20
@@ -145,6 +146,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "wnnc_orient_preset": [ctypes.c_int, P(OrientOpts)],
         "wnnc_set_far_field": [vp, ctypes.c_int, ctypes.c_int],
         "wnnc_winding_grad_x": [vp, vp, vp, f32, vp, vp],
+        "wnnc_winding_grad_x_noalloc": [vp, vp, vp, f32, vp, vp],
         "wnnc_gradient_grad_x": [vp, vp, vp, f32, vp, vp],
         "wnnc_get_far_field": [vp, P(ctypes.c_int), P(ctypes.c_int)],
         "wnnc_mlp_forward": [vp, vp, vp, i64, vp],
@@ -359,6 +361,15 @@ def wnnc_winding_grad_x(ctx, mu, sigma, w: float, g, dx_out) -> None:
     """dL/dx of L = g . A_w(mu) with respect to the (normalized) points."""
     N = mu.shape[0]
     _check(load_library().wnnc_winding_grad_x(
+        ctx, _dev(mu, "mu", shape=(N, 3)), _dev(sigma, "sigma", shape=(N,)), float(w),
+        _dev(g, "g", shape=(N,)), _dev(dx_out, "dx_out", shape=(N, 3))))
+
+
+def wnnc_winding_grad_x_noalloc(ctx, mu, sigma, w: float, g, dx_out) -> None:
+    """wnnc_winding_grad_x with the library's static scratch: allocates no
+    device memory (N <= NOALLOC_MAX_POINTS)."""
+    N = mu.shape[0]
+    _check(load_library().wnnc_winding_grad_x_noalloc(
         ctx, _dev(mu, "mu", shape=(N, 3)), _dev(sigma, "sigma", shape=(N,)), float(w),
         _dev(g, "g", shape=(N,)), _dev(dx_out, "dx_out", shape=(N, 3))))
 

@@ -216,6 +216,16 @@ wnnc_status wnnc_create(wnnc_ctx *out, int device, void *stream) {
     HIPCHK(hipGetDeviceCount(&count));
     if (device < 0 || device >= count)
         return fail(WNNC_EINVAL, "device %d out of range (%d devices)", device, count);
+    {
+        // the no-allocation entry points' scratch: its device address, once
+        // per device, with that device current
+        int prev = 0;
+        HIPCHK(hipGetDevice(&prev));
+        HIPCHK(hipSetDevice(device));
+        const hipError_t e = noalloc_setup(device);
+        HIPCHK(hipSetDevice(prev));
+        HIPCHK(e);
+    }
     wnnc_ctx_s *c = new (std::nothrow) wnnc_ctx_s();
     if (!c) return fail(WNNC_ENOMEM, "host allocation failed");
     c->device = device;
@@ -799,6 +809,23 @@ wnnc_status wnnc_winding_grad_x(wnnc_ctx ctx, const float *n, const float *sigma
     CHECK_BUILT(ctx);
     HIPCHK(ctx->gradf.ensure(3 * ctx->n));
     return winding_grad_x_impl(ctx, n, sigma, w, g, dx_out, ctx->gradf.p);
+}
+
+wnnc_status wnnc_winding_grad_x_noalloc(wnnc_ctx ctx, const float *n, const float *sigma,
+                                        float w, const float *g, float *dx_out) {
+    CHECK_CTX(ctx);
+    CHECK_BUILT(ctx);
+    if (ctx->n > kNoallocMaxPoints)
+        return fail(WNNC_EINVAL, "wnnc_winding_grad_x_noalloc: %lld points exceed the limit of %lld",
+                    (long long)ctx->n, (long long)kNoallocMaxPoints);
+    float *scratch = noalloc_scratch(ctx->device);
+    if (!scratch) return fail(WNNC_EDEVICE, "no scratch address for device %d", ctx->device);
+    // timing creates events: this entry point runs untimed
+    const unsigned saved = ctx->flags;
+    ctx->flags &= ~(WNNC_FLAG_TIME_KERNELS | WNNC_FLAG_TIME_TRAVERSAL);
+    const wnnc_status s = winding_grad_x_impl(ctx, n, sigma, w, g, dx_out, scratch);
+    ctx->flags = saved;
+    return s;
 }
 
 wnnc_status wnnc_gradient_grad_x(wnnc_ctx ctx, const float *n, const float *sigma, float w,

@@ -122,4 +122,13 @@ hipError_t launch_pred_disagree(wnnc_ctx_s *ctx, const float4 *mu, const float *
 hipError_t mlp_adam(wnnc_ctx_s *ctx, float *P, float *m, float *v, const float *g, int step,
                     float lr, float b1, float b2, float eps);
 
+// Static scratch of the no-allocation entry points (noalloc.hip): at most
+// kNoallocMaxPoints points.  noalloc_setup takes the array's address on
+// `device` (which must be current), once per device; noalloc_scratch
+// returns it (null before the set-up).
+constexpr int64_t kNoallocMaxPoints = int64_t(1) << 20;
+static_assert(kNoallocMaxPoints == WNNC_NOALLOC_MAX_POINTS, "no-allocation limit");
+hipError_t noalloc_setup(int device);
+float *noalloc_scratch(int device);
+
 }  // namespace wnnc
