@@ -84,6 +84,74 @@ def cpu_baseline(cloud, w: float, c: float):
     }
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_plan():
+    """The FP64 oracle timed as the measurement plan states it, on the host
+    cores: the treecode run (Alg. 3, 40 iterations of Alg. 4 operators) on
+    the 50k noisy ellipsoid union (widths 0.02 -> 0.08, the 0.25 % noise
+    setting of Sec. 5.2.5), T_pre (operator set-up: normalization and the
+    octree) and T_main (the iterations) separately, median of 3 on all
+    cores and one run on one thread; the exact direct sums for the 40
+    iterations on the 2k sphere and for one operator call on the 50k cloud.
+    Pair counts give the CPU rates beside the device's."""
+    import oracle
+    import synth
+    from statistics import median
+    out = {"cpu_model": _cpu_model(), "nproc": os.cpu_count(), "kind": "oracle"}
+    all_threads = oracle.num_threads()
+    c2 = synth.ellipsoid_union(50000, 2)
+
+    def tree_run(threads):
+        oracle.set_threads(threads)
+        t0 = time.perf_counter()
+        x, _, _ = oracle.normalize(c2.points)
+        t1 = time.perf_counter()
+        tm, pc = {}, [0]
+        oracle.orient(x, iters=40, w1=0.02, w2=0.08, backend="tree", pair_count=pc, timing=tm)
+        return (t1 - t0) + tm["pre"], tm["main"], pc[0]
+
+    runs = [tree_run(all_threads) for _ in range(3)]
+    pre = median(r[0] for r in runs)
+    main = median(r[1] for r in runs)
+    pairs = runs[0][2]
+    one = tree_run(1)
+    oracle.set_threads(all_threads)
+    out["treecode_ellipsoids50k_40iter"] = {
+        "threads": all_threads, "t_pre_s": round(pre, 4), "t_main_s": round(main, 3),
+        "t_main_runs_s": [round(r[1], 3) for r in runs], "pairs": pairs,
+        "gpairs_per_s": round(pairs / main / 1e9, 4),
+        "one_thread": {"t_pre_s": round(one[0], 4), "t_main_s": round(one[1], 3),
+                       "gpairs_per_s": round(one[2] / one[1] / 1e9, 4)}}
+    c1 = synth.fibonacci_sphere(2000, 0)
+    x1, _, _ = oracle.normalize(c1.points)
+    t0 = time.perf_counter()
+    oracle.orient(x1, iters=40, w1=0.002, w2=0.016, backend="direct")
+    t1 = time.perf_counter()
+    n1 = c1.n
+    out["direct_sphere2k_40iter"] = {
+        "threads": all_threads, "t_s": round(t1 - t0, 4), "pairs": 159 * n1 * n1,
+        "gpairs_per_s": round(159 * n1 * n1 / (t1 - t0) / 1e9, 4)}
+    x2, _, sc = oracle.normalize(c2.points)
+    mu = c2.normals.astype(np.float64) * (c2.area * sc * sc / c2.n)
+    t0 = time.perf_counter()
+    oracle.direct("A", x2, mu, 0.02)
+    t1 = time.perf_counter()
+    out["direct_ellipsoids50k_one_A"] = {
+        "threads": all_threads, "t_s": round(t1 - t0, 3), "pairs": c2.n * c2.n,
+        "gpairs_per_s": round(c2.n * c2.n / (t1 - t0) / 1e9, 4)}
+    return out
+
+
 def _dirs(a, b, mask):
     """Flip rate and AE_pcd (Sec. 5.1.4) of directions a against b over mask
     (rows where both are nonzero and finite)."""
@@ -322,6 +390,9 @@ def main():
     ap.add_argument("--n", type=int, default=500000)
     ap.add_argument("--iters", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-plan", action="store_true",
+                    help="only time the CPU oracle as the measurement plan states it "
+                         "(about two minutes) and print that JSON")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -329,6 +400,9 @@ def main():
               f"(multi-GPU sharding is a design note only).", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
+    if args.cpu_plan:
+        print(json.dumps(cpu_plan()), flush=True)
+        return
 
     import torch
     import paper_2405_16634_amd as w
@@ -510,6 +584,10 @@ def main():
     }
     if rank == 0 and not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cloud, w1, c)
+        # the full plan is long: its last run on this kind of host, as committed
+        plan = os.path.join(ROOT, "profiles", "cpu_oracle_plan.json")
+        if os.path.exists(plan):
+            out["cpu_baseline"]["plan_record"] = json.load(open(plan))
     ctx.close()
     if rank == 0:
         print(json.dumps(out), flush=True)

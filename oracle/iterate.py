@@ -78,6 +78,7 @@ class _Ops:
         self.c = c
         self.order = order
         self.wsafe = wsafe
+        self.pairs = None  # [count] to tally treecode pair evaluations
         if backend == "tree":
             self.tree = Tree(self.x, max_depth=max_depth, leaf_cap=leaf_cap)
         elif backend == "direct":
@@ -90,6 +91,11 @@ class _Ops:
 
     def __call__(self, op, nu, w):
         if self.backend == "tree":
+            if self.pairs is not None:
+                out, _, k = self.tree.apply(op, nu, w, self.c, order=self.order,
+                                            wsafe=self.wsafe, with_stats=True)
+                self.pairs[0] += int(k.sum())
+                return out
             return self.tree.apply(op, nu, w, self.c, order=self.order, wsafe=self.wsafe)
         if self.backend == "direct":
             return self._direct(op, self.x, nu, w)
@@ -111,17 +117,23 @@ def grad_step(ops, mu, w, b=0.5):
 def orient(x, iters=40, w1=0.002, w2=0.016, mu0=None, backend="tree", c=2.0,
            max_depth=15, leaf_cap=1, start_iter=1, grad=True, wnnc=True,
            do_rescale=True, callback=None, schedule="linear", areas=None, order=0,
-           wsafe=False):
+           wsafe=False, pair_count=None, timing=None):
     """Alg. 3 on normalized points x (n,3).  Returns mu (n,3) in FP64.
 
     grad / wnnc / do_rescale switch the three steps off for the ablations of
     Sec. 5.5 (defaults: the full method).  schedule and areas select the
     variants of the module docstring; order and wsafe the treecode's
     far-field extension (Tree.apply).  callback(i, mu, info) is called after
-    every iteration.
+    every iteration.  pair_count (a list [n]) receives the number of treecode
+    pair evaluations, timing (a dict) the seconds spent building the operators
+    ("pre") and iterating ("main"): instrumentation only.
     """
+    import time
+    t0 = time.perf_counter()
     x = np.asarray(x, dtype=np.float64)
     ops = _Ops(x, backend, c, max_depth, leaf_cap, order, wsafe)
+    ops.pairs = pair_count
+    t1 = time.perf_counter()
     mu = np.zeros_like(x) if mu0 is None else np.array(mu0, dtype=np.float64)
     for i in range(start_iter, iters + 1):
         w = width_schedule(i, iters, w1, w2, schedule)
@@ -134,4 +146,7 @@ def orient(x, iters=40, w1=0.002, w2=0.016, mu0=None, backend="tree", c=2.0,
             mu = rescale(mu, mu_hat, areas) if do_rescale else mu_hat
         if callback is not None:
             callback(i, mu, info)
+    if timing is not None:
+        timing["pre"] = t1 - t0
+        timing["main"] = time.perf_counter() - t1
     return mu
