@@ -390,6 +390,9 @@ def main():
     ap.add_argument("--n", type=int, default=500000)
     ap.add_argument("--iters", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--core-only", action="store_true",
+                    help="only the timed steps and their figures (no warm-start, far-field, "
+                         "leaf-capacity or batched sections): for profiling runs")
     ap.add_argument("--cpu-plan", action="store_true",
                     help="only time the CPU oracle as the measurement plan states it "
                          "(about two minutes) and print that JSON")
@@ -531,16 +534,20 @@ def main():
     # mean area weight in the normalized frame
     sig = cloud.area * cs0[1] ** 2 / cloud.n
     mu0_rnd = (cloud.mu0.astype(np.float64) * sig).astype(np.float32)
-    warm = warm_start_section(ctx, w, mu, stream, args.iters, w1, w2, cloud.normals, mu0_rnd)
+    warm = None if args.core_only else warm_start_section(ctx, w, mu, stream, args.iters, w1, w2,
+                                                          cloud.normals, mu0_rnd)
 
     from paper_2405_16634_amd.metrics import ae_pcd, p_co
     nrm_h = nrm.cpu().numpy()
     pco = p_co(nrm_h, cloud.normals)
     ae = ae_pcd(nrm_h, cloud.normals)
-    far = far_field_section(ctx, w, step, mu, stream, max(1, min(args.steps, 3)), cloud.normals)
-    leaf = leaf_cap_section(w, P, stream, args.iters, w1, w2, c, depth, max(1, min(args.steps, 3)),
-                            cloud.normals)
-    batched = batched_section(w, stream, args.iters, w1, w2, c, depth)
+    far = leaf = batched = None
+    if not args.core_only:
+        far = far_field_section(ctx, w, step, mu, stream, max(1, min(args.steps, 3)),
+                                cloud.normals)
+        leaf = leaf_cap_section(w, P, stream, args.iters, w1, w2, c, depth,
+                                max(1, min(args.steps, 3)), cloud.normals)
+        batched = batched_section(w, stream, args.iters, w1, w2, c, depth)
 
     out = {
         "metric": METRIC,

@@ -218,6 +218,19 @@ wnnc_status wnnc_get_tile(wnnc_ctx ctx, int *tpl);
 wnnc_status wnnc_set_split(wnnc_ctx ctx, int visits);
 wnnc_status wnnc_get_split(wnnc_ctx ctx, int *visits);
 
+/* Deferred subtrees in the traversal: while a wavefront walks the tree for
+ * its 64 targets in lockstep, a subtree that at most `lanes` of them need
+ * (after their Alg. 4 decision to open its root) is set aside; the set-aside
+ * (subtree, target) walks are then run packed across the lanes, each lane
+ * walking one target's subtree on its own, so that lanes are not idle in
+ * subtrees few targets need.  Every target makes the same decisions and
+ * adds the same terms; only the order of the FP64 additions of its sum
+ * changes.  Used with tile shape 1, the plain walk (prefetch off for the
+ * operator) and Alg. 4's far field; otherwise ignored.  lanes in 0..64,
+ * default 32; 0 walks every subtree in lockstep. */
+wnnc_status wnnc_set_defer(wnnc_ctx ctx, int lanes);
+wnnc_status wnnc_get_defer(wnnc_ctx ctx, int *lanes);
+
 /* Software-pipelined node walk in the traversal: the skip successor's
  * record is loaded while the current node is visited (with the far field of
  * order > 0 the walk keeps plain loads).  Results do not depend on it, bit

@@ -37,7 +37,8 @@ EXPORTED = [
     "wnnc_mlp_forward", "wnnc_mlp_grad", "wnnc_mlp_adam",
     "wnnc_warm_orient", "wnnc_set_prefetch", "wnnc_set_split", "wnnc_get_split",
     "wnnc_winding_at", "wnnc_set_far_field", "wnnc_get_far_field", "wnnc_winding_grad_x",
-    "wnnc_gradient_grad_x", "wnnc_energy", "wnnc_winding_grad_x_noalloc",
+    "wnnc_gradient_grad_x", "wnnc_energy", "wnnc_winding_grad_x_noalloc", "wnnc_set_defer",
+    "wnnc_get_defer",
 ]
 NOALLOC_MAX_POINTS = 1 << 20
 MLP_PARAMS = 7491
@@ -136,6 +137,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "wnnc_normalize_batched": [vp, vp, P(i64), ctypes.c_int, vp, P(dbl)],
         "wnnc_build_batched": [vp, vp, P(i64), ctypes.c_int, P(TreeOpts)],
         "wnnc_set_tile": [vp, ctypes.c_int],
+        "wnnc_set_defer": [vp, ctypes.c_int],
+        "wnnc_get_defer": [vp, P(ctypes.c_int)],
         "wnnc_get_tile": [vp, P(ctypes.c_int)],
         "wnnc_autotune": [vp, f32, P(TileTime)],
         "wnnc_set_prefetch": [vp, ctypes.c_int],
@@ -557,6 +560,14 @@ class Context:
 
     def set_tile(self, tpl: int) -> None:
         wnnc_set_tile(self._h, tpl)
+
+    def set_defer(self, lanes: int) -> None:
+        _check(load_library().wnnc_set_defer(self._h, int(lanes)))
+
+    def defer(self) -> int:
+        v = ctypes.c_int(0)
+        _check(load_library().wnnc_get_defer(self._h, ctypes.byref(v)))
+        return v.value
 
     def set_prefetch(self, on: bool) -> None:
         wnnc_set_prefetch(self._h, on)

@@ -149,6 +149,7 @@ TravArgs trav_args(wnnc_ctx_s *c, float w) {
     a.order = c->far_order;
     a.momhi = c->far_order > 0 ? c->momhi.p : nullptr;
     a.oscale = 1.0;
+    a.defer_k = c->defer_k;
     return a;
 }
 
@@ -542,6 +543,20 @@ wnnc_status wnnc_get_tile(wnnc_ctx ctx, int *tpl) {
     CHECK_CTX(ctx);
     if (!tpl) return fail(WNNC_EINVAL, "null output");
     *tpl = ctx->tpl;
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_set_defer(wnnc_ctx ctx, int lanes) {
+    CHECK_CTX(ctx);
+    if (lanes < 0 || lanes > kWave) return fail(WNNC_EINVAL, "lanes must be in 0..64");
+    ctx->defer_k = lanes;
+    return WNNC_OK;
+}
+
+wnnc_status wnnc_get_defer(wnnc_ctx ctx, int *lanes) {
+    CHECK_CTX(ctx);
+    if (!lanes) return fail(WNNC_EINVAL, "null lanes");
+    *lanes = ctx->defer_k;
     return WNNC_OK;
 }
 

@@ -92,6 +92,7 @@ struct wnnc_ctx_s {
     // per operator kind: -1 follows `prefetch`, else the autotuner's choice
     int pf_op[wnnc::kOpKinds] = {-1, -1, -1, -1, -1};
     int split = 256;               // node visits per part of a split walk (0: whole walks)
+    int defer_k = 32;              // defer subtrees needed by at most this many lanes (0: never)
     int ntasks = 0;                // tasks launched per traversal
     int ngroups = 0;               // groups (per-group partial sums)
     int nparts = 0;                // part slots

@@ -177,6 +177,7 @@ struct TravArgs {
     float w2;
     int order;               // far-field order 0, 1, 2
     double oscale;           // TR_OUT_CALLER: factor on the output (1 unless a caller scales)
+    int defer_k;             // defer subtrees needed by at most this many lanes (0: never)
 };
 
 }  // namespace wnnc

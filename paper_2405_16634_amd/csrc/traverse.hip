@@ -66,6 +66,12 @@ __device__ inline void rec_wait(v16f &r) { asm volatile("s_waitcnt lgkmcnt(0)" :
 
 constexpr double kInv4Pi = 0.0795774715459476678844;  // 1 / (4 pi)
 
+// Deferred subtrees (TPL = 1, plain walk, Alg. 4's far field): at most
+// kDeferEntries subtrees and kDeferTasks (subtree, target) tasks are held
+// per wavefront before they are walked.
+constexpr int kDeferEntries = 64;
+constexpr int kDeferTasks = 1024;
+
 // Pair term without the 1/(4 pi) factor.  d = target - source, r2 = |d|^2.
 //   A  : -(d . nu) / r^3
 //   A^T: nu d / r^3                      (nu scalar, in v.x)
@@ -381,6 +387,27 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
     int cur_depth = -1;
     uint32_t cnt = 0;
     int visits = 0;
+    // Deferred subtrees: a subtree that at most a.defer_k lanes of the group
+    // need is not walked in lockstep; its (first node, end node) goes to
+    // dent and one (entry, lane) task per such lane to dtask.  flush() then
+    // walks the tasks packed across the lanes, each lane walking one
+    // target's subtree on its own (vector record loads), and adds each
+    // task's FP64 sums to its target's slot of dacc.  The decisions and
+    // terms are those of the lockstep walk; only the order of the FP64
+    // additions differs.
+    constexpr bool DEFER = TPL == 1 && !PF && !HI && MODE != TR_PLAN;
+    __shared__ int2 dent[DEFER ? kDeferEntries : 1];
+    __shared__ uint16_t dtask[DEFER ? kDeferTasks : 1];
+    __shared__ double dacc[DEFER ? 3 : 1][DEFER ? kWave : 1];
+    __shared__ float4 dtgt[DEFER ? kWave : 1];
+    __shared__ float4 dtv[DEFER && (OP == OP_P || OP == OP_T) ? kWave : 1];
+    int dne = 0, dnt = 0;  // entries and tasks held (wave-uniform)
+    uint32_t dcnt = 0;     // pairs of this lane's deferred steps (COUNT)
+    if constexpr (DEFER) {
+        dacc[0][lane] = 0.0;
+        dacc[1][lane] = 0.0;
+        dacc[2][lane] = 0.0;
+    }
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
         const int t = first + k * kWave + lane;
@@ -433,6 +460,96 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
             node = ch;
         }
     }
+
+    // Walks the held tasks: every lane takes the next task whenever it has
+    // none, so the lanes stay busy until the tasks run out.
+    auto flush = [&]() {
+      if constexpr (DEFER) {
+        // each lane's target (and its vector), for the lanes that walk it
+        dtgt[lane] = make_float4(tx[0], ty[0], tz[0], 0.f);
+        if (OP == OP_P || OP == OP_T) dtv[lane] = tv[0];
+        __syncthreads();  // the wavefront's LDS writes are visible
+        const int nt = dnt;
+        int nextt = 0;           // next task to hand out (wave-uniform)
+        int node = 0, end = 0;   // this lane's walk
+        int tg = -1;             // its target lane (-1: no task)
+        float px = 0.f, py = 0.f, pz = 0.f;
+        float4 ptv = make_float4(0.f, 0.f, 0.f, 0.f);
+        double ps = 0.0, pgx = 0.0, pgy = 0.0, pgz = 0.0;
+        for (;;) {
+            const bool done = node >= end;
+            if (done && tg >= 0) {  // the task ended: its sums to the target
+                if (OP == OP_A) {
+                    atomicAdd(&dacc[0][tg], ps);
+                } else {
+                    atomicAdd(&dacc[0][tg], pgx);
+                    atomicAdd(&dacc[1][tg], pgy);
+                    atomicAdd(&dacc[2][tg], pgz);
+                }
+                ps = pgx = pgy = pgz = 0.0;
+                tg = -1;
+            }
+            const unsigned long long need = __ballot(done);
+            const int my = nextt + (int)__builtin_amdgcn_mbcnt_hi(
+                                       (uint32_t)(need >> 32),
+                                       __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+            nextt += __popcll(need);
+            if (done && my < nt) {
+                const int tk = dtask[my];
+                const int2 en = dent[tk >> 6];
+                node = en.x;
+                end = en.y;
+                tg = tk & 63;
+                const float4 p = dtgt[tg];
+                px = p.x, py = p.y, pz = p.z;
+                if (OP == OP_P || OP == OP_T) ptv = dtv[tg];
+            }
+            const bool act = node < end;
+            if (__ballot(act) == 0ull && nextt >= nt) break;
+            if (act) {
+                const float4 *rb =
+                    (const float4 *)((const char *)a.mom + ((uint32_t)node << 6));
+                const float4 R0 = rb[0], R1 = rb[1], R2 = rb[2];
+                const int fl = __float_as_int(R0.w);
+                const int sk = __float_as_int(R1.w);
+                int nx = node + 1;
+                if (fl & kRecZero) {
+                    nx = sk;
+                } else {
+                    const float dx = (px - R0.x) - R2.x, dy = (py - R0.y) - R2.y,
+                                dz = (pz - R0.z) - R2.z;
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    if (r2 > R2.w) {  // accepted (a single-point leaf always is)
+                        if (COUNT) ++dcnt;
+                        pair_term<OP>(dx, dy, dz, r2, make_float4(R1.x, R1.y, R1.z, 0.f), ptv,
+                                      r2 >= a.w2, ps, pgx, pgy, pgz);
+                        nx = sk;
+                    } else if (fl & kRecLeaf) {  // the points of a depth-D cell
+                        const float4 R3 = rb[3];
+                        const int jb = __float_as_int(R3.x), je = __float_as_int(R3.y);
+                        for (int j = jb; j < je; ++j) {
+                            const float4 Q = a.pts[j];
+                            float4 S;
+                            if (OP == OP_AT || OP == OP_P)
+                                S = make_float4(a.srcs[j], 0.f, 0.f, 0.f);
+                            else
+                                S = a.src4[j];
+                            const float ex = px - Q.x, ey = py - Q.y, ez = pz - Q.z;
+                            const float e2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
+                            if (COUNT) ++dcnt;
+                            pair_term<OP>(ex, ey, ez, e2, S, ptv, e2 >= a.w2, ps, pgx, pgy, pgz);
+                        }
+                        nx = sk;
+                    }
+                }
+                node = nx;
+            }
+        }
+        __syncthreads();  // every task's sums are in dacc
+        dne = 0;
+        dnt = 0;
+      }
+    };
 
     // One node visit for all groups; returns the next node in pre-order.
     auto visit = [&](const v16f &R, int node) -> int {
@@ -524,6 +641,23 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
             }
             return skip;
         }
+        if (DEFER && a.defer_k > 0 && __popcll(open[0]) <= a.defer_k) {
+            // defer the subtree for the few lanes that need it
+            const unsigned long long dm = open[0];
+            if constexpr (DEFER) {
+            if (lane == 0) dent[dne] = make_int2(node + 1, min(skip, nend));
+            if (lane_in(dm)) {
+                const int pos = dnt + (int)__builtin_amdgcn_mbcnt_hi(
+                                          (uint32_t)(dm >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)dm, 0u));
+                dtask[pos] = (uint16_t)((dne << 6) | lane);
+            }
+            }
+            dne += 1;
+            dnt += __popcll(dm);
+            if (dne == kDeferEntries || dnt > kDeferTasks - kWave) flush();
+            return skip;
+        }
         // push: lane depth + 1 takes the mask (selected by a scalar lane mask)
         const bool at = lane_in(1ull << (depth + 1));
 #pragma unroll
@@ -540,6 +674,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
     // scalar registers would crowd the record in flight)
     if (!PF || HI) {
         for (int node = nbeg; node < nend;) node = visit(ld_rec(a.mom, node), node);
+        if (DEFER && dne > 0) flush();
     } else if (nbeg < nend) {
         // Software-pipelined walk.  A wait for a scalar load covers every
         // scalar load in flight, so the skip successor's record is issued
@@ -579,6 +714,21 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
         }
     }
 
+    if constexpr (DEFER) {  // the deferred tasks' sums of each target (0 if none)
+        if (OP == OP_A) {
+            s[0] += dacc[0][lane];
+        } else {
+            gx[0] += dacc[0][lane];
+            gy[0] += dacc[1][lane];
+            gz[0] += dacc[2][lane];
+        }
+        if (COUNT) {
+            uint32_t t = dcnt;
+#pragma unroll
+            for (int d = kWave / 2; d > 0; d >>= 1) t += __shfl_xor(t, d, kWave);
+            cnt += t;
+        }
+    }
     if (COUNT) {  // cnt is wave-uniform: the pairs of all lanes
         if (lane == 0) atomicAdd(a.pairs + OP, (unsigned long long)cnt);
     }

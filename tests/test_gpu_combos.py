@@ -117,6 +117,7 @@ def test_prefetch_is_bit_identical_with_far_field_and_leaf_capacity(dev):
         x, _ = ctx.normalize(_t(cloud.points, dev))
         ctx.build(x, 2.0, 15, K)
         ctx.set_far_field(order, order > 0)
+        ctx.set_defer(0)  # the lockstep walk in both prefetch settings
         res = []
         for pf in (False, True):
             ctx.set_prefetch(pf)

@@ -162,20 +162,27 @@ def test_operators_match_oracle_treecode(dev, name, oracle_mod):
     mu = nrm * sigma[:, None]
     ctx.set_flags(w.FLAG_COUNT_PAIRS)
     for w_ in (w1, w2):
-        ctx.reset_stats()
-        s = ctx.winding(_to_dev(nrm, dev), w_, sigma=_to_dev(sigma, dev)).cpu().numpy()
-        g = ctx.gradient(_to_dev(mu, dev), w_).cpu().numpy()
-        at = ctx.adjoint(_to_dev(rho, dev), w_).cpu().numpy()
-        st = ctx.stats()
-        for op, got, nu, sign in (("A", s, mu.astype(np.float64), 1.0),
-                                  ("G", g, mu.astype(np.float64), -1.0),
-                                  ("AT", at, rho.astype(np.float64), 1.0)):
+        runs = {}
+        # the default walk (sparse subtrees deferred) and the lockstep walk
+        for defer in (ctx.defer(), 0):
+            ctx.set_defer(defer)
+            ctx.reset_stats()
+            s = ctx.winding(_to_dev(nrm, dev), w_, sigma=_to_dev(sigma, dev)).cpu().numpy()
+            g = ctx.gradient(_to_dev(mu, dev), w_).cpu().numpy()
+            at = ctx.adjoint(_to_dev(rho, dev), w_).cpu().numpy()
+            runs[defer] = (s, g, at, ctx.stats())
+        ctx.set_defer(32)
+        for op, nu, sign in (("A", mu.astype(np.float64), 1.0),
+                             ("G", mu.astype(np.float64), -1.0),
+                             ("AT", rho.astype(np.float64), 1.0)):
             ref, mag, pairs, mg = T.apply(op, nu, w_, 2.0, with_stats=True, with_margins=True)
             ref = sign * ref  # the library returns grad F = -G
             k = {"A": 0, "AT": 1, "G": 2}[op]
-            r = parity_bar.check(f"{name} {op} w={w_}", got, ref, mag, mg,
-                                 pairs_gpu=st["pairs"][k], pairs_oracle=pairs)
-            print(f"  {op} w={w_}: {parity_bar.fmt(r)}", flush=True)
+            for defer, (s, g, at, st) in runs.items():
+                got = {"A": s, "G": g, "AT": at}[op]
+                r = parity_bar.check(f"{name} {op} w={w_} defer={defer}", got, ref, mag, mg,
+                                     pairs_gpu=st["pairs"][k], pairs_oracle=pairs)
+                print(f"  {op} w={w_} defer={defer}: {parity_bar.fmt(r)}", flush=True)
     ctx.close()
     torch.cuda.synchronize()
 
