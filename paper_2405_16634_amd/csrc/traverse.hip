@@ -507,42 +507,40 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
             const bool act = node < end;
             if (__ballot(act) == 0ull && nextt >= nt) break;
             if (act) {
+                // the whole record in one round of loads; the branches below
+                // are selects, except the rare direct sum of a leaf's points
                 const float4 *rb =
                     (const float4 *)((const char *)a.mom + ((uint32_t)node << 6));
                 const float4 R0 = rb[0], R1 = rb[1], R2 = rb[2];
                 const int fl = __float_as_int(R0.w);
                 const int sk = __float_as_int(R1.w);
-                int nx = node + 1;
-                if (fl & kRecZero) {
-                    nx = sk;
-                } else {
-                    const float dx = (px - R0.x) - R2.x, dy = (py - R0.y) - R2.y,
-                                dz = (pz - R0.z) - R2.z;
-                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                    if (r2 > R2.w) {  // accepted (a single-point leaf always is)
+                const bool zero = (fl & kRecZero) != 0;  // nothing below: skip it
+                const float dx = (px - R0.x) - R2.x, dy = (py - R0.y) - R2.y,
+                            dz = (pz - R0.z) - R2.z;
+                const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                // accepted (a single-point leaf always is)
+                const bool far = !zero && r2 > R2.w;
+                if (COUNT) dcnt += far ? 1u : 0u;
+                pair_term<OP>(dx, dy, dz, r2, make_float4(R1.x, R1.y, R1.z, 0.f), ptv,
+                              far && r2 >= a.w2, ps, pgx, pgy, pgz);
+                const bool cell = !zero && !far && (fl & kRecLeaf) != 0;
+                if (cell) {  // the points of a depth-D cell (or a leaf of several)
+                    const float4 R3 = rb[3];
+                    const int jb = __float_as_int(R3.x), je = __float_as_int(R3.y);
+                    for (int j = jb; j < je; ++j) {
+                        const float4 Q = a.pts[j];
+                        float4 S;
+                        if (OP == OP_AT || OP == OP_P)
+                            S = make_float4(a.srcs[j], 0.f, 0.f, 0.f);
+                        else
+                            S = a.src4[j];
+                        const float ex = px - Q.x, ey = py - Q.y, ez = pz - Q.z;
+                        const float e2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
                         if (COUNT) ++dcnt;
-                        pair_term<OP>(dx, dy, dz, r2, make_float4(R1.x, R1.y, R1.z, 0.f), ptv,
-                                      r2 >= a.w2, ps, pgx, pgy, pgz);
-                        nx = sk;
-                    } else if (fl & kRecLeaf) {  // the points of a depth-D cell
-                        const float4 R3 = rb[3];
-                        const int jb = __float_as_int(R3.x), je = __float_as_int(R3.y);
-                        for (int j = jb; j < je; ++j) {
-                            const float4 Q = a.pts[j];
-                            float4 S;
-                            if (OP == OP_AT || OP == OP_P)
-                                S = make_float4(a.srcs[j], 0.f, 0.f, 0.f);
-                            else
-                                S = a.src4[j];
-                            const float ex = px - Q.x, ey = py - Q.y, ez = pz - Q.z;
-                            const float e2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
-                            if (COUNT) ++dcnt;
-                            pair_term<OP>(ex, ey, ez, e2, S, ptv, e2 >= a.w2, ps, pgx, pgy, pgz);
-                        }
-                        nx = sk;
+                        pair_term<OP>(ex, ey, ez, e2, S, ptv, e2 >= a.w2, ps, pgx, pgy, pgz);
                     }
                 }
-                node = nx;
+                node = (zero || far || cell) ? sk : node + 1;
             }
         }
         __syncthreads();  // every task's sums are in dacc
