@@ -51,6 +51,22 @@ def load_profile(name: str, grid=None):
     return d
 
 
+def moments_counters(st_all, calls_per_run):
+    """HBM bytes of the moment pass per call (committed counter summary of
+    the benchmark cloud's chunk and straddler passes) over this run's
+    average moment-pass time per call."""
+    path = os.path.join(ROOT, "profiles", "traffic_moments_torusknot500k.json")
+    if not os.path.exists(path):
+        return None
+    tr = json.load(open(path))
+    n_calls = sum(int(calls_per_run[k]) for k in range(3))
+    per_call_ms = st_all["moments_ms"] / max(n_calls, 1)
+    b = tr["bytes_per_call"]
+    return {"bytes_per_call": b, "ms_per_call": round(per_call_ms, 4),
+            "gb_per_s": round(b / (per_call_ms * 1e-3) / 1e9, 1),
+            "frac_of_8TBps": round(b / (per_call_ms * 1e-3) / 8e12, 4)}
+
+
 def cpu_baseline(cloud, w: float, c: float):
     """The FP64 oracle treecode on the same cloud for one WNNC iteration's
     four operator calls (A, A^T, A, G over all points; a run has 159), from
@@ -508,6 +524,24 @@ def main():
     d = per_kind[dom]
     # one wavefront (64 threads, one workgroup) per task
     grid = int(st["n_tasks"]) * 64
+    # committed counter summaries of each kind's timed walk (used only when
+    # taken on the current traversal sources and this grid)
+    for kind, dk in per_kind.items():
+        sqk = load_profile(f"sq_traverse_{kind}_torusknot500k", grid)
+        trk = load_profile(f"traffic_traverse_{kind}_torusknot500k", grid)
+        if sqk and "SQ_INSTS_VALU" in sqk["per_dispatch"]:
+            pdk = sqk["per_dispatch"]
+            dk["counters"] = {
+                "valu_insts_per_launch": pdk["SQ_INSTS_VALU"],
+                "salu_insts_per_launch": pdk.get("SQ_INSTS_SALU"),
+                # lane-instructions per counted pair (wave64 instructions x 64)
+                "valu_lane_insts_per_pair": round(pdk["SQ_INSTS_VALU"] * 64 / dk["pairs_per_launch"], 2),
+                "valu_issue_frac": round(pdk["SQ_INSTS_VALU"] / (dk["avg_ms"] * 1e-3)
+                                         / sqk["valu_issue_peak_per_s"], 4),
+                "VALUBusy": pdk.get("VALUBusy"), "VALUUtilization": pdk.get("VALUUtilization")}
+        if trk:
+            dk["hbm_bytes_per_launch"] = trk["bytes_per_launch"]
+            dk["hbm_gb_per_s"] = round(trk["bytes_per_launch"] / (dk["avg_ms"] * 1e-3) / 1e9, 1)
     tr = load_profile(f"traffic_traverse_{dom}_torusknot500k", grid)
     roofline = {"bound": "alu", "achieved": round(d["tflops"], 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(d["tflops"] / PEAK_FP32_TFLOPS, 4),
@@ -579,6 +613,7 @@ def main():
         "tile_autotune_ms": {f"tpl{k[0]}_pf{k[1]}_split{k[2]}": round(v, 4)
                              for k, v in tile_ms.items()},
         "moments_ms_per_step": round(st_all["moments_ms"], 3),
+        "moments_counters": moments_counters(st_all, calls_per_run),
         "combine_ms_per_step": round(st_all["combine_ms"], 3),
         "host_wall_s_per_step": round((t_host1 - t_host0) / args.steps, 4),
         "accuracy_vs_generator": {"P_co": round(pco, 5), "AE_pcd": round(ae, 6)},

@@ -15,6 +15,8 @@ Three summaries, all from CSV output (``rocprofv3 ... -f csv -d DIR -o NAME``):
 * ``sq``: instruction counters (SQ_INSTS_VALU, ...) per dispatch of one
   kernel, and the fraction of the chip's wave64 vector-issue ceiling they
   take over the kernel's traced duration.
+* ``moments``: the traffic of one moment-pass call (chunk pass plus
+  straddler pass) on one workload, with their traced times and counters.
 
 ``python -m paper_2405_16634_amd.profiling trace --csv F --cmd "..." --out F``
 ``python -m paper_2405_16634_amd.profiling traffic --fetch F --write F
@@ -121,6 +123,44 @@ def traffic(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, mb, kernel, cmd,
     }
 
 
+def moments(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, mb, chunk_grid, strad_grid,
+            cmd, sq_csv=None, trace_csv=None):
+    """HBM bytes of one moment-pass call on one workload: its chunk pass
+    and its straddler pass (dispatches of the given grid sizes), each from
+    the two traffic counters scaled as in `traffic`; with a kernel trace
+    and SQ counters, each pass's time and instructions too."""
+    parts = {}
+    for name, rx, grid in (("chunk", r"k_moments_chunk<[0-9], false>", chunk_grid),
+                           ("straddler", r"k_moments_strad<false>", strad_grid)):
+        d = traffic(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, mb, rx, cmd, grid)
+        part = {k: d[k] for k in ("kernel", "grid_threads", "bytes_per_launch",
+                                   "read_bytes_per_launch", "write_bytes_per_launch",
+                                   "fetch_dispatches", "write_dispatches")}
+        if trace_csv:
+            r_ = re.compile(rx)
+            durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+                    for r in _rows(trace_csv) if _match(r, r_, grid)]
+            part["trace_avg_us"] = round(sum(durs) / len(durs) * 1e6, 2)
+            part["gb_per_s"] = round(d["bytes_per_launch"] / (sum(durs) / len(durs)) / 1e9, 1)
+        if sq_csv:
+            r_ = re.compile(rx)
+            per = {}
+            for r in _rows(sq_csv):
+                if _match(r, r_, grid):
+                    per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+            part["sq"] = {k: round(sum(v) / len(v), 1) for k, v in per.items()}
+        parts[name] = part
+        calib = d["calibration"]
+    out = {"parts": parts, "calibration": calib,
+           "bytes_per_call": parts["chunk"]["bytes_per_launch"] + parts["straddler"]["bytes_per_launch"],
+           "command": cmd}
+    if trace_csv:
+        t = parts["chunk"]["trace_avg_us"] + parts["straddler"]["trace_avg_us"]
+        out["trace_us_per_call"] = round(t, 2)
+        out["gb_per_s"] = round(out["bytes_per_call"] / (t * 1e-6) / 1e9, 1)
+    return out
+
+
 # Issue ceiling of one MI355X for wave64 vector instructions: 256 CUs x 4
 # SIMDs, each issuing one wave64 instruction per 4 cycles (16 lanes), 2.4 GHz.
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
@@ -214,6 +254,16 @@ def main():
     c.add_argument("--grid", type=int, default=None, help="only dispatches of this many threads")
     c.add_argument("--cmd", required=True)
     c.add_argument("--out", required=True)
+    m = sub.add_parser("moments")
+    for k in ("fetch", "write", "cal_fetch", "cal_write"):
+        m.add_argument("--" + k.replace("_", "-"), required=True)
+    m.add_argument("--mb", type=int, default=512)
+    m.add_argument("--chunk-grid", type=int, required=True)
+    m.add_argument("--strad-grid", type=int, required=True)
+    m.add_argument("--sq", default=None)
+    m.add_argument("--trace", default=None)
+    m.add_argument("--cmd", required=True)
+    m.add_argument("--out", required=True)
     a = ap.parse_args()
     if a.what == "trace":
         dg = []
@@ -226,6 +276,12 @@ def main():
                               trace_csv=a.trace, dispatch_groups=dg)
         with open(a.out, "w") as f:
             f.write(text)
+    elif a.what == "moments":
+        d = moments(a.fetch, a.write, a.cal_fetch, a.cal_write, a.mb, a.chunk_grid, a.strad_grid,
+                    a.cmd, a.sq, a.trace)
+        with open(a.out, "w") as f:
+            json.dump(d, f, indent=1)
+            f.write("\n")
     elif a.what == "sq":
         d = sq(a.csv, a.kernel, a.trace, a.cmd, a.grid)
         with open(a.out, "w") as f:
