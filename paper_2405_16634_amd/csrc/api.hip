@@ -107,6 +107,8 @@ MomArgs mom_args(wnnc_ctx_s *c, float w, bool paper = false) {
     a.tail_off = c->tail_off.p;
     a.tail_list = c->tail_list.p;
     a.strad_node = c->strad_node.p;
+    a.strad_topo = c->strad_topo.p;
+    a.wide_list = c->wide_list.p;
     a.perm = c->perm.p;
     a.chunk_tot = c->chunk_tot.p;
     a.head = c->head.p;
@@ -116,6 +118,7 @@ MomArgs mom_args(wnnc_ctx_s *c, float w, bool paper = false) {
     a.alpha = c->scalars.p;
     a.n = (int)c->n;
     a.n_strad = c->n_strad;
+    a.n_wide = c->n_wide;
     fill_thresholds(c, w, c->far_wsafe && !paper, a.thr2);
     a.order = paper ? 0 : c->far_order;
     a.momhi = a.order > 0 ? c->momhi.p : nullptr;
@@ -245,6 +248,8 @@ wnnc_status wnnc_destroy(wnnc_ctx ctx) {
     ctx->node_off.release();
     ctx->node_strad.release();
     ctx->strad_node.release();
+    ctx->strad_topo.release();
+    ctx->wide_list.release();
     ctx->tail_off.release();
     ctx->tail_list.release();
     ctx->chunk_tot.release();

@@ -58,10 +58,13 @@ struct wnnc_ctx_s {
     DevBuf<uint32_t> node_off;     // n+1: first node started by each point
     DevBuf<int32_t> node_strad;    // m: straddler slot or -1
     DevBuf<int32_t> strad_node;    // n_strad
+    DevBuf<int4> strad_topo;       // n_strad: topology of each straddler
     int32_t n_strad = 0;
+    DevBuf<int32_t> wide_list;     // straddler slots with more than 64 chunks in between
+    int32_t n_wide = 0;
     DevBuf<uint32_t> tail_off;     // chunks+1
     DevBuf<int32_t> tail_list;     // n_strad
-    DevBuf<double> chunk_tot;      // kMomSlots per chunk
+    DevBuf<double> chunk_tot;      // kMomSlots per chunk (slot-major)
     DevBuf<double> head, tail;     // kMomSlots per straddler
     DevBuf<float4> mom;            // kRecStride per node
     DevBuf<float> wbuf;            // per-node W, filled on request

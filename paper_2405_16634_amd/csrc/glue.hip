@@ -9,22 +9,44 @@ namespace wnnc {
 // cloud), 0 when the denominator is 0.  The cloud's per-task partial sums
 // are reduced in a fixed order.  Also stores the energy E = |rho|^2 of the
 // iteration (N_c / 4 for the iteration started from mu = 0).
-__global__ __launch_bounds__(256) void k_alpha(const double *__restrict__ partial, int nslots,
-                                               const int32_t *__restrict__ task_lo,
-                                               const int64_t *__restrict__ off, int first,
-                                               double *__restrict__ alpha,
-                                               double *__restrict__ energy_row) {
-    // per thread a strided sum, per wavefront a butterfly, then the four
-    // wavefront sums in order: a fixed order, so the result is reproducible
-    __shared__ double sh[3][256 / kWave];
+constexpr int kAlphaBlock = 1024;
+constexpr int kAlphaUnroll = 8;
+
+__global__ __launch_bounds__(kAlphaBlock) void k_alpha(const double *__restrict__ partial,
+                                                       int nslots,
+                                                       const int32_t *__restrict__ task_lo,
+                                                       const int64_t *__restrict__ off, int first,
+                                                       double *__restrict__ alpha,
+                                                       double *__restrict__ energy_row) {
+    // per thread a strided sum (kAlphaUnroll loads of each row in flight at
+    // once: the loads, not the additions, set the time), per wavefront a
+    // butterfly, then the wavefront sums in order: a fixed order, so the
+    // result is reproducible
+    constexpr int kWaves = kAlphaBlock / kWave;
+    __shared__ double sh[3][kWaves];
     const int c = blockIdx.x;
     const int lo = task_lo[c], hi = task_lo[c + 1];
-    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1), wv = tid / kWave;
     double acc[3] = {0.0, 0.0, 0.0};
-    for (int i = lo + threadIdx.x; i < hi; i += 256) {
-        if (!first) acc[0] += partial[i];
-        acc[1] += partial[nslots + i];
-        acc[2] += partial[2 * nslots + i];
+    for (int base = lo; base < hi; base += kAlphaUnroll * kAlphaBlock) {
+        double v[3][kAlphaUnroll];
+#pragma unroll
+        for (int u = 0; u < kAlphaUnroll; ++u) {
+            const int i = base + u * kAlphaBlock + tid;
+            const int ic = i < hi ? i : hi - 1;  // in range; its value is not used
+            v[0][u] = partial[ic];
+            v[1][u] = partial[nslots + ic];
+            v[2][u] = partial[2 * nslots + ic];
+        }
+#pragma unroll
+        for (int u = 0; u < kAlphaUnroll; ++u) {
+            if (base + u * kAlphaBlock + tid < hi) {
+                if (!first) acc[0] += v[0][u];
+                acc[1] += v[1][u];
+                acc[2] += v[2][u];
+            }
+        }
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -33,10 +55,14 @@ __global__ __launch_bounds__(256) void k_alpha(const double *__restrict__ partia
         if (lane == 0) sh[k][wv] = acc[k];
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         double tot[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) tot[k] = (sh[k][0] + sh[k][1]) + (sh[k][2] + sh[k][3]);
+        for (int k = 0; k < 3; ++k) {
+            double t = 0.0;
+            for (int w = 0; w < kWaves; ++w) t += sh[k][w];
+            tot[k] = t;
+        }
         const double r2 = tot[1], t2 = tot[2];
         alpha[c] = t2 > 0.0 ? r2 / t2 : 0.0;
         if (energy_row) energy_row[c] = first ? 0.25 * (double)(off[c + 1] - off[c]) : tot[0];
@@ -83,7 +109,7 @@ hipError_t launch_check_finite(const float *a, int64_t n, uint32_t *flag, hipStr
 }
 
 hipError_t launch_alpha(wnnc_ctx_s *ctx, bool first, double *energy_row) {
-    hipLaunchKernelGGL(k_alpha, dim3(ctx->nclouds), dim3(256), 0, ctx->stream, ctx->partial.p,
+    hipLaunchKernelGGL(k_alpha, dim3(ctx->nclouds), dim3(kAlphaBlock), 0, ctx->stream, ctx->partial.p,
                        ctx->ngroups, ctx->task_lo.p, ctx->d_offsets.p, first ? 1 : 0,
                        ctx->scalars.p, energy_row);
     return hipGetLastError();

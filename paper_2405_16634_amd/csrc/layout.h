@@ -24,7 +24,9 @@ __host__ __device__ inline int topo_depth(int meta) { return meta & 15; }
 __host__ __device__ inline int topo_leaf(int meta) { return (meta >> 4) & 1; }
 
 // Node record read by the traversal, 64 bytes per node (one 16-dword scalar
-// load); parts [0..2] are written by every moment pass, [3] with the tree:
+// load); parts [0..2] are written by every moment pass, [3] with the tree
+// (of a single-point leaf, whose representative is its point, only [1] is
+// written by the moment pass, [0] and [2] with the tree):
 //   [0] hi(x_B).x, .y, .z, flags (int bits)
 //   [1] nu_B (3 floats; a scalar attribute in .x), skip (int bits)
 //   [2] lo(x_B).x, .y, .z, (c * width)^2 (the acceptance threshold)
@@ -32,7 +34,8 @@ __host__ __device__ inline int topo_leaf(int meta) { return (meta >> 4) & 1; }
 // with x_B = hi + lo to about 2^-48 (hi = FP32 rounding of the FP64 x_B,
 // lo = FP32 rounding of the rest), so that target - x_B keeps full FP32
 // precision when the target is close to the node.
-// flags = depth | leaf << 4 | single-point leaf << 5 | zero weight << 6.
+// flags = depth | leaf << 4 | single-point leaf << 5 | zero weight << 6
+// (never set on a single-point leaf: its term with nu_B = 0 is an exact 0).
 // The traversal addresses records with 32-bit byte offsets: at most
 // kMaxNodes nodes.
 constexpr int kRecStride = 4;
@@ -118,6 +121,8 @@ struct MomArgs {
     const uint32_t *tail_off;
     const int32_t *tail_list;
     const int32_t *strad_node;
+    const int4 *strad_topo;  // topology of each straddler
+    const int32_t *wide_list;  // straddlers summed by a whole workgroup
     const uint32_t *perm;
     const float4 *src4;      // sorted vector input
     const float *srcs;       // sorted scalar input
@@ -129,7 +134,7 @@ struct MomArgs {
     const float *cs;         // caller-order scalar input
     float4 *out4;
     float *outs;
-    double *chunk_tot;       // kMomSlots doubles per chunk
+    double *chunk_tot;       // kMomSlots doubles per chunk, slot-major
     double *head;            // kMomSlots doubles per straddler
     double *tail;            // kMomSlots doubles per straddler
     float4 *mom;             // node records, kRecStride float4 per node
@@ -138,6 +143,7 @@ struct MomArgs {
     float thr2[16];          // squared acceptance distance per depth d, into records
     int n;
     int n_strad;
+    int n_wide;
     int order;               // far-field order: 0 (Alg. 4), 1 or 2 (also writes momhi)
     int scalar;              // the attribute is scalar (set by launch_moments)
 };

@@ -8,8 +8,9 @@
 // its chunk as a difference of two prefixes.  Nodes that cross a chunk
 // boundary ("straddlers") receive a head partial from their first chunk, a
 // tail partial from their last, and the totals of the chunks in between in a
-// second launch (one wavefront per straddler).  All sums run in a fixed
-// order, so the moments are bitwise reproducible from run to run.
+// second launch (one wavefront per straddler, the whole workgroup for one
+// that spans more than a wavefront's worth of chunks).  All sums run in a
+// fixed order, so the moments are bitwise reproducible from run to run.
 //
 // With a far field of order 1 or 2 (an extension: the Taylor expansion of
 // the pair term about x_B) the same pass also sums raw moments about the
@@ -78,31 +79,32 @@ __device__ inline void raw_hi(const float4 x, double n0, double n1, double n2, b
 }
 
 // Node record: x_B = X / W and nu_B in FP32 with the node's topology (skip
-// pointer and flags) so that the traversal needs one 32-byte load per node.
+// pointer and flags) so that the traversal needs one 64-byte load per node.
+// A single-point leaf's representative is its point, so only its nu_B is
+// written here (16 bytes); its position, flags and threshold (-1: every
+// target takes it) are written once with the tree.  It carries no zero
+// flag: with nu_B = 0 its term is an exact zero.
 template <bool HI>
 __device__ inline void write_moment(const MomArgs &a, int node, const int4 t, const double *s) {
     const double W = s[0];
-    int flags = t.w & 31;  // depth | leaf << 4
-    if ((flags & kRecLeaf) && t.z - t.y == 1) flags |= kRecSingle;
-    // a single-point leaf's representative is its point: threshold -1 makes
-    // every target take it as a representative
-    float4 p, lo = make_float4(0.f, 0.f, 0.f, (flags & kRecSingle) ? -1.0f : a.thr2[t.w & 15]);
-    if (W > 0.0) {
-        const double x = s[1] / W, y = s[2] / W, z = s[3] / W;
-        const float hx = (float)x, hy = (float)y, hz = (float)z;
-        p = make_float4(hx, hy, hz, __int_as_float(flags));
-        // a single point's representative is the point itself: hi is the
-        // point exactly (the FP64 quotient is within an FP64 ulp of it), lo 0
-        if (!(flags & kRecSingle))
+    float4 *rec = a.mom + (int64_t)kRecStride * node;
+    rec[1] = make_float4((float)s[4], (float)s[5], (float)s[6], __int_as_float(t.x));
+    const bool single = (t.w & kRecLeaf) && t.z - t.y == 1;
+    if (!single) {
+        const int flags = t.w & 31;  // depth | leaf << 4
+        float4 p, lo = make_float4(0.f, 0.f, 0.f, a.thr2[t.w & 15]);
+        if (W > 0.0) {
+            const double x = s[1] / W, y = s[2] / W, z = s[3] / W;
+            const float hx = (float)x, hy = (float)y, hz = (float)z;
+            p = make_float4(hx, hy, hz, __int_as_float(flags));
             lo = make_float4((float)(x - (double)hx), (float)(y - (double)hy),
                              (float)(z - (double)hz), lo.w);
-    } else {
-        p = make_float4(0.f, 0.f, 0.f, __int_as_float(flags | kRecZero));
+        } else {
+            p = make_float4(0.f, 0.f, 0.f, __int_as_float(flags | kRecZero));
+        }
+        rec[0] = p;
+        rec[2] = lo;  // rec[3] (the point range) is written once, with the tree
     }
-    float4 *rec = a.mom + (int64_t)kRecStride * node;
-    rec[0] = p;
-    rec[1] = make_float4((float)s[4], (float)s[5], (float)s[6], __int_as_float(t.x));
-    rec[2] = lo;  // rec[3] (the point range) is written once, with the tree
     if (a.wout) a.wout[node] = W > 0.0 ? fmaxf((float)W, FLT_MIN) : 0.f;
     if (HI) {
         // central moments about x_B (0 for a node that carries nothing)
@@ -190,6 +192,13 @@ __global__ __launch_bounds__(kChunk) void k_moments_chunk(MomArgs a) {
     const int cE = min(c0 + kChunk, a.n);
     const int cnt = cE - c0;
     const int i = c0 + tid;
+    // the nodes started inside this chunk, and the first one of this thread:
+    // loaded first, so that they arrive while the prefix sums are formed
+    const int nlo = (int)a.node_off[c0];
+    const int nhi = (int)a.node_off[cE];
+    // (an unconditional load at an index clamped to [0, M): no wait for it
+    // inside a branch)
+    const int4 t0 = a.topo[max(min(nlo + tid, nhi - 1), 0)];
 
     double v[kMomVals];
 #pragma unroll
@@ -250,13 +259,13 @@ __global__ __launch_bounds__(kChunk) void k_moments_chunk(MomArgs a) {
     }
     __syncthreads();
 
-    if (tid < kMomVals) a.chunk_tot[kMomSlots * c + tid] = P[tid][cnt - 1];
+    // chunk totals slot-major (slot k of chunk c at k * nchunks + c), so that
+    // the straddler pass reads consecutive chunks with one coalesced load
+    if (tid < kMomVals) a.chunk_tot[(int64_t)tid * gridDim.x + c] = P[tid][cnt - 1];
 
     // nodes started inside this chunk
-    const int nlo = (int)a.node_off[c0];
-    const int nhi = (int)a.node_off[cE];
     for (int nd = nlo + tid; nd < nhi; nd += kChunk) {
-        const int4 t = a.topo[nd];
+        const int4 t = nd == nlo + tid ? t0 : a.topo[nd];
         const int b = t.y - c0;
         double s[kMomVals];
         if (t.z <= cE) {
@@ -281,35 +290,74 @@ __global__ __launch_bounds__(kChunk) void k_moments_chunk(MomArgs a) {
     }
 }
 
-// One wavefront per straddler: head + totals of the chunks in between + tail.
+// Straddlers: head + totals of the chunks in between + tail.  A straddler
+// with at most a wavefront's worth of chunks in between is summed by one
+// wavefront, one chunk total per lane; a wide one (the nodes near the root)
+// by a whole workgroup of its own (the first n_wide workgroups), so that
+// every straddler's loads are in flight at once.  The loads of a
+// straddler's topology, head and tail do not depend on each other.  The
+// order of the additions is fixed (butterfly within a wavefront,
+// wavefronts in order).
+constexpr int kStradBlock = 512;
+constexpr int kStradWaves = kStradBlock / kWave;
+
 template <bool HI>
-__global__ __launch_bounds__(256) void k_moments_strad(MomArgs a) {
+__global__ __launch_bounds__(kStradBlock) void k_moments_strad(MomArgs a) {
     constexpr int kMomVals = mom_vals<HI>();
-    const int lane = threadIdx.x & (kWave - 1);
-    const int sl = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
-    if (sl >= a.n_strad) return;
+    __shared__ double red[kMomVals][kStradWaves];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wv = tid / kWave;
+    const int nchunks = (a.n + kChunk - 1) / kChunk;
+    const bool wide = (int)blockIdx.x < a.n_wide;
+    const int sl = wide ? a.wide_list[blockIdx.x]
+                        : ((int)blockIdx.x - a.n_wide) * kStradWaves + wv;
+    if (sl >= a.n_strad) return;  // (never in a wide workgroup)
+    const int4 t = a.strad_topo[sl];
     const int nd = a.strad_node[sl];
-    const int4 t = a.topo[nd];
+    double hd[kMomVals], tl[kMomVals];
+#pragma unroll
+    for (int k = 0; k < kMomVals; ++k) hd[k] = tl[k] = 0.0;
+    if ((wide ? tid : lane) == 0) {
+#pragma unroll
+        for (int k = 0; k < kMomVals; ++k) {
+            hd[k] = a.head[kMomSlots * sl + k];
+            tl[k] = a.tail[kMomSlots * sl + k];
+        }
+    }
     const int cb = t.y / kChunk, ce = (t.z - 1) / kChunk;
+    if (!wide && ce - cb - 1 > kWave) return;  // summed by a workgroup of its own
     double s[kMomVals];
 #pragma unroll
     for (int k = 0; k < kMomVals; ++k) s[k] = 0.0;
-    // (unrolled so that several chunks' loads are in flight; the additions
-    // keep their order)
-#pragma unroll 4
-    for (int c = cb + 1 + lane; c < ce; c += kWave) {
+    for (int c = cb + 1 + (wide ? tid : lane); c < ce; c += wide ? kStradBlock : kWave) {
 #pragma unroll
-        for (int k = 0; k < kMomVals; ++k) s[k] += a.chunk_tot[kMomSlots * c + k];
+        for (int k = 0; k < kMomVals; ++k) s[k] += a.chunk_tot[(int64_t)k * nchunks + c];
     }
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) {
 #pragma unroll
         for (int k = 0; k < kMomVals; ++k) s[k] += __shfl_xor(s[k], d, kWave);
     }
-    if (lane == 0) {
+    if (wide) {
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < kMomVals; ++k) red[k][wv] = s[k];
+        }
+        __syncthreads();
+        if (tid == 0) {
+#pragma unroll
+            for (int k = 0; k < kMomVals; ++k) {
+                double m = 0.0;
+                for (int v = 0; v < kStradWaves; ++v) m += red[k][v];
+                s[k] = m;
+            }
+        }
+    }
+    if ((wide ? tid : lane) == 0) {
         double tot[kMomVals];
 #pragma unroll
-        for (int k = 0; k < kMomVals; ++k) tot[k] = (a.head[kMomSlots * sl + k] + s[k]) + a.tail[kMomSlots * sl + k];
+        for (int k = 0; k < kMomVals; ++k) tot[k] = (hd[k] + s[k]) + tl[k];
         write_moment<HI>(a, nd, t, tot);
     }
 }
@@ -344,8 +392,9 @@ hipError_t launch_moments_t(wnnc_ctx_s *ctx, MomMode mode, const MomArgs &a) {
             break;
     }
     if (e != hipSuccess || last) return e;
-    const unsigned nb = (unsigned)((a.n_strad + 3) / 4);
-    return launch_k(ev, true, k_moments_strad<HI>, dim3(nb), dim3(256), st, a);
+    const unsigned nb =
+        (unsigned)(a.n_wide + (a.n_strad + kStradWaves - 1) / kStradWaves);
+    return launch_k(ev, true, k_moments_strad<HI>, dim3(nb), dim3(kStradBlock), st, a);
 }
 
 hipError_t launch_moments(wnnc_ctx_s *ctx, MomMode mode, const MomArgs &args) {

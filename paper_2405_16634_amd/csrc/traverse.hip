@@ -145,6 +145,43 @@ __device__ inline void pair_term(float dx, float dy, float dz, float r2, float4 
     }
 }
 
+// The same terms of A, A^T and G added to FP32 running sums of the
+// lockstep walk (p0 for A; p0, p1, p2 for the vector operators).  The walk
+// adds the running sums to its FP64 per-target sums whenever it changes
+// depth (a descent, or the end of a subtree) and after the direct sum of a
+// leaf's points, so a running sum holds the terms of at most 8 sibling
+// nodes (or of one leaf's points) and carries a rounding error of at most
+// about 8 * 2^-24 of the sum of their magnitudes.  The last operation of
+// each term is fused into the running sum.
+
+template <int OP>
+__device__ inline void pair_term_run(float dx, float dy, float dz, float r2, float4 v, bool take,
+                                     float &p0, float &p1, float &p2) {
+    if (OP == OP_A) {
+        const float ri = __builtin_amdgcn_rsqf(r2);
+        const float ri3 = (ri * ri) * ri;
+        const float dm = fmaf(dx, v.x, fmaf(dy, v.y, dz * v.z));
+        p0 = fmaf(dm, take ? -ri3 : 0.0f, p0);
+    } else if (OP == OP_AT) {
+        const float ri = __builtin_amdgcn_rsqf(r2);
+        const float ri3 = (ri * ri) * ri;
+        const float f = take ? v.x * ri3 : 0.0f;
+        p0 = fmaf(f, dx, p0);
+        p1 = fmaf(f, dy, p1);
+        p2 = fmaf(f, dz, p2);
+    } else {  // G, masked on r^2 as in pair_term
+        const float dm = fmaf(dx, v.x, fmaf(dy, v.y, dz * v.z));
+        const float gi = __builtin_amdgcn_rsqf(take ? r2 : __builtin_huge_valf());
+        const float gi2 = gi * gi;
+        const float a3 = gi2 * gi;
+        const float b5 = a3 * gi2;
+        const float c5 = 3.0f * dm * b5;
+        p0 = fmaf(v.x, a3, fmaf(-c5, dx, p0));
+        p1 = fmaf(v.y, a3, fmaf(-c5, dy, p1));
+        p2 = fmaf(v.z, a3, fmaf(-c5, dz, p2));
+    }
+}
+
 typedef float v8f __attribute__((ext_vector_type(8)));
 
 // Higher-order far-field terms (without the 1/(4 pi) factor) for target
@@ -385,6 +422,24 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
     // needs no read of the stack
     unsigned long long cur[TPL];
     int cur_depth = -1;
+    // FP32 running sums of the lockstep walk (A, A^T, G)
+    constexpr bool RUNS = OP == OP_A || OP == OP_AT || OP == OP_G;
+    float run0[TPL], run1[TPL], run2[TPL];
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) run0[k] = run1[k] = run2[k] = 0.0f;
+    auto add_runs = [&]() {
+#pragma unroll
+        for (int k = 0; k < TPL; ++k) {
+            if (OP == OP_A) {
+                s[k] += (double)run0[k];
+            } else {
+                gx[k] += (double)run0[k];
+                gy[k] += (double)run1[k];
+                gz[k] += (double)run2[k];
+            }
+            run0[k] = run1[k] = run2[k] = 0.0f;
+        }
+    };
     uint32_t cnt = 0;
     int visits = 0;
     // Deferred subtrees: a subtree that at most a.defer_k lanes of the group
@@ -520,7 +575,11 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
                 const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
                 // accepted (a single-point leaf always is)
                 const bool far = !zero && r2 > R2.w;
-                if (COUNT) dcnt += far ? 1u : 0u;
+                // (a single-point leaf with a zero attribute adds an exact
+                // zero and, like every zero-weight node, is not counted)
+                if (COUNT)
+                    dcnt += (far && !((fl & kRecSingle) && R1.x == 0.f && R1.y == 0.f &&
+                                      R1.z == 0.f)) ? 1u : 0u;
                 pair_term<OP>(dx, dy, dz, r2, make_float4(R1.x, R1.y, R1.z, 0.f), ptv,
                               far && r2 >= a.w2, ps, pgx, pgy, pgz);
                 const bool cell = !zero && !far && (fl & kRecLeaf) != 0;
@@ -564,6 +623,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
         const float thr2 = R[11];  // -1 for a single-point leaf: always taken
         const float4 V = make_float4(R[4], R[5], R[6], 0.f);
         if (depth != cur_depth) {
+            if constexpr (RUNS) add_runs();
 #pragma unroll
             for (int k = 0; k < TPL; ++k) cur[k] = read_mask(mlo[k], mhi[k], depth);
             cur_depth = depth;
@@ -598,8 +658,14 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
             // w2 >= the smallest normal float, so the cutoff also drops r = 0
             // (and keeps denormal arguments away from the hardware rsq).
             const unsigned long long take = far & __ballot(r2 >= a.w2);
-            pair_term<OP>(dx, dy, dz, r2, V, tv[k], lane_in(take), s[k], gx[k], gy[k], gz[k]);
-            if (COUNT) cnt += (uint32_t)__popcll(far);
+            if constexpr (RUNS)
+                pair_term_run<OP>(dx, dy, dz, r2, V, lane_in(take), run0[k], run1[k], run2[k]);
+            else
+                pair_term<OP>(dx, dy, dz, r2, V, tv[k], lane_in(take), s[k], gx[k], gy[k], gz[k]);
+            // (a single-point leaf with a zero attribute adds an exact zero
+            // and, like every zero-weight node, is not counted)
+            if (COUNT && !((flags & kRecSingle) && V.x == 0.f && V.y == 0.f && V.z == 0.f))
+                cnt += (uint32_t)__popcll(far);
             open[k] = act & ~far;
             any |= open[k];
             if (HI) htake[k] = take, hdx[k] = dx, hdy[k] = dy, hdz[k] = dz, hr2[k] = r2;
@@ -632,10 +698,15 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
                     const float ex = tx[k] - Q.x, ey = ty[k] - Q.y, ez = tz[k] - Q.z;
                     const float e2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
                     const unsigned long long take = open[k] & __ballot(e2 >= a.w2);
-                    pair_term<OP>(ex, ey, ez, e2, S, tv[k], lane_in(take), s[k], gx[k], gy[k],
-                                  gz[k]);
+                    if constexpr (RUNS)
+                        pair_term_run<OP>(ex, ey, ez, e2, S, lane_in(take), run0[k], run1[k],
+                                          run2[k]);
+                    else
+                        pair_term<OP>(ex, ey, ez, e2, S, tv[k], lane_in(take), s[k], gx[k],
+                                      gy[k], gz[k]);
                     if (COUNT) cnt += (uint32_t)__popcll(open[k]);
                 }
+                if constexpr (RUNS) add_runs();
             }
             return skip;
         }
@@ -657,6 +728,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
             return skip;
         }
         // push: lane depth + 1 takes the mask (selected by a scalar lane mask)
+        if constexpr (RUNS) add_runs();
         const bool at = lane_in(1ull << (depth + 1));
 #pragma unroll
         for (int k = 0; k < TPL; ++k) {
@@ -712,6 +784,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
         }
     }
 
+    if constexpr (RUNS) add_runs();
     if constexpr (DEFER) {  // the deferred tasks' sums of each target (0 if none)
         if (OP == OP_A) {
             s[0] += dacc[0][lane];

@@ -410,6 +410,12 @@ __global__ __launch_bounds__(256) void k_node_cells(const int4 *__restrict__ top
     if ((t.w & kRecLeaf) && t.z - t.y == 1) {
         const float4 q = pts[t.y];
         cells[k] = make_float4(q.x, q.y, q.z, -1.0f);
+        // a single-point leaf's representative is its point whatever its
+        // attribute: position (hi = the point, lo = 0), flags and threshold
+        // (-1: every target takes it) are written here once; the moment
+        // pass writes only its attribute
+        mom[kRecStride * k] = make_float4(q.x, q.y, q.z, __int_as_float((t.w & 31) | kRecSingle));
+        mom[kRecStride * k + 2] = make_float4(0.f, 0.f, 0.f, -1.0f);
         return;
     }
     const int depth = t.w & 15;
@@ -433,16 +439,41 @@ __global__ __launch_bounds__(256) void k_gather_points(const float *__restrict__
 // Straddlers: nodes whose point range crosses a chunk boundary.
 __global__ __launch_bounds__(256) void k_strad_compact(const uint32_t *__restrict__ flag,
                                                        const uint32_t *__restrict__ slot,
-                                                       int64_t m, int32_t *__restrict__ node_strad,
-                                                       int32_t *__restrict__ strad_node) {
+                                                       const int4 *__restrict__ topo, int64_t m,
+                                                       int32_t *__restrict__ node_strad,
+                                                       int32_t *__restrict__ strad_node,
+                                                       int4 *__restrict__ strad_topo) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= m) return;
     if (flag[k]) {
         node_strad[k] = (int32_t)slot[k];
         strad_node[slot[k]] = (int32_t)k;
+        strad_topo[slot[k]] = topo[k];
     } else {
         node_strad[k] = -1;
     }
+}
+
+// Wide straddlers: more chunks in between than a wavefront has lanes (the
+// moment pass sums them with a whole workgroup).  flag has ns + 1 entries,
+// the last 0, for the exclusive scan that numbers them.
+__global__ __launch_bounds__(256) void k_wide_flag(const int4 *__restrict__ strad_topo, int ns,
+                                                   uint32_t *__restrict__ flag) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s > ns) return;
+    uint32_t f = 0;
+    if (s < ns) {
+        const int4 t = strad_topo[s];
+        f = (t.z - 1) / kChunk - t.y / kChunk - 1 > kWave ? 1u : 0u;
+    }
+    flag[s] = f;
+}
+
+__global__ __launch_bounds__(256) void k_wide_compact(const uint32_t *__restrict__ flag,
+                                                      const uint32_t *__restrict__ slot, int ns,
+                                                      int32_t *__restrict__ list) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < ns && flag[s]) list[slot[s]] = s;
 }
 
 __global__ __launch_bounds__(256) void k_tail_count(const int32_t *__restrict__ strad_node,
@@ -591,11 +622,13 @@ hipError_t build_tree(wnnc_ctx_s *ctx, const float *P) {
     const int64_t ns = ns32;
     ctx->n_strad = (int32_t)ns;
     TRY(ctx->strad_node.ensure(ns + 1));
+    TRY(ctx->strad_topo.ensure(ns + 1));
     TRY(ctx->tail_list.ensure(ns + 1));
     TRY(ctx->head.ensure((int64_t)kMomSlots * (ns + 1)));
     TRY(ctx->tail.ensure((int64_t)kMomSlots * (ns + 1)));
     hipLaunchKernelGGL(k_strad_compact, dim3(blocks_for(m, 256)), dim3(256), 0, st, ctx->mflag.p,
-                       ctx->mslot.p, m, ctx->node_strad.p, ctx->strad_node.p);
+                       ctx->mslot.p, ctx->topo.p, m, ctx->node_strad.p, ctx->strad_node.p,
+                       ctx->strad_topo.p);
     // chunk -> straddlers whose range ends inside it (CSR); counts reuse mflag
     uint32_t *tcnt = ctx->u32_tmp.p;  // n+1 >= chunks+1 entries
     TRY(hipMemsetAsync(tcnt, 0, (size_t)(nchunks + 1) * sizeof(uint32_t), st));
@@ -609,6 +642,18 @@ hipError_t build_tree(wnnc_ctx_s *ctx, const float *P) {
     if (ns > 0)
         hipLaunchKernelGGL(k_tail_fill, dim3(blocks_for(ns, 256)), dim3(256), 0, st,
                            ctx->strad_node.p, ctx->topo.p, (int)ns, cursor, ctx->tail_list.p);
+    // wide straddlers (flags in mflag, their numbers in mslot: both free again)
+    hipLaunchKernelGGL(k_wide_flag, dim3(blocks_for(ns + 1, 256)), dim3(256), 0, st,
+                       ctx->strad_topo.p, (int)ns, ctx->mflag.p);
+    TRY(exclusive_scan_u32(ctx->mflag.p, ctx->mslot.p, ns + 1, ctx->scan_tmp.p, st));
+    uint32_t nw32 = 0;
+    TRY(hipMemcpyAsync(&nw32, ctx->mslot.p + ns, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    TRY(ctx->wide_list.ensure((int64_t)ns + 1));
+    if (ns > 0)
+        hipLaunchKernelGGL(k_wide_compact, dim3(blocks_for(ns, 256)), dim3(256), 0, st,
+                           ctx->mflag.p, ctx->mslot.p, (int)ns, ctx->wide_list.p);
+    TRY(hipStreamSynchronize(st));
+    ctx->n_wide = (int32_t)nw32;
     TRY(hipMemsetAsync(ctx->pair_ctr.p, 0, kOpKinds * sizeof(unsigned long long), st));
     return hipGetLastError();
 }

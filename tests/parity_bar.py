@@ -29,6 +29,31 @@ TOL = 1e-5
 TIE = 1e-6
 EXEMPT_FRAC = 1e-4
 L2_TOL = 1e-5
+# Two device walks that make the same decisions and form the same FP32
+# terms but group their additions differently (tile shapes, split walks,
+# deferred subtrees): each walk adds a target's terms to FP32 running sums
+# of at most 8 terms (the children of one node, or one leaf's points) before
+# its FP64 sum, so either side is within about 8 * 2^-24 (plus one FP32
+# rounding per term) of the exact sum of its terms, relative to the sum of
+# their magnitudes M_i: a difference of at most about 1.1e-6 M_i.
+ORDER_TOL = 2e-6
+
+
+def same_terms(label, a, b, mag, tol=ORDER_TOL):
+    """Asserts |a_i - b_i| <= tol * M_i for every target (an exact tie
+    where M_i = 0); returns the largest ratio."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    mag = np.asarray(mag, np.float64)
+    err = np.abs(a - b)
+    if err.ndim == 2:
+        err = np.linalg.norm(err, axis=1)
+    pos = mag > 0
+    assert np.all(err[~pos] == 0.0), label
+    rel = err[pos] / mag[pos]
+    worst = float(rel.max()) if rel.size else 0.0
+    assert worst <= tol, f"{label}: summation-order difference {worst:.3e} M_i > {tol:g} M_i"
+    return worst
 
 
 def ties(margins):
