@@ -169,7 +169,7 @@ struct TravArgs {
     const int4 *tasks;       // per wavefront: first, last target; first, end node
     const int32_t *task_slot;  // >= 0: group slot (whole walk); < 0: -1 - part slot
     const int32_t *roots;    // first node of each cloud (nclouds + 1)
-    double *parts;           // per part slot: 3 x 64 FP64 sums (component-major)
+    float *parts;            // per part slot: 3 x 64 sums rounded to FP32 (component-major)
     int32_t *plan;           // TR_PLAN output, kPlanStride ints per group
     int ntasks;              // wavefronts launched
     int nslots;              // groups: row stride of the per-group partial sums

@@ -71,6 +71,9 @@ constexpr double kInv4Pi = 0.0795774715459476678844;  // 1 / (4 pi)
 // per wavefront before they are walked.
 constexpr int kDeferEntries = 64;
 constexpr int kDeferTasks = 1024;
+// The packed walks hand out new tasks when more than kDeferSlack lanes
+// have finished theirs.
+constexpr int kDeferSlack = 24;
 
 // Pair term without the 1/(4 pi) factor.  d = target - source, r2 = |d|^2.
 //   A  : -(d . nu) / r^3
@@ -559,48 +562,55 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
                 px = p.x, py = p.y, pz = p.z;
                 if (OP == OP_P || OP == OP_T) ptv = dtv[tg];
             }
-            const bool act = node < end;
+            bool act = node < end;
             if (__ballot(act) == 0ull && nextt >= nt) break;
-            if (act) {
-                // the whole record in one round of loads; the branches below
-                // are selects, except the rare direct sum of a leaf's points
-                const float4 *rb =
-                    (const float4 *)((const char *)a.mom + ((uint32_t)node << 6));
-                const float4 R0 = rb[0], R1 = rb[1], R2 = rb[2];
-                const int fl = __float_as_int(R0.w);
-                const int sk = __float_as_int(R1.w);
-                const bool zero = (fl & kRecZero) != 0;  // nothing below: skip it
-                const float dx = (px - R0.x) - R2.x, dy = (py - R0.y) - R2.y,
-                            dz = (pz - R0.z) - R2.z;
-                const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                // accepted (a single-point leaf always is)
-                const bool far = !zero && r2 > R2.w;
-                // (a single-point leaf with a zero attribute adds an exact
-                // zero and, like every zero-weight node, is not counted)
-                if (COUNT)
-                    dcnt += (far && !((fl & kRecSingle) && R1.x == 0.f && R1.y == 0.f &&
-                                      R1.z == 0.f)) ? 1u : 0u;
-                pair_term<OP>(dx, dy, dz, r2, make_float4(R1.x, R1.y, R1.z, 0.f), ptv,
-                              far && r2 >= a.w2, ps, pgx, pgy, pgz);
-                const bool cell = !zero && !far && (fl & kRecLeaf) != 0;
-                if (cell) {  // the points of a depth-D cell (or a leaf of several)
-                    const float4 R3 = rb[3];
-                    const int jb = __float_as_int(R3.x), je = __float_as_int(R3.y);
-                    for (int j = jb; j < je; ++j) {
-                        const float4 Q = a.pts[j];
-                        float4 S;
-                        if (OP == OP_AT || OP == OP_P)
-                            S = make_float4(a.srcs[j], 0.f, 0.f, 0.f);
-                        else
-                            S = a.src4[j];
-                        const float ex = px - Q.x, ey = py - Q.y, ez = pz - Q.z;
-                        const float e2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
-                        if (COUNT) ++dcnt;
-                        pair_term<OP>(ex, ey, ez, e2, S, ptv, e2 >= a.w2, ps, pgx, pgy, pgz);
+            // step the walks until more than kDeferSlack lanes are idle
+            // while tasks remain (then hand out more), or until all are
+            // done: the hand-out is not paid on every step
+            const int keep = nextt < nt ? kWave - kDeferSlack : 1;
+            do {
+                if (act) {
+                    // the whole record in one round of loads; the branches below
+                    // are selects, except the rare direct sum of a leaf's points
+                    const float4 *rb =
+                        (const float4 *)((const char *)a.mom + ((uint32_t)node << 6));
+                    const float4 R0 = rb[0], R1 = rb[1], R2 = rb[2];
+                    const int fl = __float_as_int(R0.w);
+                    const int sk = __float_as_int(R1.w);
+                    const bool zero = (fl & kRecZero) != 0;  // nothing below: skip it
+                    const float dx = (px - R0.x) - R2.x, dy = (py - R0.y) - R2.y,
+                                dz = (pz - R0.z) - R2.z;
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    // accepted (a single-point leaf always is)
+                    const bool far = !zero && r2 > R2.w;
+                    // (a single-point leaf with a zero attribute adds an exact
+                    // zero and, like every zero-weight node, is not counted)
+                    if (COUNT)
+                        dcnt += (far && !((fl & kRecSingle) && R1.x == 0.f && R1.y == 0.f &&
+                                          R1.z == 0.f)) ? 1u : 0u;
+                    pair_term<OP>(dx, dy, dz, r2, make_float4(R1.x, R1.y, R1.z, 0.f), ptv,
+                                  far && r2 >= a.w2, ps, pgx, pgy, pgz);
+                    const bool cell = !zero && !far && (fl & kRecLeaf) != 0;
+                    if (cell) {  // the points of a depth-D cell (or a leaf of several)
+                        const float4 R3 = rb[3];
+                        const int jb = __float_as_int(R3.x), je = __float_as_int(R3.y);
+                        for (int j = jb; j < je; ++j) {
+                            const float4 Q = a.pts[j];
+                            float4 S;
+                            if (OP == OP_AT || OP == OP_P)
+                                S = make_float4(a.srcs[j], 0.f, 0.f, 0.f);
+                            else
+                                S = a.src4[j];
+                            const float ex = px - Q.x, ey = py - Q.y, ez = pz - Q.z;
+                            const float e2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
+                            if (COUNT) ++dcnt;
+                            pair_term<OP>(ex, ey, ez, e2, S, ptv, e2 >= a.w2, ps, pgx, pgy, pgz);
+                        }
                     }
+                    node = (zero || far || cell) ? sk : node + 1;
                 }
-                node = (zero || far || cell) ? sk : node + 1;
-            }
+                act = node < end;
+            } while (__popcll(__ballot(act)) >= keep);
         }
         __syncthreads();  // every task's sums are in dacc
         dne = 0;
@@ -807,14 +817,14 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
         if (lane == 0) a.plan[(int64_t)tslot * kPlanStride] = visits;
         return;
     }
-    if (tslot < 0) {  // one part of a split walk (TPL = 1): its sums
-        double *qp = a.parts + (int64_t)(-1 - tslot) * (3 * kWave);
+    if (tslot < 0) {  // one part of a split walk (TPL = 1): its sums, rounded to FP32
+        float *qp = a.parts + (int64_t)(-1 - tslot) * (3 * kWave);
         if (OP == OP_A) {
-            qp[lane] = s[0];
+            qp[lane] = (float)s[0];
         } else {
-            qp[lane] = gx[0];
-            qp[kWave + lane] = gy[0];
-            qp[2 * kWave + lane] = gz[0];
+            qp[lane] = (float)gx[0];
+            qp[kWave + lane] = (float)gy[0];
+            qp[2 * kWave + lane] = (float)gz[0];
         }
         return;
     }
@@ -829,21 +839,40 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
 }
 
 // Groups walked in parts: one wavefront per group adds its parts' sums in
-// part order and runs the epilogue.
+// part order (in FP64; the parts are FP32, each within 2^-24 of the sum of
+// its terms' magnitudes) and runs the epilogue.  The parts are loaded
+// kCombineBatch at a time, all in flight before the additions.
+constexpr int kCombineBatch = 4;
+
 template <int OP, int MODE>
 __global__ __launch_bounds__(kWave) void k_combine(TravArgs a, const int4 *__restrict__ groups,
                                                    const int32_t *__restrict__ gslot) {
     const int lane = threadIdx.x;
     const int4 g = ldc_i4(groups + blockIdx.x);
     double s = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
-    for (int p = g.z; p < g.w; ++p) {
-        const double *qp = a.parts + (int64_t)p * (3 * kWave);
-        if (OP == OP_A) {
-            s += qp[lane];
-        } else {
-            gx += qp[lane];
-            gy += qp[kWave + lane];
-            gz += qp[2 * kWave + lane];
+    for (int p0 = g.z; p0 < g.w; p0 += kCombineBatch) {
+        float v0[kCombineBatch], v1[kCombineBatch], v2[kCombineBatch];
+#pragma unroll
+        for (int u = 0; u < kCombineBatch; ++u) {
+            // (a part past the group's last reads the last one; not added)
+            const float *qp = a.parts + (int64_t)min(p0 + u, g.w - 1) * (3 * kWave);
+            v0[u] = qp[lane];
+            if (OP != OP_A) {
+                v1[u] = qp[kWave + lane];
+                v2[u] = qp[2 * kWave + lane];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kCombineBatch; ++u) {
+            if (p0 + u < g.w) {
+                if (OP == OP_A) {
+                    s += (double)v0[u];
+                } else {
+                    gx += (double)v0[u];
+                    gy += (double)v1[u];
+                    gz += (double)v2[u];
+                }
+            }
         }
     }
     double e = 0.0, e2 = 0.0;
