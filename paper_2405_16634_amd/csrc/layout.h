@@ -34,8 +34,9 @@ __host__ __device__ inline int topo_leaf(int meta) { return (meta >> 4) & 1; }
 // with x_B = hi + lo to about 2^-48 (hi = FP32 rounding of the FP64 x_B,
 // lo = FP32 rounding of the rest), so that target - x_B keeps full FP32
 // precision when the target is close to the node.
-// flags = depth | leaf << 4 | single-point leaf << 5 | zero weight << 6
-// (never set on a single-point leaf: its term with nu_B = 0 is an exact 0).
+// flags = depth | leaf << 4 | single-point leaf << 5.  A node of zero
+// weight (every attribute in it zero) has threshold -1 and nu_B = 0: every
+// target takes it as an exact zero term, and none descends into it.
 // The traversal addresses records with 32-bit byte offsets: at most
 // kMaxNodes nodes.
 constexpr int kRecStride = 4;
@@ -62,7 +63,6 @@ constexpr int kMomHi = kMomBase + 16;
 constexpr int64_t kMaxNodes = int64_t(1) << 26;
 constexpr int kRecLeaf = 16;
 constexpr int kRecSingle = 32;
-constexpr int kRecZero = 64;
 
 enum Op { OP_A = WNNC_OP_A, OP_AT = WNNC_OP_AT, OP_G = WNNC_OP_G, OP_P = WNNC_OP_P, OP_T = WNNC_OP_T };
 constexpr int kOpKinds = 5;

@@ -82,8 +82,10 @@ __device__ inline void raw_hi(const float4 x, double n0, double n1, double n2, b
 // pointer and flags) so that the traversal needs one 64-byte load per node.
 // A single-point leaf's representative is its point, so only its nu_B is
 // written here (16 bytes); its position, flags and threshold (-1: every
-// target takes it) are written once with the tree.  It carries no zero
-// flag: with nu_B = 0 its term is an exact zero.
+// target takes it) are written once with the tree.  A node whose weight W
+// is zero (every attribute in it is zero) gets threshold -1 as well: every
+// target takes it, with nu_B = 0 an exact zero term, and none descends
+// into it.
 template <bool HI>
 __device__ inline void write_moment(const MomArgs &a, int node, const int4 t, const double *s) {
     const double W = s[0];
@@ -100,7 +102,8 @@ __device__ inline void write_moment(const MomArgs &a, int node, const int4 t, co
             lo = make_float4((float)(x - (double)hx), (float)(y - (double)hy),
                              (float)(z - (double)hz), lo.w);
         } else {
-            p = make_float4(0.f, 0.f, 0.f, __int_as_float(flags | kRecZero));
+            p = make_float4(0.f, 0.f, 0.f, __int_as_float(flags));
+            lo.w = -1.0f;
         }
         rec[0] = p;
         rec[2] = lo;  // rec[3] (the point range) is written once, with the tree

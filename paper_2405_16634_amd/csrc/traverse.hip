@@ -172,16 +172,15 @@ __device__ inline void pair_term_run(float dx, float dy, float dz, float r2, flo
         p0 = fmaf(f, dx, p0);
         p1 = fmaf(f, dy, p1);
         p2 = fmaf(f, dz, p2);
-    } else {  // G, masked on r^2 as in pair_term
+    } else {  // G, masked on r^2 as in pair_term: (nu - 3 (d . nu) d / r^2) / r^3
         const float dm = fmaf(dx, v.x, fmaf(dy, v.y, dz * v.z));
         const float gi = __builtin_amdgcn_rsqf(take ? r2 : __builtin_huge_valf());
         const float gi2 = gi * gi;
         const float a3 = gi2 * gi;
-        const float b5 = a3 * gi2;
-        const float c5 = 3.0f * dm * b5;
-        p0 = fmaf(v.x, a3, fmaf(-c5, dx, p0));
-        p1 = fmaf(v.y, a3, fmaf(-c5, dy, p1));
-        p2 = fmaf(v.z, a3, fmaf(-c5, dz, p2));
+        const float u = (3.0f * dm) * gi2;
+        p0 = fmaf(a3, fmaf(-u, dx, v.x), p0);
+        p1 = fmaf(a3, fmaf(-u, dy, v.y), p1);
+        p2 = fmaf(a3, fmaf(-u, dz, v.z), p2);
     }
 }
 
@@ -495,14 +494,12 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
             const int depth = flags & 15;
 #pragma unroll
             for (int k = 0; k < TPL; ++k) {
-                unsigned long long open = 0ull;  // a zero-weight node is not descended
-                if (!(flags & kRecZero)) {
-                    const unsigned long long act = read_mask(mlo[k], mhi[k], depth);
-                    const float dx = (tx[k] - R[0]) - R[8], dy = (ty[k] - R[1]) - R[9],
-                                dz = (tz[k] - R[2]) - R[10];
-                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                    open = act & ~__ballot(r2 > R[11]);
-                }
+                // (a zero-weight node, threshold -1, is opened by no lane)
+                const unsigned long long act = read_mask(mlo[k], mhi[k], depth);
+                const float dx = (tx[k] - R[0]) - R[8], dy = (ty[k] - R[1]) - R[9],
+                            dz = (tz[k] - R[2]) - R[10];
+                const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                const unsigned long long open = act & ~__ballot(r2 > R[11]);
                 if (lane == depth + 1) {
                     mlo[k] = (uint32_t)open;
                     mhi[k] = (uint32_t)(open >> 32);
@@ -577,20 +574,20 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
                     const float4 R0 = rb[0], R1 = rb[1], R2 = rb[2];
                     const int fl = __float_as_int(R0.w);
                     const int sk = __float_as_int(R1.w);
-                    const bool zero = (fl & kRecZero) != 0;  // nothing below: skip it
                     const float dx = (px - R0.x) - R2.x, dy = (py - R0.y) - R2.y,
                                 dz = (pz - R0.z) - R2.z;
                     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                    // accepted (a single-point leaf always is)
-                    const bool far = !zero && r2 > R2.w;
-                    // (a single-point leaf with a zero attribute adds an exact
-                    // zero and, like every zero-weight node, is not counted)
+                    // accepted (a single-point leaf and a zero-weight node
+                    // always are)
+                    const bool far = r2 > R2.w;
+                    // (a node of zero weight adds an exact zero and is not
+                    // counted)
                     if (COUNT)
-                        dcnt += (far && !((fl & kRecSingle) && R1.x == 0.f && R1.y == 0.f &&
+                        dcnt += (far && !(R2.w < 0.f && R1.x == 0.f && R1.y == 0.f &&
                                           R1.z == 0.f)) ? 1u : 0u;
                     pair_term<OP>(dx, dy, dz, r2, make_float4(R1.x, R1.y, R1.z, 0.f), ptv,
                                   far && r2 >= a.w2, ps, pgx, pgy, pgz);
-                    const bool cell = !zero && !far && (fl & kRecLeaf) != 0;
+                    const bool cell = !far && (fl & kRecLeaf) != 0;
                     if (cell) {  // the points of a depth-D cell (or a leaf of several)
                         const float4 R3 = rb[3];
                         const int jb = __float_as_int(R3.x), je = __float_as_int(R3.y);
@@ -607,7 +604,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
                             pair_term<OP>(ex, ey, ez, e2, S, ptv, e2 >= a.w2, ps, pgx, pgy, pgz);
                         }
                     }
-                    node = (zero || far || cell) ? sk : node + 1;
+                    node = (far || cell) ? sk : node + 1;
                 }
                 act = node < end;
             } while (__popcll(__ballot(act)) >= keep);
@@ -628,7 +625,6 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
         }
         const int flags = __float_as_int(R[3]);
         const int skip = __float_as_int(R[7]);
-        if (flags & kRecZero) return skip;  // every attribute in the node is zero
         const int depth = flags & 15;
         const float thr2 = R[11];  // -1 for a single-point leaf: always taken
         const float4 V = make_float4(R[4], R[5], R[6], 0.f);
@@ -672,9 +668,9 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
                 pair_term_run<OP>(dx, dy, dz, r2, V, lane_in(take), run0[k], run1[k], run2[k]);
             else
                 pair_term<OP>(dx, dy, dz, r2, V, tv[k], lane_in(take), s[k], gx[k], gy[k], gz[k]);
-            // (a single-point leaf with a zero attribute adds an exact zero
-            // and, like every zero-weight node, is not counted)
-            if (COUNT && !((flags & kRecSingle) && V.x == 0.f && V.y == 0.f && V.z == 0.f))
+            // (a node of zero weight, threshold -1 and nu_B = 0, adds an
+            // exact zero and is not counted)
+            if (COUNT && !(thr2 < 0.f && V.x == 0.f && V.y == 0.f && V.z == 0.f))
                 cnt += (uint32_t)__popcll(far);
             open[k] = act & ~far;
             any |= open[k];
