@@ -35,7 +35,7 @@ PEAK_FP32_TFLOPS = 157.3
 def load_profile(name: str, grid=None):
     """A committed rocprofv3 summary (profiles/NAME.json), if it was taken on
     the current traversal sources (and, given `grid`, on dispatches of that
-    many threads: the same workload)."""
+    many threads: the same workload and launch configuration)."""
     path = os.path.join(ROOT, "profiles", name + ".json")
     if not os.path.exists(path):
         return None
@@ -412,6 +412,9 @@ def main():
     ap.add_argument("--cpu-plan", action="store_true",
                     help="only time the CPU oracle as the measurement plan states it "
                          "(about two minutes) and print that JSON")
+    ap.add_argument("--split", type=int, default=None,
+                    help="walk split (node visits per part) used after the autotuner instead "
+                         "of its choice: for profiling runs of one launch configuration")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -449,6 +452,8 @@ def main():
     cs0 = w.wnnc_normalize(ctx.handle, P, Pn)
     w.wnnc_build(ctx.handle, Pn, c, depth)
     tile_ms = ctx.autotune(w1)
+    if args.split is not None:
+        ctx.set_split(args.split)
 
     # pair counts: one run with the counting kernels (same decisions)
     ctx.set_flags(w.FLAG_COUNT_PAIRS)
@@ -524,11 +529,12 @@ def main():
     d = per_kind[dom]
     # one wavefront (64 threads, one workgroup) per task
     grid = int(st["n_tasks"]) * 64
-    # committed counter summaries of each kind's timed walk (used only when
-    # taken on the current traversal sources and this grid)
+    # committed counter summaries of each kind's timed walk, per walk split
+    # (used only when taken on the current traversal sources and this grid)
+    split = ctx.split()
     for kind, dk in per_kind.items():
-        sqk = load_profile(f"sq_traverse_{kind}_torusknot500k", grid)
-        trk = load_profile(f"traffic_traverse_{kind}_torusknot500k", grid)
+        sqk = load_profile(f"sq_traverse_{kind}_torusknot500k_split{split}", grid)
+        trk = load_profile(f"traffic_traverse_{kind}_torusknot500k_split{split}", grid)
         if sqk and "SQ_INSTS_VALU" in sqk["per_dispatch"]:
             pdk = sqk["per_dispatch"]
             dk["counters"] = {
@@ -542,7 +548,7 @@ def main():
         if trk:
             dk["hbm_bytes_per_launch"] = trk["bytes_per_launch"]
             dk["hbm_gb_per_s"] = round(trk["bytes_per_launch"] / (dk["avg_ms"] * 1e-3) / 1e9, 1)
-    tr = load_profile(f"traffic_traverse_{dom}_torusknot500k", grid)
+    tr = load_profile(f"traffic_traverse_{dom}_torusknot500k_split{split}", grid)
     roofline = {"bound": "alu", "achieved": round(d["tflops"], 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(d["tflops"] / PEAK_FP32_TFLOPS, 4),
                 # without packed FP32 (the library is compiled without it) the ceiling is half
@@ -552,7 +558,7 @@ def main():
                 "grid_threads": grid,
                 "avg_launch_ms": round(d["avg_ms"], 4),
                 "flop_per_launch": round(d["pairs_per_launch"] * FLOPS_PER_PAIR[{"A": 0, "AT": 1, "G": 2}[dom]])}
-    sq = load_profile(f"sq_traverse_{dom}_torusknot500k", grid)
+    sq = load_profile(f"sq_traverse_{dom}_torusknot500k_split{split}", grid)
     if sq and "SQ_INSTS_VALU" in sq["per_dispatch"]:
         # the instruction-issue view: wave64 vector instructions per launch
         # (committed counters) over this run's launch time

@@ -1,6 +1,6 @@
 """Host logic of the benchmark (no device): committed counter summaries are
 used only when they were taken on the current traversal sources and on
-dispatches of the benchmark's grid size, and the benchmark refuses more than
+dispatches of the benchmark's grid size (one summary per walk split), and the benchmark refuses more than
 one GPU."""
 import json
 import os
@@ -17,7 +17,7 @@ def test_profiles_are_matched_by_source_digest_and_grid(tmp_path, monkeypatch):
     current is not a property of the code: the bench line shows it)."""
     import bench
     from paper_2405_16634_amd.profiling import traversal_digest
-    name = "traffic_traverse_A_torusknot500k"
+    name = "traffic_traverse_A_torusknot500k_split512"
     d = json.load(open(os.path.join(ROOT, "profiles", name + ".json")))
     (tmp_path / "profiles").mkdir()
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
