@@ -153,9 +153,10 @@ __device__ inline void pair_term(float dx, float dy, float dz, float r2, float4 
 // adds the running sums to its FP64 per-target sums whenever it changes
 // depth (a descent, or the end of a subtree) and after the direct sum of a
 // leaf's points, so a running sum holds the terms of at most 8 sibling
-// nodes (or of one leaf's points) and carries a rounding error of at most
-// about 8 * 2^-24 of the sum of their magnitudes.  The last operation of
-// each term is fused into the running sum.
+// nodes and of the points of at most one leaf, and carries a rounding error
+// of at most about 2^-24 times their number times the sum of their
+// magnitudes.  The last operation of each term is fused into the running
+// sum.
 
 template <int OP>
 __device__ inline void pair_term_run(float dx, float dy, float dz, float r2, float4 v, bool take,

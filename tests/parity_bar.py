@@ -31,11 +31,13 @@ EXEMPT_FRAC = 1e-4
 L2_TOL = 1e-5
 # Two device walks that make the same decisions and form the same FP32
 # terms but group their additions differently (tile shapes, split walks,
-# deferred subtrees): each walk adds a target's terms to FP32 running sums
-# of at most 8 terms (the children of one node, or one leaf's points) before
-# its FP64 sum, so either side is within about 8 * 2^-24 (plus one FP32
-# rounding per term) of the exact sum of its terms, relative to the sum of
-# their magnitudes M_i: a difference of at most about 1.1e-6 M_i.
+# deferred subtrees).  With u = 2^-24 and M_i the sum of the target's term
+# magnitudes: the lockstep walk adds a target's terms to FP32 running sums
+# of at most 8 sibling nodes (and the points of one leaf, at most 8 with
+# the leaf capacities tested) before its FP64 sum, at most about 8 u M_i of
+# rounding; a deferred step rounds each term once and adds it in FP64; a
+# split walk rounds each part's FP64 sum to FP32 once (u times the part's
+# magnitudes).  Two walks then differ by at most about 18 u M_i = 1.1e-6 M_i.
 ORDER_TOL = 2e-6
 
 
