@@ -243,14 +243,15 @@ wnnc_status wnnc_set_prefetch(wnnc_ctx ctx, int on);
  * WNNC_AUTOTUNE_CONFIGS settings on the current tree and keeps the fastest
  * (a setting later in the list must be faster by more than 1 %):
  * (tpl, split) = (1, 0), (2, 0), (4, 0), (1, 1024), (1, 512), (1, 256),
- * each with prefetch off and on (in that order).  times_out (host,
+ * (1, 128), (1, 64), each with prefetch off and on (in that order); the
+ * short splits fill the chip on small clouds (few target groups).  times_out (host,
  * WNNC_AUTOTUNE_CONFIGS entries, may be NULL) receives the settings and
  * their times per iteration.  Then, on the chosen tiles, each operator
  * kind takes the other prefetch setting if its traversal launches are
  * faster with it by more than 1 % (see wnnc_stats_t.prefetch_ops).
  * Overwrites the context's iteration buffers; instrumentation statistics
  * are kept.  Synchronizes. */
-#define WNNC_AUTOTUNE_CONFIGS 12
+#define WNNC_AUTOTUNE_CONFIGS 16
 typedef struct {
     int tpl;
     int prefetch;

@@ -42,7 +42,7 @@ EXPORTED = [
 ]
 NOALLOC_MAX_POINTS = 1 << 20
 MLP_PARAMS = 7491
-AUTOTUNE_CONFIGS = 12
+AUTOTUNE_CONFIGS = 16
 MAX_SPLIT = 1 << 20
 
 

@@ -583,7 +583,7 @@ wnnc_status wnnc_autotune(wnnc_ctx ctx, float w, wnnc_tile_time *times_out) {
     for (int k = 0; k < kOpKinds; ++k) ctx->pf_op[k] = -1;
     // (tpl, split) pairs, each with and without prefetch
     static const int cand[WNNC_AUTOTUNE_CONFIGS / 2][2] = {
-        {1, 0}, {2, 0}, {4, 0}, {1, 1024}, {1, 512}, {1, 256}};
+        {1, 0}, {2, 0}, {4, 0}, {1, 1024}, {1, 512}, {1, 256}, {1, 128}, {1, 64}};
     double best_ms = 1e300;
     int best = ctx->tpl, best_pf = ctx->prefetch, best_split = ctx->split;
     hipEvent_t e0, e1;
