@@ -139,6 +139,7 @@ TravArgs trav_args(wnnc_ctx_s *c, float w) {
     a.cloud = c->cloud_of.p;
     a.tasks = c->tasks.p;
     a.task_slot = c->task_slot.p;
+    a.chain = c->task_chain.p;
     a.roots = c->d_roots.p;
     a.parts = c->parts.p;
     a.ntasks = c->ntasks;
@@ -280,6 +281,7 @@ wnnc_status wnnc_destroy(wnnc_ctx ctx) {
     ctx->cloud_of.release();
     ctx->tasks.release();
     ctx->task_slot.release();
+    ctx->task_chain.release();
     ctx->task_lo.release();
     ctx->knn_groups.release();
     ctx->knn_tmp.release();

@@ -102,6 +102,7 @@ struct wnnc_ctx_s {
     int nsplit = 0;                // groups walked in parts
     DevBuf<int4> tasks;
     DevBuf<int32_t> task_slot;
+    DevBuf<int32_t> task_chain;    // ntasks * kChainStride: ancestors of each task's first node
     DevBuf<int32_t> task_lo;       // nclouds + 1: group range of each cloud
     DevBuf<int4> split_groups;     // nsplit: first, last target; first, end part slot
     DevBuf<int32_t> split_slot;    // nsplit: group slot

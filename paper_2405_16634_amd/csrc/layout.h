@@ -113,6 +113,11 @@ constexpr int kPlanStep = 64;
 constexpr int kPlanCap = 63;
 constexpr int kPlanStride = kPlanCap + 1;
 
+// Per task, the ancestors of its first node (a part of a split walk):
+// their count, then the nodes from the cloud's root down (at most one per
+// depth above the deepest), kChainStride ints per task.
+constexpr int kChainStride = kMaxDepth + 1;
+
 struct MomArgs {
     const float4 *pts;       // sorted points
     const int4 *topo;
@@ -168,6 +173,7 @@ struct TravArgs {
     const int32_t *cloud;    // cloud of each sorted point (for flips)
     const int4 *tasks;       // per wavefront: first, last target; first, end node
     const int32_t *task_slot;  // >= 0: group slot (whole walk); < 0: -1 - part slot
+    const int32_t *chain;    // per task: ancestors of its first node (kChainStride ints)
     const int32_t *roots;    // first node of each cloud (nclouds + 1)
     float *parts;            // per part slot: 3 x 64 sums rounded to FP32 (component-major)
     int32_t *plan;           // TR_PLAN output, kPlanStride ints per group

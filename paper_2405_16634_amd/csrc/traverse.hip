@@ -484,15 +484,19 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
         mhi[k] = lane == 0 ? (uint32_t)(act0 >> 32) : 0u;
     }
 
-    // A part: the decisions at the ancestors of its first node, from the
-    // cloud's root down (at most one ancestor per depth, at most 8 children
-    // per node, so both loops end on any input).
-    {
-        int node = ldc_i(a.roots + ldc_i(a.tcloud + first));
-        for (int d = 0; d < kMaxDepth && node < nbeg; ++d) {
-            const v16f R = ld_rec(a.mom, node);
-            const int flags = __float_as_int(R[3]);
-            const int depth = flags & 15;
+    // A part of a split walk (task slot < 0): the decisions at the ancestors
+    // of its first node, from the cloud's root down.  The ancestors are
+    // listed with the tasks (one 64-byte load), so their records do not
+    // wait for each other.  A whole walk starts at the root and has none.
+    if (TPL == 1 && tslot < 0) {  // (walks are split only with one group per wavefront)
+        typedef int v16i __attribute__((ext_vector_type(16)));
+        const v16i C = *(const WNNC_AS4 v16i *)(a.chain + (int64_t)wave * kChainStride);
+        const int na = C[0];
+#pragma unroll
+        for (int d = 0; d < kMaxDepth; ++d) {
+            if (d >= na) continue;
+            const v16f R = ld_rec(a.mom, C[1 + d]);
+            const int depth = __float_as_int(R[3]) & 15;
 #pragma unroll
             for (int k = 0; k < TPL; ++k) {
                 // (a zero-weight node, threshold -1, is opened by no lane)
@@ -506,14 +510,6 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
                     mhi[k] = (uint32_t)(open >> 32);
                 }
             }
-            // the child whose subtree holds the first node
-            int ch = node + 1;
-            for (int c = 0; c < 8; ++c) {
-                const int sk = ldc_i((const int *)(a.mom + kRecStride * ch + 1) + 3);
-                if (sk > nbeg) break;
-                ch = sk;
-            }
-            node = ch;
         }
     }
 

@@ -658,6 +658,35 @@ hipError_t build_tree(wnnc_ctx_s *ctx, const float *P) {
     return hipGetLastError();
 }
 
+// The ancestors of each task's first node, from its cloud's root down: the
+// nodes at which a part of a split walk re-evaluates its lanes' decisions
+// (none for a walk that starts at the root).  At most one ancestor per
+// depth and 8 children per node are examined, so the loops end.
+__global__ __launch_bounds__(256) void k_task_chains(const int4 *__restrict__ tasks,
+                                                     const int32_t *__restrict__ cloud,
+                                                     const int32_t *__restrict__ roots,
+                                                     const int4 *__restrict__ topo, int ntasks,
+                                                     int32_t *__restrict__ chain) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntasks) return;
+    const int4 tk = tasks[t];
+    const int nbeg = tk.z;
+    int node = roots[cloud[tk.x]];
+    int32_t *out = chain + (int64_t)t * kChainStride;
+    int cnt = 0;
+    for (int d = 0; d < kMaxDepth && node < nbeg; ++d) {
+        out[1 + cnt++] = node;
+        int ch = node + 1;  // the child whose subtree holds the first node
+        for (int c = 0; c < 8; ++c) {
+            const int sk = topo[ch].x;
+            if (sk > nbeg) break;
+            ch = sk;
+        }
+        node = ch;
+    }
+    out[0] = cnt;
+}
+
 // Wavefront tasks for tile shape tpl: each cloud's sorted targets cut into
 // runs of 64 * tpl, in Morton order, cloud after cloud.  The partial-sum
 // slot of a task is its index, so a cloud's slots are contiguous.
@@ -736,6 +765,12 @@ hipError_t make_tasks(wnnc_ctx_s *ctx, int tpl, int split) {
         TRY(hipMemcpyAsync(ctx->split_slot.p, sslot.data(), (size_t)ns * sizeof(int32_t),
                            hipMemcpyHostToDevice, ctx->stream));
     }
+    TRY(ctx->task_chain.ensure(nt * kChainStride));
+    if (nt > 0)
+        hipLaunchKernelGGL(k_task_chains, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0,
+                           ctx->stream, ctx->tasks.p, ctx->cloud_of.p, ctx->d_roots.p,
+                           ctx->topo.p, (int)nt, ctx->task_chain.p);
+    TRY(hipGetLastError());
     // the host vectors are released on return: wait for the copies
     TRY(hipStreamSynchronize(ctx->stream));
     ctx->ntasks = (int)nt;
