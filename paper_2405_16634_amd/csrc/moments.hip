@@ -299,7 +299,7 @@ __global__ __launch_bounds__(kChunk) void k_moments_chunk(MomArgs a) {
 // by a whole workgroup of its own (the first n_wide workgroups), so that
 // every straddler's loads are in flight at once.  The loads of a
 // straddler's topology, head and tail do not depend on each other.  The
-// order of the additions is fixed (butterfly within a wavefront,
+// order of the additions is fixed (a DPP scan within a wavefront,
 // wavefronts in order).
 constexpr int kStradBlock = 512;
 constexpr int kStradWaves = kStradBlock / kWave;
@@ -321,7 +321,10 @@ __global__ __launch_bounds__(kStradBlock) void k_moments_strad(MomArgs a) {
     double hd[kMomVals], tl[kMomVals];
 #pragma unroll
     for (int k = 0; k < kMomVals; ++k) hd[k] = tl[k] = 0.0;
-    if ((wide ? tid : lane) == 0) {
+    // the thread that writes the record: the last lane of a wavefront (where
+    // its scan ends), thread 0 of a wide straddler's workgroup
+    const bool writer = wide ? tid == 0 : lane == kWave - 1;
+    if (writer) {
 #pragma unroll
         for (int k = 0; k < kMomVals; ++k) {
             hd[k] = a.head[kMomSlots * sl + k];
@@ -337,13 +340,11 @@ __global__ __launch_bounds__(kStradBlock) void k_moments_strad(MomArgs a) {
 #pragma unroll
         for (int k = 0; k < kMomVals; ++k) s[k] += a.chunk_tot[(int64_t)k * nchunks + c];
     }
+    // the wavefront's sum in its last lane (a fixed-order DPP scan)
 #pragma unroll
-    for (int d = kWave / 2; d > 0; d >>= 1) {
-#pragma unroll
-        for (int k = 0; k < kMomVals; ++k) s[k] += __shfl_xor(s[k], d, kWave);
-    }
+    for (int k = 0; k < kMomVals; ++k) s[k] = wave_scan(s[k]);
     if (wide) {
-        if (lane == 0) {
+        if (lane == kWave - 1) {
 #pragma unroll
             for (int k = 0; k < kMomVals; ++k) red[k][wv] = s[k];
         }
@@ -357,7 +358,7 @@ __global__ __launch_bounds__(kStradBlock) void k_moments_strad(MomArgs a) {
             }
         }
     }
-    if ((wide ? tid : lane) == 0) {
+    if (writer) {
         double tot[kMomVals];
 #pragma unroll
         for (int k = 0; k < kMomVals; ++k) tot[k] = (hd[k] + s[k]) + tl[k];
