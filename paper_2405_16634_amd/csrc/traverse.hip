@@ -23,6 +23,7 @@
 
 #include "common.h"
 #include "internal.h"
+#include "wave.h"
 
 namespace wnnc {
 
@@ -285,11 +286,6 @@ __device__ inline bool lane_in(unsigned long long mask) {
     return __builtin_amdgcn_inverse_ballot_w64(mask);
 }
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
-    return v;
-}
 
 __device__ inline unsigned long long read_mask(uint32_t lo, uint32_t hi, int depth) {
     return (unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)lo, depth) |
@@ -366,17 +362,18 @@ __device__ inline void finish_group(const TravArgs &a, int sl, int first, int la
         for (int d = kWave / 2; d > 0; d >>= 1) tot += __shfl_xor(tot, d, kWave);
         if (lane == 0 && tot) atomicAdd(a.flips + a.tcloud[first], (unsigned long long)tot);
     }
+    // (fixed-order scans: reproducible; the last lane holds the sum)
     if (MODE == TR_SCALE) {
-        e = wave_sum(e);
-        e2 = wave_sum(e2);
-        if (lane == 0) {
+        e = wave_scan(e);
+        e2 = wave_scan(e2);
+        if (lane == kWave - 1) {
             a.partial[sl] = e;
             a.partial[a.nslots + sl] = e2;
         }
     }
     if (MODE == TR_RHO || MODE == TR_R || MODE == TR_TSUM) {
-        e = wave_sum(e);  // fixed butterfly order: reproducible
-        if (lane == 0) a.partial[sl] = e;
+        e = wave_scan(e);
+        if (lane == kWave - 1) a.partial[sl] = e;
     }
 }
 

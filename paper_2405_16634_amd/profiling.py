@@ -33,7 +33,8 @@ import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TRAVERSAL_SOURCES = [os.path.join(HERE, "csrc", "traverse.hip"),
-                     os.path.join(HERE, "csrc", "layout.h")]
+                     os.path.join(HERE, "csrc", "layout.h"),
+                     os.path.join(HERE, "csrc", "wave.h")]
 
 
 def _code_only(text: str) -> str:
