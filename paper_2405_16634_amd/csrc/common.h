@@ -63,7 +63,7 @@ struct wnnc_ctx_s {
     DevBuf<int32_t> wide_list;     // straddler slots with more than 64 chunks in between
     int32_t n_wide = 0;
     DevBuf<uint32_t> tail_off;     // chunks+1
-    DevBuf<int32_t> tail_list;     // n_strad
+    DevBuf<int2> tail_list;        // n_strad: (straddler slot, end point), by end chunk
     DevBuf<double> chunk_tot;      // kMomSlots per chunk (slot-major)
     DevBuf<double> head, tail;     // kMomSlots per straddler
     DevBuf<float4> mom;            // kRecStride per node

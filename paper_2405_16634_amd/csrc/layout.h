@@ -124,7 +124,7 @@ struct MomArgs {
     const uint32_t *node_off;
     const int32_t *node_strad;
     const uint32_t *tail_off;
-    const int32_t *tail_list;
+    const int2 *tail_list;   // (straddler slot, end point) of the straddlers ending in each chunk
     const int32_t *strad_node;
     const int4 *strad_topo;  // topology of each straddler
     const int32_t *wide_list;  // straddlers summed by a whole workgroup

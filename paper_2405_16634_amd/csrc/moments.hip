@@ -176,9 +176,14 @@ __global__ __launch_bounds__(kChunk) void k_moments_chunk(MomArgs a) {
     // loaded first, so that they arrive while the prefix sums are formed
     const int nlo = (int)a.node_off[c0];
     const int nhi = (int)a.node_off[cE];
-    // (an unconditional load at an index clamped to [0, M): no wait for it
-    // inside a branch)
-    const int4 t0 = a.topo[max(min(nlo + tid, nhi - 1), 0)];
+    const int tlo = (int)a.tail_off[c], thi = (int)a.tail_off[c + 1];
+    // (unconditional loads at indices clamped to the arrays: no wait for
+    // them inside a branch): this thread's first node, its straddler slot,
+    // and its first straddler ending in this chunk
+    const int n0 = max(min(nlo + tid, nhi - 1), 0);
+    const int4 t0 = a.topo[n0];
+    const int sl0 = a.node_strad[n0];
+    const int2 tq0 = a.tail_list[max(min(tlo + tid, thi - 1), 0)];
 
     double v[kMomVals];
 #pragma unroll
@@ -254,17 +259,17 @@ __global__ __launch_bounds__(kChunk) void k_moments_chunk(MomArgs a) {
             for (int k = 0; k < kMomVals; ++k) s[k] = P[k][e] - (b > 0 ? P[k][b - 1] : 0.0);
             write_moment<HI>(a, nd, t, s);
         } else {
-            const int sl = a.node_strad[nd];
+            const int sl = nd == nlo + tid ? sl0 : a.node_strad[nd];
 #pragma unroll
             for (int k = 0; k < kMomVals; ++k)
                 a.head[kMomSlots * sl + k] = P[k][cnt - 1] - (b > 0 ? P[k][b - 1] : 0.0);
         }
     }
     // straddlers whose range ends inside this chunk
-    const int tlo = (int)a.tail_off[c], thi = (int)a.tail_off[c + 1];
     for (int q = tlo + tid; q < thi; q += kChunk) {
-        const int sl = a.tail_list[q];
-        const int e = a.topo[a.strad_node[sl]].z - c0 - 1;
+        const int2 tq = q == tlo + tid ? tq0 : a.tail_list[q];
+        const int sl = tq.x;
+        const int e = tq.y - c0 - 1;
 #pragma unroll
         for (int k = 0; k < kMomVals; ++k) a.tail[kMomSlots * sl + k] = P[k][e];
     }

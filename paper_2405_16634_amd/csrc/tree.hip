@@ -485,15 +485,17 @@ __global__ __launch_bounds__(256) void k_tail_count(const int32_t *__restrict__ 
     atomicAdd(&cnt[(e - 1) / kChunk], 1u);
 }
 
+// (straddler slot, end point) of every straddler, listed under the chunk
+// its range ends in
 __global__ __launch_bounds__(256) void k_tail_fill(const int32_t *__restrict__ strad_node,
                                                    const int4 *__restrict__ topo, int ns,
                                                    uint32_t *__restrict__ cursor,
-                                                   int32_t *__restrict__ list) {
+                                                   int2 *__restrict__ list) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= ns) return;
     const int e = topo[strad_node[s]].z;
     const uint32_t q = atomicAdd(&cursor[(e - 1) / kChunk], 1u);
-    list[q] = s;
+    list[q] = make_int2(s, e);
 }
 
 // ------------------------------------------------------------------- host --
