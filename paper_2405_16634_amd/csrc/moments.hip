@@ -183,6 +183,11 @@ __global__ __launch_bounds__(kChunk) void k_moments_chunk(MomArgs a) {
     const int n0 = max(min(nlo + tid, nhi - 1), 0);
     const int4 t0 = a.topo[n0];
     const int sl0 = a.node_strad[n0];
+    // (and its second one: on the benchmark cloud a chunk of 512 points
+    // starts about 950 nodes, so nearly every node is one of these two)
+    const int n1 = max(min(nlo + tid + kChunk, nhi - 1), 0);
+    const int4 t1 = a.topo[n1];
+    const int sl1 = a.node_strad[n1];
     const int2 tq0 = a.tail_list[max(min(tlo + tid, thi - 1), 0)];
 
     double v[kMomVals];
@@ -250,7 +255,7 @@ __global__ __launch_bounds__(kChunk) void k_moments_chunk(MomArgs a) {
 
     // nodes started inside this chunk
     for (int nd = nlo + tid; nd < nhi; nd += kChunk) {
-        const int4 t = nd == nlo + tid ? t0 : a.topo[nd];
+        const int4 t = nd == nlo + tid ? t0 : (nd == nlo + tid + kChunk ? t1 : a.topo[nd]);
         const int b = t.y - c0;
         double s[kMomVals];
         if (t.z <= cE) {
@@ -259,7 +264,8 @@ __global__ __launch_bounds__(kChunk) void k_moments_chunk(MomArgs a) {
             for (int k = 0; k < kMomVals; ++k) s[k] = P[k][e] - (b > 0 ? P[k][b - 1] : 0.0);
             write_moment<HI>(a, nd, t, s);
         } else {
-            const int sl = nd == nlo + tid ? sl0 : a.node_strad[nd];
+            const int sl = nd == nlo + tid ? sl0
+                                           : (nd == nlo + tid + kChunk ? sl1 : a.node_strad[nd]);
 #pragma unroll
             for (int k = 0; k < kMomVals; ++k)
                 a.head[kMomSlots * sl + k] = P[k][cnt - 1] - (b > 0 ? P[k][b - 1] : 0.0);
