@@ -101,14 +101,12 @@ MomArgs mom_args(wnnc_ctx_s *c, float w, bool paper = false) {
     MomArgs a;
     memset(&a, 0, sizeof(a));
     a.pts = c->pts.p;
-    a.topo = c->topo.p;
+    a.mnode = c->mnode.p;
     a.node_off = c->node_off.p;
-    a.node_strad = c->node_strad.p;
     a.tail_off = c->tail_off.p;
     a.tail_list = c->tail_list.p;
     a.strad_node = c->strad_node.p;
     a.strad_topo = c->strad_topo.p;
-    a.wide_list = c->wide_list.p;
     a.perm = c->perm.p;
     a.chunk_tot = c->chunk_tot.p;
     a.head = c->head.p;
@@ -250,13 +248,15 @@ wnnc_status wnnc_destroy(wnnc_ctx ctx) {
     ctx->node_strad.release();
     ctx->strad_node.release();
     ctx->strad_topo.release();
-    ctx->wide_list.release();
+    ctx->wflag.release();
+    ctx->wslot.release();
     ctx->tail_off.release();
     ctx->tail_list.release();
     ctx->chunk_tot.release();
     ctx->head.release();
     ctx->tail.release();
     ctx->mom.release();
+    ctx->mnode.release();
     ctx->keys_a.release();
     ctx->keys_b.release();
     ctx->vals_b.release();

@@ -56,17 +56,17 @@ struct wnnc_ctx_s {
     DevBuf<int4> topo;             // m
     DevBuf<float4> cells;          // m: node cell box, or the point of a single-point leaf
     DevBuf<uint32_t> node_off;     // n+1: first node started by each point
-    DevBuf<int32_t> node_strad;    // m: straddler slot or -1
+    DevBuf<int32_t> node_strad;    // m: straddler slot or -1 (build)
     DevBuf<int32_t> strad_node;    // n_strad
     DevBuf<int4> strad_topo;       // n_strad: topology of each straddler
     int32_t n_strad = 0;
-    DevBuf<int32_t> wide_list;     // straddler slots with more than 64 chunks in between
-    int32_t n_wide = 0;
+    int32_t n_wide = 0;            // straddlers 0 .. n_wide - 1 have more than 64 chunks in between
     DevBuf<uint32_t> tail_off;     // chunks+1
     DevBuf<int2> tail_list;        // n_strad: (straddler slot, end point), by end chunk
     DevBuf<double> chunk_tot;      // kMomSlots per chunk (slot-major)
     DevBuf<double> head, tail;     // kMomSlots per straddler
     DevBuf<float4> mom;            // kRecStride per node
+    DevBuf<int2> mnode;            // m: the moment pass's view of each node
     DevBuf<float> wbuf;            // per-node W, filled on request
 
     // build scratch
@@ -76,6 +76,7 @@ struct wnnc_ctx_s {
     DevBuf<uint32_t> scan_tmp;
     DevBuf<uint32_t> u32_tmp;      // n+1
     DevBuf<uint32_t> mflag, mslot; // m+1
+    DevBuf<uint32_t> wflag, wslot; // m+1
     DevBuf<double> norm_tmp;
     DevBuf<int64_t> norm_off;
 

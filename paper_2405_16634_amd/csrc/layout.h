@@ -24,9 +24,10 @@ __host__ __device__ inline int topo_depth(int meta) { return meta & 15; }
 __host__ __device__ inline int topo_leaf(int meta) { return (meta >> 4) & 1; }
 
 // Node record read by the traversal, 64 bytes per node (one 16-dword scalar
-// load); parts [0..2] are written by every moment pass, [3] with the tree
-// (of a single-point leaf, whose representative is its point, only [1] is
-// written by the moment pass, [0] and [2] with the tree):
+// load).  The moment pass writes hi(x_B), nu_B and part [2]; the flags, the
+// skip pointer and part [3] are written once, with the tree (of a
+// single-point leaf, whose representative is its point, the moment pass
+// writes only nu_B: its position and threshold are written with the tree):
 //   [0] hi(x_B).x, .y, .z, flags (int bits)
 //   [1] nu_B (3 floats; a scalar attribute in .x), skip (int bits)
 //   [2] lo(x_B).x, .y, .z, (c * width)^2 (the acceptance threshold)
@@ -63,6 +64,13 @@ constexpr int kMomHi = kMomBase + 16;
 constexpr int64_t kMaxNodes = int64_t(1) << 26;
 constexpr int kRecLeaf = 16;
 constexpr int kRecSingle = 32;
+// The moment pass's view of a node started inside a chunk, one int2 per
+// node: (first point, end point | depth << kMnodeEndBits) for a node that
+// ends inside the chunk it starts in, (first point, -1 - straddler slot)
+// for one that does not.
+constexpr int kMnodeEndBits = 26;
+constexpr int kMnodeEndMask = (1 << kMnodeEndBits) - 1;
+static_assert(kMaxNodes <= (int64_t(1) << kMnodeEndBits), "end points fit the node view");
 
 enum Op { OP_A = WNNC_OP_A, OP_AT = WNNC_OP_AT, OP_G = WNNC_OP_G, OP_P = WNNC_OP_P, OP_T = WNNC_OP_T };
 constexpr int kOpKinds = 5;
@@ -120,14 +128,12 @@ constexpr int kChainStride = kMaxDepth + 1;
 
 struct MomArgs {
     const float4 *pts;       // sorted points
-    const int4 *topo;
+    const int2 *mnode;       // per node: the moment pass's view (kMnodeEndBits)
     const uint32_t *node_off;
-    const int32_t *node_strad;
     const uint32_t *tail_off;
     const int2 *tail_list;   // (straddler slot, end point) of the straddlers ending in each chunk
     const int32_t *strad_node;
     const int4 *strad_topo;  // topology of each straddler
-    const int32_t *wide_list;  // straddlers summed by a whole workgroup
     const uint32_t *perm;
     const float4 *src4;      // sorted vector input
     const float *srcs;       // sorted scalar input
@@ -148,7 +154,7 @@ struct MomArgs {
     float thr2[16];          // squared acceptance distance per depth d, into records
     int n;
     int n_strad;
-    int n_wide;
+    int n_wide;              // straddlers 0 .. n_wide - 1 are summed by a whole workgroup each
     int order;               // far-field order: 0 (Alg. 4), 1 or 2 (also writes momhi)
     int scalar;              // the attribute is scalar (set by launch_moments)
 };

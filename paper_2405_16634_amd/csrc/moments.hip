@@ -79,35 +79,41 @@ __device__ inline void raw_hi(const float4 x, double n0, double n1, double n2, b
     }
 }
 
-// Node record: x_B = X / W and nu_B in FP32 with the node's topology (skip
-// pointer and flags) so that the traversal needs one 64-byte load per node.
-// A single-point leaf's representative is its point, so only its nu_B is
-// written here (16 bytes); its position, flags and threshold (-1: every
-// target takes it) are written once with the tree.  A node whose weight W
-// is zero (every attribute in it is zero) gets threshold -1 as well: every
-// target takes it, with nu_B = 0 an exact zero term, and none descends
-// into it.
+// Stores three floats (one 12-byte store at a 16-byte aligned address).
+__device__ inline void st3(float4 *p, float x, float y, float z) {
+    float *q = (float *)p;
+    q[0] = x;
+    q[1] = y;
+    q[2] = z;
+}
+
+// Node record: x_B = X / W and nu_B in FP32 beside the node's flags and skip
+// pointer (written with the tree), so that the traversal needs one 64-byte
+// load per node.  A single-point leaf's representative is its point, so
+// only its nu_B is written here (12 bytes); its position, flags and
+// threshold (-1: every target takes it) are written with the tree.  A node
+// whose weight W is zero (every attribute in it is zero) gets threshold -1
+// as well: every target takes it, with nu_B = 0 an exact zero term, and
+// none descends into it.
 template <bool HI>
-__device__ inline void write_moment(const MomArgs &a, int node, const int4 t, const double *s) {
+__device__ inline void write_moment(const MomArgs &a, int node, int depth, bool single,
+                                    const double *s) {
     const double W = s[0];
     float4 *rec = a.mom + (int64_t)kRecStride * node;
-    rec[1] = make_float4((float)s[4], (float)s[5], (float)s[6], __int_as_float(t.x));
-    const bool single = (t.w & kRecLeaf) && t.z - t.y == 1;
+    st3(rec + 1, (float)s[4], (float)s[5], (float)s[6]);
     if (!single) {
-        const int flags = t.w & 31;  // depth | leaf << 4
-        float4 p, lo = make_float4(0.f, 0.f, 0.f, a.thr2[t.w & 15]);
+        float hx = 0.f, hy = 0.f, hz = 0.f;
+        float4 lo = make_float4(0.f, 0.f, 0.f, a.thr2[depth]);
         if (W > 0.0) {
             const double x = s[1] / W, y = s[2] / W, z = s[3] / W;
-            const float hx = (float)x, hy = (float)y, hz = (float)z;
-            p = make_float4(hx, hy, hz, __int_as_float(flags));
+            hx = (float)x, hy = (float)y, hz = (float)z;
             lo = make_float4((float)(x - (double)hx), (float)(y - (double)hy),
                              (float)(z - (double)hz), lo.w);
         } else {
-            p = make_float4(0.f, 0.f, 0.f, __int_as_float(flags));
             lo.w = -1.0f;
         }
-        rec[0] = p;
-        rec[2] = lo;  // rec[3] (the point range) is written once, with the tree
+        st3(rec, hx, hy, hz);
+        rec[2] = lo;
     }
     if (a.wout) a.wout[node] = W > 0.0 ? fmaxf((float)W, FLT_MIN) : 0.f;
     if (HI) {
@@ -178,16 +184,14 @@ __global__ __launch_bounds__(kChunk) void k_moments_chunk(MomArgs a) {
     const int nhi = (int)a.node_off[cE];
     const int tlo = (int)a.tail_off[c], thi = (int)a.tail_off[c + 1];
     // (unconditional loads at indices clamped to the arrays: no wait for
-    // them inside a branch): this thread's first node, its straddler slot,
-    // and its first straddler ending in this chunk
+    // them inside a branch): this thread's first node, its second one (on
+    // the benchmark cloud a chunk of 512 points starts about 950 nodes, so
+    // nearly every node is one of these two) and its first straddler ending
+    // in this chunk
     const int n0 = max(min(nlo + tid, nhi - 1), 0);
-    const int4 t0 = a.topo[n0];
-    const int sl0 = a.node_strad[n0];
-    // (and its second one: on the benchmark cloud a chunk of 512 points
-    // starts about 950 nodes, so nearly every node is one of these two)
+    const int2 t0 = a.mnode[n0];
     const int n1 = max(min(nlo + tid + kChunk, nhi - 1), 0);
-    const int4 t1 = a.topo[n1];
-    const int sl1 = a.node_strad[n1];
+    const int2 t1 = a.mnode[n1];
     const int2 tq0 = a.tail_list[max(min(tlo + tid, thi - 1), 0)];
 
     double v[kMomVals];
@@ -253,39 +257,50 @@ __global__ __launch_bounds__(kChunk) void k_moments_chunk(MomArgs a) {
     // the straddler pass reads consecutive chunks with one coalesced load
     if (tid < kMomVals) a.chunk_tot[(int64_t)tid * gridDim.x + c] = P[tid][cnt - 1];
 
-    // nodes started inside this chunk
-    for (int nd = nlo + tid; nd < nhi; nd += kChunk) {
-        const int4 t = nd == nlo + tid ? t0 : (nd == nlo + tid + kChunk ? t1 : a.topo[nd]);
-        const int b = t.y - c0;
+    // nodes started inside this chunk: the thread's first two from the
+    // loads above, any further ones loaded here (their fields are passed as
+    // scalars: a selection between whole vectors would keep them in
+    // private memory)
+    auto node = [&](int nd, int tb, int te) {
+        const int b = tb - c0;
         double s[kMomVals];
-        if (t.z <= cE) {
-            const int e = t.z - c0 - 1;
+        if (te >= 0) {
+            const int end = te & kMnodeEndMask;
+            const int e = end - c0 - 1;
 #pragma unroll
             for (int k = 0; k < kMomVals; ++k) s[k] = P[k][e] - (b > 0 ? P[k][b - 1] : 0.0);
-            write_moment<HI>(a, nd, t, s);
+            write_moment<HI>(a, nd, te >> kMnodeEndBits, end - tb == 1, s);
         } else {
-            const int sl = nd == nlo + tid ? sl0
-                                           : (nd == nlo + tid + kChunk ? sl1 : a.node_strad[nd]);
+            const int sl = -1 - te;
 #pragma unroll
             for (int k = 0; k < kMomVals; ++k)
                 a.head[kMomSlots * sl + k] = P[k][cnt - 1] - (b > 0 ? P[k][b - 1] : 0.0);
         }
+    };
+    if (nlo + tid < nhi) node(nlo + tid, t0.x, t0.y);
+    if (nlo + tid + kChunk < nhi) node(nlo + tid + kChunk, t1.x, t1.y);
+    for (int nd = nlo + tid + 2 * kChunk; nd < nhi; nd += kChunk) {
+        const int2 t = a.mnode[nd];
+        node(nd, t.x, t.y);
     }
     // straddlers whose range ends inside this chunk
-    for (int q = tlo + tid; q < thi; q += kChunk) {
-        const int2 tq = q == tlo + tid ? tq0 : a.tail_list[q];
-        const int sl = tq.x;
-        const int e = tq.y - c0 - 1;
+    auto tail = [&](int sl, int te) {
+        const int e = te - c0 - 1;
 #pragma unroll
         for (int k = 0; k < kMomVals; ++k) a.tail[kMomSlots * sl + k] = P[k][e];
+    };
+    if (tlo + tid < thi) tail(tq0.x, tq0.y);
+    for (int q = tlo + tid + kChunk; q < thi; q += kChunk) {
+        const int2 tq = a.tail_list[q];
+        tail(tq.x, tq.y);
     }
 }
 
 // Straddlers: head + totals of the chunks in between + tail.  A straddler
 // with at most a wavefront's worth of chunks in between is summed by one
-// wavefront, one chunk total per lane; a wide one (the nodes near the root)
-// by a whole workgroup of its own (the first n_wide workgroups), so that
-// every straddler's loads are in flight at once.  The loads of a
+// wavefront, one chunk total per lane; a wide one (the nodes near the root,
+// numbered first) by a whole workgroup of its own (the first n_wide
+// workgroups), so that every straddler's loads are in flight at once.  The loads of a
 // straddler's topology, head and tail do not depend on each other.  The
 // order of the additions is fixed (a DPP scan within a wavefront,
 // wavefronts in order).
@@ -300,9 +315,10 @@ __global__ __launch_bounds__(kStradBlock) void k_moments_strad(MomArgs a) {
     const int lane = tid & (kWave - 1);
     const int wv = tid / kWave;
     const int nchunks = (a.n + kChunk - 1) / kChunk;
+    // (the wide straddlers are slots 0 .. n_wide - 1)
     const bool wide = (int)blockIdx.x < a.n_wide;
-    const int sl = wide ? a.wide_list[blockIdx.x]
-                        : ((int)blockIdx.x - a.n_wide) * kStradWaves + wv;
+    const int sl = wide ? (int)blockIdx.x
+                        : a.n_wide + ((int)blockIdx.x - a.n_wide) * kStradWaves + wv;
     if (sl >= a.n_strad) return;  // (never in a wide workgroup)
     const int4 t = a.strad_topo[sl];
     const int nd = a.strad_node[sl];
@@ -320,7 +336,6 @@ __global__ __launch_bounds__(kStradBlock) void k_moments_strad(MomArgs a) {
         }
     }
     const int cb = t.y / kChunk, ce = (t.z - 1) / kChunk;
-    if (!wide && ce - cb - 1 > kWave) return;  // summed by a workgroup of its own
     double s[kMomVals];
 #pragma unroll
     for (int k = 0; k < kMomVals; ++k) s[k] = 0.0;
@@ -350,7 +365,7 @@ __global__ __launch_bounds__(kStradBlock) void k_moments_strad(MomArgs a) {
         double tot[kMomVals];
 #pragma unroll
         for (int k = 0; k < kMomVals; ++k) tot[k] = (hd[k] + s[k]) + tl[k];
-        write_moment<HI>(a, nd, t, tot);
+        write_moment<HI>(a, nd, topo_depth(t.w), false, tot);
     }
 }
 
@@ -385,7 +400,7 @@ hipError_t launch_moments_t(wnnc_ctx_s *ctx, MomMode mode, const MomArgs &a) {
     }
     if (e != hipSuccess || last) return e;
     const unsigned nb =
-        (unsigned)(a.n_wide + (a.n_strad + kStradWaves - 1) / kStradWaves);
+        (unsigned)(a.n_wide + (a.n_strad - a.n_wide + kStradWaves - 1) / kStradWaves);
     return launch_k(ev, true, k_moments_strad<HI>, dim3(nb), dim3(kStradBlock), st, a);
 }
 

@@ -406,16 +406,24 @@ __global__ __launch_bounds__(256) void k_node_cells(const int4 *__restrict__ top
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= m) return;
     const int4 t = topo[k];
-    mom[kRecStride * k + 3] = make_float4(__int_as_float(t.y), __int_as_float(t.z), 0.f, 0.f);
-    if ((t.w & kRecLeaf) && t.z - t.y == 1) {
+    // the parts of the record that no moment pass writes: flags,
+    // skip pointer, point range; of a single-point leaf, whose representative
+    // is its point whatever its attribute, also its position (hi = the
+    // point, lo = 0) and threshold (-1: every target takes it)
+    const bool single = (t.w & kRecLeaf) && t.z - t.y == 1;
+    float4 r0 = make_float4(0.f, 0.f, 0.f, __int_as_float(t.w & 31));
+    float4 r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (single) {
         const float4 q = pts[t.y];
-        cells[k] = make_float4(q.x, q.y, q.z, -1.0f);
-        // a single-point leaf's representative is its point whatever its
-        // attribute: position (hi = the point, lo = 0), flags and threshold
-        // (-1: every target takes it) are written here once; the moment
-        // pass writes only its attribute
-        mom[kRecStride * k] = make_float4(q.x, q.y, q.z, __int_as_float((t.w & 31) | kRecSingle));
-        mom[kRecStride * k + 2] = make_float4(0.f, 0.f, 0.f, -1.0f);
+        r0 = make_float4(q.x, q.y, q.z, __int_as_float((t.w & 31) | kRecSingle));
+        r2.w = -1.0f;
+    }
+    const float4 r1 = make_float4(0.f, 0.f, 0.f, __int_as_float(t.x));
+    const float4 r3 = make_float4(__int_as_float(t.y), __int_as_float(t.z), 0.f, 0.f);
+    float4 *ra = mom + kRecStride * k;
+    ra[0] = r0, ra[1] = r1, ra[2] = r2, ra[3] = r3;
+    if (single) {
+        cells[k] = make_float4(r0.x, r0.y, r0.z, -1.0f);
         return;
     }
     const int depth = t.w & 15;
@@ -436,44 +444,47 @@ __global__ __launch_bounds__(256) void k_gather_points(const float *__restrict__
     pts[i] = make_float4(P[3 * (int64_t)j], P[3 * (int64_t)j + 1], P[3 * (int64_t)j + 2], 0.0f);
 }
 
-// Straddlers: nodes whose point range crosses a chunk boundary.
+// Straddlers (nodes whose points cross a chunk boundary of the moment pass)
+// are numbered wide ones first: a wide straddler has more chunks in between
+// than a wavefront has lanes and is summed by a whole workgroup, the others
+// by a wavefront each.  On entry flag marks the straddlers; on return flag
+// marks the narrow ones and wflag the wide ones (both m + 1 entries, the
+// last 0, for the exclusive scans that number them).
+__global__ __launch_bounds__(256) void k_split_wide(const int4 *__restrict__ topo, int64_t m,
+                                                    uint32_t *__restrict__ flag,
+                                                    uint32_t *__restrict__ wflag) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m || !flag[k]) return;
+    const int4 t = topo[k];
+    const bool wide = (t.z - 1) / kChunk - t.y / kChunk - 1 > kWave;
+    flag[k] = wide ? 0u : 1u;
+    wflag[k] = wide ? 1u : 0u;
+}
+
+// Slot of every straddler (wide ones 0 .. n_wide - 1, then the narrow ones)
+// and the moment pass's view of every node.
 __global__ __launch_bounds__(256) void k_strad_compact(const uint32_t *__restrict__ flag,
                                                        const uint32_t *__restrict__ slot,
+                                                       const uint32_t *__restrict__ wflag,
+                                                       const uint32_t *__restrict__ wslot,
                                                        const int4 *__restrict__ topo, int64_t m,
                                                        int32_t *__restrict__ node_strad,
                                                        int32_t *__restrict__ strad_node,
-                                                       int4 *__restrict__ strad_topo) {
+                                                       int4 *__restrict__ strad_topo,
+                                                       int2 *__restrict__ mnode) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= m) return;
-    if (flag[k]) {
-        node_strad[k] = (int32_t)slot[k];
-        strad_node[slot[k]] = (int32_t)k;
-        strad_topo[slot[k]] = topo[k];
+    const int4 t = topo[k];
+    const int n_wide = (int)wslot[m];
+    const int sl = wflag[k] ? (int)wslot[k] : (flag[k] ? n_wide + (int)slot[k] : -1);
+    node_strad[k] = sl;
+    if (sl >= 0) {
+        strad_node[sl] = (int32_t)k;
+        strad_topo[sl] = t;
+        mnode[k] = make_int2(t.y, -1 - sl);
     } else {
-        node_strad[k] = -1;
+        mnode[k] = make_int2(t.y, t.z | (topo_depth(t.w) << kMnodeEndBits));
     }
-}
-
-// Wide straddlers: more chunks in between than a wavefront has lanes (the
-// moment pass sums them with a whole workgroup).  flag has ns + 1 entries,
-// the last 0, for the exclusive scan that numbers them.
-__global__ __launch_bounds__(256) void k_wide_flag(const int4 *__restrict__ strad_topo, int ns,
-                                                   uint32_t *__restrict__ flag) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s > ns) return;
-    uint32_t f = 0;
-    if (s < ns) {
-        const int4 t = strad_topo[s];
-        f = (t.z - 1) / kChunk - t.y / kChunk - 1 > kWave ? 1u : 0u;
-    }
-    flag[s] = f;
-}
-
-__global__ __launch_bounds__(256) void k_wide_compact(const uint32_t *__restrict__ flag,
-                                                      const uint32_t *__restrict__ slot, int ns,
-                                                      int32_t *__restrict__ list) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < ns && flag[s]) list[slot[s]] = s;
 }
 
 __global__ __launch_bounds__(256) void k_tail_count(const int32_t *__restrict__ strad_node,
@@ -606,6 +617,7 @@ hipError_t build_tree(wnnc_ctx_s *ctx, const float *P) {
     TRY(ctx->topo.ensure(m));
     TRY(ctx->node_strad.ensure(m));
     TRY(ctx->mom.ensure(kRecStride * m));
+    TRY(ctx->mnode.ensure(m));
     TRY(ctx->mflag.ensure(m + 1));
     TRY(ctx->mslot.ensure(m + 1));
 
@@ -617,20 +629,28 @@ hipError_t build_tree(wnnc_ctx_s *ctx, const float *P) {
     TRY(ctx->cells.ensure(m));
     hipLaunchKernelGGL(k_node_cells, dim3(blocks_for(m, 256)), dim3(256), 0, st, ctx->topo.p,
                        ctx->keys_a.p, ctx->pts.p, m, ctx->cells.p, ctx->mom.p);
+    TRY(ctx->wflag.ensure(m + 1));
+    TRY(ctx->wslot.ensure(m + 1));
+    TRY(hipMemsetAsync(ctx->wflag.p, 0, (size_t)(m + 1) * sizeof(uint32_t), st));
+    hipLaunchKernelGGL(k_split_wide, dim3(blocks_for(m, 256)), dim3(256), 0, st, ctx->topo.p, m,
+                       ctx->mflag.p, ctx->wflag.p);
     TRY(exclusive_scan_u32(ctx->mflag.p, ctx->mslot.p, m + 1, ctx->scan_tmp.p, st));
-    uint32_t ns32 = 0;
-    TRY(hipMemcpyAsync(&ns32, ctx->mslot.p + m, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    TRY(exclusive_scan_u32(ctx->wflag.p, ctx->wslot.p, m + 1, ctx->scan_tmp.p, st));
+    uint32_t nn32 = 0, nw32 = 0;
+    TRY(hipMemcpyAsync(&nn32, ctx->mslot.p + m, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    TRY(hipMemcpyAsync(&nw32, ctx->wslot.p + m, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     TRY(hipStreamSynchronize(st));
-    const int64_t ns = ns32;
+    const int64_t ns = (int64_t)nn32 + nw32;
     ctx->n_strad = (int32_t)ns;
+    ctx->n_wide = (int32_t)nw32;
     TRY(ctx->strad_node.ensure(ns + 1));
     TRY(ctx->strad_topo.ensure(ns + 1));
     TRY(ctx->tail_list.ensure(ns + 1));
     TRY(ctx->head.ensure((int64_t)kMomSlots * (ns + 1)));
     TRY(ctx->tail.ensure((int64_t)kMomSlots * (ns + 1)));
     hipLaunchKernelGGL(k_strad_compact, dim3(blocks_for(m, 256)), dim3(256), 0, st, ctx->mflag.p,
-                       ctx->mslot.p, ctx->topo.p, m, ctx->node_strad.p, ctx->strad_node.p,
-                       ctx->strad_topo.p);
+                       ctx->mslot.p, ctx->wflag.p, ctx->wslot.p, ctx->topo.p, m,
+                       ctx->node_strad.p, ctx->strad_node.p, ctx->strad_topo.p, ctx->mnode.p);
     // chunk -> straddlers whose range ends inside it (CSR); counts reuse mflag
     uint32_t *tcnt = ctx->u32_tmp.p;  // n+1 >= chunks+1 entries
     TRY(hipMemsetAsync(tcnt, 0, (size_t)(nchunks + 1) * sizeof(uint32_t), st));
@@ -644,18 +664,7 @@ hipError_t build_tree(wnnc_ctx_s *ctx, const float *P) {
     if (ns > 0)
         hipLaunchKernelGGL(k_tail_fill, dim3(blocks_for(ns, 256)), dim3(256), 0, st,
                            ctx->strad_node.p, ctx->topo.p, (int)ns, cursor, ctx->tail_list.p);
-    // wide straddlers (flags in mflag, their numbers in mslot: both free again)
-    hipLaunchKernelGGL(k_wide_flag, dim3(blocks_for(ns + 1, 256)), dim3(256), 0, st,
-                       ctx->strad_topo.p, (int)ns, ctx->mflag.p);
-    TRY(exclusive_scan_u32(ctx->mflag.p, ctx->mslot.p, ns + 1, ctx->scan_tmp.p, st));
-    uint32_t nw32 = 0;
-    TRY(hipMemcpyAsync(&nw32, ctx->mslot.p + ns, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    TRY(ctx->wide_list.ensure((int64_t)ns + 1));
-    if (ns > 0)
-        hipLaunchKernelGGL(k_wide_compact, dim3(blocks_for(ns, 256)), dim3(256), 0, st,
-                           ctx->mflag.p, ctx->mslot.p, (int)ns, ctx->wide_list.p);
     TRY(hipStreamSynchronize(st));
-    ctx->n_wide = (int32_t)nw32;
     TRY(hipMemsetAsync(ctx->pair_ctr.p, 0, kOpKinds * sizeof(unsigned long long), st));
     return hipGetLastError();
 }

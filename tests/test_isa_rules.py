@@ -1,10 +1,12 @@
 """The device code as compiled: every HIP source of the library and of the
 rate probes, built with the library's flags to gfx950 assembly, holds no
 scalar-memory store, atomic, write-back or discard (every store goes through
-vector memory) and no packed FP32 arithmetic (the flags disable it); and
-the record loads that the prefetching walk issues by inline assembly are
-left alone while in flight (no instruction names their registers before the
-wait, and no branch leaves that span).  CPU only: hipcc cross-compiles."""
+vector memory), no packed FP32 arithmetic (the flags disable it) and no
+kernel with private (scratch) memory, whose spills would be extra memory
+traffic and a per-launch set-up; and the record loads that the prefetching
+walk issues by inline assembly are left alone while in flight (no
+instruction names their registers before the wait, and no branch leaves
+that span).  CPU only: hipcc cross-compiles."""
 import glob
 import os
 import re
@@ -30,16 +32,43 @@ def _asm(src, out_dir):
     return src, open(out).read()
 
 
+_KERNEL_META = re.compile(r"^\s*\.name:\s+(\S+)\s*$|^\s*\.private_segment_fixed_size:\s+(\d+)",
+                          re.M)
+
+
+def private_sizes(text):
+    """{kernel symbol: private segment bytes per lane} from the metadata."""
+    out, name = {}, None
+    for m in _KERNEL_META.finditer(text):
+        if m.group(1) is not None:
+            name = m.group(1)
+        elif name is not None:
+            out[name] = int(m.group(2))
+    return out
+
+
 @pytest.mark.skipif(not os.path.exists(B.HIPCC), reason="hipcc not installed")
-def test_device_code_has_no_scalar_stores_and_no_packed_fp32():
+def test_device_code_has_no_scalar_stores_no_packed_fp32_and_no_scratch():
     srcs = B.sources() + [B.RATES_SRC]
     with tempfile.TemporaryDirectory() as d, ThreadPoolExecutor(max_workers=8) as ex:
         results = list(ex.map(lambda s: _asm(s, d), srcs))
     # real device code: the traversal's template instances alone are hundreds
     assert sum(text.count("s_endpgm") for _, text in results) > 300
+    kernels = 0
     for src, text in results:
         hits = FORBIDDEN.findall(text)
         assert not hits, (os.path.basename(src), sorted(set(hits)))
+        sizes = private_sizes(text)
+        kernels += len(sizes)
+        scratch = {k: v for k, v in sizes.items() if v}
+        assert not scratch, (os.path.basename(src), scratch)
+    assert kernels > 300
+
+
+def test_the_private_size_scan_reads_the_metadata():
+    meta = ("    .name:           _Z3fooPf\n    .private_segment_fixed_size: 0\n"
+            "    .name:           _Z3barPf\n    .private_segment_fixed_size: 16\n")
+    assert private_sizes(meta) == {"_Z3fooPf": 0, "_Z3barPf": 16}
 
 
 def test_the_scan_finds_what_it_looks_for():
