@@ -172,16 +172,35 @@ wnnc_status run_moments(wnnc_ctx_s *c, MomMode mode, const MomArgs &a) {
 // The walk an operator kind uses: the prefetching one or the plain one.
 int prefetch_of(const wnnc_ctx_s *c, Op op) { return c->pf_op[op] >= 0 ? c->pf_op[op] : c->prefetch; }
 
-wnnc_status run_traverse(wnnc_ctx_s *c, Op op, TravMode mode, const TravArgs &args) {
+// The walk and its combining pass; without the combining pass (combine =
+// false) the moment pass that follows runs it (run_moments_comb with the
+// same arguments).
+wnnc_status run_traverse(wnnc_ctx_s *c, Op op, TravMode mode, const TravArgs &args,
+                         bool combine = true) {
     TravArgs a = args;
     a.prefetch = prefetch_of(c, op);
     Timed tm(c, (int)op);
     HIPCHK(launch_traverse(c, op, mode, (c->flags & WNNC_FLAG_COUNT_PAIRS) != 0, a));
     tm.done();
-    Timed tc(c, kKindCombine);
-    HIPCHK(launch_combine(c, op, mode, a));
-    tc.done();
+    if (combine) {
+        Timed tc(c, kKindCombine);
+        HIPCHK(launch_combine(c, op, mode, a));
+        tc.done();
+    }
     c->calls[op] += 1;
+    return WNNC_OK;
+}
+
+wnnc_status run_moments_comb(wnnc_ctx_s *c, MomMode mode, const MomArgs &ma, Op op,
+                             const TravArgs &walk) {
+    MomArgs a = ma;
+    a.gtab = c->gtab.p;
+    a.ngroups = c->ngroups;
+    TravArgs t = walk;
+    t.prefetch = prefetch_of(c, op);
+    Timed tm(c, kKindMoments);
+    HIPCHK(launch_moments_comb(c, mode, a, t));
+    tm.done();
     return WNNC_OK;
 }
 
@@ -248,6 +267,7 @@ wnnc_status wnnc_destroy(wnnc_ctx ctx) {
     ctx->node_strad.release();
     ctx->strad_node.release();
     ctx->strad_topo.release();
+    ctx->gtab.release();
     ctx->wflag.release();
     ctx->wslot.release();
     ctx->tail_off.release();
@@ -971,6 +991,12 @@ static wnnc_status run_iterations(wnnc_ctx ctx, int iters, float w1, float w2, i
     HIPCHK(ctx->energy.ensure((int64_t)count * ctx->nclouds));
     float4 *mu = ctx->va.p, *tmp = ctx->vb.p, *r = ctx->vr.p;
     float *rho = ctx->rho.p;
+    // With the groups aligned to the moment pass's wavefronts, the moment
+    // pass that reads a walk's output also runs that walk's combining pass
+    // (one launch fewer); the G walk's is run by the next iteration's first
+    // moment pass.
+    TravArgs pend_g;
+    bool have_pend = false;
     for (int i = start; i <= stop; ++i) {
         const float wf = (float)schedule_width(sched, i, iters, w1, w2);
         double *erow = ctx->energy.p + (int64_t)(i - start) * ctx->nclouds;
@@ -984,27 +1010,40 @@ static wnnc_status run_iterations(wnnc_ctx ctx, int iters, float w1, float w2, i
         } else {
             MomArgs ma = mom_args(ctx, wf);
             ma.src4 = mu;
-            RETURN_IF(run_moments(ctx, MOM_VEC_SORTED, ma));
+            if (have_pend) {
+                RETURN_IF(run_moments_comb(ctx, MOM_COMB_RESCALE, ma, OP_G, pend_g));
+                have_pend = false;
+            } else {
+                RETURN_IF(run_moments(ctx, MOM_VEC_SORTED, ma));
+            }
             TravArgs ta = trav_args(ctx, wf);
             ta.src4 = mu;
             ta.rho = rho;
             ta.partial = ctx->partial.p;
-            RETURN_IF(run_traverse(ctx, OP_A, TR_RHO, ta));
             MomArgs mb = mom_args(ctx, wf);
             mb.srcs = rho;
-            RETURN_IF(run_moments(ctx, MOM_SCALAR_SORTED, mb));
+            const bool fuse = ctx->gtab_ok && mb.order == 0;
+            RETURN_IF(run_traverse(ctx, OP_A, TR_RHO, ta, !fuse));
+            if (fuse)
+                RETURN_IF(run_moments_comb(ctx, MOM_COMB_RHO, mb, OP_A, ta));
+            else
+                RETURN_IF(run_moments(ctx, MOM_SCALAR_SORTED, mb));
         }
         {
             TravArgs ta = trav_args(ctx, wf);
             ta.srcs = rho;
             ta.out4 = r;
             ta.partial = ctx->partial.p + nt;
-            RETURN_IF(run_traverse(ctx, OP_AT, TR_R, ta));
-        }
-        {
             MomArgs ma = mom_args(ctx, wf);
             ma.src4 = r;
-            RETURN_IF(run_moments(ctx, MOM_VEC_SORTED, ma));
+            const bool fuse = ctx->gtab_ok && ma.order == 0;
+            RETURN_IF(run_traverse(ctx, OP_AT, TR_R, ta, !fuse));
+            if (fuse)
+                RETURN_IF(run_moments_comb(ctx, MOM_COMB_R, ma, OP_AT, ta));
+            else
+                RETURN_IF(run_moments(ctx, MOM_VEC_SORTED, ma));
+        }
+        {
             TravArgs ta = trav_args(ctx, wf);
             ta.src4 = r;
             ta.partial = ctx->partial.p + 2 * nt;
@@ -1023,7 +1062,13 @@ static wnnc_status run_iterations(wnnc_ctx ctx, int iters, float w1, float w2, i
             ta.out4 = mu;
             ta.areas = areas;
             if (i == stop) ta.flips = flips;
-            RETURN_IF(run_traverse(ctx, OP_G, TR_RESCALE, ta));
+            // (the next iteration's first moment pass combines this walk)
+            const bool fuse = i < stop && ctx->gtab_ok && mom_args(ctx, wf).order == 0;
+            RETURN_IF(run_traverse(ctx, OP_G, TR_RESCALE, ta, !fuse));
+            if (fuse) {
+                pend_g = ta;
+                have_pend = true;
+            }
         }
     }
     ctx->last_energy_count = count;

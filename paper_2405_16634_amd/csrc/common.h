@@ -107,6 +107,8 @@ struct wnnc_ctx_s {
     DevBuf<int32_t> task_lo;       // nclouds + 1: group range of each cloud
     DevBuf<int4> split_groups;     // nsplit: first, last target; first, end part slot
     DevBuf<int32_t> split_slot;    // nsplit: group slot
+    DevBuf<int2> gtab;             // ngroups: part range of each group (when gtab_ok)
+    bool gtab_ok = false;          // groups are the 64-point blocks: a moment pass can combine
     DevBuf<float> parts;           // nparts * 3 * 64
     std::vector<int32_t> plan;     // host: recorded walks of the 64-target groups
     DevBuf<int32_t> d_plan;

@@ -66,6 +66,11 @@ hipError_t make_tasks(wnnc_ctx_s *ctx, int tpl, int split);
 
 // Moment pass (moments.hip): two launches, chunk pass then straddler pass.
 hipError_t launch_moments(wnnc_ctx_s *ctx, MomMode mode, const MomArgs &a);
+// A moment pass (MOM_COMB_*) whose chunk pass also runs the combining pass
+// of the walk ta just launched without it (needs a.gtab: every cloud starts
+// at a multiple of 64 points, one group per wavefront).
+hipError_t launch_moments_comb(wnnc_ctx_s *ctx, MomMode mode, const MomArgs &a,
+                               const TravArgs &ta);
 
 // Traversal (traverse.hip).
 // The walk kernel, then (when walks are split) the combining pass that adds

@@ -95,6 +95,12 @@ enum MomMode {
     MOM_SCALAR_CALLER = 3, // nu = s[perm[i]]; writes outs[i]
     MOM_AXPY = 4,          // nu = src4[i] + alpha * r4[i]; writes out4[i]
     MOM_CONST_HALF = 5,    // nu = 1/2 (scalar); writes outs[i]
+    // nu = the output of the walk just launched without its combining pass:
+    // the pass first runs that pass's epilogue for the split groups (its
+    // parts summed in order), 64-point groups aligned with its wavefronts
+    MOM_COMB_RHO = 6,      // A walk, TR_RHO: nu = rho (scalar)
+    MOM_COMB_R = 7,        // A^T walk, TR_R: nu = r
+    MOM_COMB_RESCALE = 8,  // G walk, TR_RESCALE: nu = the updated mu
 };
 
 // Key layout: the cloud index sits above the 45 Morton bits, so one sort
@@ -157,6 +163,8 @@ struct MomArgs {
     int n_wide;              // straddlers 0 .. n_wide - 1 are summed by a whole workgroup each
     int order;               // far-field order: 0 (Alg. 4), 1 or 2 (also writes momhi)
     int scalar;              // the attribute is scalar (set by launch_moments)
+    const int2 *gtab;        // MOM_COMB_*: per 64-point group, its parts [x, y) (x = y: whole walk)
+    int ngroups;             // MOM_COMB_*: groups
 };
 
 struct TravArgs {

@@ -31,6 +31,7 @@
 #include <float.h>
 
 #include "common.h"
+#include "epilogue.h"
 #include "internal.h"
 #include "wave.h"
 
@@ -165,8 +166,19 @@ __device__ inline void write_moment(const MomArgs &a, int node, int depth, bool 
     }
 }
 
+// The operator walk whose output a combining moment pass reads.
+template <int MODE>
+struct CombOf {
+    static constexpr int op = MODE == MOM_COMB_RHO ? OP_A : (MODE == MOM_COMB_R ? OP_AT : OP_G);
+    static constexpr int mode =
+        MODE == MOM_COMB_RHO ? TR_RHO : (MODE == MOM_COMB_R ? TR_R : TR_RESCALE);
+};
+
+// One chunk (the workgroup's): for the MOM_COMB_* modes ta is the walk's
+// arguments, else null.
 template <int MODE, bool HI>
-__global__ __launch_bounds__(kChunk) void k_moments_chunk(MomArgs a) {
+__device__ __forceinline__ void chunk_body(const MomArgs &a, const TravArgs *ta) {
+    constexpr bool COMB = MODE >= MOM_COMB_RHO;
     constexpr int kMomVals = mom_vals<HI>();
     __shared__ double P[kMomVals][kChunk];
     __shared__ double wtot[kMomVals][kChunk / kWave];
@@ -194,6 +206,29 @@ __global__ __launch_bounds__(kChunk) void k_moments_chunk(MomArgs a) {
     const int2 t1 = a.mnode[n1];
     const int2 tq0 = a.tail_list[max(min(tlo + tid, thi - 1), 0)];
 
+    // (MOM_COMB_*) the walk's combining pass for this wavefront's 64-point
+    // group if the group was walked in parts: its parts' sums in part order,
+    // then the walk's epilogue (output, per-group reduction), as k_combine
+    // does it
+    float4 cnu = make_float4(0.f, 0.f, 0.f, 0.f);
+    bool combined = false;
+    if constexpr (COMB) {
+        const int g = (c0 >> 6) + wv;  // (wavefront-uniform)
+        if (g < a.ngroups) {
+            const int2 pr = a.gtab[g];
+            if (pr.y > pr.x) {
+                constexpr int OP = CombOf<MODE>::op, TM = CombOf<MODE>::mode;
+                double s = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+                sum_parts<OP>(ta->parts, pr.x, pr.y, lane, s, gx, gy, gz);
+                double e = 0.0, e2 = 0.0;
+                unsigned nflip = 0;
+                if (i < a.n) finish_target<OP, TM>(*ta, i, s, gx, gy, gz, e, e2, nflip, cnu);
+                finish_group<TM>(*ta, g, g * kWave, lane, e, e2, nflip);
+                combined = true;
+            }
+        }
+    }
+
     double v[kMomVals];
 #pragma unroll
     for (int k = 0; k < kMomVals; ++k) v[k] = 0.0;
@@ -201,7 +236,15 @@ __global__ __launch_bounds__(kChunk) void k_moments_chunk(MomArgs a) {
         const float4 x = a.pts[i];
         float nu0 = 0.f, nu1 = 0.f, nu2 = 0.f;
         bool scalar = false;
-        if (MODE == MOM_VEC_SORTED) {
+        if constexpr (COMB) {
+            // (a whole walk wrote its output itself)
+            if (!combined) {
+                if (MODE == MOM_COMB_RHO) cnu.x = ta->rho[i];
+                else cnu = ta->out4[i];
+            }
+            nu0 = cnu.x, nu1 = cnu.y, nu2 = cnu.z;
+            scalar = MODE == MOM_COMB_RHO;
+        } else if (MODE == MOM_VEC_SORTED) {
             const float4 q = a.src4[i];
             nu0 = q.x, nu1 = q.y, nu2 = q.z;
         } else if (MODE == MOM_SCALAR_SORTED) {
@@ -296,6 +339,18 @@ __global__ __launch_bounds__(kChunk) void k_moments_chunk(MomArgs a) {
     }
 }
 
+template <int MODE, bool HI>
+__global__ __launch_bounds__(kChunk) void k_moments_chunk(MomArgs a) {
+    chunk_body<MODE, HI>(a, nullptr);
+}
+
+// The chunk pass that also runs the combining pass of the walk launched
+// before it (MOM_COMB_*; without the far field).
+template <int MODE>
+__global__ __launch_bounds__(kChunk) void k_moments_comb(MomArgs a, TravArgs ta) {
+    chunk_body<MODE, false>(a, &ta);
+}
+
 // Straddlers: head + totals of the chunks in between + tail.  A straddler
 // with at most a wavefront's worth of chunks in between is summed by one
 // wavefront, one chunk total per lane; a wide one (the nodes near the root,
@@ -369,6 +424,15 @@ __global__ __launch_bounds__(kStradBlock) void k_moments_strad(MomArgs a) {
     }
 }
 
+// The straddler pass (the call's last launch).
+template <bool HI>
+hipError_t launch_strad(wnnc_ctx_s *ctx, const MomArgs &a) {
+    const unsigned nb =
+        (unsigned)(a.n_wide + (a.n_strad - a.n_wide + kStradWaves - 1) / kStradWaves);
+    return launch_k(ctx->lev, true, k_moments_strad<HI>, dim3(nb), dim3(kStradBlock),
+                    ctx->stream, a);
+}
+
 template <bool HI>
 hipError_t launch_moments_t(wnnc_ctx_s *ctx, MomMode mode, const MomArgs &a) {
     const unsigned nchunks = (unsigned)((a.n + kChunk - 1) / kChunk);
@@ -397,11 +461,39 @@ hipError_t launch_moments_t(wnnc_ctx_s *ctx, MomMode mode, const MomArgs &a) {
         case MOM_CONST_HALF:
             e = launch_k(ev, last, k_moments_chunk<MOM_CONST_HALF, HI>, grid, block, st, a);
             break;
+        default:
+            break;
     }
     if (e != hipSuccess || last) return e;
-    const unsigned nb =
-        (unsigned)(a.n_wide + (a.n_strad - a.n_wide + kStradWaves - 1) / kStradWaves);
-    return launch_k(ev, true, k_moments_strad<HI>, dim3(nb), dim3(kStradBlock), st, a);
+    return launch_strad<HI>(ctx, a);
+}
+
+hipError_t launch_moments_comb(wnnc_ctx_s *ctx, MomMode mode, const MomArgs &args,
+                               const TravArgs &ta) {
+    MomArgs a = args;
+    a.scalar = mode == MOM_COMB_RHO;
+    if (a.order > 0 || !a.gtab || ta.tpl != 1) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((a.n + kChunk - 1) / kChunk)), block(kChunk);
+    const bool last = a.n_strad <= 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (mode) {
+        case MOM_COMB_RHO:
+            e = launch_k(ctx->lev, last, k_moments_comb<MOM_COMB_RHO>, grid, block, ctx->stream, a,
+                         ta);
+            break;
+        case MOM_COMB_R:
+            e = launch_k(ctx->lev, last, k_moments_comb<MOM_COMB_R>, grid, block, ctx->stream, a,
+                         ta);
+            break;
+        case MOM_COMB_RESCALE:
+            e = launch_k(ctx->lev, last, k_moments_comb<MOM_COMB_RESCALE>, grid, block,
+                         ctx->stream, a, ta);
+            break;
+        default:
+            break;
+    }
+    if (e != hipSuccess || last) return e;
+    return launch_strad<false>(ctx, a);
 }
 
 hipError_t launch_moments(wnnc_ctx_s *ctx, MomMode mode, const MomArgs &args) {

@@ -22,6 +22,7 @@
 #include <float.h>
 
 #include "common.h"
+#include "epilogue.h"
 #include "internal.h"
 #include "wave.h"
 
@@ -65,7 +66,6 @@ __device__ inline v16f rec_issue(const float4 *base, int node) {
 // The record is an operand, so that no read of it moves above the wait.
 __device__ inline void rec_wait(v16f &r) { asm volatile("s_waitcnt lgkmcnt(0)" : "+s"(r)); }
 
-constexpr double kInv4Pi = 0.0795774715459476678844;  // 1 / (4 pi)
 
 // Deferred subtrees (TPL = 1, plain walk, Alg. 4's far field): at most
 // kDeferEntries subtrees and kDeferTasks (subtree, target) tasks are held
@@ -290,91 +290,6 @@ __device__ inline bool lane_in(unsigned long long mask) {
 __device__ inline unsigned long long read_mask(uint32_t lo, uint32_t hi, int depth) {
     return (unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)lo, depth) |
            ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)hi, depth) << 32);
-}
-
-// Per-target epilogue from the FP64 sums of target t (sorted position);
-// accumulates the target's share of the per-group reductions.
-template <int OP, int MODE>
-__device__ inline void finish_target(const TravArgs &a, int t, double s, double gx, double gy,
-                                     double gz, double &e, double &e2, unsigned &nflip) {
-    if (MODE == TR_ACCUM) {
-        const int64_t j = a.tperm[t];
-        a.out[3 * j] = (float)(gx * kInv4Pi + (double)a.gradf[3 * j]);
-        a.out[3 * j + 1] = (float)(gy * kInv4Pi + (double)a.gradf[3 * j + 1]);
-        a.out[3 * j + 2] = (float)(gz * kInv4Pi + (double)a.gradf[3 * j + 2]);
-    } else if (MODE == TR_POSGRAD) {
-        // dL/dx = p + g grad F at the target's caller row
-        const int64_t j = a.tperm[t];
-        const double gj = (double)a.gc[j];
-        a.out[3 * j] = (float)(gx * kInv4Pi + gj * (double)a.gradf[3 * j]);
-        a.out[3 * j + 1] = (float)(gy * kInv4Pi + gj * (double)a.gradf[3 * j + 1]);
-        a.out[3 * j + 2] = (float)(gz * kInv4Pi + gj * (double)a.gradf[3 * j + 2]);
-    } else if (MODE == TR_OUT_CALLER) {
-        const int64_t j = a.tperm[t];
-        if (OP == OP_A) {
-            a.out[j] = (float)(s * (kInv4Pi * a.oscale));
-        } else {
-            const double sg = (OP == OP_G ? -kInv4Pi : kInv4Pi) * a.oscale;  // grad F = -G
-            a.out[3 * j] = (float)(gx * sg);
-            a.out[3 * j + 1] = (float)(gy * sg);
-            a.out[3 * j + 2] = (float)(gz * sg);
-        }
-    } else if (MODE == TR_RHO) {
-        const float rho = (float)(0.5 - s * kInv4Pi);
-        a.rho[t] = rho;
-        e += (double)rho * (double)rho;
-    } else if (MODE == TR_R) {
-        const float rx = (float)(gx * kInv4Pi), ry = (float)(gy * kInv4Pi),
-                    rz = (float)(gz * kInv4Pi);
-        a.out4[t] = make_float4(rx, ry, rz, 0.f);
-        e += (double)rx * rx + (double)ry * ry + (double)rz * rz;
-    } else if (MODE == TR_TSUM) {
-        const double tv = (double)(float)(s * kInv4Pi);
-        e += tv * tv;
-    } else if (MODE == TR_SCALE) {
-        const double tv = (double)(float)(s * kInv4Pi);
-        e += tv;
-        e2 += tv * tv;
-    } else if (MODE == TR_RESCALE) {
-        const float4 mu = a.src4[t];
-        const double g2 = gx * gx + gy * gy + gz * gz;
-        float4 o = mu;
-        if (g2 > 0.0 && g2 <= DBL_MAX) {
-            // the length kept: |mu| (Alg. 3), or a given area (Sec. 6.1.1)
-            const double mn = a.areas ? (double)a.areas[t]
-                                      : sqrt((double)mu.x * mu.x + (double)mu.y * mu.y +
-                                             (double)mu.z * mu.z);
-            const double f = mn / sqrt(g2);
-            o = make_float4((float)(gx * f), (float)(gy * f), (float)(gz * f), 0.f);
-        }
-        a.out4[t] = o;
-        if ((double)mu.x * gx + (double)mu.y * gy + (double)mu.z * gz < 0.0) ++nflip;
-    }
-}
-
-// Per-group reductions of a wavefront (one group slot), in a fixed order.
-template <int MODE>
-__device__ inline void finish_group(const TravArgs &a, int sl, int first, int lane, double e,
-                                    double e2, unsigned nflip) {
-    if (MODE == TR_RESCALE && a.flips) {
-        unsigned tot = nflip;
-#pragma unroll
-        for (int d = kWave / 2; d > 0; d >>= 1) tot += __shfl_xor(tot, d, kWave);
-        if (lane == 0 && tot) atomicAdd(a.flips + a.tcloud[first], (unsigned long long)tot);
-    }
-    // (fixed-order scans: reproducible; the last lane holds the sum)
-    if (MODE == TR_SCALE) {
-        e = wave_scan(e);
-        e2 = wave_scan(e2);
-        if (lane == kWave - 1) {
-            a.partial[sl] = e;
-            a.partial[a.nslots + sl] = e2;
-        }
-    }
-    if (MODE == TR_RHO || MODE == TR_R || MODE == TR_TSUM) {
-        e = wave_scan(e);
-        if (lane == kWave - 1) a.partial[sl] = e;
-    }
 }
 
 // One wavefront per task: TPL groups of 64 consecutive sorted targets
@@ -820,55 +735,29 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
     }
     double e = 0.0, e2 = 0.0;
     unsigned nflip = 0;
+    float4 nu;
 #pragma unroll
     for (int k = 0; k < TPL; ++k)
         if (valid[k])
             finish_target<OP, MODE>(a, first + k * kWave + lane, s[k], gx[k], gy[k], gz[k], e, e2,
-                                    nflip);
+                                    nflip, nu);
     finish_group<MODE>(a, tslot, first, lane, e, e2, nflip);
 }
 
 // Groups walked in parts: one wavefront per group adds its parts' sums in
-// part order (in FP64; the parts are FP32, each within 2^-24 of the sum of
-// its terms' magnitudes) and runs the epilogue.  The parts are loaded
-// kCombineBatch at a time, all in flight before the additions.
-constexpr int kCombineBatch = 4;
-
+// part order (sum_parts) and runs the epilogue.
 template <int OP, int MODE>
 __global__ __launch_bounds__(kWave) void k_combine(TravArgs a, const int4 *__restrict__ groups,
                                                    const int32_t *__restrict__ gslot) {
     const int lane = threadIdx.x;
     const int4 g = ldc_i4(groups + blockIdx.x);
     double s = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
-    for (int p0 = g.z; p0 < g.w; p0 += kCombineBatch) {
-        float v0[kCombineBatch], v1[kCombineBatch], v2[kCombineBatch];
-#pragma unroll
-        for (int u = 0; u < kCombineBatch; ++u) {
-            // (a part past the group's last reads the last one; not added)
-            const float *qp = a.parts + (int64_t)min(p0 + u, g.w - 1) * (3 * kWave);
-            v0[u] = qp[lane];
-            if (OP != OP_A) {
-                v1[u] = qp[kWave + lane];
-                v2[u] = qp[2 * kWave + lane];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kCombineBatch; ++u) {
-            if (p0 + u < g.w) {
-                if (OP == OP_A) {
-                    s += (double)v0[u];
-                } else {
-                    gx += (double)v0[u];
-                    gy += (double)v1[u];
-                    gz += (double)v2[u];
-                }
-            }
-        }
-    }
+    sum_parts<OP>(a.parts, g.z, g.w, lane, s, gx, gy, gz);
     double e = 0.0, e2 = 0.0;
     unsigned nflip = 0;
     const int t = g.x + lane;
-    if (t < g.y) finish_target<OP, MODE>(a, t, s, gx, gy, gz, e, e2, nflip);
+    float4 nu;
+    if (t < g.y) finish_target<OP, MODE>(a, t, s, gx, gy, gz, e, e2, nflip, nu);
     finish_group<MODE>(a, ldc_i(gslot + blockIdx.x), g.x, lane, e, e2, nflip);
 }
 

@@ -757,6 +757,21 @@ hipError_t make_tasks(wnnc_ctx_s *ctx, int tpl, int split) {
     }
     lo[ctx->nclouds] = g;
     const int64_t nt = (int64_t)tk.size(), ns = (int64_t)sg.size();
+    // per group, its part range, when the groups are the 64-point blocks of
+    // the sorted points (one group per wavefront, every cloud starting at a
+    // multiple of 64): a moment pass can then combine the parts itself
+    bool aligned = tpl == 1 && ns > 0;
+    for (int c = 0; c < ctx->nclouds && aligned; ++c) aligned = ctx->offsets[c] % kWave == 0;
+    ctx->gtab_ok = false;
+    if (aligned) {
+        std::vector<int2> gt((size_t)g, make_int2(0, 0));
+        for (int64_t q = 0; q < ns; ++q) gt[(size_t)sslot[q]] = make_int2(sg[q].z, sg[q].w);
+        TRY(ctx->gtab.ensure(g));
+        TRY(hipMemcpyAsync(ctx->gtab.p, gt.data(), (size_t)g * sizeof(int2), hipMemcpyHostToDevice,
+                           ctx->stream));
+        TRY(hipStreamSynchronize(ctx->stream));  // (gt is released on return)
+        ctx->gtab_ok = true;
+    }
     TRY(ctx->tasks.ensure(nt));
     TRY(ctx->task_slot.ensure(nt));
     TRY(ctx->task_lo.ensure(ctx->nclouds + 1));
