@@ -120,6 +120,11 @@ typedef struct {
 #define WNNC_FLAG_TIME_TRAVERSAL 8u /* time the traversal launches only (fills
                                        traverse_ms; about a third of the
                                        timing overhead of WNNC_FLAG_TIME_KERNELS) */
+#define WNNC_FLAG_SEPARATE_COMBINE 16u /* in Alg. 3's iterations, run the split
+                                          walks' combining passes as launches of
+                                          their own instead of inside the moment
+                                          pass that reads their output (the same
+                                          arithmetic, for checking; slower) */
 
 /* Operator kinds, indices of the per-kind statistics. */
 #define WNNC_OP_A 0

@@ -25,6 +25,7 @@ FLAG_COUNT_PAIRS = 1
 FLAG_TIME_KERNELS = 2
 FLAG_CHECK_FINITE = 4
 FLAG_TIME_TRAVERSAL = 8
+FLAG_SEPARATE_COMBINE = 16
 OP_A, OP_AT, OP_G = 0, 1, 2
 
 EXPORTED = [

@@ -348,7 +348,7 @@ wnnc_status wnnc_set_stream(wnnc_ctx ctx, void *stream) {
 wnnc_status wnnc_set_flags(wnnc_ctx ctx, unsigned flags) {
     CHECK_CTX(ctx);
     if (flags & ~(WNNC_FLAG_COUNT_PAIRS | WNNC_FLAG_TIME_KERNELS | WNNC_FLAG_CHECK_FINITE |
-                  WNNC_FLAG_TIME_TRAVERSAL))
+                  WNNC_FLAG_TIME_TRAVERSAL | WNNC_FLAG_SEPARATE_COMBINE))
         return fail(WNNC_EINVAL, "unknown flags 0x%x", flags);
     ctx->flags = flags;
     return WNNC_OK;
@@ -995,6 +995,7 @@ static wnnc_status run_iterations(wnnc_ctx ctx, int iters, float w1, float w2, i
     // pass that reads a walk's output also runs that walk's combining pass
     // (one launch fewer); the G walk's is run by the next iteration's first
     // moment pass.
+    const bool fuse_ok = ctx->gtab_ok && !(ctx->flags & WNNC_FLAG_SEPARATE_COMBINE);
     TravArgs pend_g;
     bool have_pend = false;
     for (int i = start; i <= stop; ++i) {
@@ -1022,7 +1023,7 @@ static wnnc_status run_iterations(wnnc_ctx ctx, int iters, float w1, float w2, i
             ta.partial = ctx->partial.p;
             MomArgs mb = mom_args(ctx, wf);
             mb.srcs = rho;
-            const bool fuse = ctx->gtab_ok && mb.order == 0;
+            const bool fuse = fuse_ok && mb.order == 0;
             RETURN_IF(run_traverse(ctx, OP_A, TR_RHO, ta, !fuse));
             if (fuse)
                 RETURN_IF(run_moments_comb(ctx, MOM_COMB_RHO, mb, OP_A, ta));
@@ -1036,7 +1037,7 @@ static wnnc_status run_iterations(wnnc_ctx ctx, int iters, float w1, float w2, i
             ta.partial = ctx->partial.p + nt;
             MomArgs ma = mom_args(ctx, wf);
             ma.src4 = r;
-            const bool fuse = ctx->gtab_ok && ma.order == 0;
+            const bool fuse = fuse_ok && ma.order == 0;
             RETURN_IF(run_traverse(ctx, OP_AT, TR_R, ta, !fuse));
             if (fuse)
                 RETURN_IF(run_moments_comb(ctx, MOM_COMB_R, ma, OP_AT, ta));
@@ -1063,7 +1064,7 @@ static wnnc_status run_iterations(wnnc_ctx ctx, int iters, float w1, float w2, i
             ta.areas = areas;
             if (i == stop) ta.flips = flips;
             // (the next iteration's first moment pass combines this walk)
-            const bool fuse = i < stop && ctx->gtab_ok && mom_args(ctx, wf).order == 0;
+            const bool fuse = i < stop && fuse_ok && mom_args(ctx, wf).order == 0;
             RETURN_IF(run_traverse(ctx, OP_G, TR_RESCALE, ta, !fuse));
             if (fuse) {
                 pend_g = ta;
