@@ -33,6 +33,7 @@ import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TRAVERSAL_SOURCES = [os.path.join(HERE, "csrc", "traverse.hip"),
+                     os.path.join(HERE, "csrc", "epilogue.h"),
                      os.path.join(HERE, "csrc", "layout.h"),
                      os.path.join(HERE, "csrc", "wave.h")]
 
