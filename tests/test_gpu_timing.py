@@ -57,7 +57,7 @@ def test_timed_run_is_identical_and_consistent():
         assert st3["traverse_ms"][k] > 0
         assert abs(st3["traverse_ms"][k] - st["traverse_ms"][k]) <= 0.2 * st["traverse_ms"][k]
     with pytest.raises(w.WnncError):
-        ctx.set_flags(16)
+        ctx.set_flags(1 << 12)
     # the untimed run after it gives the same result again
     mu2 = ctx.orient(40, 0.002, 0.016)
     assert bool((mu0 == mu2).all())
