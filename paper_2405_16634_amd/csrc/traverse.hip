@@ -317,10 +317,20 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
     // contiguous range of tasks (Morton-ordered targets) so its L2 sees one
-    // region of the tree.
+    // region of the tree.  Within an XCD, the workgroups of a block of
+    // kCuBlock go round-robin to its 32 CUs as well: workgroup j of a block
+    // takes task (j % 32) * (kCuBlock / 32) + j / 32, so that the tasks one
+    // CU runs are neighbours and share more of the tree in its scalar cache
+    // (a tail shorter than a block keeps the plain order).
+    constexpr int kCuBlock = 2048, kXcdCus = 32;
     const int G = gridDim.x, b = blockIdx.x;
     const int q = G >> 3, r = G & 7, x = b & 7;
-    const int lb = x * q + (x < r ? x : r) + (b >> 3);
+    int L = b >> 3;
+    if (L < (q + (x < r ? 1 : 0)) / kCuBlock * kCuBlock) {
+        const int j = L % kCuBlock;
+        L += (j % kXcdCus) * (kCuBlock / kXcdCus) + j / kXcdCus - j;
+    }
+    const int lb = x * q + (x < r ? x : r) + L;
     const int wave = lb * (kTravBlock / kWave) + wv;
     if (wave >= a.ntasks) return;
     const int4 task = ldc_i4(a.tasks + wave);
