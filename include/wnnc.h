@@ -245,13 +245,14 @@ wnnc_status wnnc_set_prefetch(wnnc_ctx ctx, int on);
 
 /* Autotuner: times three iterations of Alg. 3 at width w from mu = 0 (the
  * fastest of two runs after a warm-up run) for each of
- * WNNC_AUTOTUNE_CONFIGS settings on the current tree and keeps the fastest
- * (a setting later in the list must be faster by more than 1 %):
+ * WNNC_AUTOTUNE_CONFIGS settings on the current tree, times the settings
+ * within 3 % of the fastest again in turn (three rounds), and keeps the
+ * fastest (a setting later in the list must be faster by more than 1 %):
  * (tpl, split) = (1, 0), (2, 0), (4, 0), (1, 1024), (1, 512), (1, 256),
  * (1, 128), (1, 64), each with prefetch off and on (in that order); the
  * short splits fill the chip on small clouds (few target groups).  times_out (host,
  * WNNC_AUTOTUNE_CONFIGS entries, may be NULL) receives the settings and
- * their times per iteration.  Then, on the chosen tiles, each operator
+ * their times per iteration (the fastest run of each).  Then, on the chosen tiles, each operator
  * kind takes the other prefetch setting if its traversal launches are
  * faster with it by more than 1 % (see wnnc_stats_t.prefetch_ops).
  * Overwrites the context's iteration buffers; instrumentation statistics

@@ -616,23 +616,32 @@ wnnc_status wnnc_autotune(wnnc_ctx ctx, float w, wnnc_tile_time *times_out) {
     // and on the records the iteration makes).  The first run warms the
     // caches; then the fastest of kTuneReps.
     constexpr int kTuneIters = 3, kTuneReps = 2;
+    // the time per iteration of the tasks in place with prefetch pf: the
+    // fastest of reps runs after a warm-up
+    auto time_setting = [&](int pf, int reps, double *t) -> wnnc_status {
+        ctx->prefetch = pf;
+        *t = 1e300;
+        for (int rep = 0; rep <= reps; ++rep) {
+            HIPCHK(launch_zero_f4(ctx->va.p, ctx->n, ctx->stream));
+            HIPCHK(hipEventRecord(e0, ctx->stream));
+            RETURN_IF(run_iterations(ctx, kTuneIters, w, w, 1, kTuneIters, true, nullptr,
+                                     WNNC_SCHEDULE_LINEAR, nullptr));
+            HIPCHK(hipEventRecord(e1, ctx->stream));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (rep > 0) *t = std::min(*t, (double)ms / kTuneIters);
+        }
+        return WNNC_OK;
+    };
+    double tk[WNNC_AUTOTUNE_CONFIGS];
     for (int k = 0; k < WNNC_AUTOTUNE_CONFIGS / 2; ++k) {
         hipError_t e = make_tasks(ctx, cand[k][0], cand[k][1]);
         if (e != hipSuccess) return fail(WNNC_EDEVICE, "tasks: %s", hipGetErrorString(e));
         for (int pf = 0; pf < 2; ++pf) {
-            ctx->prefetch = pf;
-            double t = 1e300;
-            for (int rep = 0; rep <= kTuneReps; ++rep) {
-                HIPCHK(launch_zero_f4(ctx->va.p, ctx->n, ctx->stream));
-                HIPCHK(hipEventRecord(e0, ctx->stream));
-                RETURN_IF(run_iterations(ctx, kTuneIters, w, w, 1, kTuneIters, true, nullptr,
-                                         WNNC_SCHEDULE_LINEAR, nullptr));
-                HIPCHK(hipEventRecord(e1, ctx->stream));
-                HIPCHK(hipEventSynchronize(e1));
-                float ms = 0.f;
-                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                if (rep > 0) t = std::min(t, (double)ms / kTuneIters);
-            }
+            double t;
+            RETURN_IF(time_setting(pf, kTuneReps, &t));
+            tk[2 * k + pf] = t;
             if (times_out) {
                 wnnc_tile_time &o = times_out[2 * k + pf];
                 o.tpl = cand[k][0];
@@ -640,13 +649,39 @@ wnnc_status wnnc_autotune(wnnc_ctx ctx, float w, wnnc_tile_time *times_out) {
                 o.split = cand[k][1];
                 o.ms = t;
             }
-            // a later setting must be faster by more than 1 %: the choice
-            // stays put between settings within run-to-run noise
-            if (t < best_ms * 0.99) {
-                best_ms = t;
-                best = cand[k][0];
-                best_pf = pf;
-                best_split = cand[k][1];
+        }
+    }
+    // Settings within 3 % of the fastest are timed again, in turn over
+    // kRetimeRounds rounds (so that a drift of the clock between the first
+    // timings cannot decide), each keeping its fastest run; then, in list
+    // order, a later setting must be faster by more than 1 %: the choice
+    // stays put between settings within run-to-run noise.
+    constexpr int kRetimeRounds = 3;
+    {
+        double t0 = 1e300;
+        for (int c = 0; c < WNNC_AUTOTUNE_CONFIGS; ++c) t0 = std::min(t0, tk[c]);
+        std::vector<int> near;
+        for (int c = 0; c < WNNC_AUTOTUNE_CONFIGS; ++c)
+            if (tk[c] <= 1.03 * t0) near.push_back(c);
+        if (near.size() > 1) {
+            for (int round = 0; round < kRetimeRounds; ++round) {
+                for (int c : near) {
+                    hipError_t e = make_tasks(ctx, cand[c / 2][0], cand[c / 2][1]);
+                    if (e != hipSuccess) return fail(WNNC_EDEVICE, "tasks: %s", hipGetErrorString(e));
+                    double t;
+                    RETURN_IF(time_setting(c % 2, 1, &t));
+                    tk[c] = std::min(tk[c], t);
+                }
+            }
+        }
+        if (times_out)
+            for (int c = 0; c < WNNC_AUTOTUNE_CONFIGS; ++c) times_out[c].ms = tk[c];
+        for (int c = 0; c < WNNC_AUTOTUNE_CONFIGS; ++c) {
+            if (tk[c] < best_ms * 0.99) {
+                best_ms = tk[c];
+                best = cand[c / 2][0];
+                best_pf = c % 2;
+                best_split = cand[c / 2][1];
             }
         }
     }
