@@ -544,6 +544,13 @@ def main():
     step()
     torch.cuda.synchronize()
     st_all = ctx.stats()
+    # and once more with the split walks' combining passes as launches of
+    # their own (the moment passes alone, as the traffic counters took them)
+    ctx.set_flags(w.FLAG_TIME_KERNELS | w.FLAG_SEPARATE_COMBINE)
+    ctx.reset_stats()
+    step()
+    torch.cuda.synchronize()
+    st_sep = ctx.stats()
     ctx.set_flags(0)
 
     # build time and the main loop, separately (one more untimed-kernel step)
@@ -669,9 +676,13 @@ def main():
                  "prefetch_by_op": {KIND[k]: bool((st["prefetch_ops"] >> k) & 1) for k in range(3)}},
         "tile_autotune_ms": {f"tpl{k[0]}_pf{k[1]}_split{k[2]}": round(v, 4)
                              for k, v in tile_ms.items()},
+        # (the moment passes that read a split walk's output also run its
+        # combining pass; moments_separate times both as launches of their own)
         "moments_ms_per_step": round(st_all["moments_ms"], 3),
-        "moments_counters": moments_counters(st_all, calls_per_run),
         "combine_ms_per_step": round(st_all["combine_ms"], 3),
+        "moments_separate": {"moments_ms_per_step": round(st_sep["moments_ms"], 3),
+                             "combine_ms_per_step": round(st_sep["combine_ms"], 3)},
+        "moments_counters": moments_counters(st_sep, calls_per_run),
         "host_wall_s_per_step": round((t_host1 - t_host0) / args.steps, 4),
         "accuracy_vs_generator": {"P_co": round(pco, 5), "AE_pcd": round(ae, 6)},
         "context_paper_rtx3090_s": {"N=50k": 1.25, "N=500k": 31.63},
