@@ -321,12 +321,13 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs a) {
     // kCuBlock go round-robin to its 32 CUs as well: workgroup j of a block
     // takes task (j % 32) * (kCuBlock / 32) + j / 32, so that the tasks one
     // CU runs are neighbours and share more of the tree in its scalar cache
-    // (a tail shorter than a block keeps the plain order).
+    // (a tail shorter than a block keeps the plain order; the far-field walk,
+    // with its larger register footprint, is faster without it).
     constexpr int kCuBlock = 2048, kXcdCus = 32;
     const int G = gridDim.x, b = blockIdx.x;
     const int q = G >> 3, r = G & 7, x = b & 7;
     int L = b >> 3;
-    if (L < (q + (x < r ? 1 : 0)) / kCuBlock * kCuBlock) {
+    if (!HI && L < (q + (x < r ? 1 : 0)) / kCuBlock * kCuBlock) {
         const int j = L % kCuBlock;
         L += (j % kXcdCus) * (kCuBlock / kXcdCus) + j / kXcdCus - j;
     }
