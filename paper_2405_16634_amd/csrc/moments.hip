@@ -11,6 +11,8 @@
 // second launch (one wavefront per straddler, the whole workgroup for one
 // that spans more than a wavefront's worth of chunks).  All sums run in a
 // fixed order, so the moments are bitwise reproducible from run to run.
+// When the attribute is the output of a walk split into parts, the chunk
+// pass can also run that walk's combining pass first (k_moments_comb).
 //
 // With a far field of order 1 or 2 (an extension: the Taylor expansion of
 // the pair term about x_B) the same pass also sums raw moments about the
